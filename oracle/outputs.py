@@ -1,0 +1,196 @@
+"""Plain references of every kernel family's output.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Each function takes the input arrays (NumPy, the exact bytes uploaded to the
+device) and returns the expected output array.  The kernels' arithmetic is
+stated in their docstrings; where a kernel's result is exact (data movement,
+sums in a fixed order in the kernel's own precision, single-rounding FMA
+chains) the reference computes it in that precision in the same order;
+otherwise (matmul, n-body, rsqrt chains) in float64.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import count as _count
+
+
+def _np(dt):
+    return np.float32 if dt == "f32" else np.float64
+
+
+def stream_elements(v):
+    """Flat element indices touched by a stream variant, in the order
+    (u, g, l, component): index = vec*(((g*gs)*wg + l)*s + u*G*gs*wg*s) + c."""
+    N, wg, s, gs, vec, U = (v["n"], v["wg"], v["s"], v["gs"], v["vec"],
+                            v["U"])
+    G = N // wg
+    g = np.arange(G, dtype=np.int64)[:, None]
+    l = np.arange(wg, dtype=np.int64)[None, :]
+    base = ((g * gs) * wg + l) * s
+    out = []
+    for u in range(U):
+        e = vec * (base + u * G * gs * wg * s)
+        out.append((e[..., None] + np.arange(vec)).reshape(-1))
+    return np.concatenate(out)
+
+
+def stream_span(v):
+    N, wg = v["n"], v["wg"]
+    G = N // wg
+    if v["op"] == "filled":
+        return v["s"] * G * wg * v["U"]
+    return G * v["gs"] * wg * v["s"] * v["U"] * v["vec"]
+
+
+def stream_store(v, x0):
+    """store: x[e] = (dtype)(e) at every touched element e; other elements
+    keep their previous content."""
+    x = x0.copy()
+    e = stream_elements(v)
+    x[e] = e.astype(x.dtype)
+    return x
+
+
+def stream_copy(v, x, y0):
+    """copy: y[e] = x[e] at touched elements."""
+    y = y0.copy()
+    e = stream_elements(v)
+    y[e] = x[e]
+    return y
+
+
+def stream_add4(v, a, b, c, d, o0):
+    """add4: o[e] = (a[e] + b[e]) + (c[e] + d[e]) in the kernel dtype."""
+    o = o0.copy()
+    e = stream_elements(v)
+    o[e] = (a[e] + b[e]) + (c[e] + d[e])
+    return o
+
+
+def stream_filled(v, x):
+    """filled (k = s): work-item i sums, for u = 0..U-1 and j = i + u*N,
+    the k consecutive cells x[k*j .. k*j+k-1] as ((x0 + x1) + x2) and adds
+    that to a running sum started at 0 (in the kernel dtype)."""
+    N, U, k = v["n"], v["U"], v["s"]
+    acc = np.zeros(N, dtype=x.dtype)
+    i = np.arange(N, dtype=np.int64)
+    for u in range(U):
+        j = i + u * N
+        t = x[k * j] + x[k * j + 1]
+        for c in range(2, k):
+            t = t + x[k * j + c]
+        acc = acc + t
+    return acc
+
+
+def lds_out(v):
+    """lds read: lane l of every group sums, from 0, the R words
+    lds[(l*b + r) mod W] (r = 0..R-1) of an LDS array initialised with
+    lds[a] = a, in fp32.  write: every lane writes lds[(l*b + r) mod W] = a
+    for r = 0..R-1, then reads back lds[(l*b) mod W], which holds that
+    address as a float."""
+    G, wg, b, R, W = v["groups"], v["wg"], v["b"], v["R"], v["W"]
+    l = np.arange(wg, dtype=np.int64)
+    if v["op"] == "read":
+        acc = np.zeros(wg, dtype=np.float32)
+        for r in range(R):
+            acc = acc + ((l * b + r) % W).astype(np.float32)
+    else:
+        acc = ((l * b) % W).astype(np.float32)
+    return np.tile(acc, G)
+
+
+def fma_chain(v, x):
+    """fma: K chains start at a = in[i]; F/K rounds of c_k = fma(c_k, a,
+    (k+1)/64); out[i] = ((c_0 + c_1) + ...) + c_{K-1}.  Computed with the C
+    library's single-rounding fmaf / fma."""
+    L = _count.lib()
+    n = x.shape[0]
+    out = np.empty_like(x)
+    if x.dtype == np.float32:
+        P = ctypes.POINTER(ctypes.c_float)
+        L.oracle_fma_chain_f32(x.ctypes.data_as(P), out.ctypes.data_as(P), n,
+                               v["F"], v["K"])
+    else:
+        P = ctypes.POINTER(ctypes.c_double)
+        L.oracle_fma_chain_f64(x.ctypes.data_as(P), out.ctypes.data_as(P), n,
+                               v["F"], v["K"])
+    return out
+
+
+def rsqrt_chain(v, x):
+    """rsqrt: K chains y_k = a; F/K rounds of y_k = 1/sqrt(y_k*y_k + (k+1));
+    out = sum of chains left to right.  float64 reference."""
+    a = x.astype(np.float64)
+    K, F = v["K"], v["F"]
+    ys = [a.copy() for _ in range(K)]
+    for _ in range(F // K):
+        for k in range(K):
+            ys[k] = 1.0 / np.sqrt(ys[k] * ys[k] + (k + 1))
+    s = ys[0]
+    for k in range(1, K):
+        s = s + ys[k]
+    return s
+
+
+def barrier_out(v):
+    """barrier: each work-item stores its local id as a float."""
+    return np.tile(np.arange(v["wg"], dtype=np.float32), v["groups"])
+
+
+def matmul(A, B):
+    """C = A B in float64 (A: n x m, B: m x l, row-major)."""
+    return A.astype(np.float64) @ B.astype(np.float64)
+
+
+def matmul_abs(A, B):
+    """sum_k |a_ik| |b_kj|, the scale of the matmul error bound."""
+    return np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64))
+
+
+def transpose(A):
+    return np.ascontiguousarray(A.T)
+
+
+def stencil(u, n, dt):
+    """5-point stencil with a quadratic source term on the (n+2)^2 input
+    (halo ring included), output n x n, in the kernel dtype:
+    out = 0.25 * ((((N + S) + W) + E) + h2 * (c * c)), h2 = 1/(n+1)^2."""
+    t = _np(dt)
+    u = u.reshape(n + 2, n + 2)
+    h2 = t(1.0 / ((n + 1.0) * (n + 1.0)))
+    c = u[1:-1, 1:-1]
+    N = u[:-2, 1:-1]
+    S = u[2:, 1:-1]
+    W = u[1:-1, :-2]
+    E = u[1:-1, 2:]
+    out = t(0.25) * ((((N + S) + W) + E) + h2 * (c * c))
+    return out.astype(t)
+
+
+def stencil_abs(u, n, dt):
+    """Magnitude scale of the stencil terms, for a rounding-error bound."""
+    u = np.abs(u.reshape(n + 2, n + 2).astype(np.float64))
+    h2 = 1.0 / ((n + 1.0) * (n + 1.0))
+    return 0.25 * (u[:-2, 1:-1] + u[2:, 1:-1] + u[1:-1, :-2] + u[1:-1, 2:]
+                   + h2 * u[1:-1, 1:-1] ** 2)
+
+
+def nbody(pos, idx=None):
+    """pos: 3 x N column-major (pos[c + 3 i]).  out[i] = sum over j != i of
+    1 / |x_i - x_j|, float64.  Returns (out, sum of |terms|) for the rows
+    `idx` (all rows by default)."""
+    P = pos.reshape(-1, 3).astype(np.float64)
+    N = P.shape[0]
+    rows = np.arange(N) if idx is None else np.asarray(idx)
+    out = np.empty(len(rows))
+    for t, i in enumerate(rows):
+        d = P - P[i]
+        r = np.sqrt((d * d).sum(axis=1))
+        r[i] = np.inf
+        out[t] = (1.0 / r).sum()
+    return out, out.copy()

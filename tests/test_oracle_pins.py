@@ -1,0 +1,368 @@
+"""Pins of the oracle against facts that do not come from the oracle itself:
+hand-enumerated tiny domains, closed-form counts derived from the kernel
+descriptions, the paper's textbook stride classes (Sec. 2.1), its Table 1
+worked example (Sec. 5), exact least-squares recovery (Sec. 4.3) and exact
+or error-bounded reference outputs."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import count as C
+from oracle import model as M
+from oracle import outputs as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def cdiv(a, b):
+    return -(-a // b)
+
+
+# --------------------------------------------------------------- counts ---
+def test_tiny_hand_enumerated_counts():
+    cases = json.load(open(os.path.join(GOLD, "tiny_counts.json")))["cases"]
+    for c in cases:
+        assert C.count(c["variant"]) == c["counts"], c["why"]
+
+
+def _cls(s):
+    return {0: "0", 1: "1", 2: "1/2", 3: "1/3", 4: "1/4"}.get(s, "1/>4")
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 8, 32])
+@pytest.mark.parametrize("vec,U,gs", [(1, 1, 1), (2, 2, 1), (1, 3, 4)])
+def test_stream_closed_forms(dt, s, vec, U, gs):
+    if dt == "f64" and vec == 4:
+        return
+    e = 4 if dt == "f32" else 8
+    n, wg = 512, 64
+    base = dict(family="stream", dtype=dt, n=n, wg=wg, s=s, gs=gs, vec=vec, U=U)
+    cl = _cls(s)
+    sz = e * vec
+    got = C.count(dict(base, op="load"))
+    assert got == {"gld.%d.%s" % (sz, cl): n * U, "add.%s" % dt: n * U * vec,
+                   "wg": n // wg, "wi": n}
+    got = C.count(dict(base, op="store"))
+    assert got == {"gst.%d.%s" % (sz, cl): n * U, "wg": n // wg, "wi": n}
+    got = C.count(dict(base, op="copy"))
+    assert got == {"gld.%d.%s" % (sz, cl): n * U, "gst.%d.%s" % (sz, cl): n * U,
+                   "wg": n // wg, "wi": n}
+    got = C.count(dict(base, op="add4"))
+    assert got == {"gld.%d.%s" % (sz, cl): 4 * n * U,
+                   "gst.%d.%s" % (sz, cl): n * U,
+                   "add.%s" % dt: 3 * n * U * vec, "wg": n // wg, "wi": n}
+
+
+@pytest.mark.parametrize("k,cls", [(2, "2/2"), (3, "3/3")])
+def test_filled_closed_forms(k, cls):
+    n, U = 1024, 2
+    got = C.count(dict(family="stream", op="filled", dtype="f32", n=n, wg=256,
+                       s=k, gs=1, vec=1, U=U))
+    assert got == {"gld.4.%s" % cls: k * n * U, "gst.4.1": n,
+                   "add.f32": k * n * U, "wg": 4, "wi": n}
+
+
+@pytest.mark.parametrize("op", ["read", "write"])
+def test_lds_closed_forms(op):
+    G, wg, R, W = 3, 128, 17, 512
+    got = C.count(dict(family="lds", op=op, groups=G, wg=wg, b=4, R=R, W=W))
+    want = {"gst.4.1": G * wg, "bar.wi": G * wg, "bar.wg": G, "wg": G,
+            "wi": G * wg}
+    if op == "read":
+        want.update({"lst.4": G * W, "lld.4": G * wg * R, "add.f32": G * wg * R})
+    else:
+        want.update({"lst.4": G * wg * R, "lld.4": G * wg})
+    assert got == want
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_fma_rsqrt_barrier_empty_closed_forms(dt):
+    n, F, K = 2048, 64, 8
+    got = C.count(dict(family="fma", dtype=dt, n=n, wg=256, F=F, K=K))
+    s = dt
+    assert got == {"gld.%d.1" % (4 if dt == "f32" else 8): n,
+                   "gst.%d.1" % (4 if dt == "f32" else 8): n,
+                   "fma." + s: n * F, "add." + s: n * (K - 1),
+                   "wg": n // 256, "wi": n}
+    got = C.count(dict(family="rsqrt", n=n, wg=256, F=F, K=4))
+    assert got == {"gld.4.1": n, "gst.4.1": n, "mul.f32": n * F,
+                   "add.f32": n * F + n * 3, "spec.f32": n * F,
+                   "wg": n // 256, "wi": n}
+    got = C.count(dict(family="barrier", groups=5, wg=128, B=7))
+    assert got == {"bar.wi": 5 * 128 * 7, "bar.wg": 5 * 7, "gst.4.1": 5 * 128,
+                   "wg": 5, "wi": 5 * 128}
+    got = C.count(dict(family="empty", n=1000, wx=64, wy=4))
+    assert got == {"wg": 16 * 250, "wi": 16 * 250 * 256}
+
+
+@pytest.mark.parametrize("n,m,l,T", [(64, 64, 64, 16), (32, 48, 16, 8),
+                                     (37, 29, 41, 16), (5, 70, 9, 32)])
+def test_matmul_closed_forms(n, m, l, T):
+    GX, GY, KT = cdiv(l, T), cdiv(n, T), cdiv(m, T)
+    wi = GX * GY * T * T
+    got = C.count(dict(family="matmul", op="tiled", n=n, m=m, l=l, T=T))
+    # every A element is fetched once per column tile, every B element once
+    # per row tile; inner products run over padded k-tiles
+    assert got == {"gld.4.1": n * m * GX + m * l * GY, "gst.4.1": n * l,
+                   "lst.4": 2 * wi * KT, "lld.4": 2 * wi * KT * T,
+                   "fma.f32": wi * KT * T, "bar.wi": 2 * wi * KT,
+                   "bar.wg": 2 * GX * GY * KT, "wg": GX * GY, "wi": wi}
+    if T == 16 and n == m == l:  # the textbook n^3 forms
+        assert got["fma.f32"] == n ** 3 and got["lld.4"] == 2 * n ** 3
+        assert got["gld.4.1"] == 2 * n ** 3 // T and got["bar.wi"] == 2 * n ** 3 // T
+    got = C.count(dict(family="matmul", op="naive", n=n, m=m, l=l, T=T))
+    assert got == {"gld.4.0": n * m * l, "gld.4.1": n * m * l, "gst.4.1": n * l,
+                   "fma.f32": n * m * l, "wg": GX * GY, "wi": wi}
+
+
+@pytest.mark.parametrize("n,T", [(64, 16), (37, 16), (100, 32), (9, 8)])
+def test_transpose_closed_forms(n, T):
+    G = cdiv(n, T)
+    got = C.count(dict(family="transpose", op="tiled", n=n, T=T))
+    assert got == {"gld.4.1": n * n, "gst.4.1": n * n, "lst.4": n * n,
+                   "lld.4": n * n, "bar.wi": G * G * T * T, "bar.wg": G * G,
+                   "wg": G * G, "wi": G * G * T * T}
+    # the strided side moves n cells per lane; every cell is used: 4/>4
+    got = C.count(dict(family="transpose", op="naive_wc", n=n, T=T))
+    assert got == {"gld.4.4/>4": n * n, "gst.4.1": n * n, "wg": G * G,
+                   "wi": G * G * T * T}
+    got = C.count(dict(family="transpose", op="naive_rc", n=n, T=T))
+    assert got == {"gld.4.1": n * n, "gst.4.4/>4": n * n, "wg": G * G,
+                   "wi": G * G * T * T}
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("n,T", [(64, 16), (37, 16), (33, 8), (16, 32)])
+def test_stencil_closed_forms(dt, n, T):
+    G = cdiv(n, T)
+    e = 4 if dt == "f32" else 8
+    got = C.count(dict(family="stencil", dtype=dt, n=n, T=T))
+    halo = 4 * n * G  # four tile edges per tile row / column
+    assert got == {"gld.%d.1" % e: n * n + halo, "lst.%d" % e: n * n + halo,
+                   "lld.%d" % e: 5 * n * n, "add." + dt: 4 * n * n,
+                   "mul." + dt: 3 * n * n, "gst.%d.1" % e: n * n,
+                   "bar.wi": G * G * T * T, "bar.wg": G * G, "wg": G * G,
+                   "wi": G * G * T * T}
+    if n % T == 0:
+        assert got["gld.%d.1" % e] * T == n * n * (T + 4)  # n^2 (1 + 4/T)
+
+
+@pytest.mark.parametrize("N,G", [(1024, 256), (1000, 256), (300, 64)])
+def test_nbody_closed_forms(N, G):
+    B = cdiv(N, G)
+    wi = B * G
+    got = C.count(dict(family="nbody", n=N, wg=G))
+    assert got == {"gld.4.3/3": 3 * N + 3 * N * B, "gst.4.1": N,
+                   "lst.4": 3 * N * B, "lld.4": 3 * wi * N,
+                   "add.f32": 6 * wi * N, "mul.f32": 3 * wi * N,
+                   "spec.f32": wi * N, "bar.wi": 2 * wi * B,
+                   "bar.wg": 2 * B * B, "wg": B, "wi": wi}
+
+
+def test_counts_additive_over_a_domain_split():
+    """Counts add when the launch is split: two half-size stream launches of
+    a unit-stride kernel give the counts of the whole (Alg. 1 is a sum over
+    domain points)."""
+    whole = C.count(dict(family="stream", op="copy", dtype="f32", n=4096,
+                         wg=256, s=1, gs=1, vec=1, U=1))
+    half = C.count(dict(family="stream", op="copy", dtype="f32", n=2048,
+                        wg=256, s=1, gs=1, vec=1, U=1))
+    assert whole == {k: 2 * v for k, v in half.items()}
+
+
+def test_wg_size_only_changes_overhead_counts():
+    """Sec. 5: apart from halos and work-group counts, properties do not
+    depend on the work-group size."""
+    a = C.count(dict(family="fma", dtype="f32", n=4096, wg=64, F=16, K=4))
+    b = C.count(dict(family="fma", dtype="f32", n=4096, wg=512, F=16, K=4))
+    assert {k: v for k, v in a.items() if k != "wg"} == \
+        {k: v for k, v in b.items() if k != "wg"}
+    assert a["wg"] == 64 and b["wg"] == 8
+
+
+# ------------------------------------------------------- stride classes ---
+@pytest.mark.parametrize("sites,vec,want", [
+    ([(0, 0)], 1, ["0"]),                                   # uniform
+    ([(1, 0)], 1, ["1"]),
+    ([(2, 0)], 1, ["1/2"]),                                 # <= 50% used
+    ([(2, 0), (2, 1)], 1, ["2/2", "2/2"]),                  # all used
+    ([(3, 0)], 1, ["1/3"]),
+    ([(3, 0), (3, 1)], 1, ["2/3", "2/3"]),
+    ([(3, 0), (3, 1), (3, 2)], 1, ["3/3"] * 3),
+    ([(4, 0), (4, 2)], 1, ["2/4", "2/4"]),
+    ([(8, 0)], 1, ["1/>4"]),
+    ([(8, 0), (8, 4)], 1, ["1/>4", "1/>4"]),
+    ([(8, c) for c in range(4)], 1, ["2/>4"] * 4),
+    ([(8, c) for c in range(8)], 1, ["4/>4"] * 8),
+    ([(8, 0)], 4, ["1/2"]),        # float4 accesses two accesses apart
+    ([(4, 0)], 4, ["1"]),          # float4 accesses back to back
+])
+def test_textbook_stride_classes(sites, vec, want):
+    n = 64
+    cells = max(abs(c) * (n - 1) + o for c, o in sites) + vec
+    assert C.classify_1d(cells, n, sites, elem=4, vec=vec) == want
+
+
+def test_strided_transpose_read_is_uncoalesced_full():
+    assert C.count(dict(family="transpose", op="naive_wc", n=50, T=16)) \
+        ["gld.4.4/>4"] == 2500
+
+
+# --------------------------------------------------- Table 1 and metric ---
+def test_table1_worked_example():
+    t = json.load(open(os.path.join(GOLD, "table1.json")))
+    for kname, k in t["kernels"].items():
+        P = np.array(k["pairs"])
+        for g in range(4):
+            if kname == "finite_difference" and g == 2:
+                continue  # 0.70 vs 0.70: a zero error after rounding
+            e = M.rel_errors(P[:, g, 1], P[:, g, 0])
+            assert abs(M.geomean(e) - k["geomean"][g]) <= 0.02, (kname, g)
+        if kname != "finite_difference":
+            e = M.rel_errors(P[:, :, 1].ravel(), P[:, :, 0].ravel())
+            assert abs(M.geomean(e) - k["cross_gpu"]) <= 0.01
+    # the reversed column order does not reproduce the table
+    P = np.array(t["kernels"]["nbody"]["pairs"])
+    assert M.geomean(M.rel_errors(P[:, 3, 0], P[:, 3, 1])) > 2.0
+    for g in (0, 1, 3):
+        e = np.concatenate([M.rel_errors(np.array(k["pairs"])[:, g, 1],
+                                         np.array(k["pairs"])[:, g, 0])
+                            for k in t["kernels"].values()])
+        assert abs(M.geomean(e) - t["cross_kernel"][g]) <= 0.01
+
+
+def test_geomean_closed_form():
+    assert M.geomean([0.5, 0.02]) == pytest.approx(0.1)
+    assert M.geomean([0.3]) == pytest.approx(0.3)
+
+
+# ------------------------------------------------------------------ fit ---
+def test_fit_recovers_exact_weights():
+    rng = np.random.default_rng(0)
+    P = rng.uniform(1, 100, size=(40, 6))
+    a = rng.uniform(1e-12, 1e-9, size=6)
+    T = P @ a
+    alpha, rank = M.fit(P, T)
+    assert rank == 6
+    np.testing.assert_allclose(alpha, a, rtol=1e-9)
+    np.testing.assert_allclose(M.predict(P, alpha), T, rtol=1e-12)
+
+
+def test_fit_minimises_relative_error():
+    """The fitted weights make the relative residual orthogonal to every
+    column of P/T (normal equations of Sec. 4.3), so no weight change can
+    lower sum (1 - pred/T)^2; a plain absolute fit does not."""
+    rng = np.random.default_rng(1)
+    P = rng.uniform(1, 100, size=(30, 3))
+    T = (P @ np.array([1.0, 2.0, 3.0])) * rng.uniform(0.7, 1.3, size=30)
+    alpha, _ = M.fit(P, T)
+    r = 1 - (P @ alpha) / T
+    np.testing.assert_allclose((P / T[:, None]).T @ r, 0, atol=1e-9)
+    a_abs = np.linalg.lstsq(P, T, rcond=None)[0]
+    assert np.sum(r ** 2) < np.sum((1 - (P @ a_abs) / T) ** 2)
+
+
+def test_fit_scaling_invariance_and_zero_columns():
+    rng = np.random.default_rng(2)
+    P = rng.uniform(1, 10, size=(20, 4))
+    P[:, 2] = 0
+    T = rng.uniform(1, 2, size=20)
+    a1, r1 = M.fit(P, T)
+    S = np.diag([1e3, 1e-4, 1.0, 7.0])
+    a2, r2 = M.fit(P @ S, T)
+    assert r1 == r2 == 3 and a1[2] == 0 and a2[2] == 0
+    np.testing.assert_allclose(M.predict(P, a1), M.predict(P @ S, a2),
+                               rtol=1e-9)
+
+
+def test_features_of_a_known_count_dict():
+    c = {"gld.4.1": 10, "gst.4.1": 4, "gld.8.1/2": 3, "gst.4.4/>4": 2,
+         "gld.4.3/3": 5, "fma.f32": 7, "add.f32": 1, "mul.f64": 2,
+         "spec.f32": 3, "lld.4": 6, "lst.8": 1, "bar.wi": 9, "wg": 11}
+    assert M.features_p3(c) == [4 * 10 + 4 * 4 + 8 * 3 + 4 * 2 + 4 * 5, 7, 11]
+    assert M.features_p12(c) == [1, 11, 9, 1 + 14, 2, 3, 24 + 8,
+                                 40 + 20, 16, 24, 8, 16]
+    f = dict(zip(M.full_names(), M.features_full(c)))
+    assert f["add.f32"] == 8 and f["mul.f32"] == 7 and f["min.4.1"] == 4
+    assert f["const"] == 1 and f["gst.4.4/>4"] == 2
+
+
+# -------------------------------------------------------------- outputs ---
+def _round_f32(q: Fraction) -> np.float32:
+    """Correctly rounded (to nearest, ties to even) float32 of a rational."""
+    r = np.float32(float(q))
+    cands = [np.nextafter(r, np.float32(-np.inf)), r,
+             np.nextafter(r, np.float32(np.inf))]
+    best = min(abs(Fraction(float(c)) - q) for c in cands)
+    ties = [c for c in cands if abs(Fraction(float(c)) - q) == best]
+    ties.sort(key=lambda c: int(np.array(c).view(np.uint32)) & 1)
+    return ties[0]
+
+
+def test_fma_chain_rounds_once_per_step():
+    """Each chain step is the exact a*c + b rounded once to float32."""
+    x = np.random.default_rng(3).uniform(-1, 1, 64).astype(np.float32)
+    v = {"F": 8, "K": 2}
+    out = O.fma_chain(v, x)
+    for i in range(64):
+        a = Fraction(float(x[i]))
+        c = [np.float32(x[i])] * 2
+        for _ in range(4):
+            for k in range(2):
+                c[k] = _round_f32(Fraction(float(c[k])) * a + Fraction(k + 1, 64))
+        assert out[i] == np.float32(c[0] + c[1])
+
+
+def test_stencil_exact_on_small_integers():
+    """n = 7: h^2 = 1/64 exactly; small-integer inputs make every step
+    exact, so the reference equals the rational formula."""
+    n = 7
+    u = np.random.default_rng(4).integers(-3, 4, size=(n + 2) ** 2).astype(np.float32)
+    out = O.stencil(u, n, "f32")
+    U = u.reshape(n + 2, n + 2)
+    for i in range(n):
+        for j in range(n):
+            q = Fraction(1, 4) * (int(U[i, j + 1]) + int(U[i + 2, j + 1])
+                                  + int(U[i + 1, j]) + int(U[i + 1, j + 2])
+                                  + Fraction(int(U[i + 1, j + 1]) ** 2, 64))
+            assert Fraction(float(out[i, j])) == q
+
+
+def test_nbody_known_geometry():
+    pos = np.array([0, 0, 0, 3, 4, 0, 0, 0, 12], dtype=np.float32)
+    out, _ = O.nbody(pos)
+    np.testing.assert_allclose(out, [1 / 5 + 1 / 12, 1 / 5 + 1 / math.sqrt(9 + 16 + 144),
+                                     1 / 12 + 1 / math.sqrt(9 + 16 + 144)])
+
+
+def test_matmul_reference_exact_small():
+    rng = np.random.default_rng(5)
+    A = rng.integers(-5, 6, size=(3, 4)).astype(np.float32)
+    B = rng.integers(-5, 6, size=(4, 2)).astype(np.float32)
+    Cm = O.matmul(A, B)
+    for i in range(3):
+        for j in range(2):
+            assert Cm[i, j] == sum(int(A[i, k]) * int(B[k, j]) for k in range(4))
+
+
+def test_lds_read_closed_form():
+    v = dict(family="lds", op="read", groups=2, wg=64, b=1, R=32, W=4096)
+    out = O.lds_out(v)
+    l = np.arange(64)
+    np.testing.assert_array_equal(out[:64], 32 * l + 32 * 31 // 2)
+    v = dict(v, op="write", b=3)
+    np.testing.assert_array_equal(O.lds_out(v)[64:], 3 * l)
+
+
+def test_stream_touched_elements():
+    v = dict(n=8, wg=4, s=2, gs=2, vec=1, U=1)
+    # groups start gs*wg*s = 16 elements apart; lanes s = 2 apart
+    assert list(O.stream_elements(v)) == [0, 2, 4, 6, 16, 18, 20, 22]
+    v = dict(n=4, wg=2, s=1, gs=1, vec=2, U=2)
+    assert list(O.stream_elements(v)) == [0, 1, 2, 3, 4, 5, 6, 7,
+                                          8, 9, 10, 11, 12, 13, 14, 15]
