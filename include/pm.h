@@ -1,0 +1,227 @@
+/*
+ * pm.h -- C ABI of libpm: a hardware-fitted linear run-time model for
+ * MI355X (gfx950) after Stevens and Kloeckner, "A Unified, Hardware-Fitted,
+ * Cross-GPU Performance Model" (arXiv 1604.04997).
+ *
+ * The model (Sec. 2):  T(n) ~ sum_i alpha_i p_i(n).  The p_i are operation
+ * counts of a kernel variant -- global accesses by size, direction and
+ * amortized stride class (Sec. 2.1), LDS accesses, flops by kind and dtype
+ * (Sec. 2.2), barriers (Sec. 2.3), work-groups and a constant (Sec. 2.4).
+ * The alpha_i are fitted once per device to measured run times of
+ * performance-instructive kernels (Sec. 4).
+ *
+ * Conventions for every call:
+ *   - return value: pm_status, 0 on success, < 0 on error; no C++ exception
+ *     crosses this boundary; pm_last_error() gives a message for the last
+ *     failing call on the calling thread (valid until its next call);
+ *   - every array argument is owned by the caller; the library never frees
+ *     or keeps caller memory past the call (the *_device calls read and
+ *     write caller device memory asynchronously on the caller's stream,
+ *     until that stream reaches the point where the call was enqueued);
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device allocations on the context's device;
+ *   - a context is used by one thread at a time.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PM_OK = 0,
+    PM_EINVAL = -1,     /* bad argument or variant descriptor */
+    PM_ENOMEM = -2,     /* device memory (or the context's HBM budget) exhausted */
+    PM_EDEVICE = -3,    /* a HIP runtime call failed */
+    PM_ERANK = -4,      /* fit: no non-zero feature column */
+    PM_EOVERFLOW = -5,  /* a count does not fit in int64 */
+    PM_ETIMEDOUT = -6,  /* measure: deadline passed */
+    PM_EBUSY = -7       /* context in use */
+} pm_status;
+
+/* Kernel families (each is a hand-written HIP kernel of the suite). */
+enum {
+    PM_FAM_STREAM = 0,    /* global-memory stream (Sec. 4.1 stride-1/-2/-3 classes) */
+    PM_FAM_LDS = 1,       /* LDS reads / writes at a bank stride */
+    PM_FAM_FMA = 2,       /* FMA chains (Sec. 4.1 arithmetic operations) */
+    PM_FAM_RSQRT = 3,     /* rsqrt chains */
+    PM_FAM_BARRIER = 4,   /* barrier loops (Sec. 2.3) */
+    PM_FAM_EMPTY = 5,     /* empty kernel (Sec. 4.1, launch overhead) */
+    PM_FAM_MATMUL = 6,    /* tiled / naive matrix multiplication */
+    PM_FAM_TRANSPOSE = 7, /* LDS-tiled / naive transpose */
+    PM_FAM_STENCIL = 8,   /* 5-point finite difference stencil (Sec. 5) */
+    PM_FAM_NBODY = 9,     /* all-pairs n-body sum of 1/r (Sec. 5) */
+    PM_NFAMILY = 10
+};
+enum { PM_F32 = 0, PM_F64 = 1 };
+/* op values per family */
+enum { PM_STREAM_LOAD = 0, PM_STREAM_STORE = 1, PM_STREAM_COPY = 2,
+       PM_STREAM_ADD4 = 3, PM_STREAM_FILLED = 4 };
+enum { PM_LDS_READ = 0, PM_LDS_WRITE = 1 };
+enum { PM_MATMUL_TILED = 0, PM_MATMUL_NAIVE = 1 };
+enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC = 2 };
+
+/*
+ * One kernel variant: family + parameters (all sizes in elements).
+ *   STREAM    n[0] work-items (multiple of wg[0]), wg[0], stride = lane
+ *             stride s (FILLED: k in {2,3}), gstride = group stride,
+ *             vec = elements per access (1,2,4; 16 bytes max),
+ *             reps = accesses per work-item U.  Element of access u of
+ *             work-item (g,l): vec*(((g*gs)*wg + l)*s + u*G*gs*wg*s).
+ *   LDS       n[0] groups, wg[0], stride = bank stride b, reps = R,
+ *             words = W (power of two, multiple of wg, <= 16384)
+ *   FMA       dtype, n[0] work-items, wg[0], reps = F, chains = K (F%K==0,
+ *             K in {1,2,4,8,16})
+ *   RSQRT     n[0], wg[0], reps = F, chains = K (K in {1,2,4,8}); fp32
+ *   BARRIER   n[0] groups, wg[0], reps = B
+ *   EMPTY     n[0] = side of a virtual n x n matrix, wg[0] x wg[1]
+ *   MATMUL    op, n[0..2] = n, m, l (C[n,l] = A[n,m] B[m,l], row-major),
+ *             tile T in {8,16,32} (work-group T x T); fp32
+ *   TRANSPOSE op, n[0] = n (n x n, row-major), tile T in {8,16,32}; fp32
+ *   STENCIL   dtype, n[0] = interior side n (input (n+2)^2 with halo),
+ *             tile T in {8,16,32}
+ *   NBODY     n[0] bodies (positions 3 x n column-major), wg[0] block size
+ *             (64..1024, multiple of 64); fp32
+ * Unused fields must be zero.  `seed` is carried for the caller's records.
+ */
+typedef struct {
+    uint32_t family, dtype, op, flags;
+    int64_t n[3];
+    int32_t wg[2];
+    int32_t tile, stride, gstride, vec, reps, chains, words, pad;
+    uint64_t seed;
+} pm_variant;
+
+/*
+ * Count vector (int64), layout:
+ *   [0, 90)    global accesses [dir][size][class]: dir 0 load / 1 store,
+ *              size 4/8/16 bytes, class 0 '0', 1 '1', 2..3 '1/2','2/2',
+ *              4..6 '1/3'..'3/3', 7..10 '1/4'..'4/4', 11..14 '1/>4'..'4/>4'
+ *   [90, 96)   LDS accesses [dir][size]
+ *   [96, 108)  flops [kind][dtype]: kind add/sub, mul, div, exp/pow,
+ *              special (rsqrt, sqrt, ...), fma; dtype f32, f64
+ *   108 barriers summed over work-items, 109 barriers summed over groups,
+ *   110 work-groups, 111 work-items
+ * pm_count_name() gives the name of each slot.
+ */
+#define PM_NCOUNT 112
+typedef struct { int64_t c[PM_NCOUNT]; } pm_counts;
+
+/* Feature projections of a count vector:
+ *   PM_PROJ_P3    [global load+store bytes, fp32 FMAs, work-groups]
+ *   PM_PROJ_P12   [1, work-groups, barriers (sum over work-items),
+ *                  fp32 add+mul (FMA = 2), fp64 add+mul, special+div+exp,
+ *                  LDS bytes, global-load bytes of classes 0,1,2/2,3/3,4/4,
+ *                  global-store bytes of those classes, global-load bytes
+ *                  of the other classes, global-store bytes of those,
+ *                  min(stride-1 load bytes, stride-1 store bytes)]
+ *   PM_PROJ_FULL  the paper's property list: 90 global access counts,
+ *                  6 LDS counts, 10 flop counts (FMA = one add and one mul),
+ *                  barriers, work-groups, const 1, 45 min(load, store)
+ *                  counts per (size, class) -- 154 features */
+enum { PM_PROJ_P3 = 0, PM_PROJ_P12 = 1, PM_PROJ_FULL = 2 };
+#define PM_NFEAT_MAX 160
+typedef struct {
+    uint32_t nfeat, proj;
+    double alpha[PM_NFEAT_MAX]; /* seconds per unit of each feature */
+} pm_model;
+
+typedef struct pm_ctx pm_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the context may hold (0 = 64 GiB).  Owns its streams,
+ * events and device arenas. */
+pm_status pm_create(pm_ctx **out, int device, size_t hbm_budget_bytes);
+void pm_destroy(pm_ctx *ctx);
+const char *pm_last_error(void);
+
+/* Name of count slot i (0 <= i < PM_NCOUNT), e.g. "gld.4.1/2", "fma.f32". */
+pm_status pm_count_name(int i, char *buf, size_t cap);
+
+/*
+ * Kernel properties of nv variants (host arrays v[nv], out[nv]), counted on
+ * the GPU by enumerating each variant's iteration domain: per instruction
+ * the number of points of its guarded domain (Sec. 3.2, Alg. 1 and
+ * Eq. opcount), per array the footprint and its gap-filled counterpart
+ * (Alg. 2) that fix the amortized stride fraction (Sec. 2.1).  All nv
+ * variants are counted together in one batched pass; the result does not
+ * depend on nv or on the batch's composition.  Synchronous.
+ * Errors: PM_EINVAL for an invalid descriptor (the message names the
+ * variant), PM_EOVERFLOW if a count exceeds int64, PM_ENOMEM if a single
+ * variant's footprint bitmaps exceed the HBM budget.
+ */
+pm_status pm_count(pm_ctx *ctx, const pm_variant *v, size_t nv, pm_counts *out);
+
+/* pm_count followed by T = sum_i alpha_i f_i(counts) (Sec. 2) for each
+ * variant, in FP64.  t_sec: host array [nv]. */
+pm_status pm_predict(pm_ctx *ctx, const pm_model *m, const pm_variant *v,
+                     size_t nv, double *t_sec);
+
+/*
+ * Device-resident batched path: d_v[nv] (device) -> d_counts[nv] (device,
+ * may be NULL), d_t[nv] (device, FP64 predictions with model m; ignored if
+ * m or d_t is NULL), d_status[nv] (device int32: 0 or a pm_status per
+ * variant).  Enqueued on `hip_stream` (a hipStream_t; NULL = the context's
+ * stream); returns without waiting.  Variants whose footprint bitmaps do
+ * not fit in the context's bitmap arena get status PM_ENOMEM and are not
+ * counted; pm_reserve() sizes the arena.  At most PM_BATCH_MAX variants.
+ */
+#define PM_BATCH_MAX 65536
+pm_status pm_count_device(pm_ctx *ctx, const pm_variant *d_v, size_t nv,
+                          pm_counts *d_counts, const pm_model *m, double *d_t,
+                          int32_t *d_status, void *hip_stream);
+
+/* Size the context's device arenas for batches of up to nv variants whose
+ * footprint bitmaps total up to bitmap_bytes.  Fails with PM_ENOMEM beyond
+ * the HBM budget. */
+pm_status pm_reserve(pm_ctx *ctx, size_t nv, size_t bitmap_bytes);
+
+/* Bytes of footprint bitmap one variant needs (host computation). */
+pm_status pm_bitmap_bytes(const pm_variant *v, size_t *bytes);
+
+/* Derived features of one count vector (host): f[*nfeat]. */
+pm_status pm_features(const pm_counts *c, uint32_t proj, double *f,
+                      uint32_t *nfeat);
+
+/*
+ * Fit (Sec. 4.3): the weights minimising sum_j (1 - sum_i a_i f_ji / T_j)^2
+ * over nrows measured variants (counts P[nrows], run times T[nrows] in
+ * seconds), by column-pivoted Householder QR in FP64 on the host.  Feature
+ * columns that are zero in every row are left out and get weight 0.
+ * out: the model; cond (nullable): |R_00| / |R_rr| of the kept columns;
+ * resid (nullable, [nrows]): 1 - pred_j / T_j; rank (nullable).
+ * PM_ERANK if no column is non-zero.
+ */
+pm_status pm_fit(const pm_counts *P, const double *T, size_t nrows,
+                 uint32_t proj, pm_model *out, double *cond, double *resid,
+                 uint32_t *rank);
+
+/* Device buffers a variant's kernel takes: bytes[i] and role[i] (0 input,
+ * 1 output, 2 input+output, 3 sentinel output that must stay unchanged),
+ * *nbufs <= PM_MAXBUF. */
+#define PM_MAXBUF 8
+pm_status pm_buffers(const pm_variant *v, size_t *bytes, uint32_t *role,
+                     uint32_t *nbufs);
+
+/* Launch the variant's kernel once on `hip_stream` (async).  bufs: device
+ * pointers as listed by pm_buffers, each at least that many bytes. */
+pm_status pm_launch(pm_ctx *ctx, const pm_variant *v, void *const *bufs,
+                    const size_t *bytes, uint32_t nbufs, void *hip_stream);
+
+/*
+ * Measure (Sec. 4.2): `warmup` untimed launches, then `reps` launches each
+ * timed with HIP events on `hip_stream`; t_reps[reps] (nullable) receives
+ * each time in seconds and *t_min the minimum.  Synchronous.
+ */
+pm_status pm_measure(pm_ctx *ctx, const pm_variant *v, void *const *bufs,
+                     const size_t *bytes, uint32_t nbufs, void *hip_stream,
+                     int warmup, int reps, double *t_reps, double *t_min);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_H */

@@ -1,0 +1,451 @@
+// C ABI of libpm (include/pm.h): contexts, counting, prediction, fit,
+// kernel launch and measurement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "counter.h"
+#include "desc.h"
+#include "fit.h"
+#include "pm.h"
+#include "pm_testing.h"
+#include "suite.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+const char *status_name(int s) {
+    switch (s) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid descriptor or argument";
+    case PM_ENOMEM: return "out of device memory / HBM budget";
+    case PM_EDEVICE: return "HIP runtime error";
+    case PM_ERANK: return "no non-zero feature column";
+    case PM_EOVERFLOW: return "count exceeds int64";
+    case PM_ETIMEDOUT: return "deadline passed";
+    case PM_EBUSY: return "context busy";
+    }
+    return "unknown";
+}
+
+#define HIPCHK(x)                                                               \
+    do {                                                                        \
+        hipError_t e_ = (x);                                                    \
+        if (e_ != hipSuccess)                                                   \
+            return set_err(PM_EDEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Validation by expanding the descriptor on the host.
+struct HostBuild {
+    std::unique_ptr<pm::Prog> prog{new pm::Prog};
+    std::unique_ptr<pm::Job[]> jobs{new pm::Job[pm::MAXJOB]};
+};
+thread_local HostBuild g_hb;
+
+int validate(const pm_variant *v) {
+    if (!v) return set_err(PM_EINVAL, "null variant");
+    int st = pm::build_prog(*v, g_hb.prog.get(), g_hb.jobs.get());
+    if (st != PM_OK)
+        return set_err(st, std::string("variant of family ") + std::to_string(v->family) +
+                               ": " + status_name(st));
+    return PM_OK;
+}
+
+// Restores the calling thread's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct pm_ctx {
+    int device = 0;
+    size_t budget = 0;
+    int n_cu = 256;
+    hipStream_t stream = nullptr;
+    pm::Arena ar;
+    size_t arena_alloc = 0;  // bytes held by ar (without bitmap)
+    size_t bitmap_alloc = 0;
+    // host-call staging
+    pm_variant *d_var = nullptr;
+    pm_counts *d_counts = nullptr;
+    double *d_pred = nullptr;
+    int32_t *d_status = nullptr;
+    pm_variant *h_var = nullptr;
+    pm_counts *h_counts = nullptr;
+    double *h_pred = nullptr;
+    int32_t *h_status = nullptr;
+    int64_t *h_meta = nullptr;
+    std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+void free_arena(pm_ctx *c) {
+    pm::Arena &a = c->ar;
+    (void)hipFree(a.prog);
+    (void)hipFree(a.jobs);
+    (void)hipFree(a.varwords);
+    (void)hipFree(a.varoff);
+    (void)hipFree(a.jobpref);
+    (void)hipFree(a.arrpref);
+    (void)hipFree(a.jobres);
+    (void)hipFree(a.foot);
+    (void)hipFree(a.meta);
+    (void)hipFree(c->d_var);
+    (void)hipFree(c->d_counts);
+    (void)hipFree(c->d_pred);
+    (void)hipFree(c->d_status);
+    (void)hipHostFree(c->h_var);
+    (void)hipHostFree(c->h_counts);
+    (void)hipHostFree(c->h_pred);
+    (void)hipHostFree(c->h_status);
+    uint64_t *bm = a.bitmap;
+    size_t bw = a.bitmap_words;
+    a = pm::Arena{};
+    a.bitmap = bm;
+    a.bitmap_words = bw;
+    c->d_var = nullptr;
+    c->d_counts = nullptr;
+    c->d_pred = nullptr;
+    c->d_status = nullptr;
+    c->h_var = nullptr;
+    c->h_counts = nullptr;
+    c->h_pred = nullptr;
+    c->h_status = nullptr;
+    c->arena_alloc = 0;
+}
+
+int grow_cap(pm_ctx *c, size_t nv) {
+    if (nv <= c->ar.cap) return PM_OK;
+    size_t cap = std::max<size_t>(nv, std::min<size_t>(2 * c->ar.cap, PM_BATCH_MAX));
+    cap = std::max(cap, nv);
+    size_t per = pm::arena_bytes_per_variant() + sizeof(pm_variant) + sizeof(pm_counts) +
+                 sizeof(double) + sizeof(int32_t);
+    if (per * cap + c->bitmap_alloc > c->budget)
+        return set_err(PM_ENOMEM, "batch arena exceeds the context's HBM budget");
+    (void)hipStreamSynchronize(c->stream);
+    free_arena(c);
+    pm::Arena &a = c->ar;
+    HIPCHK(hipMalloc(&a.prog, sizeof(pm::Prog) * cap));
+    HIPCHK(hipMalloc(&a.jobs, sizeof(pm::Job) * cap * pm::MAXJOB));
+    HIPCHK(hipMalloc(&a.varwords, 8 * cap));
+    HIPCHK(hipMalloc(&a.varoff, 8 * cap));
+    HIPCHK(hipMalloc(&a.jobpref, 8 * cap * pm::MAXJOB));
+    HIPCHK(hipMalloc(&a.arrpref, 8 * cap * pm::MAXARR));
+    HIPCHK(hipMalloc(&a.jobres, 8 * cap * pm::MAXJOB));
+    HIPCHK(hipMalloc(&a.foot, 16 * cap * pm::MAXARR));
+    HIPCHK(hipMalloc(&a.meta, 64));
+    HIPCHK(hipMalloc(&c->d_var, sizeof(pm_variant) * cap));
+    HIPCHK(hipMalloc(&c->d_counts, sizeof(pm_counts) * cap));
+    HIPCHK(hipMalloc(&c->d_pred, sizeof(double) * cap));
+    HIPCHK(hipMalloc(&c->d_status, sizeof(int32_t) * cap));
+    HIPCHK(hipHostMalloc(&c->h_var, sizeof(pm_variant) * cap, 0));
+    HIPCHK(hipHostMalloc(&c->h_counts, sizeof(pm_counts) * cap, 0));
+    HIPCHK(hipHostMalloc(&c->h_pred, sizeof(double) * cap, 0));
+    HIPCHK(hipHostMalloc(&c->h_status, sizeof(int32_t) * cap, 0));
+    a.cap = cap;
+    c->arena_alloc = per * cap;
+    return PM_OK;
+}
+
+int grow_bitmap(pm_ctx *c, size_t words) {
+    if (words <= c->ar.bitmap_words) return PM_OK;
+    size_t w = std::max(words, c->ar.bitmap_words * 2);
+    if (c->arena_alloc + w * 8 > c->budget) w = words;
+    if (c->arena_alloc + w * 8 > c->budget)
+        return set_err(PM_ENOMEM, "footprint bitmaps exceed the context's HBM budget");
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->ar.bitmap);
+    c->ar.bitmap = nullptr;
+    c->ar.bitmap_words = 0;
+    c->bitmap_alloc = 0;
+    HIPCHK(hipMalloc(&c->ar.bitmap, w * 8));
+    c->ar.bitmap_words = w;
+    c->bitmap_alloc = w * 8;
+    return PM_OK;
+}
+
+// Count (and optionally predict) nv <= cap variants from host memory.
+int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
+                   const pm_model *m, double *t) {
+    int st = grow_cap(c, nv);
+    if (st) return st;
+    std::memcpy(c->h_var, v, sizeof(pm_variant) * nv);
+    for (int attempt = 0; attempt < 2; attempt++) {
+        HIPCHK(hipMemcpyAsync(c->d_var, c->h_var, sizeof(pm_variant) * nv, hipMemcpyHostToDevice, c->stream));
+        st = pm::launch_batch(c->ar, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
+                              c->d_status, c->stream, c->n_cu);
+        if (st) return set_err(st, "counter launch failed");
+        HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_meta, c->ar.meta, 64, hipMemcpyDeviceToHost, c->stream));
+        if (out) HIPCHK(hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(pm_counts) * nv, hipMemcpyDeviceToHost, c->stream));
+        if (m) HIPCHK(hipMemcpyAsync(c->h_pred, c->d_pred, 8 * nv, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        bool nomem = false;
+        for (size_t i = 0; i < nv; i++) nomem |= c->h_status[i] == PM_ENOMEM;
+        if (!nomem) break;
+        if (attempt == 1) return set_err(PM_ENOMEM, "footprint bitmaps do not fit");
+        st = grow_bitmap(c, (size_t)c->h_meta[4]);
+        if (st) return st;
+    }
+    int first = PM_OK;
+    for (size_t i = 0; i < nv; i++) {
+        if (c->h_status[i] != PM_OK && first == PM_OK) {
+            first = c->h_status[i];
+            set_err(first, "variant " + std::to_string(i) + ": " + status_name(first));
+        }
+    }
+    if (out) std::memcpy(out, c->h_counts, sizeof(pm_counts) * nv);
+    if (m && t) std::memcpy(t, c->h_pred, 8 * nv);
+    return first;
+}
+
+// Split into batches that fit the budget: halves on PM_ENOMEM.
+int run_host(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
+             const pm_model *m, double *t) {
+    int first = PM_OK;
+    for (size_t off = 0; off < nv; off += PM_BATCH_MAX) {
+        size_t nb = std::min<size_t>(PM_BATCH_MAX, nv - off);
+        int st = run_host_batch(c, v + off, nb, out ? out + off : nullptr, m, t ? t + off : nullptr);
+        if (st == PM_ENOMEM && nb > 1) {
+            size_t h = nb / 2;
+            st = run_host(c, v + off, h, out ? out + off : nullptr, m, t ? t + off : nullptr);
+            int st2 = run_host(c, v + off + h, nb - h, out ? out + off + h : nullptr, m,
+                               t ? t + off + h : nullptr);
+            if (st == PM_OK) st = st2;
+        }
+        if (st != PM_OK && first == PM_OK) first = st;
+    }
+    return first;
+}
+
+int check_bufs(const pm_variant *v, void *const *bufs, const size_t *bytes, uint32_t nbufs) {
+    size_t need[PM_MAXBUF];
+    uint32_t role[PM_MAXBUF], nb = 0;
+    int st = pm::buffers(*v, need, role, &nb);
+    if (st) return set_err(st, "no buffer layout for this family");
+    if (nbufs < nb) return set_err(PM_EINVAL, "kernel takes " + std::to_string(nb) + " buffers");
+    for (uint32_t i = 0; i < nb; i++) {
+        if (!bufs || !bufs[i]) return set_err(PM_EINVAL, "null buffer " + std::to_string(i));
+        if (!bytes || bytes[i] < need[i])
+            return set_err(PM_EINVAL, "buffer " + std::to_string(i) + " smaller than " +
+                                          std::to_string(need[i]) + " bytes");
+    }
+    return PM_OK;
+}
+
+int measure_impl(pm_ctx *c, const pm_variant *v, void *const *bufs, const size_t *bytes,
+                     uint32_t nbufs, void *stream, int warmup, int reps, double *t_reps,
+                     double *t_min) {
+    if (!c || !t_min || reps < 1 || warmup < 0) return set_err(PM_EINVAL, "bad argument");
+    int st = validate(v);
+    if (st) return st;
+    st = check_bufs(v, bufs, bytes, nbufs);
+    if (st) return st;
+    DeviceGuard g(c->device);
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    while ((int)c->events.size() < 2 * reps) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->events.push_back(e);
+    }
+    for (int w = 0; w < warmup; w++)
+        if ((st = pm::launch(*v, bufs, s))) return set_err(st, "kernel launch failed");
+    for (int r = 0; r < reps; r++) {
+        HIPCHK(hipEventRecord(c->events[2 * r], s));
+        if ((st = pm::launch(*v, bufs, s))) return set_err(st, "kernel launch failed");
+        HIPCHK(hipEventRecord(c->events[2 * r + 1], s));
+    }
+    HIPCHK(hipEventSynchronize(c->events[2 * reps - 1]));
+    double best = 1e300;
+    for (int r = 0; r < reps; r++) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->events[2 * r], c->events[2 * r + 1]));
+        double sec = (double)ms * 1e-3;
+        if (t_reps) t_reps[r] = sec;
+        best = std::min(best, sec);
+    }
+    *t_min = best;
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pm_last_error(void) { return g_err.c_str(); }
+
+pm_status pm_create(pm_ctx **out, int device, size_t budget) {
+    if (!out) return (pm_status)set_err(PM_EINVAL, "null out");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return (pm_status)set_err(PM_EDEVICE, "no HIP device " + std::to_string(device));
+    DeviceGuard g(device);
+    auto c = std::make_unique<pm_ctx>();
+    c->device = device;
+    c->budget = budget ? budget : (size_t)64 << 30;
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        c->n_cu = 256;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+        return (pm_status)set_err(PM_EDEVICE, "stream creation failed");
+    if (hipHostMalloc(&c->h_meta, 64, 0) != hipSuccess)
+        return (pm_status)set_err(PM_EDEVICE, "pinned allocation failed");
+    *out = c.release();
+    return PM_OK;
+}
+
+void pm_destroy(pm_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_arena(c);
+    (void)hipFree(c->ar.bitmap);
+    (void)hipHostFree(c->h_meta);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+pm_status pm_count_name(int i, char *buf, size_t cap) {
+    static const char *cls[pm::NCLS] = {"0", "1", "1/2", "2/2", "1/3", "2/3", "3/3", "1/4",
+                                        "2/4", "3/4", "4/4", "1/>4", "2/>4", "3/>4", "4/>4"};
+    static const char *kind[6] = {"add", "mul", "div", "exp", "spec", "fma"};
+    static const char *sz[3] = {"4", "8", "16"};
+    if (i < 0 || i >= PM_NCOUNT || !buf || cap == 0) return (pm_status)set_err(PM_EINVAL, "bad slot");
+    if (i < pm::C_LDS) {
+        int d = i / 45, r = i % 45;
+        snprintf(buf, cap, "%s.%s.%s", d ? "gst" : "gld", sz[r / 15], cls[r % 15]);
+    } else if (i < pm::C_FLOP) {
+        int r = i - pm::C_LDS;
+        snprintf(buf, cap, "%s.%s", r / 3 ? "lst" : "lld", sz[r % 3]);
+    } else if (i < pm::C_BARWI) {
+        int r = i - pm::C_FLOP;
+        snprintf(buf, cap, "%s.%s", kind[r / 2], r % 2 ? "f64" : "f32");
+    } else {
+        static const char *tail[4] = {"bar.wi", "bar.wg", "wg", "wi"};
+        snprintf(buf, cap, "%s", tail[i - pm::C_BARWI]);
+    }
+    return PM_OK;
+}
+
+pm_status pm_count(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out) {
+    if (!c || (!v && nv) || (!out && nv)) return (pm_status)set_err(PM_EINVAL, "null argument");
+    if (nv == 0) return PM_OK;
+    DeviceGuard g(c->device);
+    return (pm_status)run_host(c, v, nv, out, nullptr, nullptr);
+}
+
+pm_status pm_predict(pm_ctx *c, const pm_model *m, const pm_variant *v, size_t nv, double *t) {
+    if (!c || !m || (!v && nv) || (!t && nv)) return (pm_status)set_err(PM_EINVAL, "null argument");
+    if (pm::nfeat(m->proj) < 0 || (int)m->nfeat != pm::nfeat(m->proj))
+        return (pm_status)set_err(PM_EINVAL, "model projection / feature count mismatch");
+    if (nv == 0) return PM_OK;
+    DeviceGuard g(c->device);
+    return (pm_status)run_host(c, v, nv, nullptr, m, t);
+}
+
+pm_status pm_count_device(pm_ctx *c, const pm_variant *d_v, size_t nv, pm_counts *d_counts,
+                          const pm_model *m, double *d_t, int32_t *d_status, void *stream) {
+    if (!c || (!d_v && nv) || (!d_status && nv)) return (pm_status)set_err(PM_EINVAL, "null argument");
+    if (nv > PM_BATCH_MAX) return (pm_status)set_err(PM_EINVAL, "batch larger than PM_BATCH_MAX");
+    if (m && (pm::nfeat(m->proj) < 0 || (int)m->nfeat != pm::nfeat(m->proj)))
+        return (pm_status)set_err(PM_EINVAL, "model projection / feature count mismatch");
+    if (nv == 0) return PM_OK;
+    DeviceGuard g(c->device);
+    int st = grow_cap(c, nv);
+    if (st) return (pm_status)st;
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    st = pm::launch_batch(c->ar, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu);
+    if (st) return (pm_status)set_err(st, "counter launch failed");
+    return PM_OK;
+}
+
+pm_status pm_reserve(pm_ctx *c, size_t nv, size_t bitmap_bytes) {
+    if (!c) return (pm_status)set_err(PM_EINVAL, "null context");
+    if (nv > PM_BATCH_MAX) return (pm_status)set_err(PM_EINVAL, "batch larger than PM_BATCH_MAX");
+    DeviceGuard g(c->device);
+    int st = grow_cap(c, nv);
+    if (st) return (pm_status)st;
+    return (pm_status)grow_bitmap(c, (bitmap_bytes + 7) / 8);
+}
+
+pm_status pm_bitmap_bytes(const pm_variant *v, size_t *bytes) {
+    if (!bytes) return (pm_status)set_err(PM_EINVAL, "null out");
+    int st = validate(v);
+    if (st) return (pm_status)st;
+    *bytes = (size_t)g_hb.prog->bitmap_words * 8;
+    return PM_OK;
+}
+
+pm_status pm_features(const pm_counts *cnt, uint32_t proj, double *f, uint32_t *nf) {
+    if (!cnt || !f) return (pm_status)set_err(PM_EINVAL, "null argument");
+    int n = pm::features(cnt->c, proj, f);
+    if (n < 0) return (pm_status)set_err(PM_EINVAL, "unknown projection");
+    if (nf) *nf = (uint32_t)n;
+    return PM_OK;
+}
+
+pm_status pm_fit(const pm_counts *P, const double *T, size_t nrows, uint32_t proj, pm_model *out,
+                 double *cond, double *resid, uint32_t *rank) {
+    int st = pm::fit_model(P, T, nrows, proj, out, cond, resid, rank);
+    if (st == PM_EINVAL) return (pm_status)set_err(st, "fit: bad projection, empty input or non-positive time");
+    if (st == PM_ERANK) return (pm_status)set_err(st, "fit: no non-zero feature column");
+    return (pm_status)st;
+}
+
+pm_status pm_buffers(const pm_variant *v, size_t *bytes, uint32_t *role, uint32_t *nbufs) {
+    if (!bytes || !role || !nbufs) return (pm_status)set_err(PM_EINVAL, "null argument");
+    int st = validate(v);
+    if (st) return (pm_status)st;
+    return (pm_status)pm::buffers(*v, bytes, role, nbufs);
+}
+
+pm_status pm_launch(pm_ctx *c, const pm_variant *v, void *const *bufs, const size_t *bytes,
+                    uint32_t nbufs, void *stream) {
+    if (!c) return (pm_status)set_err(PM_EINVAL, "null context");
+    int st = validate(v);
+    if (st) return (pm_status)st;
+    st = check_bufs(v, bufs, bytes, nbufs);
+    if (st) return (pm_status)st;
+    DeviceGuard g(c->device);
+    st = pm::launch(*v, bufs, stream ? (hipStream_t)stream : c->stream);
+    if (st) return (pm_status)set_err(st, "kernel launch failed");
+    return PM_OK;
+}
+
+pm_status pm_measure(pm_ctx *c, const pm_variant *v, void *const *bufs, const size_t *bytes,
+                     uint32_t nbufs, void *stream, int warmup, int reps, double *t_reps,
+                     double *t_min) {
+    return (pm_status)measure_impl(c, v, bufs, bytes, nbufs, stream, warmup, reps, t_reps, t_min);
+}
+
+// ------------------------------------------------------------- testing ---
+pm_status pm_count_host(const pm_variant *v, pm_counts *out, int64_t *foot) {
+    if (!v || !out) return (pm_status)set_err(PM_EINVAL, "null argument");
+    int st = pm::count_host(*v, out, foot);
+    if (st) set_err(st, status_name(st));
+    return (pm_status)st;
+}
+
+}  // extern "C"

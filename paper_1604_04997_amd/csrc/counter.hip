@@ -1,0 +1,374 @@
+// GPU counter: kernel properties of a batch of variants (Sec. 3.2).
+//
+// One batch runs as six launches on one stream:
+//   k_build     one thread per variant: descriptor, statement components,
+//               jobs and footprint-bitmap needs (desc.h)
+//   k_scan      one work-group: prefix sums of bitmap words per variant,
+//               work chunks per job and fill segments per array; variants
+//               whose bitmaps overflow the arena get PM_ENOMEM
+//   k_clear     zero the used bitmap words and the per-job / per-array sums
+//   k_count     persistent: every wavefront takes chunks from one atomic
+//               ticket until the queue is empty; count chunks sum inner
+//               interval lengths (Alg. 1), footprint chunks OR cell runs
+//               into the bitmaps (Alg. 2)
+//   k_fill      per array segment: |F| and |Fill| (F with every strided
+//               cell widened to its run of stride*vec cells)
+//   k_finalize  one thread per variant: count vector (Eq. opcount) and,
+//               with a model, the FP64 prediction sum_i alpha_i f_i
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "counter.h"
+#include "desc.h"
+
+namespace pm {
+
+constexpr int SCAN_THREADS = 1024;
+constexpr int FILL_THREADS = 256;
+constexpr int FILL_WORDS_PER_THREAD = 16;  // 4096 words per segment
+constexpr int COUNT_THREADS = 256;
+
+__global__ void k_build(int nv, const pm_variant *__restrict__ var, Prog *prog,
+                        Job *jobs, int32_t *status, int64_t *varwords,
+                        int64_t *jobpref, int64_t *arrpref) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    pm_variant v = var[i];
+    Prog *p = &prog[i];
+    Job *J = &jobs[(size_t)i * MAXJOB];
+    int st = build_prog(v, p, J);
+    status[i] = st;
+    // dense per-variant sizes for the prefix sums
+    varwords[i] = st == PM_OK ? p->bitmap_words : 0;
+    for (int j = 0; j < MAXJOB; j++)
+        jobpref[(size_t)i * MAXJOB + j] = (st == PM_OK && j < p->njob) ? J[j].chunks : 0;
+    for (int a = 0; a < MAXARR; a++)
+        arrpref[(size_t)i * MAXARR + a] =
+            (st == PM_OK && a < p->narr && p->arr[a].w) ? p->arr[a].segs : 0;
+}
+
+// Block-wide inclusive scan of per-thread int64 values (SCAN_THREADS).
+__device__ int64_t block_scan_incl(int64_t x, int64_t *sh) {
+    int t = threadIdx.x;
+    sh[t] = x;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        int64_t y = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += y;
+        __syncthreads();
+    }
+    int64_t r = sh[t];
+    __syncthreads();
+    return r;
+}
+
+// In-place prefix sum of a[0, n) by one work-group (each thread a
+// contiguous slice); elements with !ok(i) count as 0.  Inclusive, or
+// exclusive if `excl`.  Returns the total.
+template <class OK>
+__device__ int64_t scan_inplace(int64_t n, int64_t *a, OK ok, bool excl,
+                                int64_t *sh) {
+    int t = threadIdx.x;
+    int64_t per = (n + SCAN_THREADS - 1) / SCAN_THREADS;
+    int64_t lo = t * per < n ? t * per : n;
+    int64_t hi = lo + per < n ? lo + per : n;
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; i++) s += ok(i) ? a[i] : 0;
+    int64_t incl = block_scan_incl(s, sh);
+    int64_t run = incl - s;
+    for (int64_t i = lo; i < hi; i++) {
+        int64_t x = ok(i) ? a[i] : 0;
+        if (excl) {
+            a[i] = run;
+            run += x;
+        } else {
+            run += x;
+            a[i] = run;
+        }
+    }
+    int64_t tot = sh[SCAN_THREADS - 1];
+    __syncthreads();
+    return tot;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
+       int64_t *jobpref, int64_t *arrpref, int64_t *meta, int64_t arena_words) {
+    __shared__ int64_t sh[SCAN_THREADS];
+    for (int64_t i = threadIdx.x; i < nv; i += SCAN_THREADS) varoff[i] = varwords[i];
+    __syncthreads();
+    int64_t need = scan_inplace(nv, varoff, [](int64_t) { return true; }, true, sh);
+    int64_t used = 0;
+    for (int64_t i = threadIdx.x; i < nv; i += SCAN_THREADS) {
+        int64_t end = varoff[i] + varwords[i];
+        if (varwords[i] > 0 && end > arena_words) status[i] = PM_ENOMEM;
+        else if (end > used) used = end;
+    }
+    sh[threadIdx.x] = used;
+    __syncthreads();
+    for (int off = SCAN_THREADS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off && sh[threadIdx.x + off] > sh[threadIdx.x])
+            sh[threadIdx.x] = sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    used = sh[0];
+    __syncthreads();
+    auto okj = [&](int64_t j) { return status[j / MAXJOB] == PM_OK; };
+    int64_t tc = scan_inplace((int64_t)nv * MAXJOB, jobpref, okj, false, sh);
+    auto oka = [&](int64_t j) { return status[j / MAXARR] == PM_OK; };
+    int64_t ts = scan_inplace((int64_t)nv * MAXARR, arrpref, oka, false, sh);
+    if (threadIdx.x == 0) {
+        meta[0] = tc;
+        meta[1] = used;
+        meta[2] = ts;
+        meta[3] = 0;  // ticket
+        meta[4] = need;
+    }
+}
+
+__global__ void k_clear(int nv, uint64_t *bitmap, int64_t *jobres,
+                        int64_t *foot, const int64_t *meta) {
+    int64_t words = meta[1];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < words; i += stride) bitmap[i] = 0;
+    for (int64_t i = t; i < (int64_t)nv * MAXJOB; i += stride) jobres[i] = 0;
+    for (int64_t i = t; i < (int64_t)nv * MAXARR * 2; i += stride) foot[i] = 0;
+}
+
+// first index j in [0, n) with pref[j] > x (pref non-decreasing)
+__device__ int64_t upper(const int64_t *pref, int64_t n, int64_t x) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (pref[mid] > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+struct DevOr {
+    __device__ void operator()(uint64_t *p, uint64_t m) const {
+        atomicOr((unsigned long long *)p, (unsigned long long)m);
+    }
+};
+
+__global__ void __launch_bounds__(COUNT_THREADS)
+k_count(int nv, const Job *jobs, const int64_t *jobpref, const int64_t *varoff,
+        uint64_t *bitmap, int64_t *jobres, int64_t *meta) {
+    const int lane = threadIdx.x & 63;
+    const int64_t total = meta[0];
+    const int64_t njobs = (int64_t)nv * MAXJOB;
+    while (true) {
+        int64_t ch = 0;
+        if (lane == 0) ch = atomicAdd((unsigned long long *)&meta[3], 1ull);
+        ch = __shfl(ch, 0);
+        if (ch >= total) break;
+        int64_t j = upper(jobpref, njobs, ch);
+        int64_t local = ch - (j ? jobpref[j - 1] : 0);
+        const Job &J = jobs[j];
+        int64_t it0 = local * J.chunk_items;
+        int64_t it1 = it0 + J.chunk_items;
+        if (it1 > J.items) it1 = J.items;
+        if (J.kind == JOB_COUNT) {
+            int64_t s = 0;
+            for (int64_t it = it0 + lane; it < it1; it += 64) s += count_item(J, it);
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (lane == 0 && s) atomicAdd((unsigned long long *)&jobres[j], (unsigned long long)s);
+        } else {
+            uint64_t *vb = bitmap + varoff[j / MAXJOB];
+            for (int64_t it = it0; it < it1; it++) foot_item(J, it, vb, lane, 64, DevOr{});
+        }
+    }
+}
+
+__global__ void __launch_bounds__(FILL_THREADS)
+k_fill(int nv, const Prog *prog, const int64_t *arrpref, const int64_t *varoff,
+       const uint64_t *bitmap, int64_t *foot, const int64_t *meta) {
+    __shared__ int64_t sh[FILL_THREADS];
+    __shared__ unsigned long long red[2];
+    const int64_t total = meta[2];
+    const int64_t narr = (int64_t)nv * MAXARR;
+    const int t = threadIdx.x;
+    for (int64_t sg = blockIdx.x; sg < total; sg += gridDim.x) {
+        int64_t j = upper(arrpref, narr, sg);
+        int64_t local = sg - (j ? arrpref[j - 1] : 0);
+        int64_t v = j / MAXARR;
+        const ArrInfo &A = prog[v].arr[j % MAXARR];
+        const uint64_t *F = bitmap + varoff[v] + A.f_off;
+        const uint64_t *Bm = bitmap + varoff[v] + A.b_off;
+        const int64_t w = A.w;
+        const int64_t seg_words = (int64_t)FILL_THREADS * FILL_WORDS_PER_THREAD;
+        int64_t k0 = local * seg_words;
+        int64_t k1 = k0 + seg_words < A.words ? k0 + seg_words : A.words;
+        int64_t a = k0 + (int64_t)t * FILL_WORDS_PER_THREAD;
+        int64_t e = a + FILL_WORDS_PER_THREAD < k1 ? a + FILL_WORDS_PER_THREAD : k1;
+        int64_t mylast = -1;
+        for (int64_t k = e - 1; k >= a; k--) {
+            uint64_t b = Bm[k];
+            if (b) {
+                mylast = last_bit(b, k);
+                break;
+            }
+        }
+        // the last strided cell before the segment, within reach w
+        int64_t L = (w + 63) / 64 + 1;
+        int64_t lb0 = k0 - L > 0 ? k0 - L : 0;
+        int64_t blast = -1;
+        for (int64_t k = lb0 + t; k < k0; k += FILL_THREADS) {
+            int64_t x = last_bit(Bm[k], k);
+            if (x > blast) blast = x;
+        }
+        sh[t] = blast;
+        __syncthreads();
+        for (int off = FILL_THREADS / 2; off > 0; off >>= 1) {
+            if (t < off && sh[t + off] > sh[t]) sh[t] = sh[t + off];
+            __syncthreads();
+        }
+        blast = sh[0];
+        __syncthreads();
+        // exclusive max-scan of mylast over threads
+        sh[t] = mylast;
+        __syncthreads();
+        for (int off = 1; off < FILL_THREADS; off <<= 1) {
+            int64_t y = t >= off ? sh[t - off] : -1;
+            __syncthreads();
+            if (y > sh[t]) sh[t] = y;
+            __syncthreads();
+        }
+        int64_t carry = t ? sh[t - 1] : -1;
+        if (blast > carry) carry = blast;
+        __syncthreads();
+        unsigned long long pf = 0, pfill = 0;
+        for (int64_t k = a; k < e; k++) {
+            uint64_t b = Bm[k];
+            uint64_t d = dilate_word(b, w) | carry_mask(carry, w, k);
+            uint64_t f = F[k];
+            pf += __popcll(f);
+            pfill += __popcll(f | d);
+            if (b) carry = last_bit(b, k);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            pf += __shfl_xor(pf, off);
+            pfill += __shfl_xor(pfill, off);
+        }
+        if (t == 0) red[0] = red[1] = 0;
+        __syncthreads();
+        if ((t & 63) == 0) {
+            atomicAdd(&red[0], pf);
+            atomicAdd(&red[1], pfill);
+        }
+        __syncthreads();
+        if (t == 0) {
+            atomicAdd((unsigned long long *)&foot[j * 2], red[0]);
+            atomicAdd((unsigned long long *)&foot[j * 2 + 1], red[1]);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_finalize(int nv, const Prog *prog, const int64_t *jobres,
+                           const int64_t *foot, int32_t *status,
+                           pm_counts *counts, pm_model model, int has_model,
+                           double *pred) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    int64_t c[PM_NCOUNT];
+    int64_t F[MAXARR], Fill[MAXARR];
+    for (int a = 0; a < MAXARR; a++) {
+        F[a] = foot[((int64_t)i * MAXARR + a) * 2];
+        Fill[a] = foot[((int64_t)i * MAXARR + a) * 2 + 1];
+    }
+    int st = status[i];
+    if (st == PM_OK) {
+        st = finalize(prog[i], jobres + (int64_t)i * MAXJOB, F, Fill, c);
+        status[i] = st;
+    } else {
+        for (int k = 0; k < PM_NCOUNT; k++) c[k] = 0;
+    }
+    if (counts)
+        for (int k = 0; k < PM_NCOUNT; k++) counts[i].c[k] = c[k];
+    if (has_model && pred) pred[i] = st == PM_OK ? predict(c, model) : 0.0;
+}
+
+// ---------------------------------------------------------------- host ---
+int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
+                 pm_counts *d_counts, const pm_model *model, double *d_pred,
+                 int32_t *d_status, hipStream_t s, int n_cu) {
+    if (nv <= 0) return PM_OK;
+    int tb = 64;
+    hipLaunchKernelGGL(k_build, dim3((nv + tb - 1) / tb), dim3(tb), 0, s, nv,
+                       d_var, ar.prog, ar.jobs, d_status, ar.varwords,
+                       ar.jobpref, ar.arrpref);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
+                       (const int64_t *)ar.varwords, ar.varoff, ar.jobpref,
+                       ar.arrpref, ar.meta, (int64_t)ar.bitmap_words);
+    hipLaunchKernelGGL(k_clear, dim3(n_cu * 8), dim3(256), 0, s, nv, ar.bitmap,
+                       ar.jobres, ar.foot, (const int64_t *)ar.meta);
+    hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s, nv,
+                       (const Job *)ar.jobs, (const int64_t *)ar.jobpref,
+                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, ar.meta);
+    hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s, nv,
+                       (const Prog *)ar.prog, (const int64_t *)ar.arrpref,
+                       (const int64_t *)ar.varoff, (const uint64_t *)ar.bitmap,
+                       ar.foot, (const int64_t *)ar.meta);
+    pm_model m{};
+    int has = 0;
+    if (model) {
+        m = *model;
+        has = 1;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3((nv + tb - 1) / tb), dim3(tb), 0, s, nv,
+                       (const Prog *)ar.prog, (const int64_t *)ar.jobres,
+                       (const int64_t *)ar.foot, d_status, d_counts, m, has, d_pred);
+    return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+size_t arena_bytes_per_variant() {
+    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (2 + 2 * MAXJOB + 3 * MAXARR);
+}
+
+// ------------------------------------------------------- host execution ---
+struct HostOr {
+    void operator()(uint64_t *p, uint64_t m) const { *p |= m; }
+};
+
+int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out) {
+    std::vector<Prog> P(1);
+    std::vector<Job> J(MAXJOB);
+    Prog &p = P[0];
+    int st = build_prog(v, &p, J.data());
+    for (int i = 0; i < PM_NCOUNT; i++) out->c[i] = 0;
+    if (st != PM_OK) return st;
+    std::vector<uint64_t> bm((size_t)p.bitmap_words + 1, 0);
+    int64_t jobres[MAXJOB] = {0};
+    for (int j = 0; j < p.njob; j++) {
+        if (J[j].kind == JOB_COUNT)
+            for (int64_t it = 0; it < J[j].items; it++) jobres[j] += count_item(J[j], it);
+        else
+            for (int64_t it = 0; it < J[j].items; it++) foot_item(J[j], it, bm.data(), 0, 1, HostOr{});
+    }
+    int64_t F[MAXARR] = {0}, Fill[MAXARR] = {0};
+    for (int a = 0; a < p.narr; a++) {
+        const ArrInfo &A = p.arr[a];
+        if (!A.w) continue;
+        const uint64_t *f = bm.data() + A.f_off, *b = bm.data() + A.b_off;
+        int64_t carry = -1;
+        for (int64_t k = 0; k < A.words; k++) {
+            uint64_t d = dilate_word(b[k], A.w) | carry_mask(carry, A.w, k);
+            F[a] += __builtin_popcountll(f[k]);
+            Fill[a] += __builtin_popcountll(f[k] | d);
+            if (b[k]) carry = last_bit(b[k], k);
+        }
+    }
+    if (foot_out)
+        for (int a = 0; a < MAXARR; a++) {
+            foot_out[2 * a] = F[a];
+            foot_out[2 * a + 1] = Fill[a];
+        }
+    return finalize(p, jobres, F, Fill, out->c);
+}
+
+}  // namespace pm

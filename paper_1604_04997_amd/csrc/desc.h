@@ -1,0 +1,1239 @@
+// Kernel-variant descriptors and the per-variant parts of the counter.
+//
+// A variant (pm_variant) is expanded into a program: a list of statements,
+// each an instruction of the kernel with
+//   - a box domain over up to MAXVAR loop variables (group ids, local ids,
+//     loop counters), each ranging over [0, ext),
+//   - affine guards (sum c_v x_v + k >= 0) that restrict the domain,
+//   - the global accesses it performs, each with an affine flat element
+//     index (the index map I_j of Sec. 3.2, Alg. 2),
+//   - per-instance tallies: LDS accesses, flops by kind/dtype, barriers.
+// The count of every property is sum over statements of |domain| times the
+// statement's tally (Sec. 3.2, Alg. 1, Eq. opcount).
+//
+// |domain| is computed without visiting every point:
+//   * variables in no guard multiply the count by their extent;
+//   * guarded variables split into connected components (variables linked
+//     by a common guard); the count is the product of component counts;
+//   * two variables a, b fuse into one of extent ext_a*ext_b when every
+//     affine form of the component has coef_b == coef_a*ext_a;
+//   * a one-variable component is an interval, counted in closed form;
+//     larger components become GPU jobs that enumerate all variables but
+//     one and intersect the guards for the last (inner) one.
+// Footprints (Alg. 2) of arrays with a lane stride >= 2 are marked in
+// bitmaps by footprint jobs over the same fused domains.
+//
+// Everything here is __host__ __device__: the build and finalize kernels
+// run it on the GPU, and a host entry point runs it for unit tests.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pm.h"
+
+#define PM_HD __host__ __device__ inline
+
+namespace pm {
+
+constexpr int MAXVAR = 8;
+constexpr int MAXGUARD = 6;
+constexpr int MAXACC = 6;
+constexpr int MAXSTMT = 12;
+constexpr int MAXARR = 6;
+constexpr int MAXJOB = 24;
+constexpr int MAXCOMP = 4;
+constexpr int NCLS = 15;
+
+// count-vector layout (see pm.h)
+constexpr int C_GACC = 0;
+constexpr int C_LDS = 90;
+constexpr int C_FLOP = 96;
+constexpr int C_BARWI = 108;
+constexpr int C_BARWG = 109;
+constexpr int C_WG = 110;
+constexpr int C_WI = 111;
+
+enum { K_ADD = 0, K_MUL, K_DIV, K_EXP, K_SPEC, K_FMA };
+enum { D_LD = 0, D_ST = 1 };
+enum { JOB_NONE = 0, JOB_COUNT = 1, JOB_FOOT = 2 };
+
+// inner points handled by one footprint work item
+constexpr int64_t SEG_CONTIG = 16384;
+constexpr int64_t SEG_STRIDED = 1024;
+// work items per chunk taken from the queue by one wavefront
+constexpr int64_t CHUNK_COUNT = 2048;
+constexpr int64_t CHUNK_FOOT = 4;
+
+struct Aff {
+    int64_t c[MAXVAR];
+    int64_t k;
+};
+
+PM_HD Aff aff(int64_t k) {
+    Aff a;
+    for (int i = 0; i < MAXVAR; i++) a.c[i] = 0;
+    a.k = k;
+    return a;
+}
+PM_HD Aff av(Aff a, int v, int64_t coef) {
+    a.c[v] += coef;
+    return a;
+}
+
+struct GAcc {
+    int32_t arr, dir, elem, vec;
+    Aff idx;
+};
+
+struct Stmt {
+    int32_t nvar, lane, nguard, nacc;
+    int64_t ext[MAXVAR];
+    Aff guard[MAXGUARD];
+    GAcc acc[MAXACC];
+    int32_t lds[2][3];
+    int32_t flop[6][2];
+    int32_t bar;
+    int32_t ncomp;
+    int32_t comp_job[MAXCOMP];
+    int64_t fixed;  // product of free extents and closed-form components
+};
+
+struct ArrInfo {
+    int64_t cells;
+    int64_t words;  // bitmap words (0: no footprint needed)
+    int64_t f_off;  // word offset of F inside the variant's bitmap region
+    int64_t b_off;  // word offset of B (cells of strided accesses); == f_off if same
+    int64_t w;      // fill width of strided accesses: stride * vec cells
+    int64_t segs;   // fill-pass segments
+};
+
+struct Prog {
+    int32_t status, nstmt, narr, njob;
+    int32_t wg_size, pad;
+    int64_t n_wg;
+    int64_t bitmap_words;
+    ArrInfo arr[MAXARR];
+    Stmt st[MAXSTMT];
+};
+
+struct Job {
+    int32_t kind, nv, ng, arr;
+    int32_t vec, mark_b, pad0, pad1;
+    int64_t ext[MAXVAR];             // var 0 is the inner variable
+    int64_t g[MAXGUARD][MAXVAR + 1]; // guard coefficients, constant last
+    int64_t ic[MAXVAR + 1];          // footprint index map, constant last
+    int64_t seg, nseg, outer, items, chunk_items, chunks;
+    int64_t f_off, b_off;            // bitmap word offsets (variant-relative)
+};
+
+// ------------------------------------------------------------- helpers ---
+PM_HD bool mul_ovf(int64_t a, int64_t b, int64_t *r) {
+    return __builtin_mul_overflow(a, b, r);
+}
+PM_HD bool add_ovf(int64_t a, int64_t b, int64_t *r) {
+    return __builtin_add_overflow(a, b, r);
+}
+PM_HD int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// floor(a / b) and ceil(a / b) for b > 0, any sign of a
+PM_HD int64_t fdiv(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+PM_HD int64_t ceil_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    return (a % b != 0 && a > 0) ? q + 1 : q;
+}
+PM_HD int64_t iabs(int64_t a) { return a < 0 ? -a : a; }
+PM_HD int size_index(int bytes) {
+    return bytes == 4 ? 0 : bytes == 8 ? 1 : bytes == 16 ? 2 : -1;
+}
+PM_HD bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// -------------------------------------------------------------- builder ---
+struct B {
+    Prog *p;
+    PM_HD void fail(int st) {
+        if (p->status == PM_OK) p->status = st;
+    }
+    PM_HD Stmt *stmt(int lane) {
+        if (p->nstmt >= MAXSTMT) {
+            fail(PM_EINVAL);
+            return nullptr;
+        }
+        Stmt *s = &p->st[p->nstmt++];
+        s->nvar = 0;
+        s->lane = lane;
+        s->nguard = 0;
+        s->nacc = 0;
+        for (int i = 0; i < MAXVAR; i++) s->ext[i] = 1;
+        for (int d = 0; d < 2; d++)
+            for (int z = 0; z < 3; z++) s->lds[d][z] = 0;
+        for (int k = 0; k < 6; k++) s->flop[k][0] = s->flop[k][1] = 0;
+        s->bar = 0;
+        s->ncomp = 0;
+        s->fixed = 0;
+        return s;
+    }
+    // declare variables in order; returns their ids 0..
+    PM_HD int var(Stmt *s, int64_t ext) {
+        if (s->nvar >= MAXVAR || ext < 0) {
+            fail(PM_EINVAL);
+            return 0;
+        }
+        s->ext[s->nvar] = ext;
+        return s->nvar++;
+    }
+    PM_HD void ge0(Stmt *s, Aff a) {  // a >= 0
+        if (s->nguard >= MAXGUARD) {
+            fail(PM_EINVAL);
+            return;
+        }
+        s->guard[s->nguard++] = a;
+    }
+    PM_HD void lt(Stmt *s, Aff a, int64_t b) {  // a < b  <=>  (b-1) - a >= 0
+        Aff g = aff(b - 1 - a.k);
+        for (int i = 0; i < MAXVAR; i++) g.c[i] = -a.c[i];
+        ge0(s, g);
+    }
+    PM_HD void ge(Stmt *s, Aff a, int64_t b) {  // a >= b
+        a.k -= b;
+        ge0(s, a);
+    }
+    PM_HD void eq(Stmt *s, Aff a, int64_t b) {
+        ge(s, a, b);
+        lt(s, a, b + 1);
+    }
+    PM_HD void acc(Stmt *s, int arr, int dir, int elem, int vec, Aff idx) {
+        if (s->nacc >= MAXACC || arr >= p->narr) {
+            fail(PM_EINVAL);
+            return;
+        }
+        GAcc &g = s->acc[s->nacc++];
+        g.arr = arr;
+        g.dir = dir;
+        g.elem = elem;
+        g.vec = vec;
+        g.idx = idx;
+    }
+    PM_HD void array(int a, int64_t cells) {
+        if (a >= MAXARR) {
+            fail(PM_EINVAL);
+            return;
+        }
+        p->arr[a].cells = cells;
+        p->arr[a].words = 0;
+        p->arr[a].f_off = p->arr[a].b_off = -1;
+        p->arr[a].w = 0;
+        p->arr[a].segs = 0;
+        if (a + 1 > p->narr) p->narr = a + 1;
+    }
+};
+
+PM_HD int64_t prod3(B &b, int64_t x, int64_t y, int64_t z) {
+    int64_t r;
+    if (mul_ovf(x, y, &r) || mul_ovf(r, z, &r)) {
+        b.fail(PM_EOVERFLOW);
+        return 0;
+    }
+    return r;
+}
+
+// --- stream: global-memory accesses at a lane stride and group stride ---
+PM_HD void build_stream(B &b, const pm_variant &v) {
+    int64_t N = v.n[0], wg = v.wg[0], s = v.stride, gs = v.gstride,
+            vec = v.vec, U = v.reps;
+    int e = v.dtype == PM_F64 ? 8 : 4;
+    int dt = v.dtype == PM_F64 ? 1 : 0;
+    if (N <= 0 || wg <= 0 || wg > 1024 || N % wg || s < 1 || gs < 1 ||
+        U < 1 || !(vec == 1 || vec == 2 || vec == 4) || e * vec > 16 ||
+        v.op > PM_STREAM_FILLED) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    int64_t G = N / wg;
+    b.p->n_wg = G;
+    b.p->wg_size = (int32_t)wg;
+    if (v.op == PM_STREAM_FILLED) {
+        int64_t k = s;
+        if (!(k == 2 || k == 3) || vec != 1 || gs != 1) {
+            b.fail(PM_EINVAL);
+            return;
+        }
+        b.array(0, prod3(b, k, N, U));
+        b.array(1, N);
+        Stmt *S = b.stmt(1);
+        if (!S) return;
+        int g = b.var(S, G), l = b.var(S, wg), u = b.var(S, U);
+        for (int c = 0; c < k; c++)
+            b.acc(S, 0, D_LD, e, 1, av(av(av(aff(c), g, k * wg), l, k), u, k * G * wg));
+        S->flop[K_ADD][dt] = (int32_t)k;
+        Stmt *T = b.stmt(1);
+        if (!T) return;
+        g = b.var(T, G);
+        l = b.var(T, wg);
+        b.acc(T, 1, D_ST, e, 1, av(av(aff(0), g, wg), l, 1));
+        return;
+    }
+    int64_t span = prod3(b, G * gs, wg * s, U * vec);
+    int na = v.op == PM_STREAM_ADD4 ? 5 : v.op == PM_STREAM_COPY ? 2 : 1;
+    for (int a = 0; a < na; a++) b.array(a, span);
+    Stmt *S = b.stmt(1);
+    if (!S) return;
+    int g = b.var(S, G), l = b.var(S, wg), u = b.var(S, U);
+    Aff x = av(av(av(aff(0), g, vec * gs * wg * s), l, vec * s), u, vec * G * gs * wg * s);
+    switch (v.op) {
+    case PM_STREAM_LOAD:  // summed in a register; the sentinel store never runs
+        b.acc(S, 0, D_LD, e, (int)vec, x);
+        S->flop[K_ADD][dt] = (int32_t)vec;
+        break;
+    case PM_STREAM_STORE:
+        b.acc(S, 0, D_ST, e, (int)vec, x);
+        break;
+    case PM_STREAM_COPY:
+        b.acc(S, 0, D_LD, e, (int)vec, x);
+        b.acc(S, 1, D_ST, e, (int)vec, x);
+        break;
+    default:  // add4
+        for (int a = 0; a < 4; a++) b.acc(S, a, D_LD, e, (int)vec, x);
+        b.acc(S, 4, D_ST, e, (int)vec, x);
+        S->flop[K_ADD][dt] = (int32_t)(3 * vec);
+    }
+}
+
+// --- LDS: R accesses per work-item at bank stride b ---
+PM_HD void build_lds(B &b, const pm_variant &v) {
+    int64_t G = v.n[0], wg = v.wg[0], R = v.reps, W = v.words;
+    if (G <= 0 || wg <= 0 || wg > 1024 || R < 0 || v.stride < 1 ||
+        !pow2(W) || W > 16384 || W % wg || v.op > PM_LDS_WRITE) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    b.p->n_wg = G;
+    b.p->wg_size = (int32_t)wg;
+    b.array(0, G * wg);
+    Stmt *S = b.stmt(1);
+    if (!S) return;
+    int g = b.var(S, G), l = b.var(S, wg);
+    b.acc(S, 0, D_ST, 4, 1, av(av(aff(0), g, wg), l, 1));
+    S->bar = 1;
+    Stmt *L = b.stmt(1);
+    if (!L) return;
+    b.var(L, G);
+    b.var(L, wg);
+    b.var(L, R);
+    if (v.op == PM_LDS_READ) {
+        S->lds[D_ST][0] = (int32_t)(W / wg);  // initialisation
+        L->lds[D_LD][0] = 1;
+        L->flop[K_ADD][0] = 1;
+    } else {
+        L->lds[D_ST][0] = 1;
+        S->lds[D_LD][0] = 1;  // read-back
+    }
+}
+
+// --- FMA / rsqrt chains: 1 load, F ops, 1 store per work-item ---
+PM_HD void build_chain(B &b, const pm_variant &v, bool rsq) {
+    int64_t N = v.n[0], wg = v.wg[0], F = v.reps, K = v.chains;
+    int e = v.dtype == PM_F64 ? 8 : 4;
+    int dt = v.dtype == PM_F64 ? 1 : 0;
+    bool kok = rsq ? (K == 1 || K == 2 || K == 4 || K == 8)
+                   : (K == 1 || K == 2 || K == 4 || K == 8 || K == 16);
+    if (N <= 0 || wg <= 0 || wg > 1024 || N % wg || !kok || F < 0 || F % K ||
+        F > (1 << 24) || (rsq && v.dtype != PM_F32)) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    b.p->n_wg = N / wg;
+    b.p->wg_size = (int32_t)wg;
+    b.array(0, N);
+    b.array(1, N);
+    Stmt *S = b.stmt(1);
+    if (!S) return;
+    int g = b.var(S, N / wg), l = b.var(S, wg);
+    Aff i = av(av(aff(0), g, wg), l, 1);
+    b.acc(S, 0, D_LD, e, 1, i);
+    b.acc(S, 1, D_ST, e, 1, i);
+    if (rsq) {
+        S->flop[K_MUL][dt] = (int32_t)F;
+        S->flop[K_ADD][dt] = (int32_t)(F + K - 1);
+        S->flop[K_SPEC][dt] = (int32_t)F;
+    } else {
+        S->flop[K_FMA][dt] = (int32_t)F;
+        S->flop[K_ADD][dt] = (int32_t)(K - 1);
+    }
+}
+
+PM_HD void build_barrier(B &b, const pm_variant &v) {
+    int64_t G = v.n[0], wg = v.wg[0], Bn = v.reps;
+    if (G <= 0 || wg <= 0 || wg > 1024 || Bn < 0 || Bn > (1 << 20)) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    b.p->n_wg = G;
+    b.p->wg_size = (int32_t)wg;
+    b.array(0, G * wg);
+    Stmt *S = b.stmt(1);
+    if (!S) return;
+    int g = b.var(S, G), l = b.var(S, wg);
+    S->bar = (int32_t)Bn;
+    b.acc(S, 0, D_ST, 4, 1, av(av(aff(0), g, wg), l, 1));
+}
+
+PM_HD void build_empty(B &b, const pm_variant &v) {
+    int64_t n = v.n[0], wx = v.wg[0], wy = v.wg[1] ? v.wg[1] : 1;
+    if (n <= 0 || wx <= 0 || wy <= 0 || wx * wy > 1024) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    b.p->n_wg = prod3(b, cdiv(n, wx), cdiv(n, wy), 1);
+    b.p->wg_size = (int32_t)(wx * wy);
+}
+
+PM_HD bool tile_ok(int T) { return T == 8 || T == 16 || T == 32; }
+
+// --- matmul: C[n,l] = A[n,m] B[m,l], T x T work-groups ---
+PM_HD void build_matmul(B &b, const pm_variant &v) {
+    int64_t n = v.n[0], m = v.n[1], L = v.n[2], T = v.tile;
+    if (n <= 0 || m <= 0 || L <= 0 || !tile_ok((int)T) || v.dtype != PM_F32 ||
+        v.op > PM_MATMUL_NAIVE || n > (1 << 24) || m > (1 << 24) || L > (1 << 24)) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    int64_t GX = cdiv(L, T), GY = cdiv(n, T), KT = cdiv(m, T);
+    b.p->n_wg = GX * GY;
+    b.p->wg_size = (int32_t)(T * T);
+    b.array(0, n * m);
+    b.array(1, m * L);
+    b.array(2, n * L);
+    // variables: 0 gy, 1 gx, 2 ly, 3 lx, then loop counters
+    auto head = [&](Stmt *S) {
+        b.var(S, GY);
+        b.var(S, GX);
+        b.var(S, T);
+        b.var(S, T);
+    };
+    Aff row = av(av(aff(0), 0, T), 2, 1), col = av(av(aff(0), 1, T), 3, 1);
+    if (v.op == PM_MATMUL_TILED) {
+        Stmt *S = b.stmt(3);  // A tile element -> LDS
+        if (!S) return;
+        head(S);
+        int kt = b.var(S, KT);
+        b.lt(S, row, n);
+        b.lt(S, av(av(aff(0), kt, T), 3, 1), m);
+        b.acc(S, 0, D_LD, 4, 1, av(av(av(av(aff(0), 0, T * m), 2, m), kt, T), 3, 1));
+        Stmt *Sb = b.stmt(3);  // B tile element -> LDS
+        if (!Sb) return;
+        head(Sb);
+        kt = b.var(Sb, KT);
+        b.lt(Sb, av(av(aff(0), kt, T), 2, 1), m);
+        b.lt(Sb, col, L);
+        b.acc(Sb, 1, D_LD, 4, 1, av(av(av(av(aff(0), kt, T * L), 2, L), 1, T), 3, 1));
+        Stmt *Sl = b.stmt(3);  // LDS stores (zero-padded outside) + 2 barriers
+        if (!Sl) return;
+        head(Sl);
+        b.var(Sl, KT);
+        Sl->lds[D_ST][0] = 2;
+        Sl->bar = 2;
+        Stmt *Si = b.stmt(3);  // inner product step
+        if (!Si) return;
+        head(Si);
+        b.var(Si, KT);
+        b.var(Si, T);
+        Si->lds[D_LD][0] = 2;
+        Si->flop[K_FMA][0] = 1;
+    } else {
+        Stmt *S = b.stmt(3);
+        if (!S) return;
+        head(S);
+        int k = b.var(S, m);
+        b.lt(S, row, n);
+        b.lt(S, col, L);
+        b.acc(S, 0, D_LD, 4, 1, av(av(av(aff(0), 0, T * m), 2, m), k, 1));
+        b.acc(S, 1, D_LD, 4, 1, av(av(av(aff(0), k, L), 1, T), 3, 1));
+        S->flop[K_FMA][0] = 1;
+    }
+    Stmt *Sc = b.stmt(3);
+    if (!Sc) return;
+    head(Sc);
+    b.lt(Sc, row, n);
+    b.lt(Sc, col, L);
+    b.acc(Sc, 2, D_ST, 4, 1, av(av(av(av(aff(0), 0, T * L), 2, L), 1, T), 3, 1));
+}
+
+// --- transpose: out[c][r] = in[r][c], n x n ---
+PM_HD void build_transpose(B &b, const pm_variant &v) {
+    int64_t n = v.n[0], T = v.tile;
+    if (n <= 0 || n > (1 << 24) || !tile_ok((int)T) || v.dtype != PM_F32 ||
+        v.op > PM_TRANSPOSE_NAIVE_RC) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    int64_t G = cdiv(n, T);
+    b.p->n_wg = G * G;
+    b.p->wg_size = (int32_t)(T * T);
+    b.array(0, n * n);
+    b.array(1, n * n);
+    auto head = [&](Stmt *S) {
+        b.var(S, G);  // 0 gy
+        b.var(S, G);  // 1 gx
+        b.var(S, T);  // 2 ly
+        b.var(S, T);  // 3 lx
+    };
+    Aff r = av(av(aff(0), 0, T), 2, 1), c = av(av(aff(0), 1, T), 3, 1);
+    Aff rn_c = av(av(av(av(aff(0), 0, T * n), 2, n), 1, T), 3, 1);  // r*n + c
+    Aff cn_r = av(av(av(av(aff(0), 1, T * n), 3, n), 0, T), 2, 1);  // c*n + r
+    if (v.op == PM_TRANSPOSE_TILED) {
+        Stmt *S = b.stmt(3);
+        if (!S) return;
+        head(S);
+        b.lt(S, r, n);
+        b.lt(S, c, n);
+        b.acc(S, 0, D_LD, 4, 1, rn_c);
+        S->lds[D_ST][0] = 1;
+        Stmt *Sb = b.stmt(3);
+        if (!Sb) return;
+        head(Sb);
+        Sb->bar = 1;
+        Stmt *St = b.stmt(3);  // r2 = gx*T + ly, c2 = gy*T + lx
+        if (!St) return;
+        head(St);
+        b.lt(St, av(av(aff(0), 1, T), 2, 1), n);
+        b.lt(St, av(av(aff(0), 0, T), 3, 1), n);
+        St->lds[D_LD][0] = 1;
+        b.acc(St, 1, D_ST, 4, 1, av(av(av(av(aff(0), 1, T * n), 2, n), 0, T), 3, 1));
+    } else {
+        Stmt *S = b.stmt(3);
+        if (!S) return;
+        head(S);
+        b.lt(S, r, n);
+        b.lt(S, c, n);
+        if (v.op == PM_TRANSPOSE_NAIVE_WC) {
+            b.acc(S, 0, D_LD, 4, 1, cn_r);
+            b.acc(S, 1, D_ST, 4, 1, rn_c);
+        } else {
+            b.acc(S, 0, D_LD, 4, 1, rn_c);
+            b.acc(S, 1, D_ST, 4, 1, cn_r);
+        }
+    }
+}
+
+// --- 5-point stencil on an (n+2)^2 input with halo, T x T tiles in LDS ---
+PM_HD void build_stencil(B &b, const pm_variant &v) {
+    int64_t n = v.n[0], T = v.tile;
+    if (n <= 0 || n > (1 << 24) || !tile_ok((int)T)) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    int e = v.dtype == PM_F64 ? 8 : 4;
+    int dt = v.dtype == PM_F64 ? 1 : 0;
+    int z = e == 8 ? 1 : 0;
+    int64_t G = cdiv(n, T), P = n + 2;
+    b.p->n_wg = G * G;
+    b.p->wg_size = (int32_t)(T * T);
+    b.array(0, P * P);
+    b.array(1, n * n);
+    Aff i = av(av(aff(0), 0, T), 2, 1), j = av(av(aff(0), 1, T), 3, 1);
+    // flat index of input cell (i + di, j + dj)
+    auto at = [&](int64_t di, int64_t dj) {
+        return av(av(av(av(aff(di * P + dj), 0, T * P), 2, P), 1, T), 3, 1);
+    };
+    Aff ly = av(aff(0), 2, 1), lx = av(aff(0), 3, 1);
+    for (int q = 0; q < 7; q++) {
+        Stmt *S = b.stmt(3);
+        if (!S) return;
+        b.var(S, G);
+        b.var(S, G);
+        b.var(S, T);
+        b.var(S, T);
+        S->lds[D_ST][z] = 1;
+        switch (q) {
+        case 0:  // the tile
+            b.lt(S, i, n), b.lt(S, j, n);
+            b.acc(S, 0, D_LD, e, 1, at(1, 1));
+            break;
+        case 1:  // top halo row, loaded by ly == 0
+            b.eq(S, ly, 0), b.lt(S, j, n);
+            b.acc(S, 0, D_LD, e, 1, at(0, 1));
+            break;
+        case 2:  // bottom halo row of a full tile, loaded by ly == T-1
+            b.eq(S, ly, T - 1), b.lt(S, i, n), b.lt(S, j, n);
+            b.acc(S, 0, D_LD, e, 1, at(2, 1));
+            break;
+        case 3:  // bottom halo row of the last, partial tile row
+            b.lt(S, ly, T - 1), b.eq(S, i, n - 1), b.lt(S, j, n);
+            b.acc(S, 0, D_LD, e, 1, at(2, 1));
+            break;
+        case 4:  // left halo column, loaded by lx == 0
+            b.eq(S, lx, 0), b.lt(S, i, n);
+            b.acc(S, 0, D_LD, e, 1, at(1, 0));
+            break;
+        case 5:  // right halo column of a full tile
+            b.eq(S, lx, T - 1), b.lt(S, i, n), b.lt(S, j, n);
+            b.acc(S, 0, D_LD, e, 1, at(1, 2));
+            break;
+        default:  // right halo column of the last, partial tile column
+            b.lt(S, lx, T - 1), b.eq(S, j, n - 1), b.lt(S, i, n);
+            b.acc(S, 0, D_LD, e, 1, at(1, 2));
+        }
+    }
+    Stmt *Sb = b.stmt(3);
+    if (!Sb) return;
+    b.var(Sb, G), b.var(Sb, G), b.var(Sb, T), b.var(Sb, T);
+    Sb->bar = 1;
+    Stmt *Sc = b.stmt(3);
+    if (!Sc) return;
+    b.var(Sc, G), b.var(Sc, G), b.var(Sc, T), b.var(Sc, T);
+    b.lt(Sc, i, n), b.lt(Sc, j, n);
+    Sc->lds[D_LD][z] = 5;
+    Sc->flop[K_ADD][dt] = 4;  // N+S, +W, +E, + h^2 c^2
+    Sc->flop[K_MUL][dt] = 3;  // c*c, h^2*(.), 0.25*(.)
+    b.acc(Sc, 1, D_ST, e, 1, av(av(av(av(aff(0), 0, T * n), 2, n), 1, T), 3, 1));
+}
+
+// --- all-pairs n-body: out[i] = sum_{j != i} rsqrt(|x_i - x_j|^2) ---
+PM_HD void build_nbody(B &b, const pm_variant &v) {
+    int64_t N = v.n[0], Gs = v.wg[0];
+    if (N <= 0 || N > (1 << 26) || Gs < 64 || Gs > 1024 || Gs % 64 ||
+        v.dtype != PM_F32) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    int64_t GB = cdiv(N, Gs);
+    b.p->n_wg = GB;
+    b.p->wg_size = (int32_t)Gs;
+    b.array(0, 3 * N);
+    b.array(1, N);
+    Stmt *S = b.stmt(1);  // own position
+    if (!S) return;
+    int g = b.var(S, GB), l = b.var(S, Gs);
+    Aff i = av(av(aff(0), g, Gs), l, 1);
+    b.lt(S, i, N);
+    for (int c = 0; c < 3; c++)
+        b.acc(S, 0, D_LD, 4, 1, av(av(aff(c), g, 3 * Gs), l, 3));
+    Stmt *Sk = b.stmt(1);  // a block of positions -> LDS
+    if (!Sk) return;
+    g = b.var(Sk, GB), l = b.var(Sk, Gs);
+    int jb = b.var(Sk, GB);
+    b.lt(Sk, av(av(aff(0), jb, Gs), l, 1), N);
+    for (int c = 0; c < 3; c++)
+        b.acc(Sk, 0, D_LD, 4, 1, av(av(aff(c), jb, 3 * Gs), l, 3));
+    Sk->lds[D_ST][0] = 3;
+    Stmt *Sb = b.stmt(1);
+    if (!Sb) return;
+    b.var(Sb, GB), b.var(Sb, Gs), b.var(Sb, GB);
+    Sb->bar = 2;
+    Stmt *Sp = b.stmt(1);  // one pair
+    if (!Sp) return;
+    b.var(Sp, GB), b.var(Sp, Gs);
+    jb = b.var(Sp, GB);
+    int jj = b.var(Sp, Gs);
+    b.lt(Sp, av(av(aff(0), jb, Gs), jj, 1), N);
+    Sp->lds[D_LD][0] = 3;
+    Sp->flop[K_ADD][0] = 6;   // 3 differences, 2 adds in r^2, 1 accumulate
+    Sp->flop[K_MUL][0] = 3;
+    Sp->flop[K_SPEC][0] = 1;  // rsqrt; the self pair is masked by a select
+    Stmt *So = b.stmt(1);
+    if (!So) return;
+    g = b.var(So, GB), l = b.var(So, Gs);
+    b.lt(So, av(av(aff(0), g, Gs), l, 1), N);
+    b.acc(So, 1, D_ST, 4, 1, av(av(aff(0), g, Gs), l, 1));
+}
+
+// ------------------------------------------------------ job preparation ---
+// Fuse variables of a job whose affine forms treat (a, b) as one
+// mixed-radix digit pair; returns the new variable count.
+PM_HD int fuse(int nv, int64_t *ext, int nf, int64_t (*f)[MAXVAR + 1],
+               bool *ovf) {
+    bool again = true;
+    while (again && nv > 1) {
+        again = false;
+        for (int a = 0; a < nv && !again; a++)
+            for (int bb = 0; bb < nv && !again; bb++) {
+                if (a == bb) continue;
+                bool ok = true;
+                for (int q = 0; q < nf && ok; q++) {
+                    int64_t want;
+                    if (mul_ovf(f[q][a], ext[a], &want) || f[q][bb] != want) ok = false;
+                }
+                if (!ok) continue;
+                int64_t e2;
+                if (mul_ovf(ext[a], ext[bb], &e2)) {
+                    *ovf = true;
+                    return nv;
+                }
+                ext[a] = e2;
+                // remove bb
+                for (int t = bb; t < nv - 1; t++) {
+                    ext[t] = ext[t + 1];
+                    for (int q = 0; q < nf; q++) f[q][t] = f[q][t + 1];
+                }
+                for (int q = 0; q < nf; q++) f[q][nv - 1] = 0;
+                nv--;
+                again = true;
+            }
+    }
+    return nv;
+}
+
+// Inclusive bounds of var x in [0, ext) under guards c*x + k >= 0 on a
+// single variable; returns the count.
+PM_HD int64_t interval_count(int64_t ext, int ng, const int64_t (*g)[MAXVAR + 1]) {
+    int64_t lo = 0, hi = ext;  // [lo, hi)
+    for (int q = 0; q < ng; q++) {
+        int64_t a = g[q][0], r = g[q][MAXVAR];
+        if (a > 0) {
+            int64_t t = ceil_div(-r, a);
+            if (t > lo) lo = t;
+        } else if (a < 0) {
+            int64_t t = fdiv(r, -a) + 1;
+            if (t < hi) hi = t;
+        } else if (r < 0) {
+            return 0;
+        }
+    }
+    return hi > lo ? hi - lo : 0;
+}
+
+// Range [lo, hi) of the inner variable (var 0) for fixed outer values:
+// r[q] is guard q evaluated on the outer variables.
+PM_HD void inner_range(const Job &J, const int64_t *r, int64_t *lo_out,
+                       int64_t *hi_out) {
+    int64_t lo = 0, hi = J.ext[0];
+    for (int q = 0; q < J.ng; q++) {
+        int64_t a = J.g[q][0];
+        if (a == 1) {
+            if (-r[q] > lo) lo = -r[q];
+        } else if (a == -1) {
+            if (r[q] + 1 < hi) hi = r[q] + 1;
+        } else if (a > 0) {
+            int64_t t = ceil_div(-r[q], a);
+            if (t > lo) lo = t;
+        } else if (a < 0) {
+            int64_t t = fdiv(r[q], -a) + 1;
+            if (t < hi) hi = t;
+        } else if (r[q] < 0) {
+            hi = lo;
+        }
+    }
+    *lo_out = lo;
+    *hi_out = hi > lo ? hi : lo;
+}
+
+// Decompose outer point o (over vars 1..nv-1, var 1 fastest) and evaluate
+// the guards and the index map on it.
+PM_HD void eval_outer(const Job &J, int64_t o, int64_t *r, int64_t *base) {
+    for (int q = 0; q < J.ng; q++) r[q] = J.g[q][MAXVAR];
+    int64_t b = J.ic[MAXVAR];
+    for (int v = 1; v < J.nv; v++) {
+        int64_t e = J.ext[v];
+        int64_t x = o % e;
+        o /= e;
+        for (int q = 0; q < J.ng; q++) r[q] += J.g[q][v] * x;
+        b += J.ic[v] * x;
+    }
+    *base = b;
+}
+
+// Lane stride of an access in units of the access size (-1: not whole).
+PM_HD int64_t lane_stride(const Stmt &s, const GAcc &a) {
+    int64_t d = iabs(a.idx.c[s.lane]);
+    if (d % a.vec) return -1;
+    return d / a.vec;
+}
+
+// Expand a variant into its program and jobs.  `jobs` has MAXJOB slots.
+// Returns the status; sets per-array bitmap needs and prog->bitmap_words.
+PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
+    p->status = PM_OK;
+    p->nstmt = p->narr = p->njob = 0;
+    p->wg_size = 1;
+    p->n_wg = 0;
+    p->bitmap_words = 0;
+    B b{p};
+    switch (v.family) {
+    case PM_FAM_STREAM: build_stream(b, v); break;
+    case PM_FAM_LDS: build_lds(b, v); break;
+    case PM_FAM_FMA: build_chain(b, v, false); break;
+    case PM_FAM_RSQRT: build_chain(b, v, true); break;
+    case PM_FAM_BARRIER: build_barrier(b, v); break;
+    case PM_FAM_EMPTY: build_empty(b, v); break;
+    case PM_FAM_MATMUL: build_matmul(b, v); break;
+    case PM_FAM_TRANSPOSE: build_transpose(b, v); break;
+    case PM_FAM_STENCIL: build_stencil(b, v); break;
+    case PM_FAM_NBODY: build_nbody(b, v); break;
+    default: b.fail(PM_EINVAL);
+    }
+    for (int j = 0; j < MAXJOB; j++) {
+        jobs[j].kind = JOB_NONE;
+        jobs[j].chunks = 0;
+    }
+    if (p->status != PM_OK) return p->status;
+
+    // arrays needing footprints and their fill widths
+    for (int si = 0; si < p->nstmt; si++) {
+        Stmt &s = p->st[si];
+        for (int q = 0; q < s.nacc; q++) {
+            GAcc &a = s.acc[q];
+            int64_t st = lane_stride(s, a);
+            if (st < 0 || size_index(a.elem * a.vec) < 0) return b.fail(PM_EINVAL), p->status;
+            if (st >= 2) {
+                ArrInfo &A = p->arr[a.arr];
+                int64_t w = st * a.vec;
+                if (A.w && A.w != w) return b.fail(PM_EINVAL), p->status;
+                A.w = w;
+            }
+        }
+    }
+    int64_t off = 0;
+    for (int ai = 0; ai < p->narr; ai++) {
+        ArrInfo &A = p->arr[ai];
+        if (!A.w) continue;
+        bool mixed = false;  // any access of stride <= 1 to this array?
+        for (int si = 0; si < p->nstmt; si++)
+            for (int q = 0; q < p->st[si].nacc; q++)
+                if (p->st[si].acc[q].arr == ai && lane_stride(p->st[si], p->st[si].acc[q]) < 2)
+                    mixed = true;
+        A.words = (A.cells + A.w + 8 + 63) / 64 + 1;
+        A.f_off = off;
+        off += A.words;
+        if (mixed) {
+            A.b_off = off;
+            off += A.words;
+        } else {
+            A.b_off = A.f_off;
+        }
+        A.segs = cdiv(A.words, 4096);
+    }
+    p->bitmap_words = off;
+
+    int nj = 0;
+    for (int si = 0; si < p->nstmt; si++) {
+        Stmt &s = p->st[si];
+        s.ncomp = 0;
+        s.fixed = 1;
+        bool empty = false;
+        for (int x = 0; x < s.nvar; x++)
+            if (s.ext[x] == 0) empty = true;
+        bool guarded[MAXVAR];
+        int par[MAXVAR];
+        for (int x = 0; x < MAXVAR; x++) {
+            guarded[x] = false;
+            par[x] = x;
+        }
+        for (int q = 0; q < s.nguard; q++) {
+            int first = -1;
+            for (int x = 0; x < s.nvar; x++) {
+                if (!s.guard[q].c[x]) continue;
+                guarded[x] = true;
+                if (first < 0) {
+                    first = x;
+                } else {  // union(first, x)
+                    int ra = first, rb = x;
+                    while (par[ra] != ra) ra = par[ra];
+                    while (par[rb] != rb) rb = par[rb];
+                    if (ra != rb) par[rb] = ra;
+                }
+            }
+            if (first < 0 && s.guard[q].k < 0) empty = true;
+        }
+        if (empty) {
+            s.fixed = 0;
+            continue;
+        }
+        for (int x = 0; x < s.nvar; x++)
+            if (!guarded[x] && mul_ovf(s.fixed, s.ext[x], &s.fixed))
+                return b.fail(PM_EOVERFLOW), p->status;
+        // one count per component
+        for (int root = 0; root < s.nvar; root++) {
+            int rr = root;
+            while (par[rr] != rr) rr = par[rr];
+            if (!guarded[root] || rr != root) continue;
+            Job J;
+            J.kind = JOB_COUNT;
+            J.nv = 0;
+            J.ng = 0;
+            J.arr = -1;
+            J.vec = 1;
+            J.mark_b = 0;
+            int map[MAXVAR];
+            for (int x = 0; x < s.nvar; x++) {
+                int t = x;
+                while (par[t] != t) t = par[t];
+                map[x] = (guarded[x] && t == root) ? J.nv++ : -1;
+            }
+            for (int x = 0; x < s.nvar; x++)
+                if (map[x] >= 0) J.ext[map[x]] = s.ext[x];
+            for (int q = 0; q < s.nguard; q++) {
+                bool mine = false;
+                for (int x = 0; x < s.nvar; x++)
+                    if (s.guard[q].c[x] && map[x] >= 0) mine = true;
+                if (!mine) continue;
+                for (int t = 0; t <= MAXVAR; t++) J.g[J.ng][t] = 0;
+                for (int x = 0; x < s.nvar; x++)
+                    if (map[x] >= 0) J.g[J.ng][map[x]] = s.guard[q].c[x];
+                J.g[J.ng][MAXVAR] = s.guard[q].k;
+                J.ng++;
+            }
+            bool ovf = false;
+            J.nv = fuse(J.nv, J.ext, J.ng, J.g, &ovf);
+            if (ovf) return b.fail(PM_EOVERFLOW), p->status;
+            if (J.nv == 1) {  // an interval: closed form
+                int64_t c = interval_count(J.ext[0], J.ng, J.g);
+                if (mul_ovf(s.fixed, c, &s.fixed)) return b.fail(PM_EOVERFLOW), p->status;
+                continue;
+            }
+            // inner variable: the largest extent
+            int in = 0;
+            for (int x = 1; x < J.nv; x++)
+                if (J.ext[x] > J.ext[in]) in = x;
+            if (in) {
+                int64_t te = J.ext[0];
+                J.ext[0] = J.ext[in];
+                J.ext[in] = te;
+                for (int q = 0; q < J.ng; q++) {
+                    int64_t tg = J.g[q][0];
+                    J.g[q][0] = J.g[q][in];
+                    J.g[q][in] = tg;
+                }
+            }
+            for (int t = 0; t <= MAXVAR; t++) J.ic[t] = 0;
+            J.outer = 1;
+            for (int x = 1; x < J.nv; x++)
+                if (mul_ovf(J.outer, J.ext[x], &J.outer)) return b.fail(PM_EOVERFLOW), p->status;
+            J.seg = J.ext[0];
+            J.nseg = 1;
+            J.items = J.outer;
+            J.chunk_items = CHUNK_COUNT;
+            J.chunks = cdiv(J.items, J.chunk_items);
+            J.f_off = J.b_off = 0;
+            if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
+            s.comp_job[s.ncomp++] = nj;
+            jobs[nj++] = J;
+        }
+        // footprint jobs for accesses to arrays with a strided access
+        for (int q = 0; q < s.nacc; q++) {
+            GAcc &a = s.acc[q];
+            ArrInfo &A = p->arr[a.arr];
+            if (!A.w) continue;
+            Job J;
+            J.kind = JOB_FOOT;
+            J.nv = 0;
+            J.ng = 0;
+            J.arr = a.arr;
+            J.vec = a.vec;
+            J.mark_b = lane_stride(s, a) >= 2 && A.b_off != A.f_off;
+            J.f_off = A.f_off;
+            J.b_off = lane_stride(s, a) >= 2 ? A.b_off : -1;
+            int map[MAXVAR];
+            for (int x = 0; x < s.nvar; x++)
+                map[x] = (guarded[x] || a.idx.c[x]) ? J.nv++ : -1;
+            for (int x = 0; x < s.nvar; x++)
+                if (map[x] >= 0) J.ext[map[x]] = s.ext[x];
+            for (int t = 0; t <= MAXVAR; t++) J.ic[t] = 0;
+            for (int x = 0; x < s.nvar; x++)
+                if (map[x] >= 0) J.ic[map[x]] = a.idx.c[x];
+            J.ic[MAXVAR] = a.idx.k;
+            for (int g = 0; g < s.nguard; g++) {
+                for (int t = 0; t <= MAXVAR; t++) J.g[J.ng][t] = 0;
+                for (int x = 0; x < s.nvar; x++)
+                    if (map[x] >= 0) J.g[J.ng][map[x]] = s.guard[g].c[x];
+                J.g[J.ng][MAXVAR] = s.guard[g].k;
+                J.ng++;
+            }
+            // fuse over guards and the index map together
+            int64_t F[MAXGUARD + 1][MAXVAR + 1];
+            for (int g = 0; g < J.ng; g++)
+                for (int t = 0; t <= MAXVAR; t++) F[g][t] = J.g[g][t];
+            for (int t = 0; t <= MAXVAR; t++) F[J.ng][t] = J.ic[t];
+            bool ovf = false;
+            J.nv = fuse(J.nv, J.ext, J.ng + 1, F, &ovf);
+            if (ovf) return b.fail(PM_EOVERFLOW), p->status;
+            for (int g = 0; g < J.ng; g++)
+                for (int t = 0; t <= MAXVAR; t++) J.g[g][t] = F[g][t];
+            for (int t = 0; t <= MAXVAR; t++) J.ic[t] = F[J.ng][t];
+            if (J.nv == 0) {  // a single access point
+                J.nv = 1;
+                J.ext[0] = 1;
+            }
+            // inner variable: smallest non-zero index coefficient
+            int in = -1;
+            for (int x = 0; x < J.nv; x++) {
+                if (!J.ic[x]) continue;
+                if (in < 0 || iabs(J.ic[x]) < iabs(J.ic[in]) ||
+                    (iabs(J.ic[x]) == iabs(J.ic[in]) && J.ext[x] > J.ext[in]))
+                    in = x;
+            }
+            if (in < 0) in = 0;
+            if (in) {
+                int64_t te = J.ext[0];
+                J.ext[0] = J.ext[in];
+                J.ext[in] = te;
+                int64_t ti = J.ic[0];
+                J.ic[0] = J.ic[in];
+                J.ic[in] = ti;
+                for (int g = 0; g < J.ng; g++) {
+                    int64_t tg = J.g[g][0];
+                    J.g[g][0] = J.g[g][in];
+                    J.g[g][in] = tg;
+                }
+            }
+            J.outer = 1;
+            for (int x = 1; x < J.nv; x++)
+                if (mul_ovf(J.outer, J.ext[x], &J.outer)) return b.fail(PM_EOVERFLOW), p->status;
+            J.seg = iabs(J.ic[0]) <= J.vec ? SEG_CONTIG : SEG_STRIDED;
+            J.nseg = cdiv(J.ext[0], J.seg);
+            if (mul_ovf(J.outer, J.nseg, &J.items)) return b.fail(PM_EOVERFLOW), p->status;
+            J.chunk_items = CHUNK_FOOT;
+            J.chunks = cdiv(J.items, J.chunk_items);
+            if (nj >= MAXJOB) return b.fail(PM_EINVAL), p->status;
+            jobs[nj++] = J;
+        }
+    }
+    p->njob = nj;
+    return p->status;
+}
+
+// --------------------------------------------------- footprint marking ---
+// Marks of one footprint item: cells first + step*t, t in [0, cnt), each
+// covering vec cells, OR-ed into bitmap bm.  Work is split over `nl`
+// lanes; lane `ln` does its share.  ORfn(word_ptr, mask) performs the OR.
+template <class ORF>
+PM_HD void mark_run(uint64_t *bm, int64_t first, int64_t step, int64_t cnt,
+                    int64_t vec, int ln, int nl, ORF orf) {
+    if (cnt <= 0) return;
+    if (step <= vec) {  // one contiguous range
+        int64_t a = first, e = first + step * (cnt - 1) + vec;  // [a, e)
+        int64_t w0 = a >> 6, w1 = (e - 1) >> 6;
+        for (int64_t w = w0 + ln; w <= w1; w += nl) {
+            uint64_t m = ~0ull;
+            if (w == w0) m &= ~0ull << (a & 63);
+            if (w == w1) m &= ~0ull >> (63 - ((e - 1) & 63));
+            orf(bm + w, m);
+        }
+    } else if (step <= 64) {  // several accesses per word: build word masks
+        int64_t e = first + step * (cnt - 1) + vec;
+        int64_t w0 = first >> 6, w1 = (e - 1) >> 6;
+        for (int64_t w = w0 + ln; w <= w1; w += nl) {
+            int64_t lo = w << 6, hi = lo + 64;
+            int64_t t = lo - vec + 1 - first;
+            t = t <= 0 ? 0 : ceil_div(t, step);
+            uint64_t m = 0;
+            for (; t < cnt; t++) {
+                int64_t c = first + step * t;
+                if (c >= hi) break;
+                for (int64_t z = 0; z < vec; z++) {
+                    int64_t cz = c + z;
+                    if (cz >= lo && cz < hi) m |= 1ull << (cz - lo);
+                }
+            }
+            if (m) orf(bm + w, m);
+        }
+    } else {  // one access per word
+        for (int64_t t = ln; t < cnt; t += nl) {
+            int64_t c = first + step * t;
+            for (int64_t z = 0; z < vec; z++) {
+                int64_t cz = c + z;
+                orf(bm + (cz >> 6), 1ull << (cz & 63));
+            }
+        }
+    }
+}
+
+// Process footprint item `it` of job J (lane ln of nl cooperating lanes).
+template <class ORF>
+PM_HD void foot_item(const Job &J, int64_t it, uint64_t *vbase, int ln, int nl,
+                     ORF orf) {
+    int64_t o = it / J.nseg, sg = it % J.nseg;
+    int64_t r[MAXGUARD], base, lo, hi;
+    eval_outer(J, o, r, &base);
+    inner_range(J, r, &lo, &hi);
+    int64_t s0 = sg * J.seg, s1 = s0 + J.seg;
+    if (lo < s0) lo = s0;
+    if (hi > s1) hi = s1;
+    if (hi <= lo) return;
+    int64_t c0 = J.ic[0];
+    int64_t first, step;
+    if (c0 >= 0) {
+        first = base + c0 * lo;
+        step = c0;
+    } else {
+        first = base + c0 * (hi - 1);
+        step = -c0;
+    }
+    int64_t cnt = hi - lo;
+    if (step == 0) cnt = 1;
+    mark_run(vbase + J.f_off, first, step, cnt, J.vec, ln, nl, orf);
+    if (J.mark_b) mark_run(vbase + J.b_off, first, step, cnt, J.vec, ln, nl, orf);
+}
+
+// Count of count-job item `it` (one outer point).
+PM_HD int64_t count_item(const Job &J, int64_t it) {
+    int64_t r[MAXGUARD], base, lo, hi;
+    eval_outer(J, it, r, &base);
+    inner_range(J, r, &lo, &hi);
+    return hi - lo;
+}
+
+// ------------------------------------------------------------ fill pass ---
+// Dilation of the set bits of m by [0, w) inside one word.
+PM_HD uint64_t dilate_word(uint64_t m, int64_t w) {
+    int64_t ext = 1;
+    while (ext < w && ext < 64) {
+        int64_t sh = ext < w - ext ? ext : w - ext;
+        m |= m << sh;
+        ext += sh;
+    }
+    return m;
+}
+// Bits of word k covered by a run [last, last + w) that started before it.
+PM_HD uint64_t carry_mask(int64_t last, int64_t w, int64_t k) {
+    if (last < 0) return 0;
+    int64_t n = last + w - (k << 6);
+    if (n <= 0) return 0;
+    if (n >= 64) return ~0ull;
+    return (1ull << n) - 1;
+}
+PM_HD int64_t last_bit(uint64_t m, int64_t k) {
+    return m ? (k << 6) + 63 - __builtin_clzll(m) : -1;
+}
+
+// ------------------------------------------------------------- finalize ---
+PM_HD int class_index(int64_t s, int64_t F, int64_t Fill) {
+    if (s == 0) return 0;
+    if (s == 1) return 1;
+    int64_t q = s < 4 ? s : 4;
+    if (Fill <= 0) return s == 2 ? 2 : s == 3 ? 4 : s == 4 ? 7 : 11;
+    int64_t k = cdiv(q * F, Fill);
+    if (k < 1) k = 1;
+    if (k > q) k = q;
+    int base = s == 2 ? 2 : s == 3 ? 4 : s == 4 ? 7 : 11;
+    return base + (int)(k - 1);
+}
+
+// Assemble the count vector from statement counts (component job results
+// `jobres`) and per-array footprint sizes F/Fill.  Returns a status.
+PM_HD int finalize(const Prog &p, const int64_t *jobres, const int64_t *F,
+                   const int64_t *Fill, int64_t *c) {
+    for (int i = 0; i < PM_NCOUNT; i++) c[i] = 0;
+    if (p.status != PM_OK) return p.status;
+    bool ovf = false;
+    auto addm = [&](int slot, int64_t cnt, int64_t mult) {
+        int64_t t;
+        if (mul_ovf(cnt, mult, &t) || add_ovf(c[slot], t, &c[slot])) ovf = true;
+    };
+    for (int si = 0; si < p.nstmt; si++) {
+        const Stmt &s = p.st[si];
+        int64_t cnt = s.fixed;
+        for (int q = 0; q < s.ncomp; q++)
+            if (mul_ovf(cnt, jobres[s.comp_job[q]], &cnt)) ovf = true;
+        if (cnt == 0) continue;
+        for (int q = 0; q < s.nacc; q++) {
+            const GAcc &a = s.acc[q];
+            int64_t st = lane_stride(s, a);
+            int z = size_index(a.elem * a.vec);
+            int cl = class_index(st, F[a.arr], Fill[a.arr]);
+            addm(C_GACC + (a.dir * 3 + z) * NCLS + cl, cnt, 1);
+        }
+        for (int d = 0; d < 2; d++)
+            for (int z = 0; z < 3; z++)
+                if (s.lds[d][z]) addm(C_LDS + d * 3 + z, cnt, s.lds[d][z]);
+        for (int k = 0; k < 6; k++)
+            for (int d = 0; d < 2; d++)
+                if (s.flop[k][d]) addm(C_FLOP + k * 2 + d, cnt, s.flop[k][d]);
+        if (s.bar) addm(C_BARWI, cnt, s.bar);
+    }
+    c[C_WG] = p.n_wg;
+    if (mul_ovf(p.n_wg, (int64_t)p.wg_size, &c[C_WI])) ovf = true;
+    c[C_BARWG] = p.wg_size ? c[C_BARWI] / p.wg_size : 0;
+    return ovf ? PM_EOVERFLOW : PM_OK;
+}
+
+// ------------------------------------------------------------- features ---
+PM_HD int nfeat(uint32_t proj) {
+    return proj == PM_PROJ_P3 ? 3 : proj == PM_PROJ_P12 ? 12 : proj == PM_PROJ_FULL ? 154 : -1;
+}
+
+PM_HD bool full_use_class(int cl) {  // '0', '1', '2/2', '3/3', '4/4'
+    return cl == 0 || cl == 1 || cl == 3 || cl == 6 || cl == 10;
+}
+
+PM_HD int features(const int64_t *c, uint32_t proj, double *f) {
+    const int SZ[3] = {4, 8, 16};
+    if (proj == PM_PROJ_P3) {
+        double gb = 0;
+        for (int d = 0; d < 2; d++)
+            for (int z = 0; z < 3; z++)
+                for (int cl = 0; cl < NCLS; cl++)
+                    gb += (double)SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + cl];
+        f[0] = gb;
+        f[1] = (double)c[C_FLOP + K_FMA * 2 + 0];
+        f[2] = (double)c[C_WG];
+        return 3;
+    }
+    if (proj == PM_PROJ_P12) {
+        double full[2] = {0, 0}, part[2] = {0, 0}, s1[2] = {0, 0};
+        for (int d = 0; d < 2; d++)
+            for (int z = 0; z < 3; z++)
+                for (int cl = 0; cl < NCLS; cl++) {
+                    double bytes = (double)SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + cl];
+                    if (full_use_class(cl)) full[d] += bytes;
+                    else part[d] += bytes;
+                    if (cl == 1) s1[d] += bytes;
+                }
+        double ldsb = 0;
+        for (int d = 0; d < 2; d++)
+            for (int z = 0; z < 3; z++) ldsb += (double)SZ[z] * (double)c[C_LDS + d * 3 + z];
+        f[0] = 1.0;
+        f[1] = (double)c[C_WG];
+        f[2] = (double)c[C_BARWI];
+        f[3] = (double)c[C_FLOP + K_ADD * 2] + (double)c[C_FLOP + K_MUL * 2] +
+               2.0 * (double)c[C_FLOP + K_FMA * 2];
+        f[4] = (double)c[C_FLOP + K_ADD * 2 + 1] + (double)c[C_FLOP + K_MUL * 2 + 1] +
+               2.0 * (double)c[C_FLOP + K_FMA * 2 + 1];
+        double sp = 0;
+        for (int d = 0; d < 2; d++)
+            sp += (double)c[C_FLOP + K_SPEC * 2 + d] + (double)c[C_FLOP + K_DIV * 2 + d] +
+                  (double)c[C_FLOP + K_EXP * 2 + d];
+        f[5] = sp;
+        f[6] = ldsb;
+        f[7] = full[0];
+        f[8] = full[1];
+        f[9] = part[0];
+        f[10] = part[1];
+        f[11] = s1[0] < s1[1] ? s1[0] : s1[1];
+        return 12;
+    }
+    if (proj == PM_PROJ_FULL) {
+        int t = 0;
+        for (int i = 0; i < 90; i++) f[t++] = (double)c[C_GACC + i];
+        for (int i = 0; i < 6; i++) f[t++] = (double)c[C_LDS + i];
+        for (int k = 0; k < 5; k++)
+            for (int d = 0; d < 2; d++) {
+                double x = (double)c[C_FLOP + k * 2 + d];
+                if (k == K_ADD || k == K_MUL) x += (double)c[C_FLOP + K_FMA * 2 + d];
+                f[t++] = x;
+            }
+        f[t++] = (double)c[C_BARWI];
+        f[t++] = (double)c[C_WG];
+        f[t++] = 1.0;
+        for (int z = 0; z < 3; z++)
+            for (int cl = 0; cl < NCLS; cl++) {
+                int64_t ld = c[C_GACC + (0 * 3 + z) * NCLS + cl];
+                int64_t st = c[C_GACC + (1 * 3 + z) * NCLS + cl];
+                f[t++] = (double)(ld < st ? ld : st);
+            }
+        return t;
+    }
+    return -1;
+}
+
+// T = sum_i alpha_i f_i, accumulated in feature order.
+PM_HD double predict(const int64_t *c, const pm_model &m) {
+    double f[PM_NFEAT_MAX];
+    int nf = features(c, m.proj, f);
+    double t = 0.0;
+    for (int i = 0; i < nf && i < (int)m.nfeat; i++) t += m.alpha[i] * f[i];
+    return t;
+}
+
+}  // namespace pm
