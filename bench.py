@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark of the hardware-fitted linear run-time model on one MI355X.
+
+Timed step: one batched pass of the counter + FP64 prediction (libpm's
+six counter kernels) over the batched-sweep workload -- 4096 tiled/naive
+matmul, stencil and transpose variants whose main iteration domains hold
+2^U(16,30) points, extents not multiples of the tile -- with the variants
+already resident in HBM.  Reported `value`: variants counted and predicted
+per second.
+
+Also reported, outside the timed region:
+  * the plain per-variant path (one synchronous pm_count call per variant,
+    host in / host out) and the batched/plain ratio;
+  * the model itself: the instructive suite measured (4 warm-ups, 26 timed
+    runs, minimum) and fitted (relative-error least squares), then the test
+    suite measured and predicted: geometric-mean relative error;
+  * per-kernel HIP-event times of the counter over the timed steps and the
+    roofline of the dominant kernel;
+  * the CPU oracle (simulated execution) on a bounded sample of the same
+    workload, extrapolated by its event rate.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-model]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # bytes/s, MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def domain_points(v):
+    """Points of the variant's main iteration domain."""
+    f = v["family"]
+    if f == "matmul":
+        return v["n"] * v["m"] * v["l"]
+    if f in ("stencil", "transpose"):
+        return v["n"] * v["n"]
+    if f == "nbody":
+        return v["n"] * v["n"]
+    return v.get("n", 0)
+
+
+def measure_suite(ctx, P, variants, warmup=4, reps=26):
+    import torch
+    T = []
+    for i, v in enumerate(variants):
+        ts, _ = P.device_buffers(v, v.get("seed", i), fast=True)
+        t, _ = ctx.measure(v, ts, warmup=warmup, reps=reps)
+        T.append(t)
+        del ts
+        if i % 25 == 0:
+            log("  measured %d/%d (%s: %.3g ms)" % (i + 1, len(variants), v["family"], t * 1e3))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return np.array(T)
+
+
+def model_phase(ctx, P, proj_list=("p12", "full")):
+    from synth import suite_instructive, suite_test
+    meas = suite_instructive()
+    test = suite_test()
+    log("model: measuring %d instructive variants" % len(meas))
+    Tm = measure_suite(ctx, P, meas)
+    cm = ctx.count_raw(meas)
+    log("model: measuring %d test variants" % len(test))
+    Tt = measure_suite(ctx, P, test)
+    ct = ctx.count_raw(test)
+    out = {}
+    models = {}
+    for proj in proj_list:
+        m, cond, resid, rank = P.fit(cm, Tm, proj)
+        pred = np.array([P.features(ct[i], proj) @ P.model_alpha(m) for i in range(len(test))])
+        err = np.abs(pred - Tt) / Tt
+        fam = {}
+        for f in ("matmul", "transpose", "stencil", "nbody"):
+            e = [err[i] for i, v in enumerate(test) if v["family"] == f]
+            fam[f] = round(float(math.exp(np.mean(np.log(np.maximum(e, 1e-12))))), 4)
+        gm = float(math.exp(np.mean(np.log(np.maximum(err, 1e-12)))))
+        fit_err = float(math.exp(np.mean(np.log(np.maximum(np.abs(resid), 1e-12)))))
+        out[proj] = {"geomean": round(gm, 4), "per_family": fam, "rank": rank,
+                     "cond": float("%.3g" % cond), "fit_geomean": round(fit_err, 4)}
+        models[proj] = m
+    return out, models, (meas, Tm, test, Tt)
+
+
+def cpu_baseline(workload, gpu_counts, budget_s=15.0):
+    """Simulated-execution oracle on a bounded random sample of the workload:
+    variants in random order until ~budget_s of oracle time; its event rate
+    (events = sum of a variant's count vector) extrapolates the whole
+    workload."""
+    from oracle import count as OC
+    rng = np.random.default_rng(42)
+    order = rng.permutation(len(workload))
+    ev_all = gpu_counts.sum(axis=1).astype(np.float64)
+    t_used, ev_used, done = 0.0, 0.0, 0
+    for i in order:
+        if ev_all[i] > 3e8:  # one oracle call must stay a few seconds
+            continue
+        t0 = time.perf_counter()
+        OC.count(workload[i])
+        t_used += time.perf_counter() - t0
+        ev_used += ev_all[i]
+        done += 1
+        if t_used > budget_s:
+            break
+    rate = ev_used / t_used
+    est = ev_all.sum() / rate
+    return {"value": round(len(workload) / est, 4), "unit": "variants/s",
+            "cores": 1, "kind": "oracle",
+            "sample": "%d of %d workload variants (random order, those under "
+                      "3e8 events), %.1f s, %.3g events/s; value = 4096 / "
+                      "(all variants' events / that rate)" % (done, len(workload), t_used, rate)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--skip-model", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=1024)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the counter's work is per variant and "
+              "independent, so a multi-GPU run would shard the variant list; "
+              "this build runs and reports --gpus 1 only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1604_04997_amd as P
+    from synth import suite_batched
+
+    assert torch.cuda.is_available(), "no GPU"
+    dev = torch.cuda.get_device_properties(0)
+    log("device:", dev.name, "CUs:", dev.multi_processor_count)
+    ctx = P.Context(0, hbm_budget=128 << 30)
+
+    # ------------------------------------------------------------- model --
+    model_info, models = None, {}
+    if not args.skip_model:
+        model_info, models, _ = model_phase(ctx, P)
+        log("model:", json.dumps(model_info))
+    m = models.get("p12") or P.model_struct("p12", [1e-12] * 12)
+
+    # ------------------------------------------------------ batched step --
+    vs = suite_batched(4096)
+    nv = len(vs)
+    va = P.variant_array(vs)
+    d_v = torch.frombuffer(bytearray(bytes(memoryview(va).cast("B"))), dtype=torch.uint8).cuda()
+    d_c = torch.zeros((nv, P.PM_NCOUNT), dtype=torch.int64, device="cuda")
+    d_t = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    d_s = torch.zeros(nv, dtype=torch.int32, device="cuda")
+    bm_bytes = sum(P.bitmap_bytes(v) for v in vs)
+    ctx.reserve(nv, bm_bytes)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        ctx.count_device(d_v.data_ptr(), nv, d_c.data_ptr(), m, d_t.data_ptr(),
+                         d_s.data_ptr(), stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert int((d_s != 0).sum()) == 0, "variants failed: %s" % d_s.unique()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phase_ms, nb = ctx.profile_read()
+    ctx.profile(False)
+    stats = ctx.batch_stats()
+    assert int((d_s != 0).sum()) == 0
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = nv / ((t1 - t0) / args.steps)
+    counts = d_c.cpu().numpy()
+    points = float(sum(domain_points(v) for v in vs))
+    log("batched: %.3f ms/step, %.0f variants/s; kernels %s" % (ms_step, value, phase_ms))
+
+    # -------------------------------------------------------- plain path --
+    ns = min(args.plain_sample, nv)
+    rng = np.random.default_rng(1)
+    idx = rng.permutation(nv)[:ns]
+    one = [P.variant_array([vs[i]]) for i in idx]
+    for a in one[:8]:
+        ctx.count_raw(a)
+    tp0 = time.perf_counter()
+    for a in one:
+        ctx.count_raw(a)
+    tp1 = time.perf_counter()
+    plain = ns / (tp1 - tp0)
+    t_call = (tp1 - tp0) / ns
+    log("plain: %.0f variants/s (%.1f us per call, %d-variant sample)" % (plain, t_call * 1e6, ns))
+
+    # ---------------------------------------------------------- roofline --
+    # the dominant kernel and its algorithmic bytes: clear writes the used
+    # bitmap words, fill reads F and B words of every strided array, count
+    # ORs footprint words (read-modify-write)
+    words = stats["bitmap_words"]
+    dom = max(phase_ms, key=phase_ms.get)
+    alg_bytes = {"clear": 8 * words, "fill": 8 * words, "count": 16 * words}.get(dom)
+    roof = None
+    if alg_bytes:
+        ach = alg_bytes / (phase_ms[dom] * 1e-3)
+        roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(ach / 1e9, 2),
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(ach / HBM_PEAK, 4),
+                "traffic": None, "alg_bytes_per_launch": alg_bytes}
+    else:
+        roof = {"kernel": "k_" + dom, "bound": "alu", "achieved": None, "peak": None,
+                "unit": None, "frac": None, "traffic": None}
+
+    # ----------------------------------------------------------- CPU leg --
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(vs, counts, args.cpu_seconds)
+        log("cpu oracle:", cpu)
+
+    line = {
+        "metric": "geomean rel. prediction error; variants counted+predicted/sec, batched vs plain",
+        "value": round(value, 1), "unit": "variants/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "batched autotune sweep: 4096 matmul/stencil/transpose "
+                               "variants, main domains 2^16..2^30 points, counted + "
+                               "predicted in one pass", "variants": nv,
+                   "domain_points": points, "model": "p12"},
+        "points_per_s": float("%.4g" % (points * value / nv)),
+        "plain_variants_per_s": round(plain, 1), "plain_us_per_call": round(t_call * 1e6, 2),
+        "batched_over_plain": round(value / plain, 2),
+        "geomean_rel_err": model_info,
+        "kernel_ms": {k: round(x, 4) for k, x in phase_ms.items()},
+        "batch_stats": stats,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,9 @@ def lib():
             "pm_measure": (ctypes.c_int, [vp, P(Variant), P(vp), P(ctypes.c_size_t), ctypes.c_uint32, vp,
                                           ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]),
             "pm_count_host": (ctypes.c_int, [P(Variant), P(Counts), P(ctypes.c_int64)]),
+            "pm_profile": (ctypes.c_int, [vp, ctypes.c_int]),
+            "pm_profile_read": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int)]),
+            "pm_batch_stats": (ctypes.c_int, [vp, P(ctypes.c_int64)]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -268,6 +271,24 @@ class Context:
         _check(lib().pm_predict(self._h, ctypes.byref(model), va, len(va), t))
         return np.array(t[:])
 
+    PHASES = ("build", "scan", "clear", "count", "fill", "finalize")
+
+    def profile(self, enable: bool = True):
+        _check(lib().pm_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """({kernel: mean milliseconds}, batches) since profiling started."""
+        ms = (ctypes.c_double * 6)()
+        nb = ctypes.c_int()
+        _check(lib().pm_profile_read(self._h, ms, ctypes.byref(nb)))
+        return dict(zip(self.PHASES, ms[:])), nb.value
+
+    def batch_stats(self) -> dict:
+        st = (ctypes.c_int64 * 8)()
+        _check(lib().pm_batch_stats(self._h, st))
+        return {"chunks": st[0], "bitmap_words": st[1], "fill_segments": st[2],
+                "bitmap_words_requested": st[4]}
+
     def reserve(self, nv: int, bitmap_bytes_: int):
         _check(lib().pm_reserve(self._h, nv, bitmap_bytes_))
 
@@ -307,11 +328,30 @@ class Context:
         return tmin.value, list(tr[:])
 
 
-def device_buffers(d: dict, seed: int, device: str = "cuda:0"):
+def device_buffers(d: dict, seed: int, device: str = "cuda:0",
+                   fast: bool = False):
     """Allocate the variant's buffers with torch on `device`; inputs get
     seeded uniform[-1, 1] values (synth.uniform), outputs zeros, sentinel
-    outputs NaN.  Returns (tensors, host copies of the initial contents)."""
+    outputs NaN.  Returns (tensors, host copies of the initial contents).
+    fast=True draws the inputs on the device instead (same distribution,
+    torch's generator; no host copies) for timing runs."""
     import torch
+    if fast:
+        g = torch.Generator(device=device)
+        g.manual_seed(seed)
+        tdt = torch.float64 if d.get("dtype", "f32") == "f64" else torch.float32
+        esz = 8 if tdt == torch.float64 else 4
+        out_t = []
+        for nbytes, role in buffers(d):
+            t = torch.empty(nbytes // esz, dtype=tdt, device=device)
+            if role in (0, 2):
+                t.uniform_(-1.0, 1.0, generator=g)
+            elif role == 3:
+                t.fill_(float("nan"))
+            else:
+                t.zero_()
+            out_t.append(t)
+        return out_t, None
 
     from synth import uniform
     dt = d.get("dtype", "f32")

@@ -96,6 +96,19 @@ struct pm_ctx {
     int32_t *h_status = nullptr;
     int64_t *h_meta = nullptr;
     std::vector<hipEvent_t> events;
+    bool profile = false;
+    std::vector<hipEvent_t> pev;  // (PM_NPHASE + 1) per recorded batch
+    int pcount = 0;
+    hipEvent_t *next_events() {
+        if (!profile || pcount >= PM_PROFILE_MAX) return nullptr;
+        size_t need = (size_t)(pcount + 1) * (PM_NPHASE + 1);
+        while (pev.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pev.push_back(e);
+        }
+        return &pev[(size_t)(pcount++) * (PM_NPHASE + 1)];
+    }
 };
 
 namespace {
@@ -194,7 +207,7 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
     for (int attempt = 0; attempt < 2; attempt++) {
         HIPCHK(hipMemcpyAsync(c->d_var, c->h_var, sizeof(pm_variant) * nv, hipMemcpyHostToDevice, c->stream));
         st = pm::launch_batch(c->ar, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
-                              c->d_status, c->stream, c->n_cu);
+                              c->d_status, c->stream, c->n_cu, c->next_events());
         if (st) return set_err(st, "counter launch failed");
         HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(c->h_meta, c->ar.meta, 64, hipMemcpyDeviceToHost, c->stream));
@@ -323,6 +336,7 @@ void pm_destroy(pm_ctx *c) {
     (void)hipFree(c->ar.bitmap);
     (void)hipHostFree(c->h_meta);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -376,7 +390,8 @@ pm_status pm_count_device(pm_ctx *c, const pm_variant *d_v, size_t nv, pm_counts
     int st = grow_cap(c, nv);
     if (st) return (pm_status)st;
     hipStream_t s = stream ? (hipStream_t)stream : c->stream;
-    st = pm::launch_batch(c->ar, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu);
+    st = pm::launch_batch(c->ar, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu,
+                          c->next_events());
     if (st) return (pm_status)set_err(st, "counter launch failed");
     return PM_OK;
 }
@@ -388,6 +403,45 @@ pm_status pm_reserve(pm_ctx *c, size_t nv, size_t bitmap_bytes) {
     int st = grow_cap(c, nv);
     if (st) return (pm_status)st;
     return (pm_status)grow_bitmap(c, (bitmap_bytes + 7) / 8);
+}
+
+pm_status pm_profile(pm_ctx *c, int enable) {
+    if (!c) return (pm_status)set_err(PM_EINVAL, "null context");
+    c->profile = enable != 0;
+    c->pcount = 0;
+    return PM_OK;
+}
+
+pm_status pm_profile_read(pm_ctx *c, double *ms, int *nbatch) {
+    if (!c || !ms) return (pm_status)set_err(PM_EINVAL, "null argument");
+    DeviceGuard g(c->device);
+    int n = c->pcount;
+    for (int i = 0; i < PM_NPHASE; i++) ms[i] = 0;
+    for (int b = 0; b < n; b++) {
+        hipEvent_t *e = &c->pev[(size_t)b * (PM_NPHASE + 1)];
+        if (hipEventSynchronize(e[PM_NPHASE]) != hipSuccess)
+            return (pm_status)set_err(PM_EDEVICE, "event wait failed");
+        for (int i = 0; i < PM_NPHASE; i++) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, e[i], e[i + 1]) != hipSuccess)
+                return (pm_status)set_err(PM_EDEVICE, "no timing recorded");
+            ms[i] += t;
+        }
+    }
+    if (n)
+        for (int i = 0; i < PM_NPHASE; i++) ms[i] /= n;
+    if (nbatch) *nbatch = n;
+    c->pcount = 0;
+    return PM_OK;
+}
+
+pm_status pm_batch_stats(pm_ctx *c, int64_t *stats) {
+    if (!c || !stats || !c->ar.meta) return (pm_status)set_err(PM_EINVAL, "no batch has run");
+    DeviceGuard g(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(stats, c->ar.meta, 64, hipMemcpyDeviceToHost) != hipSuccess)
+        return (pm_status)set_err(PM_EDEVICE, "stats copy failed");
+    return PM_OK;
 }
 
 pm_status pm_bitmap_bytes(const pm_variant *v, size_t *bytes) {

@@ -31,9 +31,11 @@ size_t arena_bytes_per_variant();
 
 // Enqueue the six counter launches for nv variants already in device
 // memory (d_var) on stream s.  d_counts / model / d_pred may be null.
+// ev: null, or 7 events recorded around the six launches.
 int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
-                 int32_t *d_status, hipStream_t s, int n_cu);
+                 int32_t *d_status, hipStream_t s, int n_cu,
+                 hipEvent_t *ev = nullptr);
 
 // Host execution of the same per-variant code (descriptor, jobs, items,
 // fill, finalize), one variant at a time; for unit tests on machines

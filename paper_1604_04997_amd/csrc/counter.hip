@@ -101,9 +101,12 @@ k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
     __syncthreads();
     int64_t need = scan_inplace(nv, varoff, [](int64_t) { return true; }, true, sh);
     int64_t used = 0;
+    // only variants that hold bitmap words bound the region to clear: a
+    // variant without bitmaps may sit at an offset past the arena's end
     for (int64_t i = threadIdx.x; i < nv; i += SCAN_THREADS) {
+        if (varwords[i] == 0) continue;
         int64_t end = varoff[i] + varwords[i];
-        if (varwords[i] > 0 && end > arena_words) status[i] = PM_ENOMEM;
+        if (end > arena_words) status[i] = PM_ENOMEM;
         else if (end > used) used = end;
     }
     sh[threadIdx.x] = used;
@@ -129,8 +132,8 @@ k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
 }
 
 __global__ void k_clear(int nv, uint64_t *bitmap, int64_t *jobres,
-                        int64_t *foot, const int64_t *meta) {
-    int64_t words = meta[1];
+                        int64_t *foot, const int64_t *meta, int64_t arena_words) {
+    int64_t words = meta[1] < arena_words ? meta[1] : arena_words;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t i = t; i < words; i += stride) bitmap[i] = 0;
@@ -296,24 +299,35 @@ __global__ void k_finalize(int nv, const Prog *prog, const int64_t *jobres,
 // ---------------------------------------------------------------- host ---
 int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
-                 int32_t *d_status, hipStream_t s, int n_cu) {
+                 int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev) {
     if (nv <= 0) return PM_OK;
     int tb = 64;
+    int q = 0;
+    auto mark = [&]() {
+        if (ev) (void)hipEventRecord(ev[q++], s);
+    };
+    mark();
     hipLaunchKernelGGL(k_build, dim3((nv + tb - 1) / tb), dim3(tb), 0, s, nv,
                        d_var, ar.prog, ar.jobs, d_status, ar.varwords,
                        ar.jobpref, ar.arrpref);
+    mark();
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
                        (const int64_t *)ar.varwords, ar.varoff, ar.jobpref,
                        ar.arrpref, ar.meta, (int64_t)ar.bitmap_words);
+    mark();
     hipLaunchKernelGGL(k_clear, dim3(n_cu * 8), dim3(256), 0, s, nv, ar.bitmap,
-                       ar.jobres, ar.foot, (const int64_t *)ar.meta);
+                       ar.jobres, ar.foot, (const int64_t *)ar.meta,
+                       (int64_t)ar.bitmap_words);
+    mark();
     hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s, nv,
                        (const Job *)ar.jobs, (const int64_t *)ar.jobpref,
                        (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, ar.meta);
+    mark();
     hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s, nv,
                        (const Prog *)ar.prog, (const int64_t *)ar.arrpref,
                        (const int64_t *)ar.varoff, (const uint64_t *)ar.bitmap,
                        ar.foot, (const int64_t *)ar.meta);
+    mark();
     pm_model m{};
     int has = 0;
     if (model) {
@@ -323,6 +337,7 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
     hipLaunchKernelGGL(k_finalize, dim3((nv + tb - 1) / tb), dim3(tb), 0, s, nv,
                        (const Prog *)ar.prog, (const int64_t *)ar.jobres,
                        (const int64_t *)ar.foot, d_status, d_counts, m, has, d_pred);
+    mark();
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 

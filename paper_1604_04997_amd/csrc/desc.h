@@ -124,6 +124,7 @@ struct Job {
     int64_t ic[MAXVAR + 1];          // footprint index map, constant last
     int64_t seg, nseg, outer, items, chunk_items, chunks;
     int64_t f_off, b_off;            // bitmap word offsets (variant-relative)
+    int64_t words;                   // words of each of this array's bitmaps
 };
 
 // ------------------------------------------------------------- helpers ---
@@ -906,6 +907,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             J.chunk_items = CHUNK_COUNT;
             J.chunks = cdiv(J.items, J.chunk_items);
             J.f_off = J.b_off = 0;
+            J.words = 0;
             if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
             s.comp_job[s.ncomp++] = nj;
             jobs[nj++] = J;
@@ -924,6 +926,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             J.mark_b = lane_stride(s, a) >= 2 && A.b_off != A.f_off;
             J.f_off = A.f_off;
             J.b_off = lane_stride(s, a) >= 2 ? A.b_off : -1;
+            J.words = A.words;
             int map[MAXVAR];
             for (int x = 0; x < s.nvar; x++)
                 map[x] = (guarded[x] || a.idx.c[x]) ? J.nv++ : -1;
@@ -997,10 +1000,14 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
 // Marks of one footprint item: cells first + step*t, t in [0, cnt), each
 // covering vec cells, OR-ed into bitmap bm.  Work is split over `nl`
 // lanes; lane `ln` does its share.  ORfn(word_ptr, mask) performs the OR.
+// Words outside [0, nwords) are never touched.
 template <class ORF>
-PM_HD void mark_run(uint64_t *bm, int64_t first, int64_t step, int64_t cnt,
-                    int64_t vec, int ln, int nl, ORF orf) {
-    if (cnt <= 0) return;
+PM_HD void mark_run(uint64_t *bm, int64_t nwords, int64_t first, int64_t step,
+                    int64_t cnt, int64_t vec, int ln, int nl, ORF orf) {
+    if (cnt <= 0 || first < 0) return;
+    auto orb = [&](int64_t w, uint64_t m) {
+        if (w >= 0 && w < nwords) orf(bm + w, m);
+    };
     if (step <= vec) {  // one contiguous range
         int64_t a = first, e = first + step * (cnt - 1) + vec;  // [a, e)
         int64_t w0 = a >> 6, w1 = (e - 1) >> 6;
@@ -1008,7 +1015,7 @@ PM_HD void mark_run(uint64_t *bm, int64_t first, int64_t step, int64_t cnt,
             uint64_t m = ~0ull;
             if (w == w0) m &= ~0ull << (a & 63);
             if (w == w1) m &= ~0ull >> (63 - ((e - 1) & 63));
-            orf(bm + w, m);
+            orb(w, m);
         }
     } else if (step <= 64) {  // several accesses per word: build word masks
         int64_t e = first + step * (cnt - 1) + vec;
@@ -1026,14 +1033,14 @@ PM_HD void mark_run(uint64_t *bm, int64_t first, int64_t step, int64_t cnt,
                     if (cz >= lo && cz < hi) m |= 1ull << (cz - lo);
                 }
             }
-            if (m) orf(bm + w, m);
+            if (m) orb(w, m);
         }
     } else {  // one access per word
         for (int64_t t = ln; t < cnt; t += nl) {
             int64_t c = first + step * t;
             for (int64_t z = 0; z < vec; z++) {
                 int64_t cz = c + z;
-                orf(bm + (cz >> 6), 1ull << (cz & 63));
+                orb(cz >> 6, 1ull << (cz & 63));
             }
         }
     }
@@ -1062,8 +1069,8 @@ PM_HD void foot_item(const Job &J, int64_t it, uint64_t *vbase, int ln, int nl,
     }
     int64_t cnt = hi - lo;
     if (step == 0) cnt = 1;
-    mark_run(vbase + J.f_off, first, step, cnt, J.vec, ln, nl, orf);
-    if (J.mark_b) mark_run(vbase + J.b_off, first, step, cnt, J.vec, ln, nl, orf);
+    mark_run(vbase + J.f_off, J.words, first, step, cnt, J.vec, ln, nl, orf);
+    if (J.mark_b) mark_run(vbase + J.b_off, J.words, first, step, cnt, J.vec, ln, nl, orf);
 }
 
 // Count of count-job item `it` (one outer point).

@@ -1,0 +1,128 @@
+"""Closed-form kernel properties, derived by hand from the kernel
+descriptions (work-item by work-item counting, Sec. 3.2 Alg. 1), valid at
+any size.  Used to check counts at sizes no enumeration finishes."""
+
+
+def cdiv(a, b):
+    return -(-a // b)
+
+
+def matmul(v):
+    n, m, l, T = v["n"], v["m"], v["l"], v["T"]
+    GX, GY, KT = cdiv(l, T), cdiv(n, T), cdiv(m, T)
+    wi = GX * GY * T * T
+    if v["op"] == "tiled":
+        return {"gld.4.1": n * m * GX + m * l * GY, "gst.4.1": n * l,
+                "lst.4": 2 * wi * KT, "lld.4": 2 * wi * KT * T,
+                "fma.f32": wi * KT * T, "bar.wi": 2 * wi * KT,
+                "bar.wg": 2 * GX * GY * KT, "wg": GX * GY, "wi": wi}
+    return {"gld.4.0": n * m * l, "gld.4.1": n * m * l, "gst.4.1": n * l,
+            "fma.f32": n * m * l, "wg": GX * GY, "wi": wi}
+
+
+def transpose(v):
+    n, T = v["n"], v["T"]
+    G = cdiv(n, T)
+    base = {"wg": G * G, "wi": G * G * T * T}
+    strided = "4/>4" if n > 4 else {2: "2/2", 3: "3/3", 4: "4/4"}.get(n, "1")
+    if v["op"] == "tiled":
+        base.update({"gld.4.1": n * n, "gst.4.1": n * n, "lst.4": n * n,
+                     "lld.4": n * n, "bar.wi": G * G * T * T, "bar.wg": G * G})
+    elif v["op"] == "naive_wc":
+        base.update({"gld.4." + strided: n * n, "gst.4.1": n * n})
+    else:
+        base.update({"gld.4.1": n * n, "gst.4." + strided: n * n})
+    out = {}
+    for k, x in base.items():
+        out[k] = out.get(k, 0) + x
+    return out
+
+
+def stencil(v):
+    n, T, dt = v["n"], v["T"], v.get("dtype", "f32")
+    e = 4 if dt == "f32" else 8
+    G = cdiv(n, T)
+    halo = 4 * n * G
+    return {"gld.%d.1" % e: n * n + halo, "lst.%d" % e: n * n + halo,
+            "lld.%d" % e: 5 * n * n, "add." + dt: 4 * n * n,
+            "mul." + dt: 3 * n * n, "gst.%d.1" % e: n * n,
+            "bar.wi": G * G * T * T, "bar.wg": G * G, "wg": G * G,
+            "wi": G * G * T * T}
+
+
+def nbody(v):
+    N, G = v["n"], v["wg"]
+    B = cdiv(N, G)
+    wi = B * G
+    return {"gld.4.3/3": 3 * N + 3 * N * B, "gst.4.1": N, "lst.4": 3 * N * B,
+            "lld.4": 3 * wi * N, "add.f32": 6 * wi * N, "mul.f32": 3 * wi * N,
+            "spec.f32": wi * N, "bar.wi": 2 * wi * B, "bar.wg": 2 * B * B,
+            "wg": B, "wi": wi}
+
+
+def stream(v):
+    dt = v.get("dtype", "f32")
+    e = 4 if dt == "f32" else 8
+    n, wg, s, U, vec = v["n"], v["wg"], v["s"], v.get("U", 1), v.get("vec", 1)
+    base = {"wg": n // wg, "wi": n}
+    if v["op"] == "filled":
+        cl = {2: "2/2", 3: "3/3"}[s]
+        base.update({"gld.%d.%s" % (e, cl): s * n * U, "gst.%d.1" % e: n,
+                     "add." + dt: s * n * U})
+        return base
+    cl = {1: "1", 2: "1/2", 3: "1/3", 4: "1/4"}.get(s, "1/>4")
+    key = "%d.%s" % (e * vec, cl)
+    if v["op"] == "load":
+        base.update({"gld." + key: n * U, "add." + dt: n * U * vec})
+    elif v["op"] == "store":
+        base["gst." + key] = n * U
+    elif v["op"] == "copy":
+        base.update({"gld." + key: n * U, "gst." + key: n * U})
+    else:
+        base.update({"gld." + key: 4 * n * U, "gst." + key: n * U,
+                     "add." + dt: 3 * n * U * vec})
+    return base
+
+
+def chain(v):
+    dt = v.get("dtype", "f32")
+    e = 4 if dt == "f32" else 8
+    n, F, K = v["n"], v["F"], v["K"]
+    out = {"gld.%d.1" % e: n, "gst.%d.1" % e: n, "wg": n // v["wg"], "wi": n}
+    if v["family"] == "fma":
+        out.update({"fma." + dt: n * F, "add." + dt: n * (K - 1)})
+    else:
+        out.update({"mul.f32": n * F, "add.f32": n * F + n * (K - 1),
+                    "spec.f32": n * F})
+    return {k: x for k, x in out.items() if x}
+
+
+def lds(v):
+    G, wg, R, W = v["groups"], v["wg"], v["R"], v["W"]
+    out = {"gst.4.1": G * wg, "bar.wi": G * wg, "bar.wg": G, "wg": G, "wi": G * wg}
+    if v["op"] == "read":
+        out.update({"lst.4": G * W, "lld.4": G * wg * R, "add.f32": G * wg * R})
+    else:
+        out.update({"lst.4": G * wg * R, "lld.4": G * wg})
+    return {k: x for k, x in out.items() if x}
+
+
+def barrier(v):
+    G, wg, B = v["groups"], v["wg"], v["B"]
+    out = {"bar.wi": G * wg * B, "bar.wg": G * B, "gst.4.1": G * wg, "wg": G,
+           "wi": G * wg}
+    return {k: x for k, x in out.items() if x}
+
+
+def empty(v):
+    gx, gy = cdiv(v["n"], v["wx"]), cdiv(v["n"], v.get("wy", 1))
+    return {"wg": gx * gy, "wi": gx * gy * v["wx"] * v.get("wy", 1)}
+
+
+FORMS = {"matmul": matmul, "transpose": transpose, "stencil": stencil,
+         "nbody": nbody, "stream": stream, "fma": chain, "rsqrt": chain,
+         "lds": lds, "barrier": barrier, "empty": empty}
+
+
+def counts(v):
+    return FORMS[v["family"]](v)

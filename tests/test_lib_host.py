@@ -232,3 +232,11 @@ def test_buffers_layout():
     b = P.buffers(dict(family="stream", op="load", dtype="f64", n=512, wg=256, s=2,
                        gs=2, vec=2, U=2))
     assert b == [(8 * 2 * 2 * 256 * 2 * 2 * 2, 0), (8 * 512, 3)]
+
+
+def test_host_counts_full_size_closed_forms():
+    """The full workloads (batched sweep, instructive and test suites) at
+    their real sizes against closed forms derived from the kernels."""
+    from closed_forms import counts as closed
+    for v in suite_batched(4096) + suite_instructive() + suite_test() + suite_tiny():
+        assert P.count_host(v) == closed(v), v
