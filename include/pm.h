@@ -86,8 +86,11 @@ enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC 
  *             tile T in {8,16,32}
  *   NBODY     n[0] bodies (positions 3 x n column-major), wg[0] block size
  *             (64..1024, multiple of 64); fp32
+ * flags: PM_FLAG_BITMAP counts every footprint with bitmaps, also where
+ * the interval form applies (same counts; for cross-checks).
  * Unused fields must be zero.  `seed` is carried for the caller's records.
  */
+#define PM_FLAG_BITMAP 1u
 typedef struct {
     uint32_t family, dtype, op, flags;
     int64_t n[3];

@@ -45,7 +45,7 @@ __global__ void k_build(int nv, const pm_variant *__restrict__ var, Prog *prog,
         jobpref[(size_t)i * MAXJOB + j] = (st == PM_OK && j < p->njob) ? J[j].chunks : 0;
     for (int a = 0; a < MAXARR; a++)
         arrpref[(size_t)i * MAXARR + a] =
-            (st == PM_OK && a < p->narr && p->arr[a].w) ? p->arr[a].segs : 0;
+            (st == PM_OK && a < p->narr && p->arr[a].w && p->arr[a].words) ? p->arr[a].segs : 0;
 }
 
 // Block-wide inclusive scan of per-thread int64 values (SCAN_THREADS).
@@ -160,7 +160,7 @@ struct DevOr {
 
 __global__ void __launch_bounds__(COUNT_THREADS)
 k_count(int nv, const Job *jobs, const int64_t *jobpref, const int64_t *varoff,
-        uint64_t *bitmap, int64_t *jobres, int64_t *meta) {
+        uint64_t *bitmap, int64_t *jobres, int64_t *foot, int64_t *meta) {
     const int lane = threadIdx.x & 63;
     const int64_t total = meta[0];
     const int64_t njobs = (int64_t)nv * MAXJOB;
@@ -180,6 +180,21 @@ k_count(int nv, const Job *jobs, const int64_t *jobpref, const int64_t *varoff,
             for (int64_t it = it0 + lane; it < it1; it += 64) s += count_item(J, it);
             for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
             if (lane == 0 && s) atomicAdd((unsigned long long *)&jobres[j], (unsigned long long)s);
+        } else if (J.kind == JOB_IVAL) {
+            int64_t sf = 0, sl = 0;
+            for (int64_t it = it0 + lane; it < it1; it += 64) {
+                int64_t df, dl;
+                ival_item(J, it, &df, &dl);
+                sf += df;
+                sl += dl;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                sf += __shfl_xor(sf, off);
+                sl += __shfl_xor(sl, off);
+            }
+            int64_t fa = ((j / MAXJOB) * MAXARR + J.arr) * 2;
+            if (lane == 0 && sf) atomicAdd((unsigned long long *)&foot[fa], (unsigned long long)sf);
+            if (lane == 0 && sl) atomicAdd((unsigned long long *)&foot[fa + 1], (unsigned long long)sl);
         } else {
             uint64_t *vb = bitmap + varoff[j / MAXJOB];
             for (int64_t it = it0; it < it1; it++) foot_item(J, it, vb, lane, 64, DevOr{});
@@ -321,7 +336,7 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
     mark();
     hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s, nv,
                        (const Job *)ar.jobs, (const int64_t *)ar.jobpref,
-                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, ar.meta);
+                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, ar.foot, ar.meta);
     mark();
     hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s, nv,
                        (const Prog *)ar.prog, (const int64_t *)ar.arrpref,
@@ -359,16 +374,24 @@ int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out) {
     if (st != PM_OK) return st;
     std::vector<uint64_t> bm((size_t)p.bitmap_words + 1, 0);
     int64_t jobres[MAXJOB] = {0};
-    for (int j = 0; j < p.njob; j++) {
-        if (J[j].kind == JOB_COUNT)
-            for (int64_t it = 0; it < J[j].items; it++) jobres[j] += count_item(J[j], it);
-        else
-            for (int64_t it = 0; it < J[j].items; it++) foot_item(J[j], it, bm.data(), 0, 1, HostOr{});
-    }
     int64_t F[MAXARR] = {0}, Fill[MAXARR] = {0};
+    for (int j = 0; j < p.njob; j++) {
+        if (J[j].kind == JOB_COUNT) {
+            for (int64_t it = 0; it < J[j].items; it++) jobres[j] += count_item(J[j], it);
+        } else if (J[j].kind == JOB_IVAL) {
+            for (int64_t it = 0; it < J[j].items; it++) {
+                int64_t df, dl;
+                ival_item(J[j], it, &df, &dl);
+                F[J[j].arr] += df;
+                Fill[J[j].arr] += dl;
+            }
+        } else {
+            for (int64_t it = 0; it < J[j].items; it++) foot_item(J[j], it, bm.data(), 0, 1, HostOr{});
+        }
+    }
     for (int a = 0; a < p.narr; a++) {
         const ArrInfo &A = p.arr[a];
-        if (!A.w) continue;
+        if (!A.w || !A.words) continue;
         const uint64_t *f = bm.data() + A.f_off, *b = bm.data() + A.b_off;
         int64_t carry = -1;
         for (int64_t k = 0; k < A.words; k++) {

@@ -55,7 +55,7 @@ constexpr int C_WI = 111;
 
 enum { K_ADD = 0, K_MUL, K_DIV, K_EXP, K_SPEC, K_FMA };
 enum { D_LD = 0, D_ST = 1 };
-enum { JOB_NONE = 0, JOB_COUNT = 1, JOB_FOOT = 2 };
+enum { JOB_NONE = 0, JOB_COUNT = 1, JOB_FOOT = 2, JOB_IVAL = 3 };
 
 // inner points handled by one footprint work item
 constexpr int64_t SEG_CONTIG = 16384;
@@ -104,7 +104,7 @@ struct ArrInfo {
     int64_t f_off;  // word offset of F inside the variant's bitmap region
     int64_t b_off;  // word offset of B (cells of strided accesses); == f_off if same
     int64_t w;      // fill width of strided accesses: stride * vec cells
-    int64_t segs;   // fill-pass segments
+    int64_t segs;   // fill-pass segments (0: interval mode or no footprint)
 };
 
 struct Prog {
@@ -125,6 +125,7 @@ struct Job {
     int64_t seg, nseg, outer, items, chunk_items, chunks;
     int64_t f_off, b_off;            // bitmap word offsets (variant-relative)
     int64_t words;                   // words of each of this array's bitmaps
+    int64_t w;                       // interval mode: fill width of a strided access, else 0
 };
 
 // ------------------------------------------------------------- helpers ---
@@ -742,6 +743,80 @@ PM_HD int64_t lane_stride(const Stmt &s, const GAcc &a) {
     return d / a.vec;
 }
 
+// ---------------------------------------------------------- interval mode
+// An array with a single footprint job whose fused domain has the inner
+// variable t (index coefficient step > 0) and at most one outer variable x
+// (coefficient c1 > 0), with no guard coupling t and x: every non-empty
+// outer point covers the same inner range [lo, hi), so its cells are
+// first(x) + step*t, t in [0, cnt), first(x) increasing in x, and the
+// non-empty x form one interval.  Then
+//   F    = union over x of its cells (a contiguous run when step <= vec,
+//          else cnt disjoint accesses of vec cells),
+//   Fill = union over x of [first, last cell + w)   (strided access), or F.
+// Sorted runs of equal length: |union| = sum of each run's length minus its
+// overlap with the previous run, so every run contributes independently.
+PM_HD bool ival_ok(const Job &J) {
+    if (J.nv > 2 || J.ic[0] <= 0) return false;
+    if (J.nv == 2 && J.ic[1] <= 0) return false;
+    int64_t lo = 0, hi = J.ext[0];
+    for (int q = 0; q < J.ng; q++) {
+        if (J.nv == 2 && J.g[q][0] && J.g[q][1]) return false;
+        if (!J.g[q][0]) continue;
+        int64_t a = J.g[q][0], r = J.g[q][MAXVAR];
+        if (a > 0) {
+            int64_t t = ceil_div(-r, a);
+            if (t > lo) lo = t;
+        } else {
+            int64_t t = fdiv(r, -a) + 1;
+            if (t < hi) hi = t;
+        }
+    }
+    int64_t cnt = hi > lo ? hi - lo : 0;
+    int64_t step = J.ic[0], vec = J.vec;
+    if (cnt == 0) return true;
+    if (step > vec && J.nv == 2 && J.ic[1] < step * (cnt - 1) + vec) return false;  // runs interleave
+    if (J.w && step >= vec + J.w) return false;  // widened accesses leave gaps
+    return true;
+}
+
+// Run of outer point x: false if empty; else [a, e) spans its cells and
+// [a, g) its widened cells.
+PM_HD bool ival_run(const Job &J, int64_t x, int64_t *a, int64_t *e, int64_t *g,
+                    int64_t *cnt) {
+    int64_t r[MAXGUARD], base, lo, hi;
+    eval_outer(J, x, r, &base);
+    inner_range(J, r, &lo, &hi);
+    if (hi <= lo) return false;
+    int64_t step = J.ic[0];
+    *cnt = hi - lo;
+    *a = base + step * lo;
+    int64_t last = base + step * (hi - 1) + J.vec;  // one past the last cell
+    *e = last;
+    *g = J.w ? last - 1 + J.w : last;
+    return true;
+}
+
+// Contributions of outer point `it` to |F| and |Fill|.
+PM_HD void ival_item(const Job &J, int64_t it, int64_t *dF, int64_t *dFill) {
+    int64_t a, e, g, cnt, ap, ep, gp, cp;
+    *dF = *dFill = 0;
+    if (!ival_run(J, it, &a, &e, &g, &cnt)) return;
+    bool prev = it > 0 && ival_run(J, it - 1, &ap, &ep, &gp, &cp);
+    int64_t step = J.ic[0];
+    if (step <= J.vec) {
+        int64_t s0 = prev && ep > a ? ep : a;
+        *dF = e > s0 ? e - s0 : 0;
+    } else {
+        *dF = cnt * J.vec;
+    }
+    if (J.w || step <= J.vec) {
+        int64_t s0 = prev && gp > a ? gp : a;
+        *dFill = g > s0 ? g - s0 : 0;
+    } else {
+        *dFill = *dF;  // stride <= 1 access with gaps: Fill = F
+    }
+}
+
 // Expand a variant into its program and jobs.  `jobs` has MAXJOB slots.
 // Returns the status; sets per-array bitmap needs and prog->bitmap_words.
 PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
@@ -785,28 +860,6 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             }
         }
     }
-    int64_t off = 0;
-    for (int ai = 0; ai < p->narr; ai++) {
-        ArrInfo &A = p->arr[ai];
-        if (!A.w) continue;
-        bool mixed = false;  // any access of stride <= 1 to this array?
-        for (int si = 0; si < p->nstmt; si++)
-            for (int q = 0; q < p->st[si].nacc; q++)
-                if (p->st[si].acc[q].arr == ai && lane_stride(p->st[si], p->st[si].acc[q]) < 2)
-                    mixed = true;
-        A.words = (A.cells + A.w + 8 + 63) / 64 + 1;
-        A.f_off = off;
-        off += A.words;
-        if (mixed) {
-            A.b_off = off;
-            off += A.words;
-        } else {
-            A.b_off = A.f_off;
-        }
-        A.segs = cdiv(A.words, 4096);
-    }
-    p->bitmap_words = off;
-
     int nj = 0;
     for (int si = 0; si < p->nstmt; si++) {
         Stmt &s = p->st[si];
@@ -908,6 +961,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             J.chunks = cdiv(J.items, J.chunk_items);
             J.f_off = J.b_off = 0;
             J.words = 0;
+            J.w = 0;
             if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
             s.comp_job[s.ncomp++] = nj;
             jobs[nj++] = J;
@@ -923,10 +977,10 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             J.ng = 0;
             J.arr = a.arr;
             J.vec = a.vec;
-            J.mark_b = lane_stride(s, a) >= 2 && A.b_off != A.f_off;
-            J.f_off = A.f_off;
-            J.b_off = lane_stride(s, a) >= 2 ? A.b_off : -1;
-            J.words = A.words;
+            J.mark_b = lane_stride(s, a) >= 2;  // strided: its cells are widened
+            J.f_off = J.b_off = -1;             // set with the array's mode below
+            J.words = 0;
+            J.w = J.mark_b ? A.w : 0;
             int map[MAXVAR];
             for (int x = 0; x < s.nvar; x++)
                 map[x] = (guarded[x] || a.idx.c[x]) ? J.nv++ : -1;
@@ -993,6 +1047,51 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
         }
     }
     p->njob = nj;
+
+    // Each strided array: interval mode when its footprint is a sorted
+    // sequence of runs (see ival_item), else bitmaps.
+    int64_t off = 0;
+    for (int ai = 0; ai < p->narr; ai++) {
+        ArrInfo &A = p->arr[ai];
+        if (!A.w) continue;
+        int nfj = 0, fj = -1;
+        for (int j = 0; j < nj; j++)
+            if (jobs[j].kind == JOB_FOOT && jobs[j].arr == ai) nfj++, fj = j;
+        if (nfj == 1 && !(v.flags & PM_FLAG_BITMAP) && ival_ok(jobs[fj])) {
+            Job &J = jobs[fj];
+            J.kind = JOB_IVAL;
+            J.items = J.nv == 2 ? J.ext[1] : 1;
+            J.seg = J.ext[0];
+            J.nseg = 1;
+            J.chunk_items = CHUNK_COUNT;
+            J.chunks = cdiv(J.items, J.chunk_items);
+            A.words = 0;
+            A.segs = 0;
+            continue;
+        }
+        bool mixed = false;  // a stride <= 1 access: widened cells kept apart
+        for (int j = 0; j < nj; j++)
+            if (jobs[j].kind == JOB_FOOT && jobs[j].arr == ai && !jobs[j].mark_b) mixed = true;
+        A.words = (A.cells + A.w + 8 + 63) / 64 + 1;
+        A.f_off = off;
+        off += A.words;
+        if (mixed) {
+            A.b_off = off;
+            off += A.words;
+        } else {
+            A.b_off = A.f_off;
+        }
+        A.segs = cdiv(A.words, 4096);
+        for (int j = 0; j < nj; j++) {
+            Job &J = jobs[j];
+            if (J.kind != JOB_FOOT || J.arr != ai) continue;
+            J.f_off = A.f_off;
+            J.b_off = J.mark_b ? A.b_off : -1;
+            J.mark_b = J.mark_b && A.b_off != A.f_off;
+            J.words = A.words;
+        }
+    }
+    p->bitmap_words = off;
     return p->status;
 }
 

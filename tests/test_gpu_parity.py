@@ -42,6 +42,7 @@ def _strip(d):
 # ---------------------------------------------------------------- counts --
 def test_counts_match_oracle_in_one_batch(ctx):
     vs = FAMILY_CASES + suite_batched(count=64, lo_log2=8, hi_log2=13)
+    vs = vs + [dict(v, bitmap=True) for v in vs]  # both footprint methods
     print("counting %d variants in one batch" % len(vs), flush=True)
     got = ctx.count(vs)
     for v, g in zip(vs, got):
@@ -50,6 +51,7 @@ def test_counts_match_oracle_in_one_batch(ctx):
 
 def test_counts_full_size_closed_forms(ctx):
     vs = suite_batched(4096) + suite_instructive() + suite_test() + suite_tiny()
+    vs = vs + [dict(v, bitmap=True) for v in suite_batched(512, seed=3)]
     print("counting %d full-size variants" % len(vs), flush=True)
     got = ctx.count(vs)
     for v, g in zip(vs, got):
@@ -93,7 +95,8 @@ def test_device_resident_path_and_prediction(ctx):
 
 
 def test_small_budget_reports_enomem():
-    big = dict(family="transpose", op="naive_wc", n=30000, T=16)
+    # bitmap footprints: (30000^2 + 30000) bits, more than the 64 MiB budget
+    big = dict(family="transpose", op="naive_wc", n=30000, T=16, bitmap=True)
     c = P.Context(0, hbm_budget=64 << 20)
     try:
         with pytest.raises(P.PMError) as e:

@@ -99,6 +99,7 @@ FAMILY_CASES = [
 @pytest.mark.parametrize("v", FAMILY_CASES, ids=lambda v: "-".join(str(x) for x in v.values()))
 def test_host_counts_match_oracle(v):
     _same(v)
+    _same(dict(v, bitmap=True))  # bitmap footprints instead of intervals
 
 
 def test_host_counts_on_batched_workload_sample():
