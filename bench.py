@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--autotune-problems", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the counter's work is per variant and "
@@ -211,13 +213,57 @@ def main():
     t_call = (tp1 - tp0) / ns
     log("plain: %.0f variants/s (%.1f us per call, %d-variant sample)" % (plain, t_call * 1e6, ns))
 
+    # ---------------------------------------------------------- autotune --
+    tune = None
+    if models and args.autotune_problems > 0:
+        from paper_1604_04997_amd import autotune
+        probs, seen = [], set()
+        for fam in ("matmul", "stencil", "transpose"):
+            k = 0
+            for v in vs:
+                if v["family"] != fam or domain_points(v) > (1 << 27):
+                    continue
+                key = autotune.problem_key(v)
+                if key in seen:
+                    continue
+                seen.add(key)
+                probs.append({x: y for x, y in v.items() if x not in ("op", "T", "seed")})
+                k += 1
+                if k >= args.autotune_problems:
+                    break
+        log("autotune: %d problems, every configuration measured" % len(probs))
+        res = autotune.rank_and_measure(ctx, models["p12"], probs, measure_all=True)
+        tune = autotune.summary(res)
+        tune["per_family"] = {}
+        for fam in ("matmul", "stencil", "transpose"):
+            rr = [r for r in res if r["problem"]["family"] == fam]
+            if rr:
+                tune["per_family"][fam] = autotune.summary(rr)
+        log("autotune:", json.dumps(tune))
+
+    # ----------------------------------------------------------- serving --
+    serving = None
+    if args.serve_seconds > 0:
+        from paper_1604_04997_amd import serve
+        from synth import serving_trace
+        trace = serving_trace(rate=2000.0, duration=args.serve_seconds)
+        srv = serve.Server(ctx, m)
+        _, st_b = srv.run(trace)
+        _, st_p = serve.run_plain(ctx, m, trace)
+        serving = {"requests": len(trace), "rate_per_s": 2000.0,
+                   "batched": {k: (round(x, 4) if isinstance(x, float) else x)
+                               for k, x in st_b.items()},
+                   "plain": {k: (round(x, 4) if isinstance(x, float) else x)
+                             for k, x in st_p.items()}}
+        log("serving:", json.dumps(serving))
+
     # ---------------------------------------------------------- roofline --
     # the dominant kernel and its algorithmic bytes: clear writes the used
     # bitmap words, fill reads F and B words of every strided array, count
     # ORs footprint words (read-modify-write)
     words = stats["bitmap_words"]
     dom = max(phase_ms, key=phase_ms.get)
-    alg_bytes = {"clear": 8 * words, "fill": 8 * words, "count": 16 * words}.get(dom)
+    alg_bytes = {"clear": 8 * words, "fill": 8 * words, "count": 16 * words}.get(dom) if words else None
     roof = None
     if alg_bytes:
         ach = alg_bytes / (phase_ms[dom] * 1e-3)
@@ -250,6 +296,7 @@ def main():
         "geomean_rel_err": model_info,
         "kernel_ms": {k: round(x, 4) for k, x in phase_ms.items()},
         "batch_stats": stats,
+        "autotune": tune, "serving": serving,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -186,7 +186,8 @@ pm_status pm_reserve(pm_ctx *ctx, size_t nv, size_t bitmap_bytes);
 /* Per-kernel timing of the batched counter.  pm_profile(ctx, 1) starts a
  * timing window: every batch until pm_profile_read (at most
  * PM_PROFILE_MAX batches) records HIP events around each of its six
- * launches (descriptor build, prefix sums, clear, count, fill, finalize)
+ * launches (fused per-variant build + count + finalize, then for variants
+ * that need footprint bitmaps: prefix sums, clear, count, fill, finalize)
  * on the stream they run on.  pm_profile_read waits for the recorded
  * batches and writes the mean duration of each kernel in milliseconds to
  * ms[6] (host) and the number of batches to *nbatch; the window then

@@ -1,0 +1,94 @@
+"""Model-ranked configuration selection (the paper's Sec. 6.2 use: pick the
+fastest of several equivalent kernel configurations from predictions).
+
+A *problem* is one computation at one size (family, op-independent sizes,
+dtype); its *configurations* are the kernel variants that compute it
+(tile size, tiled vs naive, coalescing side).  All configurations of all
+problems are counted and predicted in one batched pass on the GPU; per
+problem the predicted-fastest configurations are measured and compared
+with the measured-fastest.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import device_buffers, variant_array
+
+TILES = (8, 16, 32)
+
+
+def configurations(v: dict):
+    """All kernel variants that compute the same result as `v`."""
+    f = v["family"]
+    if f == "matmul":
+        return [dict(v, op=op, T=T) for op in ("tiled", "naive") for T in TILES]
+    if f == "transpose":
+        return [dict(v, op=op, T=T) for op in ("tiled", "naive_wc", "naive_rc")
+                for T in TILES]
+    if f == "stencil":
+        return [dict(v, T=T) for T in TILES]
+    if f == "nbody":
+        return [dict(v, wg=g) for g in (64, 128, 256, 512, 1024)]
+    return [dict(v)]
+
+
+def problem_key(v: dict):
+    keep = {k: x for k, x in v.items() if k not in ("op", "T", "wg", "seed")}
+    return tuple(sorted(keep.items()))
+
+
+def rank_and_measure(ctx, model, problems, top_k: int = 3, measure_all=False,
+                     warmup: int = 4, reps: int = 26):
+    """For each problem: predict every configuration (one batched count +
+    predict), measure the top_k predicted (or all), and report the choice.
+
+    Returns a list of dicts with the problem, predicted and measured times
+    of the measured configurations, the chosen configuration (predicted
+    best), the measured best among those measured, and the slowdown of the
+    choice against that best."""
+    import torch
+    cfgs, owner = [], []
+    for pi, p in enumerate(problems):
+        for c in configurations(p):
+            cfgs.append(c)
+            owner.append(pi)
+    pred = ctx.predict(model, variant_array(cfgs))
+    out = []
+    for pi, p in enumerate(problems):
+        idx = [i for i, o in enumerate(owner) if o == pi]
+        order = sorted(idx, key=lambda i: pred[i])
+        meas_idx = order if measure_all else order[:top_k]
+        meas = {}
+        for i in meas_idx:
+            ts, _ = device_buffers(cfgs[i], cfgs[i].get("seed", i), fast=True)
+            meas[i], _ = ctx.measure(cfgs[i], ts, warmup=warmup, reps=reps)
+            del ts
+        torch.cuda.empty_cache()
+        best = min(meas, key=meas.get)
+        chosen = order[0]
+        rec = {"problem": p, "n_configs": len(idx),
+               "configs": [cfgs[i] for i in meas_idx],
+               "predicted": [float(pred[i]) for i in meas_idx],
+               "measured": [float(meas[i]) for i in meas_idx],
+               "chosen": cfgs[chosen], "measured_best": cfgs[best],
+               "slowdown": float(meas[chosen] / meas[best])}
+        if len(meas_idx) >= 3:
+            rp = np.argsort(np.argsort([pred[i] for i in meas_idx]))
+            rm = np.argsort(np.argsort([meas[i] for i in meas_idx]))
+            rec["spearman"] = float(np.corrcoef(rp, rm)[0, 1])
+        out.append(rec)
+    return out
+
+
+def summary(results):
+    """Geomean slowdown of the predicted choice, fraction of problems where
+    it is the measured best, mean rank correlation."""
+    sl = [r["slowdown"] for r in results]
+    sp = [r["spearman"] for r in results if "spearman" in r and not math.isnan(r["spearman"])]
+    return {"problems": len(results),
+            "choice_is_best": float(np.mean([s <= 1.0 + 1e-12 for s in sl])),
+            "geomean_slowdown": float(math.exp(np.mean(np.log(sl)))),
+            "max_slowdown": float(max(sl)),
+            "mean_spearman": float(np.mean(sp)) if sp else None}

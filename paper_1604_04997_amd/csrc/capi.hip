@@ -119,8 +119,8 @@ void free_arena(pm_ctx *c) {
     (void)hipFree(a.jobs);
     (void)hipFree(a.varwords);
     (void)hipFree(a.varoff);
-    (void)hipFree(a.jobpref);
-    (void)hipFree(a.arrpref);
+    (void)hipFree(a.varchunks);
+    (void)hipFree(a.varsegs);
     (void)hipFree(a.jobres);
     (void)hipFree(a.foot);
     (void)hipFree(a.meta);
@@ -156,15 +156,16 @@ int grow_cap(pm_ctx *c, size_t nv) {
                  sizeof(double) + sizeof(int32_t);
     if (per * cap + c->bitmap_alloc > c->budget)
         return set_err(PM_ENOMEM, "batch arena exceeds the context's HBM budget");
-    (void)hipStreamSynchronize(c->stream);
+    // batches may be in flight on caller streams: wait for the device
+    (void)hipDeviceSynchronize();
     free_arena(c);
     pm::Arena &a = c->ar;
     HIPCHK(hipMalloc(&a.prog, sizeof(pm::Prog) * cap));
     HIPCHK(hipMalloc(&a.jobs, sizeof(pm::Job) * cap * pm::MAXJOB));
     HIPCHK(hipMalloc(&a.varwords, 8 * cap));
     HIPCHK(hipMalloc(&a.varoff, 8 * cap));
-    HIPCHK(hipMalloc(&a.jobpref, 8 * cap * pm::MAXJOB));
-    HIPCHK(hipMalloc(&a.arrpref, 8 * cap * pm::MAXARR));
+    HIPCHK(hipMalloc(&a.varchunks, 8 * cap));
+    HIPCHK(hipMalloc(&a.varsegs, 8 * cap));
     HIPCHK(hipMalloc(&a.jobres, 8 * cap * pm::MAXJOB));
     HIPCHK(hipMalloc(&a.foot, 16 * cap * pm::MAXARR));
     HIPCHK(hipMalloc(&a.meta, 64));
@@ -187,7 +188,7 @@ int grow_bitmap(pm_ctx *c, size_t words) {
     if (c->arena_alloc + w * 8 > c->budget) w = words;
     if (c->arena_alloc + w * 8 > c->budget)
         return set_err(PM_ENOMEM, "footprint bitmaps exceed the context's HBM budget");
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipDeviceSynchronize();
     (void)hipFree(c->ar.bitmap);
     c->ar.bitmap = nullptr;
     c->ar.bitmap_words = 0;

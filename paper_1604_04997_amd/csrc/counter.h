@@ -19,8 +19,8 @@ struct Arena {
     Job *jobs = nullptr;         // [cap * MAXJOB]
     int64_t *varwords = nullptr; // [cap]
     int64_t *varoff = nullptr;   // [cap]
-    int64_t *jobpref = nullptr;  // [cap * MAXJOB]
-    int64_t *arrpref = nullptr;  // [cap * MAXARR]
+    int64_t *varchunks = nullptr; // [cap]: chunks, then their inclusive prefix
+    int64_t *varsegs = nullptr;   // [cap]: fill segments, then their inclusive prefix
     int64_t *jobres = nullptr;   // [cap * MAXJOB]
     int64_t *foot = nullptr;     // [cap * MAXARR * 2]
     int64_t *meta = nullptr;     // [8]: chunks, words used, fill segments, ticket, words requested

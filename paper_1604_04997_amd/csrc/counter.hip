@@ -1,20 +1,23 @@
 // GPU counter: kernel properties of a batch of variants (Sec. 3.2).
 //
-// One batch runs as six launches on one stream:
-//   k_build     one thread per variant: descriptor, statement components,
-//               jobs and footprint-bitmap needs (desc.h)
-//   k_scan      one work-group: prefix sums of bitmap words per variant,
-//               work chunks per job and fill segments per array; variants
-//               whose bitmaps overflow the arena get PM_ENOMEM
-//   k_clear     zero the used bitmap words and the per-job / per-array sums
-//   k_count     persistent: every wavefront takes chunks from one atomic
-//               ticket until the queue is empty; count chunks sum inner
-//               interval lengths (Alg. 1), footprint chunks OR cell runs
-//               into the bitmaps (Alg. 2)
+// k_fused     one work-group per variant: builds the descriptor and its jobs
+//             in LDS (desc.h), runs the count jobs (guarded points per
+//             statement, Alg. 1) and interval-mode footprint jobs (Alg. 2)
+//             with all its threads, and writes the count vector (Eq.
+//             opcount) and the FP64 prediction.  A variant whose footprints
+//             need bitmaps (or whose jobs exceed FUSED_MAX_ITEMS items) is
+//             handed on: its descriptor is copied to HBM, status PM_DEFER.
+// For handed-on variants only:
+//   k_scan      one work-group: prefix sums of bitmap words, work chunks and
+//               fill segments per variant; bitmaps that overflow the arena
+//               give PM_ENOMEM
+//   k_clear     zero the used bitmap words
+//   k_count     every wavefront takes chunks round-robin: count chunks sum
+//               inner interval lengths, footprint chunks OR cell runs into
+//               the bitmaps
 //   k_fill      per array segment: |F| and |Fill| (F with every strided
 //               cell widened to its run of stride*vec cells)
-//   k_finalize  one thread per variant: count vector (Eq. opcount) and,
-//               with a model, the FP64 prediction sum_i alpha_i f_i
+//   k_finalize  one thread per variant: count vector and prediction
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -28,24 +31,136 @@ constexpr int SCAN_THREADS = 1024;
 constexpr int FILL_THREADS = 256;
 constexpr int FILL_WORDS_PER_THREAD = 16;  // 4096 words per segment
 constexpr int COUNT_THREADS = 256;
+constexpr int FUSED_THREADS = 256;
+constexpr int64_t FUSED_MAX_ITEMS = 1 << 20;
+constexpr int PM_DEFER = 1;  // internal status: finish in the general pipeline
+constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
+constexpr int BUILD_LANES = 16;        // variants built per wavefront in k_build
 
-__global__ void k_build(int nv, const pm_variant *__restrict__ var, Prog *prog,
-                        Job *jobs, int32_t *status, int64_t *varwords,
-                        int64_t *jobpref, int64_t *arrpref) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One thread per variant (BUILD_LANES active lanes per wavefront): the
+// descriptor and jobs go to HBM and every valid variant continues in the
+// general pipeline.
+__global__ void __launch_bounds__(64)
+k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
+        int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
+        int64_t *jobres, int64_t *foot) {
+    if ((int)threadIdx.x >= BUILD_LANES) return;
+    const int64_t i = (int64_t)blockIdx.x * BUILD_LANES + threadIdx.x;
     if (i >= nv) return;
     pm_variant v = var[i];
     Prog *p = &prog[i];
-    Job *J = &jobs[(size_t)i * MAXJOB];
-    int st = build_prog(v, p, J);
+    int st = build_prog(v, p, &jobs[i * MAXJOB]);
+    if (st == PM_OK) st = PM_DEFER;
     status[i] = st;
-    // dense per-variant sizes for the prefix sums
-    varwords[i] = st == PM_OK ? p->bitmap_words : 0;
-    for (int j = 0; j < MAXJOB; j++)
-        jobpref[(size_t)i * MAXJOB + j] = (st == PM_OK && j < p->njob) ? J[j].chunks : 0;
-    for (int a = 0; a < MAXARR; a++)
-        arrpref[(size_t)i * MAXARR + a] =
-            (st == PM_OK && a < p->narr && p->arr[a].w && p->arr[a].words) ? p->arr[a].segs : 0;
+    varwords[i] = st == PM_DEFER ? p->bitmap_words : 0;
+    varchunks[i] = st == PM_DEFER ? p->chunks : 0;
+    varsegs[i] = st == PM_DEFER ? p->segs : 0;
+    for (int j = 0; j < MAXJOB; j++) jobres[i * MAXJOB + j] = 0;
+    for (int a = 0; a < 2 * MAXARR; a++) foot[i * MAXARR * 2 + a] = 0;
+}
+
+// Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
+__device__ int64_t block_sum(int64_t x, int64_t *red) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = x;
+    __syncthreads();
+    int64_t t = 0;
+    for (int k = 0; k < FUSED_THREADS / 64; k++) t += red[k];
+    return t;
+}
+
+__global__ void __launch_bounds__(FUSED_THREADS)
+k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
+        int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
+        int64_t *jobres, int64_t *foot, pm_counts *counts, pm_model model,
+        int has_model, double *pred) {
+    __shared__ Prog P;
+    __shared__ Job J[MAXJOB];
+    __shared__ int64_t jr[MAXJOB];
+    __shared__ int64_t fs[MAXARR][2];
+    __shared__ int64_t cnt[PM_NCOUNT];
+    __shared__ int64_t red[FUSED_THREADS / 64];
+    __shared__ int st_sh;
+    const int i = blockIdx.x;
+    const int t = threadIdx.x;
+    if (i >= nv) return;
+    if (t == 0) {
+        pm_variant v = var[i];
+        int st = build_prog(v, &P, J);
+        int64_t items = 0;
+        for (int j = 0; j < P.njob; j++) items += J[j].items;
+        if (st == PM_OK && (P.bitmap_words > 0 || items > FUSED_MAX_ITEMS)) st = PM_DEFER;
+        st_sh = st;
+    }
+    if (t < MAXJOB) jr[t] = 0;
+    if (t < 2 * MAXARR) fs[t / 2][t % 2] = 0;
+    __syncthreads();
+    const int st = st_sh;
+    if (t == 0) {
+        status[i] = st;
+        varwords[i] = st == PM_DEFER ? P.bitmap_words : 0;
+        varchunks[i] = st == PM_DEFER ? P.chunks : 0;
+        varsegs[i] = st == PM_DEFER ? P.segs : 0;
+    }
+    if (st == PM_DEFER) {  // hand the descriptor and zeroed sums on
+        const uint64_t *src = (const uint64_t *)&P;
+        uint64_t *dst = (uint64_t *)&prog[i];
+        for (size_t k = t; k < sizeof(Prog) / 8; k += FUSED_THREADS) dst[k] = src[k];
+        const uint64_t *js = (const uint64_t *)J;
+        uint64_t *jd = (uint64_t *)&jobs[(size_t)i * MAXJOB];
+        size_t nw = (size_t)P.njob * sizeof(Job) / 8;
+        for (size_t k = t; k < nw; k += FUSED_THREADS) jd[k] = js[k];
+        if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
+        if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
+        return;
+    }
+    if (st == PM_OK) {
+        for (int j = 0; j < P.njob; j++) {
+            const Job &Jb = J[j];
+            int64_t s0 = 0, s1 = 0;
+            if (Jb.kind == JOB_COUNT) {
+                for (int64_t it = t; it < Jb.items; it += FUSED_THREADS) s0 += count_item(Jb, it);
+            } else {
+                for (int64_t it = t; it < Jb.items; it += FUSED_THREADS) {
+                    int64_t df, dl;
+                    ival_item(Jb, it, &df, &dl);
+                    s0 += df;
+                    s1 += dl;
+                }
+            }
+            s0 = block_sum(s0, red);
+            if (Jb.kind == JOB_IVAL) s1 = block_sum(s1, red);
+            if (t == 0) {
+                if (Jb.kind == JOB_COUNT) {
+                    jr[j] = s0;
+                } else {
+                    fs[Jb.arr][0] += s0;
+                    fs[Jb.arr][1] += s1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        int64_t F[MAXARR], Fill[MAXARR];
+        for (int a = 0; a < MAXARR; a++) {
+            F[a] = fs[a][0];
+            Fill[a] = fs[a][1];
+        }
+        int s2 = st;
+        if (st == PM_OK) s2 = finalize(P, jr, F, Fill, cnt);
+        else
+            for (int k = 0; k < PM_NCOUNT; k++) cnt[k] = 0;
+        if (s2 != PM_OK)
+            for (int k = 0; k < PM_NCOUNT; k++) cnt[k] = 0;
+        status[i] = s2;
+        if (has_model && pred) pred[i] = s2 == PM_OK ? predict(cnt, model) : 0.0;
+    }
+    __syncthreads();
+    if (counts)
+        for (int k = t; k < PM_NCOUNT; k += FUSED_THREADS) counts[i].c[k] = cnt[k];
 }
 
 // Block-wide inclusive scan of per-thread int64 values (SCAN_THREADS).
@@ -95,7 +210,7 @@ __device__ int64_t scan_inplace(int64_t n, int64_t *a, OK ok, bool excl,
 
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
-       int64_t *jobpref, int64_t *arrpref, int64_t *meta, int64_t arena_words) {
+       int64_t *varchunks, int64_t *varsegs, int64_t *meta, int64_t arena_words) {
     __shared__ int64_t sh[SCAN_THREADS];
     for (int64_t i = threadIdx.x; i < nv; i += SCAN_THREADS) varoff[i] = varwords[i];
     __syncthreads();
@@ -118,10 +233,9 @@ k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
     }
     used = sh[0];
     __syncthreads();
-    auto okj = [&](int64_t j) { return status[j / MAXJOB] == PM_OK; };
-    int64_t tc = scan_inplace((int64_t)nv * MAXJOB, jobpref, okj, false, sh);
-    auto oka = [&](int64_t j) { return status[j / MAXARR] == PM_OK; };
-    int64_t ts = scan_inplace((int64_t)nv * MAXARR, arrpref, oka, false, sh);
+    auto ok = [&](int64_t i) { return status[i] == PM_DEFER; };
+    int64_t tc = scan_inplace(nv, varchunks, ok, false, sh);
+    int64_t ts = scan_inplace(nv, varsegs, ok, false, sh);
     if (threadIdx.x == 0) {
         meta[0] = tc;
         meta[1] = used;
@@ -131,14 +245,11 @@ k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
     }
 }
 
-__global__ void k_clear(int nv, uint64_t *bitmap, int64_t *jobres,
-                        int64_t *foot, const int64_t *meta, int64_t arena_words) {
+__global__ void k_clear(uint64_t *bitmap, const int64_t *meta, int64_t arena_words) {
     int64_t words = meta[1] < arena_words ? meta[1] : arena_words;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t i = t; i < words; i += stride) bitmap[i] = 0;
-    for (int64_t i = t; i < (int64_t)nv * MAXJOB; i += stride) jobres[i] = 0;
-    for (int64_t i = t; i < (int64_t)nv * MAXARR * 2; i += stride) foot[i] = 0;
 }
 
 // first index j in [0, n) with pref[j] > x (pref non-decreasing)
@@ -159,18 +270,22 @@ struct DevOr {
 };
 
 __global__ void __launch_bounds__(COUNT_THREADS)
-k_count(int nv, const Job *jobs, const int64_t *jobpref, const int64_t *varoff,
-        uint64_t *bitmap, int64_t *jobres, int64_t *foot, int64_t *meta) {
+k_count(int nv, const Prog *prog, const Job *jobs, const int64_t *varchunks,
+        const int64_t *varoff, uint64_t *bitmap, int64_t *jobres, int64_t *foot,
+        int64_t *meta) {
     const int lane = threadIdx.x & 63;
     const int64_t total = meta[0];
-    const int64_t njobs = (int64_t)nv * MAXJOB;
-    while (true) {
-        int64_t ch = 0;
-        if (lane == 0) ch = atomicAdd((unsigned long long *)&meta[3], 1ull);
-        ch = __shfl(ch, 0);
-        if (ch >= total) break;
-        int64_t j = upper(jobpref, njobs, ch);
-        int64_t local = ch - (j ? jobpref[j - 1] : 0);
+    const int64_t nwave = (int64_t)gridDim.x * (blockDim.x / 64);
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    for (int64_t ch = wave; ch < total; ch += nwave) {
+        // chunk -> variant (prefix over variants) -> job (prefix inside it)
+        int64_t v = upper(varchunks, nv, ch);
+        int64_t local = ch - (v ? varchunks[v - 1] : 0);
+        const int64_t *cum = prog[v].jobcum;
+        int jl = 0;
+        while (cum[jl] <= local) jl++;
+        local -= jl ? cum[jl - 1] : 0;
+        int64_t j = v * MAXJOB + jl;
         const Job &J = jobs[j];
         int64_t it0 = local * J.chunk_items;
         int64_t it1 = it0 + J.chunk_items;
@@ -203,18 +318,21 @@ k_count(int nv, const Job *jobs, const int64_t *jobpref, const int64_t *varoff,
 }
 
 __global__ void __launch_bounds__(FILL_THREADS)
-k_fill(int nv, const Prog *prog, const int64_t *arrpref, const int64_t *varoff,
+k_fill(int nv, const Prog *prog, const int64_t *varsegs, const int64_t *varoff,
        const uint64_t *bitmap, int64_t *foot, const int64_t *meta) {
     __shared__ int64_t sh[FILL_THREADS];
     __shared__ unsigned long long red[2];
     const int64_t total = meta[2];
-    const int64_t narr = (int64_t)nv * MAXARR;
     const int t = threadIdx.x;
     for (int64_t sg = blockIdx.x; sg < total; sg += gridDim.x) {
-        int64_t j = upper(arrpref, narr, sg);
-        int64_t local = sg - (j ? arrpref[j - 1] : 0);
-        int64_t v = j / MAXARR;
-        const ArrInfo &A = prog[v].arr[j % MAXARR];
+        int64_t v = upper(varsegs, nv, sg);
+        int64_t local = sg - (v ? varsegs[v - 1] : 0);
+        const int64_t *cum = prog[v].arrcum;
+        int al = 0;
+        while (cum[al] <= local) al++;
+        local -= al ? cum[al - 1] : 0;
+        int64_t j = v * MAXARR + al;
+        const ArrInfo &A = prog[v].arr[al];
         const uint64_t *F = bitmap + varoff[v] + A.f_off;
         const uint64_t *Bm = bitmap + varoff[v] + A.b_off;
         const int64_t w = A.w;
@@ -300,12 +418,13 @@ __global__ void k_finalize(int nv, const Prog *prog, const int64_t *jobres,
         Fill[a] = foot[((int64_t)i * MAXARR + a) * 2 + 1];
     }
     int st = status[i];
-    if (st == PM_OK) {
+    if (st == PM_OK) return;  // finished in k_fused
+    if (st == PM_DEFER) {
         st = finalize(prog[i], jobres + (int64_t)i * MAXJOB, F, Fill, c);
         status[i] = st;
-    } else {
-        for (int k = 0; k < PM_NCOUNT; k++) c[k] = 0;
     }
+    if (st != PM_OK)
+        for (int k = 0; k < PM_NCOUNT; k++) c[k] = 0;
     if (counts)
         for (int k = 0; k < PM_NCOUNT; k++) counts[i].c[k] = c[k];
     if (has_model && pred) pred[i] = st == PM_OK ? predict(c, model) : 0.0;
@@ -321,34 +440,39 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
     auto mark = [&]() {
         if (ev) (void)hipEventRecord(ev[q++], s);
     };
-    mark();
-    hipLaunchKernelGGL(k_build, dim3((nv + tb - 1) / tb), dim3(tb), 0, s, nv,
-                       d_var, ar.prog, ar.jobs, d_status, ar.varwords,
-                       ar.jobpref, ar.arrpref);
-    mark();
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
-                       (const int64_t *)ar.varwords, ar.varoff, ar.jobpref,
-                       ar.arrpref, ar.meta, (int64_t)ar.bitmap_words);
-    mark();
-    hipLaunchKernelGGL(k_clear, dim3(n_cu * 8), dim3(256), 0, s, nv, ar.bitmap,
-                       ar.jobres, ar.foot, (const int64_t *)ar.meta,
-                       (int64_t)ar.bitmap_words);
-    mark();
-    hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s, nv,
-                       (const Job *)ar.jobs, (const int64_t *)ar.jobpref,
-                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, ar.foot, ar.meta);
-    mark();
-    hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s, nv,
-                       (const Prog *)ar.prog, (const int64_t *)ar.arrpref,
-                       (const int64_t *)ar.varoff, (const uint64_t *)ar.bitmap,
-                       ar.foot, (const int64_t *)ar.meta);
-    mark();
     pm_model m{};
     int has = 0;
     if (model) {
         m = *model;
         has = 1;
     }
+    mark();
+    if (nv <= FUSED_MAX_NV)
+        hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
+                           ar.prog, ar.jobs, d_status, ar.varwords, ar.varchunks,
+                           ar.varsegs, ar.jobres, ar.foot, d_counts, m, has, d_pred);
+    else
+        hipLaunchKernelGGL(k_build, dim3((nv + BUILD_LANES - 1) / BUILD_LANES), dim3(64), 0, s,
+                           nv, d_var, ar.prog, ar.jobs, d_status, ar.varwords,
+                           ar.varchunks, ar.varsegs, ar.jobres, ar.foot);
+    mark();
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
+                       (const int64_t *)ar.varwords, ar.varoff, ar.varchunks,
+                       ar.varsegs, ar.meta, (int64_t)ar.bitmap_words);
+    mark();
+    hipLaunchKernelGGL(k_clear, dim3(n_cu * 8), dim3(256), 0, s, ar.bitmap,
+                       (const int64_t *)ar.meta, (int64_t)ar.bitmap_words);
+    mark();
+    hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s, nv,
+                       (const Prog *)ar.prog, (const Job *)ar.jobs,
+                       (const int64_t *)ar.varchunks, (const int64_t *)ar.varoff,
+                       ar.bitmap, ar.jobres, ar.foot, ar.meta);
+    mark();
+    hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s, nv,
+                       (const Prog *)ar.prog, (const int64_t *)ar.varsegs,
+                       (const int64_t *)ar.varoff, (const uint64_t *)ar.bitmap,
+                       ar.foot, (const int64_t *)ar.meta);
+    mark();
     hipLaunchKernelGGL(k_finalize, dim3((nv + tb - 1) / tb), dim3(tb), 0, s, nv,
                        (const Prog *)ar.prog, (const int64_t *)ar.jobres,
                        (const int64_t *)ar.foot, d_status, d_counts, m, has, d_pred);
@@ -357,7 +481,7 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
 }
 
 size_t arena_bytes_per_variant() {
-    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (2 + 2 * MAXJOB + 3 * MAXARR);
+    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (4 + MAXJOB + 2 * MAXARR);
 }
 
 // ------------------------------------------------------- host execution ---

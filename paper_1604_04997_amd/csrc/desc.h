@@ -112,6 +112,10 @@ struct Prog {
     int32_t wg_size, pad;
     int64_t n_wg;
     int64_t bitmap_words;
+    int64_t chunks;            // work chunks of all jobs
+    int64_t segs;              // fill segments of all bitmap arrays
+    int64_t jobcum[MAXJOB];    // inclusive prefix of job chunks
+    int64_t arrcum[MAXARR];    // inclusive prefix of array fill segments
     ArrInfo arr[MAXARR];
     Stmt st[MAXSTMT];
 };
@@ -825,6 +829,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
     p->wg_size = 1;
     p->n_wg = 0;
     p->bitmap_words = 0;
+    p->chunks = p->segs = 0;
     B b{p};
     switch (v.family) {
     case PM_FAM_STREAM: build_stream(b, v); break;
@@ -1092,6 +1097,18 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
         }
     }
     p->bitmap_words = off;
+    int64_t cum = 0;
+    for (int j = 0; j < MAXJOB; j++) {
+        cum += j < nj ? jobs[j].chunks : 0;
+        p->jobcum[j] = cum;
+    }
+    p->chunks = cum;
+    cum = 0;
+    for (int a = 0; a < MAXARR; a++) {
+        cum += (a < p->narr && p->arr[a].w && p->arr[a].words) ? p->arr[a].segs : 0;
+        p->arrcum[a] = cum;
+    }
+    p->segs = cum;
     return p->status;
 }
 
