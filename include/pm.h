@@ -168,8 +168,8 @@ pm_status pm_predict(pm_ctx *ctx, const pm_model *m, const pm_variant *v,
  * Device-resident batched path: d_v[nv] (device) -> d_counts[nv] (device,
  * may be NULL), d_t[nv] (device, FP64 predictions with model m; ignored if
  * m or d_t is NULL), d_status[nv] (device int32: 0 or a pm_status per
- * variant).  Enqueued on `hip_stream` (a hipStream_t; NULL = the context's
- * stream); returns without waiting.  Variants whose footprint bitmaps do
+ * variant).  Enqueued on `hip_stream` (a hipStream_t, used as given: NULL
+ * is HIP's null stream); returns without waiting.  Variants whose footprint bitmaps do
  * not fit in the context's bitmap arena get status PM_ENOMEM and are not
  * counted; pm_reserve() sizes the arena.  At most PM_BATCH_MAX variants.
  */
@@ -228,14 +228,16 @@ pm_status pm_fit(const pm_counts *P, const double *T, size_t nrows,
 pm_status pm_buffers(const pm_variant *v, size_t *bytes, uint32_t *role,
                      uint32_t *nbufs);
 
-/* Launch the variant's kernel once on `hip_stream` (async).  bufs: device
- * pointers as listed by pm_buffers, each at least that many bytes. */
+/* Launch the variant's kernel once on `hip_stream` (async; NULL is HIP's
+ * null stream).  bufs: device pointers as listed by pm_buffers, each at
+ * least that many bytes. */
 pm_status pm_launch(pm_ctx *ctx, const pm_variant *v, void *const *bufs,
                     const size_t *bytes, uint32_t nbufs, void *hip_stream);
 
 /*
  * Measure (Sec. 4.2): `warmup` untimed launches, then `reps` launches each
- * timed with HIP events on `hip_stream`; t_reps[reps] (nullable) receives
+ * timed with HIP events on `hip_stream` (NULL is HIP's null stream);
+ * t_reps[reps] (nullable) receives
  * each time in seconds and *t_min the minimum.  Synchronous.
  */
 pm_status pm_measure(pm_ctx *ctx, const pm_variant *v, void *const *bufs,

@@ -310,11 +310,20 @@ class Context:
         sizes = (ctypes.c_size_t * max(n, 1))(*[t.numel() * t.element_size() for t in tensors])
         return ptrs, sizes, n
 
+    @staticmethod
+    def _stream(stream_ptr):
+        """The given hipStream_t, else torch's current stream, so that kernels
+        are ordered after the torch work that filled their buffers."""
+        if stream_ptr is not None:
+            return ctypes.c_void_p(stream_ptr)
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
     def launch(self, d: dict, tensors, stream_ptr=None):
         v = variant_struct(d)
         ptrs, sizes, n = self._bufs(tensors)
         _check(lib().pm_launch(self._h, ctypes.byref(v), ptrs, sizes, n,
-                               ctypes.c_void_p(stream_ptr) if stream_ptr else None))
+                               self._stream(stream_ptr)))
 
     def measure(self, d: dict, tensors, warmup: int = 4, reps: int = 26,
                 stream_ptr=None):
@@ -324,8 +333,8 @@ class Context:
         tr = (ctypes.c_double * reps)()
         tmin = ctypes.c_double()
         _check(lib().pm_measure(self._h, ctypes.byref(v), ptrs, sizes, n,
-                                ctypes.c_void_p(stream_ptr) if stream_ptr else None,
-                                warmup, reps, tr, ctypes.byref(tmin)))
+                                self._stream(stream_ptr), warmup, reps, tr,
+                                ctypes.byref(tmin)))
         return tmin.value, list(tr[:])
 
 

@@ -277,7 +277,7 @@ int measure_impl(pm_ctx *c, const pm_variant *v, void *const *bufs, const size_t
     st = check_bufs(v, bufs, bytes, nbufs);
     if (st) return st;
     DeviceGuard g(c->device);
-    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL: HIP's null stream
     while ((int)c->events.size() < 2 * reps) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
@@ -390,7 +390,7 @@ pm_status pm_count_device(pm_ctx *c, const pm_variant *d_v, size_t nv, pm_counts
     DeviceGuard g(c->device);
     int st = grow_cap(c, nv);
     if (st) return (pm_status)st;
-    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL: HIP's null stream
     st = pm::launch_batch(c->ar, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu,
                           c->next_events());
     if (st) return (pm_status)set_err(st, "counter launch failed");
@@ -484,7 +484,7 @@ pm_status pm_launch(pm_ctx *c, const pm_variant *v, void *const *bufs, const siz
     st = check_bufs(v, bufs, bytes, nbufs);
     if (st) return (pm_status)st;
     DeviceGuard g(c->device);
-    st = pm::launch(*v, bufs, stream ? (hipStream_t)stream : c->stream);
+    st = pm::launch(*v, bufs, (hipStream_t)stream);  // NULL: HIP's null stream
     if (st) return (pm_status)set_err(st, "kernel launch failed");
     return PM_OK;
 }

@@ -179,15 +179,12 @@ class Server:
             if not realtime and not arrivals and not wait_p and not wait_m:
                 torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        lat = np.array([r["done"] - r["arrival"] for r in rec.values()])
-        npred = sum(1 for r in rec.values() if r["kind"] == "predict")
-        stats = {"requests": total, "predict": npred, "measure": total - npred,
-                 "wall_s": wall, "batches": n_batches,
+        out = [rec[i] for i in range(total)]
+        stats = {"requests": total, "wall_s": wall, "batches": n_batches,
                  "mean_batch": float(np.mean(batch_sizes)) if batch_sizes else 0.0,
-                 "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                 "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                 "variants_per_s": npred / wall}
-        return [rec[i] for i in range(total)], stats
+                 "max_batch": int(max(batch_sizes)) if batch_sizes else 0}
+        stats.update(latency_stats(out, wall))
+        return out, stats
 
 
 def run_plain(ctx: Context, model: Model, trace, realtime: bool = True,
@@ -213,9 +210,22 @@ def run_plain(ctx: Context, model: Model, trace, realtime: bool = True,
                         "done": time.perf_counter() - t0, "t_min": tmin})
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lat = np.array([r["done"] - r["arrival"] for r in rec])
+    stats = {"requests": len(rec), "wall_s": wall}
+    stats.update(latency_stats(rec, wall))
+    return rec, stats
+
+
+def latency_stats(rec, wall):
+    """p50 / p99 latency (ms) over all requests and per kind; predicted
+    variants per second of wall time."""
+    out = {}
+    for name, sel in (("", None), ("predict_", "predict"), ("measure_", "measure")):
+        lat = np.array([r["done"] - r["arrival"] for r in rec if sel is None or r["kind"] == sel])
+        if len(lat):
+            out[name + "p50_ms"] = float(np.percentile(lat, 50) * 1e3)
+            out[name + "p99_ms"] = float(np.percentile(lat, 99) * 1e3)
     npred = sum(1 for r in rec if r["kind"] == "predict")
-    return rec, {"requests": len(rec), "wall_s": wall,
-                 "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                 "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                 "variants_per_s": npred / wall}
+    out["predict"] = npred
+    out["measure"] = len(rec) - npred
+    out["variants_per_s"] = npred / wall
+    return out

@@ -68,6 +68,11 @@ def suite_tiny():
 # workload 2: full performance-instructive measurement suite
 # ---------------------------------------------------------------------------
 def suite_instructive(roofline_points: bool = True):
+    """Performance-instructive kernels: global stream access by dtype,
+    direction, lane and group stride and size; stride-2/3 filled access;
+    LDS by bank stride; FMA and rsqrt chains; barriers; empty kernels;
+    tiled and naive matrix multiplication in four shapes; three transpose
+    configurations."""
     out = []
     ns = (1 << 20, 1 << 23, 1 << 26)
     for dt in ("f32", "f64"):
@@ -85,10 +90,22 @@ def suite_instructive(roofline_points: bool = True):
             out.append(_v("stream", op="load", dtype="f32", n=n, wg=256, s=1,
                           gs=gs, vec=1, U=1))
     for n in ns:
-        out.append(_v("stream", op="filled", dtype="f32", n=n, wg=256, s=3,
-                      gs=1, vec=1, U=1))
+        for k in (2, 3):
+            out.append(_v("stream", op="filled", dtype="f32", n=n, wg=256, s=k,
+                          gs=1, vec=1, U=1))
         out.append(_v("stream", op="add4", dtype="f32", n=n, wg=256, s=1,
                       gs=1, vec=1, U=1))
+    # matrix multiplication, tiled: shapes n=m=l, l=n/2, m=n/2, n=m/2
+    for n in (384, 768, 1536):
+        for (a, b, c) in ((n, n, n), (n, n, n // 2), (n, n // 2, n), (n // 2, n, n)):
+            for T in (16, 32):
+                out.append(_v("matmul", op="tiled", n=a, m=b, l=c, T=T))
+        for T in (16, 32):
+            out.append(_v("matmul", op="naive", n=n, m=n, l=n, T=T))
+    # transpose: LDS-tiled, naive with coalesced writes, naive with coalesced reads
+    for n in (1536, 3072, 6144):
+        for op in ("tiled", "naive_wc", "naive_rc"):
+            out.append(_v("transpose", op=op, n=n, T=16))
     if roofline_points:
         for dt in ("f32", "f64"):
             for op in ("load", "copy"):
