@@ -97,6 +97,40 @@ def model_phase(ctx, P, proj_list=("p12", "full")):
     return out, models, (meas, Tm, test, Tt)
 
 
+def suite_roofline(ctx, P):
+    """Unit-stride stream kernels against the 8 TB/s HBM peak (1 GiB+
+    working sets, far past the 256 MB last-level cache) and FMA loops
+    against the vector FP32 / FP64 peaks."""
+    res = {"stream": [], "fma": []}
+    for op, mult in (("load", 1), ("copy", 2)):
+        for dt, esz in (("f32", 4), ("f64", 8)):
+            for vec, U in ((1, 1), (1, 4), (4 if dt == "f32" else 2, 1),
+                           (4 if dt == "f32" else 2, 4)):
+                elems = (1 << 28) if dt == "f32" else (1 << 27)
+                v = dict(family="stream", op=op, dtype=dt, n=elems // (vec * U), wg=256,
+                         s=1, gs=1, vec=vec, U=U)
+                ts, _ = P.device_buffers(v, 11, fast=True)
+                t, _ = ctx.measure(v, ts, warmup=3, reps=20)
+                del ts
+                gbs = mult * elems * esz / t
+                res["stream"].append({"op": op, "dtype": dt, "vec": vec, "U": U,
+                                      "bytes": mult * elems * esz, "ms": round(t * 1e3, 4),
+                                      "GB/s": round(gbs / 1e9, 1),
+                                      "frac_8TBs": round(gbs / HBM_PEAK, 4)})
+    for dt, peak_nopk, peak_pub in (("f32", 78.6e12, 157.3e12), ("f64", 78.6e12, 78.6e12)):
+        v = dict(family="fma", dtype=dt, n=1 << 24, wg=256, F=1024, K=16)
+        ts, _ = P.device_buffers(v, 12, fast=True)
+        t, _ = ctx.measure(v, ts, warmup=3, reps=20)
+        del ts
+        fl = 2.0 * 1024 * (1 << 24) / t
+        res["fma"].append({"dtype": dt, "TFLOP/s": round(fl / 1e12, 2),
+                           "frac_vector_peak_no_packed": round(fl / peak_nopk, 4),
+                           "frac_published_peak": round(fl / peak_pub, 4)})
+    import torch
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(workload, gpu_counts, budget_s=15.0):
     """Simulated-execution oracle on a bounded random sample of the workload:
     variants in random order until ~budget_s of oracle time; its event rate
@@ -250,11 +284,14 @@ def main():
         srv = serve.Server(ctx, m)
         _, st_b = srv.run(trace)
         _, st_p = serve.run_plain(ctx, m, trace)
+        # capacity: the same requests all queued at once
+        _, cap_b = srv.run(trace, realtime=False)
+        _, cap_p = serve.run_plain(ctx, m, trace, realtime=False)
+        rnd = lambda d: {k: (round(x, 4) if isinstance(x, float) else x)  # noqa: E731
+                         for k, x in d.items()}
         serving = {"requests": len(trace), "rate_per_s": 2000.0,
-                   "batched": {k: (round(x, 4) if isinstance(x, float) else x)
-                               for k, x in st_b.items()},
-                   "plain": {k: (round(x, 4) if isinstance(x, float) else x)
-                             for k, x in st_p.items()}}
+                   "batched": rnd(st_b), "plain": rnd(st_p),
+                   "saturated_batched": rnd(cap_b), "saturated_plain": rnd(cap_p)}
         log("serving:", json.dumps(serving))
 
     # ---------------------------------------------------------- roofline --
@@ -273,6 +310,12 @@ def main():
     else:
         roof = {"kernel": "k_" + dom, "bound": "alu", "achieved": None, "peak": None,
                 "unit": None, "frac": None, "traffic": None}
+
+    # ------------------------------------------------- suite rooflines --
+    suite_roof = None
+    if not args.skip_model:
+        suite_roof = suite_roofline(ctx, P)
+        log("suite roofline:", json.dumps(suite_roof))
 
     # ----------------------------------------------------------- CPU leg --
     cpu = None
@@ -296,7 +339,7 @@ def main():
         "geomean_rel_err": model_info,
         "kernel_ms": {k: round(x, 4) for k, x in phase_ms.items()},
         "batch_stats": stats,
-        "autotune": tune, "serving": serving,
+        "autotune": tune, "serving": serving, "suite_roofline": suite_roof,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

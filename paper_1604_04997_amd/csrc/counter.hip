@@ -119,27 +119,11 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     if (st == PM_OK) {
         for (int j = 0; j < P.njob; j++) {
             const Job &Jb = J[j];
-            int64_t s0 = 0, s1 = 0;
-            if (Jb.kind == JOB_COUNT) {
-                for (int64_t it = t; it < Jb.items; it += FUSED_THREADS) s0 += count_item(Jb, it);
-            } else {
-                for (int64_t it = t; it < Jb.items; it += FUSED_THREADS) {
-                    int64_t df, dl;
-                    ival_item(Jb, it, &df, &dl);
-                    s0 += df;
-                    s1 += dl;
-                }
-            }
+            if (Jb.kind != JOB_COUNT) continue;  // uniform over the group
+            int64_t s0 = 0;
+            for (int64_t it = t; it < Jb.items; it += FUSED_THREADS) s0 += count_item(Jb, it);
             s0 = block_sum(s0, red);
-            if (Jb.kind == JOB_IVAL) s1 = block_sum(s1, red);
-            if (t == 0) {
-                if (Jb.kind == JOB_COUNT) {
-                    jr[j] = s0;
-                } else {
-                    fs[Jb.arr][0] += s0;
-                    fs[Jb.arr][1] += s1;
-                }
-            }
+            if (t == 0) jr[j] = s0;
         }
         __syncthreads();
     }
@@ -295,21 +279,6 @@ k_count(int nv, const Prog *prog, const Job *jobs, const int64_t *varchunks,
             for (int64_t it = it0 + lane; it < it1; it += 64) s += count_item(J, it);
             for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
             if (lane == 0 && s) atomicAdd((unsigned long long *)&jobres[j], (unsigned long long)s);
-        } else if (J.kind == JOB_IVAL) {
-            int64_t sf = 0, sl = 0;
-            for (int64_t it = it0 + lane; it < it1; it += 64) {
-                int64_t df, dl;
-                ival_item(J, it, &df, &dl);
-                sf += df;
-                sl += dl;
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                sf += __shfl_xor(sf, off);
-                sl += __shfl_xor(sl, off);
-            }
-            int64_t fa = ((j / MAXJOB) * MAXARR + J.arr) * 2;
-            if (lane == 0 && sf) atomicAdd((unsigned long long *)&foot[fa], (unsigned long long)sf);
-            if (lane == 0 && sl) atomicAdd((unsigned long long *)&foot[fa + 1], (unsigned long long)sl);
         } else {
             uint64_t *vb = bitmap + varoff[j / MAXJOB];
             for (int64_t it = it0; it < it1; it++) foot_item(J, it, vb, lane, 64, DevOr{});
@@ -502,14 +471,7 @@ int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out) {
     for (int j = 0; j < p.njob; j++) {
         if (J[j].kind == JOB_COUNT) {
             for (int64_t it = 0; it < J[j].items; it++) jobres[j] += count_item(J[j], it);
-        } else if (J[j].kind == JOB_IVAL) {
-            for (int64_t it = 0; it < J[j].items; it++) {
-                int64_t df, dl;
-                ival_item(J[j], it, &df, &dl);
-                F[J[j].arr] += df;
-                Fill[J[j].arr] += dl;
-            }
-        } else {
+        } else if (J[j].kind == JOB_FOOT) {
             for (int64_t it = 0; it < J[j].items; it++) foot_item(J[j], it, bm.data(), 0, 1, HostOr{});
         }
     }
@@ -527,8 +489,8 @@ int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out) {
     }
     if (foot_out)
         for (int a = 0; a < MAXARR; a++) {
-            foot_out[2 * a] = F[a];
-            foot_out[2 * a + 1] = Fill[a];
+            foot_out[2 * a] = F[a] + (a < p.narr ? p.arr[a].fixF : 0);
+            foot_out[2 * a + 1] = Fill[a] + (a < p.narr ? p.arr[a].fixFill : 0);
         }
     return finalize(p, jobres, F, Fill, out->c);
 }

@@ -55,7 +55,7 @@ constexpr int C_WI = 111;
 
 enum { K_ADD = 0, K_MUL, K_DIV, K_EXP, K_SPEC, K_FMA };
 enum { D_LD = 0, D_ST = 1 };
-enum { JOB_NONE = 0, JOB_COUNT = 1, JOB_FOOT = 2, JOB_IVAL = 3 };
+enum { JOB_NONE = 0, JOB_COUNT = 1, JOB_FOOT = 2 };
 
 // inner points handled by one footprint work item
 constexpr int64_t SEG_CONTIG = 16384;
@@ -105,6 +105,7 @@ struct ArrInfo {
     int64_t b_off;  // word offset of B (cells of strided accesses); == f_off if same
     int64_t w;      // fill width of strided accesses: stride * vec cells
     int64_t segs;   // fill-pass segments (0: interval mode or no footprint)
+    int64_t fixF, fixFill;  // interval mode: |F| and |Fill| in closed form
 };
 
 struct Prog {
@@ -231,6 +232,7 @@ struct B {
         p->arr[a].f_off = p->arr[a].b_off = -1;
         p->arr[a].w = 0;
         p->arr[a].segs = 0;
+        p->arr[a].fixF = p->arr[a].fixFill = 0;
         if (a + 1 > p->narr) p->narr = a + 1;
     }
 };
@@ -757,8 +759,7 @@ PM_HD int64_t lane_stride(const Stmt &s, const GAcc &a) {
 //   F    = union over x of its cells (a contiguous run when step <= vec,
 //          else cnt disjoint accesses of vec cells),
 //   Fill = union over x of [first, last cell + w)   (strided access), or F.
-// Sorted runs of equal length: |union| = sum of each run's length minus its
-// overlap with the previous run, so every run contributes independently.
+// The sizes then follow in closed form (ival_sizes).
 PM_HD bool ival_ok(const Job &J) {
     if (J.nv > 2 || J.ic[0] <= 0) return false;
     if (J.nv == 2 && J.ic[1] <= 0) return false;
@@ -783,42 +784,46 @@ PM_HD bool ival_ok(const Job &J) {
     return true;
 }
 
-// Run of outer point x: false if empty; else [a, e) spans its cells and
-// [a, g) its widened cells.
-PM_HD bool ival_run(const Job &J, int64_t x, int64_t *a, int64_t *e, int64_t *g,
-                    int64_t *cnt) {
-    int64_t r[MAXGUARD], base, lo, hi;
-    eval_outer(J, x, r, &base);
-    inner_range(J, r, &lo, &hi);
-    if (hi <= lo) return false;
-    int64_t step = J.ic[0];
-    *cnt = hi - lo;
-    *a = base + step * lo;
-    int64_t last = base + step * (hi - 1) + J.vec;  // one past the last cell
-    *e = last;
-    *g = J.w ? last - 1 + J.w : last;
-    return true;
-}
-
-// Contributions of outer point `it` to |F| and |Fill|.
-PM_HD void ival_item(const Job &J, int64_t it, int64_t *dF, int64_t *dFill) {
-    int64_t a, e, g, cnt, ap, ep, gp, cp;
-    *dF = *dFill = 0;
-    if (!ival_run(J, it, &a, &e, &g, &cnt)) return;
-    bool prev = it > 0 && ival_run(J, it - 1, &ap, &ep, &gp, &cp);
-    int64_t step = J.ic[0];
-    if (step <= J.vec) {
-        int64_t s0 = prev && ep > a ? ep : a;
-        *dF = e > s0 ? e - s0 : 0;
-    } else {
-        *dF = cnt * J.vec;
+// |F| and |Fill| of an array in interval mode.  Non-empty outer points x
+// form an interval of nx values; each covers cnt accesses first(x) +
+// step*t, first(x) = a0 + c1*x.  A run of accesses spans
+// L = step*(cnt-1) + vec cells and, widened, Lf = L - 1 + w; nx runs spaced
+// c1 apart cover L + (nx-1)*min(L, c1) cells when each run is contiguous
+// (step <= vec) and nx*cnt*vec cells otherwise (runs are disjoint).
+PM_HD int ival_sizes(const Job &J, int64_t *F, int64_t *Fill) {
+    int64_t lo = 0, hi = J.ext[0], xlo = 0, xhi = J.nv == 2 ? J.ext[1] : 1;
+    for (int q = 0; q < J.ng; q++) {
+        int v = J.g[q][0] ? 0 : (J.nv == 2 && J.g[q][1]) ? 1 : -1;
+        int64_t a = v >= 0 ? J.g[q][v] : 0, r = J.g[q][MAXVAR];
+        int64_t &l = v == 1 ? xlo : lo, &h = v == 1 ? xhi : hi;
+        if (v < 0) {
+            if (r < 0) h = l;
+        } else if (a > 0) {
+            int64_t t = ceil_div(-r, a);
+            if (t > l) l = t;
+        } else {
+            int64_t t = fdiv(r, -a) + 1;
+            if (t < h) h = t;
+        }
     }
-    if (J.w || step <= J.vec) {
-        int64_t s0 = prev && gp > a ? gp : a;
-        *dFill = g > s0 ? g - s0 : 0;
+    *F = *Fill = 0;
+    int64_t cnt = hi - lo, nx = xhi - xlo;
+    if (cnt <= 0 || nx <= 0) return PM_OK;
+    int64_t step = J.ic[0], vec = J.vec, c1 = J.nv == 2 ? J.ic[1] : 0;
+    int64_t L, Lf, t;
+    bool ovf = mul_ovf(step, cnt - 1, &L) || add_ovf(L, vec, &L);
+    if (step <= vec) {
+        ovf |= mul_ovf(nx - 1, L < c1 ? L : c1, &t) || add_ovf(L, t, F);
     } else {
-        *dFill = *dF;  // stride <= 1 access with gaps: Fill = F
+        ovf |= mul_ovf(nx, cnt, &t) || mul_ovf(t, vec, F);
     }
+    if (J.w) {
+        ovf |= add_ovf(L, J.w - 1, &Lf);
+        ovf |= mul_ovf(nx - 1, Lf < c1 ? Lf : c1, &t) || add_ovf(Lf, t, Fill);
+    } else {
+        *Fill = *F;
+    }
+    return ovf ? PM_EOVERFLOW : PM_OK;
 }
 
 // Expand a variant into its program and jobs.  `jobs` has MAXJOB slots.
@@ -1053,8 +1058,8 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
     }
     p->njob = nj;
 
-    // Each strided array: interval mode when its footprint is a sorted
-    // sequence of runs (see ival_item), else bitmaps.
+    // Each strided array: interval mode when its footprint is a sequence of
+    // equally spaced runs (ival_ok, sizes in closed form), else bitmaps.
     int64_t off = 0;
     for (int ai = 0; ai < p->narr; ai++) {
         ArrInfo &A = p->arr[ai];
@@ -1064,12 +1069,9 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             if (jobs[j].kind == JOB_FOOT && jobs[j].arr == ai) nfj++, fj = j;
         if (nfj == 1 && !(v.flags & PM_FLAG_BITMAP) && ival_ok(jobs[fj])) {
             Job &J = jobs[fj];
-            J.kind = JOB_IVAL;
-            J.items = J.nv == 2 ? J.ext[1] : 1;
-            J.seg = J.ext[0];
-            J.nseg = 1;
-            J.chunk_items = CHUNK_COUNT;
-            J.chunks = cdiv(J.items, J.chunk_items);
+            if (ival_sizes(J, &A.fixF, &A.fixFill) != PM_OK) return b.fail(PM_EOVERFLOW), p->status;
+            J.kind = JOB_NONE;  // nothing left to enumerate
+            J.items = J.chunks = 0;
             A.words = 0;
             A.segs = 0;
             continue;
@@ -1254,7 +1256,8 @@ PM_HD int finalize(const Prog &p, const int64_t *jobres, const int64_t *F,
             const GAcc &a = s.acc[q];
             int64_t st = lane_stride(s, a);
             int z = size_index(a.elem * a.vec);
-            int cl = class_index(st, F[a.arr], Fill[a.arr]);
+            int cl = class_index(st, F[a.arr] + p.arr[a.arr].fixF,
+                                 Fill[a.arr] + p.arr[a.arr].fixFill);
             addm(C_GACC + (a.dir * 3 + z) * NCLS + cl, cnt, 1);
         }
         for (int d = 0; d < 2; d++)

@@ -44,6 +44,7 @@ __global__ void k_stream(T *x0, T *x1, T *x2, T *x3, T *x4, int64_t G,
     const int64_t base = ((g * gs) * wg + l) * s;
     const int64_t ust = G * gs * wg * s;
     T acc = 0;
+#pragma unroll 4
     for (int u = 0; u < U; u++) {
         int64_t e = base + u * ust;
         if (OP == PM_STREAM_LOAD) {
