@@ -171,6 +171,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--autotune-problems", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy 2^26 fp32 once (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the counter's work is per variant and "
@@ -231,6 +234,14 @@ def main():
     counts = d_c.cpu().numpy()
     points = float(sum(domain_points(v) for v in vs))
     log("batched: %.3f ms/step, %.0f variants/s; kernels %s" % (ms_step, value, phase_ms))
+
+    if args.copy_calibration:
+        cv = dict(family="stream", op="copy", dtype="f32", n=1 << 26, wg=256, s=1,
+                  gs=1, vec=1, U=1)
+        cts, _ = P.device_buffers(cv, 3, fast=True)
+        ctx.launch(cv, cts)
+        torch.cuda.synchronize()
+        del cts
 
     # -------------------------------------------------------- plain path --
     ns = min(args.plain_sample, nv)
