@@ -20,6 +20,7 @@
 //   k_finalize  one thread per variant: count vector and prediction
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <vector>
 
 #include "counter.h"
@@ -41,11 +42,11 @@ constexpr int BUILD_LANES = 16;        // variants built per wavefront in k_buil
 // descriptor and jobs go to HBM and every valid variant continues in the
 // general pipeline.
 __global__ void __launch_bounds__(64)
-k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
+k_build(int nv, int lanes, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
         int64_t *jobres, int64_t *foot) {
-    if ((int)threadIdx.x >= BUILD_LANES) return;
-    const int64_t i = (int64_t)blockIdx.x * BUILD_LANES + threadIdx.x;
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t i = (int64_t)blockIdx.x * lanes + threadIdx.x;
     if (i >= nv) return;
     pm_variant v = var[i];
     Prog *p = &prog[i];
@@ -400,10 +401,21 @@ __global__ void k_finalize(int nv, const Prog *prog, const int64_t *jobres,
 }
 
 // ---------------------------------------------------------------- host ---
+// Variants built per wavefront by k_build: PM_BUILD_LANES (1..64) if set.
+static int build_lanes_setting() {
+    static int lanes = [] {
+        const char *e = getenv("PM_BUILD_LANES");
+        int v = e ? atoi(e) : BUILD_LANES;
+        return v < 1 ? 1 : v > 64 ? 64 : v;
+    }();
+    return lanes;
+}
+
 int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev) {
     if (nv <= 0) return PM_OK;
+    const int build_lanes = build_lanes_setting();
     int tb = 64;
     int q = 0;
     auto mark = [&]() {
@@ -421,8 +433,8 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
                            ar.prog, ar.jobs, d_status, ar.varwords, ar.varchunks,
                            ar.varsegs, ar.jobres, ar.foot, d_counts, m, has, d_pred);
     else
-        hipLaunchKernelGGL(k_build, dim3((nv + BUILD_LANES - 1) / BUILD_LANES), dim3(64), 0, s,
-                           nv, d_var, ar.prog, ar.jobs, d_status, ar.varwords,
+        hipLaunchKernelGGL(k_build, dim3((nv + build_lanes - 1) / build_lanes), dim3(64), 0, s,
+                           nv, build_lanes, d_var, ar.prog, ar.jobs, d_status, ar.varwords,
                            ar.varchunks, ar.varsegs, ar.jobres, ar.foot);
     mark();
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
