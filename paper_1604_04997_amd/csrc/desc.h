@@ -124,9 +124,10 @@ struct Prog {
 struct Job {
     int32_t kind, nv, ng, arr;
     int32_t vec, mark_b, pad0, pad1;
-    int64_t ext[MAXVAR];             // var 0 is the inner variable
-    int64_t g[MAXGUARD][MAXVAR + 1]; // guard coefficients, constant last
-    int64_t ic[MAXVAR + 1];          // footprint index map, constant last
+    int64_t ext[MAXVAR];                 // var 0 is the inner variable
+    // affine forms, constant last: rows [0, ng) are the guards (>= 0), row
+    // ng is the footprint index map (zero for count jobs)
+    int64_t f[MAXGUARD + 1][MAXVAR + 1];
     int64_t seg, nseg, outer, items, chunk_items, chunks;
     int64_t f_off, b_off;            // bitmap word offsets (variant-relative)
     int64_t words;                   // words of each of this array's bitmaps
@@ -708,7 +709,7 @@ PM_HD void inner_range(const Job &J, const int64_t *r, int64_t *lo_out,
                        int64_t *hi_out) {
     int64_t lo = 0, hi = J.ext[0];
     for (int q = 0; q < J.ng; q++) {
-        int64_t a = J.g[q][0];
+        int64_t a = J.f[q][0];
         if (a == 1) {
             if (-r[q] > lo) lo = -r[q];
         } else if (a == -1) {
@@ -730,14 +731,14 @@ PM_HD void inner_range(const Job &J, const int64_t *r, int64_t *lo_out,
 // Decompose outer point o (over vars 1..nv-1, var 1 fastest) and evaluate
 // the guards and the index map on it.
 PM_HD void eval_outer(const Job &J, int64_t o, int64_t *r, int64_t *base) {
-    for (int q = 0; q < J.ng; q++) r[q] = J.g[q][MAXVAR];
-    int64_t b = J.ic[MAXVAR];
+    for (int q = 0; q < J.ng; q++) r[q] = J.f[q][MAXVAR];
+    int64_t b = J.f[J.ng][MAXVAR];
     for (int v = 1; v < J.nv; v++) {
         int64_t e = J.ext[v];
         int64_t x = o % e;
         o /= e;
-        for (int q = 0; q < J.ng; q++) r[q] += J.g[q][v] * x;
-        b += J.ic[v] * x;
+        for (int q = 0; q < J.ng; q++) r[q] += J.f[q][v] * x;
+        b += J.f[J.ng][v] * x;
     }
     *base = b;
 }
@@ -761,13 +762,13 @@ PM_HD int64_t lane_stride(const Stmt &s, const GAcc &a) {
 //   Fill = union over x of [first, last cell + w)   (strided access), or F.
 // The sizes then follow in closed form (ival_sizes).
 PM_HD bool ival_ok(const Job &J) {
-    if (J.nv > 2 || J.ic[0] <= 0) return false;
-    if (J.nv == 2 && J.ic[1] <= 0) return false;
+    if (J.nv > 2 || J.f[J.ng][0] <= 0) return false;
+    if (J.nv == 2 && J.f[J.ng][1] <= 0) return false;
     int64_t lo = 0, hi = J.ext[0];
     for (int q = 0; q < J.ng; q++) {
-        if (J.nv == 2 && J.g[q][0] && J.g[q][1]) return false;
-        if (!J.g[q][0]) continue;
-        int64_t a = J.g[q][0], r = J.g[q][MAXVAR];
+        if (J.nv == 2 && J.f[q][0] && J.f[q][1]) return false;
+        if (!J.f[q][0]) continue;
+        int64_t a = J.f[q][0], r = J.f[q][MAXVAR];
         if (a > 0) {
             int64_t t = ceil_div(-r, a);
             if (t > lo) lo = t;
@@ -777,9 +778,9 @@ PM_HD bool ival_ok(const Job &J) {
         }
     }
     int64_t cnt = hi > lo ? hi - lo : 0;
-    int64_t step = J.ic[0], vec = J.vec;
+    int64_t step = J.f[J.ng][0], vec = J.vec;
     if (cnt == 0) return true;
-    if (step > vec && J.nv == 2 && J.ic[1] < step * (cnt - 1) + vec) return false;  // runs interleave
+    if (step > vec && J.nv == 2 && J.f[J.ng][1] < step * (cnt - 1) + vec) return false;  // runs interleave
     if (J.w && step >= vec + J.w) return false;  // widened accesses leave gaps
     return true;
 }
@@ -793,8 +794,8 @@ PM_HD bool ival_ok(const Job &J) {
 PM_HD int ival_sizes(const Job &J, int64_t *F, int64_t *Fill) {
     int64_t lo = 0, hi = J.ext[0], xlo = 0, xhi = J.nv == 2 ? J.ext[1] : 1;
     for (int q = 0; q < J.ng; q++) {
-        int v = J.g[q][0] ? 0 : (J.nv == 2 && J.g[q][1]) ? 1 : -1;
-        int64_t a = v >= 0 ? J.g[q][v] : 0, r = J.g[q][MAXVAR];
+        int v = J.f[q][0] ? 0 : (J.nv == 2 && J.f[q][1]) ? 1 : -1;
+        int64_t a = v >= 0 ? J.f[q][v] : 0, r = J.f[q][MAXVAR];
         int64_t &l = v == 1 ? xlo : lo, &h = v == 1 ? xhi : hi;
         if (v < 0) {
             if (r < 0) h = l;
@@ -809,7 +810,7 @@ PM_HD int ival_sizes(const Job &J, int64_t *F, int64_t *Fill) {
     *F = *Fill = 0;
     int64_t cnt = hi - lo, nx = xhi - xlo;
     if (cnt <= 0 || nx <= 0) return PM_OK;
-    int64_t step = J.ic[0], vec = J.vec, c1 = J.nv == 2 ? J.ic[1] : 0;
+    int64_t step = J.f[J.ng][0], vec = J.vec, c1 = J.nv == 2 ? J.f[J.ng][1] : 0;
     int64_t L, Lf, t;
     bool ovf = mul_ovf(step, cnt - 1, &L) || add_ovf(L, vec, &L);
     if (step <= vec) {
@@ -912,7 +913,8 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             int rr = root;
             while (par[rr] != rr) rr = par[rr];
             if (!guarded[root] || rr != root) continue;
-            Job J;
+            if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
+            Job &J = jobs[nj];  // built in place; kept only if it enumerates
             J.kind = JOB_COUNT;
             J.nv = 0;
             J.ng = 0;
@@ -932,17 +934,17 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
                 for (int x = 0; x < s.nvar; x++)
                     if (s.guard[q].c[x] && map[x] >= 0) mine = true;
                 if (!mine) continue;
-                for (int t = 0; t <= MAXVAR; t++) J.g[J.ng][t] = 0;
+                for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;
                 for (int x = 0; x < s.nvar; x++)
-                    if (map[x] >= 0) J.g[J.ng][map[x]] = s.guard[q].c[x];
-                J.g[J.ng][MAXVAR] = s.guard[q].k;
+                    if (map[x] >= 0) J.f[J.ng][map[x]] = s.guard[q].c[x];
+                J.f[J.ng][MAXVAR] = s.guard[q].k;
                 J.ng++;
             }
             bool ovf = false;
-            J.nv = fuse(J.nv, J.ext, J.ng, J.g, &ovf);
+            J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
             if (ovf) return b.fail(PM_EOVERFLOW), p->status;
-            if (J.nv == 1) {  // an interval: closed form
-                int64_t c = interval_count(J.ext[0], J.ng, J.g);
+            if (J.nv == 1) {  // an interval: closed form, the slot is reused
+                int64_t c = interval_count(J.ext[0], J.ng, J.f);
                 if (mul_ovf(s.fixed, c, &s.fixed)) return b.fail(PM_EOVERFLOW), p->status;
                 continue;
             }
@@ -955,12 +957,12 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
                 J.ext[0] = J.ext[in];
                 J.ext[in] = te;
                 for (int q = 0; q < J.ng; q++) {
-                    int64_t tg = J.g[q][0];
-                    J.g[q][0] = J.g[q][in];
-                    J.g[q][in] = tg;
+                    int64_t tg = J.f[q][0];
+                    J.f[q][0] = J.f[q][in];
+                    J.f[q][in] = tg;
                 }
             }
-            for (int t = 0; t <= MAXVAR; t++) J.ic[t] = 0;
+            for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;  // no index map
             J.outer = 1;
             for (int x = 1; x < J.nv; x++)
                 if (mul_ovf(J.outer, J.ext[x], &J.outer)) return b.fail(PM_EOVERFLOW), p->status;
@@ -972,16 +974,15 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             J.f_off = J.b_off = 0;
             J.words = 0;
             J.w = 0;
-            if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
-            s.comp_job[s.ncomp++] = nj;
-            jobs[nj++] = J;
+            s.comp_job[s.ncomp++] = nj++;
         }
         // footprint jobs for accesses to arrays with a strided access
         for (int q = 0; q < s.nacc; q++) {
             GAcc &a = s.acc[q];
             ArrInfo &A = p->arr[a.arr];
             if (!A.w) continue;
-            Job J;
+            if (nj >= MAXJOB) return b.fail(PM_EINVAL), p->status;
+            Job &J = jobs[nj];
             J.kind = JOB_FOOT;
             J.nv = 0;
             J.ng = 0;
@@ -996,28 +997,22 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
                 map[x] = (guarded[x] || a.idx.c[x]) ? J.nv++ : -1;
             for (int x = 0; x < s.nvar; x++)
                 if (map[x] >= 0) J.ext[map[x]] = s.ext[x];
-            for (int t = 0; t <= MAXVAR; t++) J.ic[t] = 0;
-            for (int x = 0; x < s.nvar; x++)
-                if (map[x] >= 0) J.ic[map[x]] = a.idx.c[x];
-            J.ic[MAXVAR] = a.idx.k;
             for (int g = 0; g < s.nguard; g++) {
-                for (int t = 0; t <= MAXVAR; t++) J.g[J.ng][t] = 0;
+                for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;
                 for (int x = 0; x < s.nvar; x++)
-                    if (map[x] >= 0) J.g[J.ng][map[x]] = s.guard[g].c[x];
-                J.g[J.ng][MAXVAR] = s.guard[g].k;
+                    if (map[x] >= 0) J.f[J.ng][map[x]] = s.guard[g].c[x];
+                J.f[J.ng][MAXVAR] = s.guard[g].k;
                 J.ng++;
             }
+            int64_t *ic = J.f[J.ng];  // the index map after the guards
+            for (int t = 0; t <= MAXVAR; t++) ic[t] = 0;
+            for (int x = 0; x < s.nvar; x++)
+                if (map[x] >= 0) ic[map[x]] = a.idx.c[x];
+            ic[MAXVAR] = a.idx.k;
             // fuse over guards and the index map together
-            int64_t F[MAXGUARD + 1][MAXVAR + 1];
-            for (int g = 0; g < J.ng; g++)
-                for (int t = 0; t <= MAXVAR; t++) F[g][t] = J.g[g][t];
-            for (int t = 0; t <= MAXVAR; t++) F[J.ng][t] = J.ic[t];
             bool ovf = false;
-            J.nv = fuse(J.nv, J.ext, J.ng + 1, F, &ovf);
+            J.nv = fuse(J.nv, J.ext, J.ng + 1, J.f, &ovf);
             if (ovf) return b.fail(PM_EOVERFLOW), p->status;
-            for (int g = 0; g < J.ng; g++)
-                for (int t = 0; t <= MAXVAR; t++) J.g[g][t] = F[g][t];
-            for (int t = 0; t <= MAXVAR; t++) J.ic[t] = F[J.ng][t];
             if (J.nv == 0) {  // a single access point
                 J.nv = 1;
                 J.ext[0] = 1;
@@ -1025,9 +1020,9 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             // inner variable: smallest non-zero index coefficient
             int in = -1;
             for (int x = 0; x < J.nv; x++) {
-                if (!J.ic[x]) continue;
-                if (in < 0 || iabs(J.ic[x]) < iabs(J.ic[in]) ||
-                    (iabs(J.ic[x]) == iabs(J.ic[in]) && J.ext[x] > J.ext[in]))
+                if (!ic[x]) continue;
+                if (in < 0 || iabs(ic[x]) < iabs(ic[in]) ||
+                    (iabs(ic[x]) == iabs(ic[in]) && J.ext[x] > J.ext[in]))
                     in = x;
             }
             if (in < 0) in = 0;
@@ -1035,25 +1030,21 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
                 int64_t te = J.ext[0];
                 J.ext[0] = J.ext[in];
                 J.ext[in] = te;
-                int64_t ti = J.ic[0];
-                J.ic[0] = J.ic[in];
-                J.ic[in] = ti;
-                for (int g = 0; g < J.ng; g++) {
-                    int64_t tg = J.g[g][0];
-                    J.g[g][0] = J.g[g][in];
-                    J.g[g][in] = tg;
+                for (int g = 0; g <= J.ng; g++) {
+                    int64_t tg = J.f[g][0];
+                    J.f[g][0] = J.f[g][in];
+                    J.f[g][in] = tg;
                 }
             }
             J.outer = 1;
             for (int x = 1; x < J.nv; x++)
                 if (mul_ovf(J.outer, J.ext[x], &J.outer)) return b.fail(PM_EOVERFLOW), p->status;
-            J.seg = iabs(J.ic[0]) <= J.vec ? SEG_CONTIG : SEG_STRIDED;
+            J.seg = iabs(ic[0]) <= J.vec ? SEG_CONTIG : SEG_STRIDED;
             J.nseg = cdiv(J.ext[0], J.seg);
             if (mul_ovf(J.outer, J.nseg, &J.items)) return b.fail(PM_EOVERFLOW), p->status;
             J.chunk_items = CHUNK_FOOT;
             J.chunks = cdiv(J.items, J.chunk_items);
-            if (nj >= MAXJOB) return b.fail(PM_EINVAL), p->status;
-            jobs[nj++] = J;
+            nj++;
         }
     }
     p->njob = nj;
@@ -1176,7 +1167,7 @@ PM_HD void foot_item(const Job &J, int64_t it, uint64_t *vbase, int ln, int nl,
     if (lo < s0) lo = s0;
     if (hi > s1) hi = s1;
     if (hi <= lo) return;
-    int64_t c0 = J.ic[0];
+    int64_t c0 = J.f[J.ng][0];
     int64_t first, step;
     if (c0 >= 0) {
         first = base + c0 * lo;
