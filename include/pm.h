@@ -55,12 +55,15 @@ enum {
     PM_FAM_TRANSPOSE = 7, /* LDS-tiled / naive transpose */
     PM_FAM_STENCIL = 8,   /* 5-point finite difference stencil (Sec. 5) */
     PM_FAM_NBODY = 9,     /* all-pairs n-body sum of 1/r (Sec. 5) */
-    PM_NFAMILY = 10
+    PM_FAM_ARITH = 10,    /* division / exponential chains (Sec. 4.1 arithmetic operations) */
+    PM_FAM_CONV = 11,     /* three 7x7 filters over three RGB images (Sec. 5) */
+    PM_NFAMILY = 12
 };
 enum { PM_F32 = 0, PM_F64 = 1 };
 /* op values per family */
 enum { PM_STREAM_LOAD = 0, PM_STREAM_STORE = 1, PM_STREAM_COPY = 2,
-       PM_STREAM_ADD4 = 3, PM_STREAM_FILLED = 4 };
+       PM_STREAM_ADD4 = 3, PM_STREAM_FILLED = 4, PM_STREAM_AXPBY = 5 };
+enum { PM_ARITH_DIV = 0, PM_ARITH_EXP = 1 };
 enum { PM_LDS_READ = 0, PM_LDS_WRITE = 1 };
 enum { PM_MATMUL_TILED = 0, PM_MATMUL_NAIVE = 1 };
 enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC = 2 };
@@ -84,8 +87,16 @@ enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC 
  *   TRANSPOSE op, n[0] = n (n x n, row-major), tile T in {8,16,32}; fp32
  *   STENCIL   dtype, n[0] = interior side n (input (n+2)^2 with halo),
  *             tile T in {8,16,32}
+ *             AXPBY: out = 0.75 x + (-1.25) y elementwise (vector scale
+ *             and add, Sec. 4.1).
  *   NBODY     n[0] bodies (positions 3 x n column-major), wg[0] block size
  *             (64..1024, multiple of 64); fp32
+ *   ARITH     op DIV: chains y = (k+1) / (y*y + 1); op EXP: y = exp(-(y*y));
+ *             dtype, n[0] work-items, wg[0], reps = F, chains = K (as FMA)
+ *   CONV      n[0] = output side n; tile T in {8,16} (work-group T x T);
+ *             r[i][j][x][y] = sum_{u,v<7, c<3} img[i][x+6-u][y+6-v][c] *
+ *             filt[j][u][v][c] for 3 images (n+6)^2 x 3 and 3 filters
+ *             7 x 7 x 3, channel fastest; fp32
  * flags: PM_FLAG_BITMAP counts every footprint with bitmaps, also where
  * the interval form applies (same counts; for cross-checks).
  * Unused fields must be zero.  `seed` is carried for the caller's records.

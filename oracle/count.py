@@ -14,9 +14,11 @@ _SO = os.path.join(_HERE, "_count_oracle.so")
 
 FAMILIES = {"stream": 0, "lds": 1, "fma": 2, "rsqrt": 3, "barrier": 4,
             "empty": 5, "matmul": 6, "transpose": 7, "stencil": 8,
-            "nbody": 9}
+            "nbody": 9, "arith": 10, "conv": 11}
 OPS = {
-    "stream": {"load": 0, "store": 1, "copy": 2, "add4": 3, "filled": 4},
+    "stream": {"load": 0, "store": 1, "copy": 2, "add4": 3, "filled": 4,
+               "axpby": 5},
+    "arith": {"div": 0, "exp": 1},
     "lds": {"read": 0, "write": 1},
     "matmul": {"tiled": 0, "naive": 1},
     "transpose": {"tiled": 0, "naive_wc": 1, "naive_rc": 2},
@@ -88,7 +90,7 @@ def params(v: dict) -> list:
     wgx = v.get("wg", v.get("wx", v.get("T", 0)))
     wgy = v.get("wy", 1)
     reps = {"stream": v.get("U", 1), "lds": v.get("R", 0),
-            "fma": v.get("F", 0), "rsqrt": v.get("F", 0),
+            "fma": v.get("F", 0), "rsqrt": v.get("F", 0), "arith": v.get("F", 0),
             "barrier": v.get("B", 0)}.get(fam, 0)
     return [FAMILIES[fam], eb, op, n, v.get("m", 0), v.get("l", 0), wgx, wgy,
             v.get("T", 0), v.get("s", v.get("b", 1)), v.get("gs", 1),

@@ -170,7 +170,7 @@ static void bar(sim_t *S, int lane0) {
 }
 
 /* ---------------------------------------------------------------- stream */
-enum { ST_LOAD, ST_STORE, ST_COPY, ST_ADD4, ST_FILLED };
+enum { ST_LOAD, ST_STORE, ST_COPY, ST_ADD4, ST_FILLED, ST_AXPBY };
 
 static void sim_stream(sim_t *S, const oparams *p) {
     int64_t N = p->n, wg = p->wgx, s = p->s, gs = p->gs, vec = p->vec,
@@ -195,7 +195,7 @@ static void sim_stream(sim_t *S, const oparams *p) {
             }
     } else {
         int64_t span = G * gs * wg * s * U * vec;
-        int na = p->op == ST_ADD4 ? 5 : p->op == ST_COPY ? 2 : 1;
+        int na = p->op == ST_ADD4 ? 5 : p->op == ST_AXPBY ? 3 : p->op == ST_COPY ? 2 : 1;
         for (int a = 0; a < na; a++) new_array(S, a, span);
         for (int64_t g = 0; g < G; g++)
             for (int64_t l = 0; l < wg; l++)
@@ -219,6 +219,13 @@ static void sim_stream(sim_t *S, const oparams *p) {
                             gacc(S, a, a, D_LD, e, (int)vec, x, xn);
                         gacc(S, 4, 4, D_ST, e, (int)vec, x, xn);
                         flop(S, K_ADD, e, 3 * vec);
+                        break;
+                    case ST_AXPBY: /* out = alpha x + beta y */
+                        gacc(S, 0, 0, D_LD, e, (int)vec, x, xn);
+                        gacc(S, 1, 1, D_LD, e, (int)vec, x, xn);
+                        gacc(S, 2, 2, D_ST, e, (int)vec, x, xn);
+                        flop(S, K_MUL, e, 2 * vec);
+                        flop(S, K_ADD, e, vec);
                         break;
                     default:
                         fail(S, "bad stream op");
@@ -254,6 +261,8 @@ static void sim_lds(sim_t *S, const oparams *p) {
 }
 
 /* --------------------------------------------------------- fma and rsqrt */
+/* mode 0: FMA chain; 1: rsqrt chain y = rsqrt(y*y + d); 2: division
+ * chain y = d / (y*y + 1); 3: exponential chain y = exp(-(y*y)) */
 static void sim_fma(sim_t *S, const oparams *p, int rsqrt) {
     int64_t N = p->n, wg = p->wgx, F = p->reps, K = p->K;
     int e = (int)p->ebytes;
@@ -263,10 +272,17 @@ static void sim_fma(sim_t *S, const oparams *p, int rsqrt) {
     for (int64_t i = 0; i < N; i++) {
         gacc(S, 0, 0, D_LD, e, 1, i, i + 1);
         for (int64_t f = 0; f < F; f++) {
-            if (rsqrt) { /* y = rsqrt(y*y + d) */
+            if (rsqrt == 1) { /* y = rsqrt(y*y + d) */
                 flop(S, K_MUL, e, 1);
                 flop(S, K_ADD, e, 1);
                 flop(S, K_SPEC, e, 1);
+            } else if (rsqrt == 2) { /* y = d / (y*y + 1) */
+                flop(S, K_MUL, e, 1);
+                flop(S, K_ADD, e, 1);
+                flop(S, K_DIV, e, 1);
+            } else if (rsqrt == 3) { /* y = exp(-(y*y)): negation not counted */
+                flop(S, K_MUL, e, 1);
+                flop(S, K_EXP, e, 1);
             } else {
                 flop(S, K_FMA, e, 1);
             }
@@ -468,6 +484,59 @@ static void sim_nbody(sim_t *S, const oparams *p) {
     S->wi += G * Gs;
 }
 
+/* ----------------------------------------------------------------- conv */
+/* Three 7x7 filters over three RGB images (Sec. 5): r[i][j][x][y] = sum over
+ * u, v in [0,7), c < 3 of img[i][x+6-u][y+6-v][c] * filt[j][u][v][c];
+ * images (n+6)^2 x 3 (channel fastest), T x T work-groups, one per output
+ * tile and (image, filter) pair; the (T+6)^2 x 3 image tile and the filter
+ * are staged through LDS. */
+static void sim_conv(sim_t *S, const oparams *p) {
+    int64_t n = p->n, T = p->T, P = n + 6, G = cdiv(n, T), TT = T + 6;
+    int64_t KF = cdiv(147, T * T), KA = cdiv(TT, T);
+    new_array(S, 0, 3 * P * P * 3);
+    new_array(S, 1, 3 * 147);
+    new_array(S, 2, 9 * n * n);
+    for (int64_t zi = 0; zi < 3; zi++)
+        for (int64_t zj = 0; zj < 3; zj++)
+            for (int64_t gy = 0; gy < G; gy++)
+                for (int64_t gx = 0; gx < G; gx++)
+                    for (int64_t ly = 0; ly < T; ly++)
+                        for (int64_t lx = 0; lx < T; lx++) {
+                            int lane0 = lx == 0 && ly == 0;
+                            for (int64_t k = 0; k < KF; k++) {
+                                int64_t t = k * T * T + ly * T + lx;
+                                if (t < 147) {
+                                    gacc(S, 0, 1, D_LD, 4, 1, zj * 147 + t, zj * 147 + t + 1);
+                                    lds(S, D_ST, 4, 1);
+                                }
+                            }
+                            for (int64_t a = 0; a < KA; a++)
+                                for (int64_t b = 0; b < KA; b++) {
+                                    int64_t r = a * T + ly, q = b * T + lx;
+                                    int64_t X = gy * T + r, Y = gx * T + q;
+                                    if (r < TT && q < TT && X < P && Y < P)
+                                        for (int64_t c = 0; c < 3; c++) {
+                                            int64_t id = ((zi * P + X) * P + Y) * 3 + c;
+                                            gacc(S, 1 + (int)c, 0, D_LD, 4, 1, id, id + 3);
+                                            lds(S, D_ST, 4, 1);
+                                        }
+                                }
+                            bar(S, lane0);
+                            int64_t x = gy * T + ly, y = gx * T + lx;
+                            if (x < n && y < n) {
+                                for (int64_t u = 0; u < 7; u++)
+                                    for (int64_t v = 0; v < 7; v++) {
+                                        lds(S, D_LD, 4, 6);
+                                        flop(S, K_FMA, 4, 3);
+                                    }
+                                int64_t o = ((zi * 3 + zj) * n + x) * n + y;
+                                gacc(S, 4, 2, D_ST, 4, 1, o, o + 1);
+                            }
+                        }
+    S->wg += 9 * G * G;
+    S->wi += 9 * G * G * T * T;
+}
+
 /* ------------------------------------------------------ classification */
 static int class_index(int64_t s, int64_t F, int64_t Fill) {
     if (s == 0) return 0;
@@ -568,6 +637,8 @@ int oracle_count(const int64_t *p_in, int64_t *out, char *msg, int msgcap) {
     case 7: sim_transpose(S, &p); break;
     case 8: sim_stencil(S, &p); break;
     case 9: sim_nbody(S, &p); break;
+    case 10: sim_fma(S, &p, p.op == 0 ? 2 : 3); break;
+    case 11: sim_conv(S, &p); break;
     default: fail(S, "unknown family");
     }
     if (!S->err) finish(S, out);

@@ -71,6 +71,15 @@ def stream_add4(v, a, b, c, d, o0):
     return o
 
 
+def stream_axpby(v, x, y, o0):
+    """axpby: o[e] = 0.75 * x[e] + (-1.25) * y[e] in the kernel dtype."""
+    o = o0.copy()
+    e = stream_elements(v)
+    t = x.dtype.type
+    o[e] = t(0.75) * x[e] + t(-1.25) * y[e]
+    return o
+
+
 def stream_filled(v, x):
     """filled (k = s): work-item i sums, for u = 0..U-1 and j = i + u*N,
     the k consecutive cells x[k*j .. k*j+k-1] as ((x0 + x1) + x2) and adds
@@ -135,6 +144,55 @@ def rsqrt_chain(v, x):
     for k in range(1, K):
         s = s + ys[k]
     return s
+
+
+def div_chain(v, x):
+    """arith div: K chains y_k = a; F/K rounds of y_k = (k+1) / (y_k*y_k + 1)
+    in the kernel dtype (every step one IEEE rounding); out = sum of chains
+    left to right."""
+    t = x.dtype.type
+    K, F = v["K"], v["F"]
+    ys = [x.copy() for _ in range(K)]
+    for _ in range(F // K):
+        for k in range(K):
+            ys[k] = t(k + 1) / (ys[k] * ys[k] + t(1))
+    s = ys[0]
+    for k in range(1, K):
+        s = s + ys[k]
+    return s
+
+
+def exp_chain(v, x):
+    """arith exp: K chains y_k = a; F/K rounds of y_k = exp(-(y_k*y_k));
+    out = sum of chains.  float64 reference."""
+    a = x.astype(np.float64)
+    K, F = v["K"], v["F"]
+    ys = [a.copy() for _ in range(K)]
+    for _ in range(F // K):
+        for k in range(K):
+            ys[k] = np.exp(-(ys[k] * ys[k]))
+    s = ys[0]
+    for k in range(1, K):
+        s = s + ys[k]
+    return s
+
+
+def conv(img, filt, n):
+    """Three 7x7 filters over three RGB images (n+6)^2 x 3, channel fastest:
+    r[i][j][x][y] = sum over u, v < 7 and c < 3 of
+    img[i][x+6-u][y+6-v][c] * filt[j][u][v][c], in float64.  Returns
+    (r, sum of |terms|) with shape (3, 3, n, n)."""
+    P = n + 6
+    I = img.reshape(3, P, P, 3).astype(np.float64)
+    Fw = filt.reshape(3, 7, 7, 3).astype(np.float64)
+    r = np.zeros((3, 3, n, n))
+    a = np.zeros((3, 3, n, n))
+    for u in range(7):
+        for v in range(7):
+            win = I[:, 6 - u:6 - u + n, 6 - v:6 - v + n, :]  # (3, n, n, 3)
+            r += np.einsum("ixyc,jc->ijxy", win, Fw[:, u, v, :])
+            a += np.einsum("ixyc,jc->ijxy", np.abs(win), np.abs(Fw[:, u, v, :]))
+    return r, a
 
 
 def barrier_out(v):

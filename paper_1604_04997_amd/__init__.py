@@ -24,9 +24,12 @@ PROJ = {"p3": 0, "p12": 1, "full": 2}
 NFEAT = {"p3": 3, "p12": 12, "full": 154}
 
 FAMILY = {"stream": 0, "lds": 1, "fma": 2, "rsqrt": 3, "barrier": 4,
-          "empty": 5, "matmul": 6, "transpose": 7, "stencil": 8, "nbody": 9}
+          "empty": 5, "matmul": 6, "transpose": 7, "stencil": 8, "nbody": 9,
+          "arith": 10, "conv": 11}
 OPS = {
-    "stream": {"load": 0, "store": 1, "copy": 2, "add4": 3, "filled": 4},
+    "stream": {"load": 0, "store": 1, "copy": 2, "add4": 3, "filled": 4,
+               "axpby": 5},
+    "arith": {"div": 0, "exp": 1},
     "lds": {"read": 0, "write": 1},
     "matmul": {"tiled": 0, "naive": 1},
     "transpose": {"tiled": 0, "naive_wc": 1, "naive_rc": 2},
@@ -140,7 +143,7 @@ def variant_struct(d: dict) -> Variant:
     elif fam == "lds":
         v.n[0], v.wg[0] = d["groups"], d["wg"]
         v.stride, v.reps, v.words = d["b"], d["R"], d["W"]
-    elif fam in ("fma", "rsqrt"):
+    elif fam in ("fma", "rsqrt", "arith"):
         v.n[0], v.wg[0], v.reps, v.chains = d["n"], d["wg"], d["F"], d["K"]
     elif fam == "barrier":
         v.n[0], v.wg[0], v.reps = d["groups"], d["wg"], d["B"]
@@ -148,7 +151,7 @@ def variant_struct(d: dict) -> Variant:
         v.n[0], v.wg[0], v.wg[1] = d["n"], d["wx"], d.get("wy", 1)
     elif fam == "matmul":
         v.n[0], v.n[1], v.n[2], v.tile = d["n"], d["m"], d["l"], d["T"]
-    elif fam in ("transpose", "stencil"):
+    elif fam in ("transpose", "stencil", "conv"):
         v.n[0], v.tile = d["n"], d["T"]
     elif fam == "nbody":
         v.n[0], v.wg[0] = d["n"], d["wg"]

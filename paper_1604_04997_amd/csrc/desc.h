@@ -255,7 +255,7 @@ PM_HD void build_stream(B &b, const pm_variant &v) {
     int dt = v.dtype == PM_F64 ? 1 : 0;
     if (N <= 0 || wg <= 0 || wg > 1024 || N % wg || s < 1 || gs < 1 ||
         U < 1 || !(vec == 1 || vec == 2 || vec == 4) || e * vec > 16 ||
-        v.op > PM_STREAM_FILLED) {
+        v.op > PM_STREAM_AXPBY) {
         b.fail(PM_EINVAL);
         return;
     }
@@ -284,7 +284,8 @@ PM_HD void build_stream(B &b, const pm_variant &v) {
         return;
     }
     int64_t span = prod3(b, G * gs, wg * s, U * vec);
-    int na = v.op == PM_STREAM_ADD4 ? 5 : v.op == PM_STREAM_COPY ? 2 : 1;
+    int na = v.op == PM_STREAM_ADD4 ? 5 : v.op == PM_STREAM_AXPBY ? 3 :
+             v.op == PM_STREAM_COPY ? 2 : 1;
     for (int a = 0; a < na; a++) b.array(a, span);
     Stmt *S = b.stmt(1);
     if (!S) return;
@@ -301,6 +302,13 @@ PM_HD void build_stream(B &b, const pm_variant &v) {
     case PM_STREAM_COPY:
         b.acc(S, 0, D_LD, e, (int)vec, x);
         b.acc(S, 1, D_ST, e, (int)vec, x);
+        break;
+    case PM_STREAM_AXPBY:  // out = alpha x + beta y
+        b.acc(S, 0, D_LD, e, (int)vec, x);
+        b.acc(S, 1, D_LD, e, (int)vec, x);
+        b.acc(S, 2, D_ST, e, (int)vec, x);
+        S->flop[K_MUL][dt] = (int32_t)(2 * vec);
+        S->flop[K_ADD][dt] = (int32_t)vec;
         break;
     default:  // add4
         for (int a = 0; a < 4; a++) b.acc(S, a, D_LD, e, (int)vec, x);
@@ -341,14 +349,16 @@ PM_HD void build_lds(B &b, const pm_variant &v) {
 }
 
 // --- FMA / rsqrt chains: 1 load, F ops, 1 store per work-item ---
-PM_HD void build_chain(B &b, const pm_variant &v, bool rsq) {
+// kind 0: FMA, 1: rsqrt, 2: division, 3: exponential
+PM_HD void build_chain(B &b, const pm_variant &v, int kind) {
     int64_t N = v.n[0], wg = v.wg[0], F = v.reps, K = v.chains;
     int e = v.dtype == PM_F64 ? 8 : 4;
     int dt = v.dtype == PM_F64 ? 1 : 0;
-    bool kok = rsq ? (K == 1 || K == 2 || K == 4 || K == 8)
-                   : (K == 1 || K == 2 || K == 4 || K == 8 || K == 16);
+    bool rsq = kind == 1;
+    bool kok = kind ? (K == 1 || K == 2 || K == 4 || K == 8)
+                    : (K == 1 || K == 2 || K == 4 || K == 8 || K == 16);
     if (N <= 0 || wg <= 0 || wg > 1024 || N % wg || !kok || F < 0 || F % K ||
-        F > (1 << 24) || (rsq && v.dtype != PM_F32)) {
+        F > (1 << 24) || (rsq && v.dtype != PM_F32) || (kind >= 2 && v.op > PM_ARITH_EXP)) {
         b.fail(PM_EINVAL);
         return;
     }
@@ -362,10 +372,18 @@ PM_HD void build_chain(B &b, const pm_variant &v, bool rsq) {
     Aff i = av(av(aff(0), g, wg), l, 1);
     b.acc(S, 0, D_LD, e, 1, i);
     b.acc(S, 1, D_ST, e, 1, i);
-    if (rsq) {
+    if (rsq) {  // y = rsqrt(y*y + d)
         S->flop[K_MUL][dt] = (int32_t)F;
         S->flop[K_ADD][dt] = (int32_t)(F + K - 1);
         S->flop[K_SPEC][dt] = (int32_t)F;
+    } else if (kind == 2) {  // y = d / (y*y + 1)
+        S->flop[K_MUL][dt] = (int32_t)F;
+        S->flop[K_ADD][dt] = (int32_t)(F + K - 1);
+        S->flop[K_DIV][dt] = (int32_t)F;
+    } else if (kind == 3) {  // y = exp(-(y*y)); the negation is not counted
+        S->flop[K_MUL][dt] = (int32_t)F;
+        S->flop[K_EXP][dt] = (int32_t)F;
+        S->flop[K_ADD][dt] = (int32_t)(K - 1);
     } else {
         S->flop[K_FMA][dt] = (int32_t)F;
         S->flop[K_ADD][dt] = (int32_t)(K - 1);
@@ -648,6 +666,75 @@ PM_HD void build_nbody(B &b, const pm_variant &v) {
     b.acc(So, 1, D_ST, 4, 1, av(av(aff(0), g, Gs), l, 1));
 }
 
+// --- convolution: three 7x7 filters over three RGB images ---
+// Work-group (gx, gy, image zi, filter zj), T x T work-items; the filter and
+// the (T+6)^2 x 3 image tile are staged through LDS.
+PM_HD void build_conv(B &b, const pm_variant &v) {
+    int64_t n = v.n[0], T = v.tile;
+    if (n <= 0 || n > (1 << 20) || !(T == 8 || T == 16) || v.dtype != PM_F32) {
+        b.fail(PM_EINVAL);
+        return;
+    }
+    int64_t P = n + 6, G = cdiv(n, T), TT = T + 6;
+    int64_t KF = cdiv(147, T * T), KA = cdiv(TT, T);
+    b.p->n_wg = 9 * G * G;
+    b.p->wg_size = (int32_t)(T * T);
+    b.array(0, 3 * P * P * 3);
+    b.array(1, 3 * 147);
+    b.array(2, 9 * n * n);
+    // variables: 0 gy, 1 gx, 2 zi, 3 zj, 4 ly, 5 lx, then loop counters
+    auto head = [&](Stmt *S) {
+        b.var(S, G);
+        b.var(S, G);
+        b.var(S, 3);
+        b.var(S, 3);
+        b.var(S, T);
+        b.var(S, T);
+    };
+    Stmt *Sf = b.stmt(5);  // filter element t = k*T^2 + ly*T + lx -> LDS
+    if (!Sf) return;
+    head(Sf);
+    int k = b.var(Sf, KF);
+    Aff t = av(av(av(aff(0), k, T * T), 4, T), 5, 1);
+    b.lt(Sf, t, 147);
+    b.acc(Sf, 1, D_LD, 4, 1, av(av(av(av(aff(0), 3, 147), k, T * T), 4, T), 5, 1));
+    Sf->lds[D_ST][0] = 1;
+    Stmt *Si = b.stmt(5);  // image tile cell (a*T + ly, b*T + lx), 3 channels
+    if (!Si) return;
+    head(Si);
+    int a = b.var(Si, KA), bb = b.var(Si, KA);
+    b.lt(Si, av(av(aff(0), a, T), 4, 1), TT);
+    b.lt(Si, av(av(aff(0), bb, T), 5, 1), TT);
+    b.lt(Si, av(av(av(aff(0), 0, T), a, T), 4, 1), P);
+    b.lt(Si, av(av(av(aff(0), 1, T), bb, T), 5, 1), P);
+    for (int c = 0; c < 3; c++)  // ((zi*P + X)*P + Y)*3 + c
+        b.acc(Si, 0, D_LD, 4, 1,
+              av(av(av(av(av(av(av(aff(c), 2, P * P * 3), 0, T * P * 3), a, T * P * 3),
+                             4, P * 3), 1, T * 3), bb, T * 3), 5, 3));
+    Si->lds[D_ST][0] = 3;
+    Stmt *Sb = b.stmt(5);
+    if (!Sb) return;
+    head(Sb);
+    Sb->bar = 1;
+    Stmt *Sm = b.stmt(5);  // one filter tap (u, v), three channels
+    if (!Sm) return;
+    head(Sm);
+    b.var(Sm, 7);
+    b.var(Sm, 7);
+    Aff x = av(av(aff(0), 0, T), 4, 1), y = av(av(aff(0), 1, T), 5, 1);
+    b.lt(Sm, x, n);
+    b.lt(Sm, y, n);
+    Sm->lds[D_LD][0] = 6;
+    Sm->flop[K_FMA][0] = 3;
+    Stmt *So = b.stmt(5);
+    if (!So) return;
+    head(So);
+    b.lt(So, x, n);
+    b.lt(So, y, n);  // ((zi*3 + zj)*n + x)*n + y
+    b.acc(So, 2, D_ST, 4, 1,
+          av(av(av(av(av(av(aff(0), 2, 3 * n * n), 3, n * n), 0, T * n), 4, n), 1, T), 5, 1));
+}
+
 // ------------------------------------------------------ job preparation ---
 // Fuse variables of a job whose affine forms treat (a, b) as one
 // mixed-radix digit pair; returns the new variable count.
@@ -840,8 +927,10 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
     switch (v.family) {
     case PM_FAM_STREAM: build_stream(b, v); break;
     case PM_FAM_LDS: build_lds(b, v); break;
-    case PM_FAM_FMA: build_chain(b, v, false); break;
-    case PM_FAM_RSQRT: build_chain(b, v, true); break;
+    case PM_FAM_FMA: build_chain(b, v, 0); break;
+    case PM_FAM_RSQRT: build_chain(b, v, 1); break;
+    case PM_FAM_ARITH: build_chain(b, v, v.op == PM_ARITH_EXP ? 3 : 2); break;
+    case PM_FAM_CONV: build_conv(b, v); break;
     case PM_FAM_BARRIER: build_barrier(b, v); break;
     case PM_FAM_EMPTY: build_empty(b, v); break;
     case PM_FAM_MATMUL: build_matmul(b, v); break;

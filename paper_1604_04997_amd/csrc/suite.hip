@@ -58,6 +58,13 @@ __global__ void k_stream(T *x0, T *x1, T *x2, T *x3, T *x4, int64_t G,
             ((VT *)x0)[e] = vset<VT, T>(t);
         } else if (OP == PM_STREAM_COPY) {
             ((VT *)x1)[e] = ((const VT *)x0)[e];
+        } else if (OP == PM_STREAM_AXPBY) {
+            VT a = ((const VT *)x0)[e], b = ((const VT *)x1)[e];
+            T t[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; q++)
+                t[q] = (T)0.75 * comp(a, q) + (T)(-1.25) * comp(b, q);
+            ((VT *)x2)[e] = vset<VT, T>(t);
         } else {  // add4
             VT a = ((const VT *)x0)[e], b = ((const VT *)x1)[e];
             VT c = ((const VT *)x2)[e], d = ((const VT *)x3)[e];
@@ -146,6 +153,66 @@ __global__ void k_rsqrt(const float *in, float *out, int F) {
 #pragma unroll
     for (int k = 1; k < K; k++) s = s + y[k];
     out[i] = s;
+}
+
+// division chains y = (k+1) / (y*y + 1) and exponential chains y = exp(-(y*y))
+template <typename T> __device__ inline T expT(T x);
+template <> __device__ inline float expT(float x) { return expf(x); }
+template <> __device__ inline double expT(double x) { return exp(x); }
+
+template <typename T, int K, int OP>
+__global__ void k_arith(const T *in, T *out, int F) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const T a = in[i];
+    T y[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) y[k] = a;
+    for (int f = 0; f < F / K; f++) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (OP == PM_ARITH_DIV) y[k] = (T)(k + 1) / (y[k] * y[k] + (T)1);
+            else y[k] = expT(-(y[k] * y[k]));
+        }
+    }
+    T s = y[0];
+#pragma unroll
+    for (int k = 1; k < K; k++) s = s + y[k];
+    out[i] = s;
+}
+
+// --------------------------------------------------------- convolution
+// r[i][j][x][y] = sum_{u,v<7, c<3} img[i][x+6-u][y+6-v][c] * filt[j][u][v][c]
+template <int T>
+__global__ void __launch_bounds__(T * T)
+k_conv(const float *img, const float *filt, float *out, int n) {
+    constexpr int TT = T + 6, KF = (147 + T * T - 1) / (T * T), KA = (TT + T - 1) / T;
+    __shared__ float tile[TT][TT][3];
+    __shared__ float fl[147];
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int gx = blockIdx.x, gy = blockIdx.y, zi = blockIdx.z / 3, zj = blockIdx.z % 3;
+    const int64_t P = n + 6;
+    for (int k = 0; k < KF; k++) {
+        const int t = k * T * T + ly * T + lx;
+        if (t < 147) fl[t] = filt[zj * 147 + t];
+    }
+    for (int a = 0; a < KA; a++)
+        for (int b = 0; b < KA; b++) {
+            const int r = a * T + ly, q = b * T + lx;
+            const int64_t X = (int64_t)gy * T + r, Y = (int64_t)gx * T + q;
+            if (r < TT && q < TT && X < P && Y < P)
+                for (int c = 0; c < 3; c++) tile[r][q][c] = img[((zi * P + X) * P + Y) * 3 + c];
+        }
+    __syncthreads();
+    const int x = gy * T + ly, y = gx * T + lx;
+    if (x < n && y < n) {
+        float acc = 0.f;
+        for (int u = 0; u < 7; u++)
+            for (int v = 0; v < 7; v++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    acc = __builtin_fmaf(tile[ly + 6 - u][lx + 6 - v][c], fl[(u * 7 + v) * 3 + c], acc);
+        out[(((int64_t)zi * 3 + zj) * n + x) * n + y] = acc;
+    }
 }
 
 // --------------------------------------------------------- barrier, empty
@@ -299,6 +366,7 @@ int buffers(const pm_variant &v, size_t *bytes, uint32_t *role, uint32_t *nb) {
         }
         int64_t span = e * G * v.gstride * v.wg[0] * v.stride * v.reps * v.vec;
         if (v.op == PM_STREAM_LOAD) add(span, 0), add(e * v.n[0], 3);
+        else if (v.op == PM_STREAM_AXPBY) add(span, 0), add(span, 0), add(span, 2);
         else if (v.op == PM_STREAM_STORE) add(span, 2);
         else if (v.op == PM_STREAM_COPY) add(span, 0), add(span, 2);
         else {
@@ -310,7 +378,13 @@ int buffers(const pm_variant &v, size_t *bytes, uint32_t *role, uint32_t *nb) {
     case PM_FAM_LDS:
     case PM_FAM_BARRIER: add(4 * v.n[0] * v.wg[0], 1); break;
     case PM_FAM_FMA:
+    case PM_FAM_ARITH:
     case PM_FAM_RSQRT: add(e * v.n[0], 0), add(e * v.n[0], 1); break;
+    case PM_FAM_CONV: {
+        int64_t P = v.n[0] + 6;
+        add(4 * 9 * P * P, 0), add(4 * 441, 0), add(4 * 9 * v.n[0] * v.n[0], 1);
+        break;
+    }
     case PM_FAM_EMPTY: break;
     case PM_FAM_MATMUL:
         add(4 * v.n[0] * v.n[1], 0), add(4 * v.n[1] * v.n[2], 0), add(4 * v.n[0] * v.n[2], 1);
@@ -340,6 +414,9 @@ static void launch_stream_t(const pm_variant &v, void *const *b, hipStream_t s) 
     case PM_STREAM_COPY:
         hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_COPY>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
         break;
+    case PM_STREAM_AXPBY:
+        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_AXPBY>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
+        break;
     default:
         hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_ADD4>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
     }
@@ -356,6 +433,19 @@ static void launch_fma_t(const pm_variant &v, void *const *b, hipStream_t s) {
     case 4: hipLaunchKernelGGL((k_fma<T, 4>), gr, bl, 0, s, in, out, v.reps); break;
     case 8: hipLaunchKernelGGL((k_fma<T, 8>), gr, bl, 0, s, in, out, v.reps); break;
     default: hipLaunchKernelGGL((k_fma<T, 16>), gr, bl, 0, s, in, out, v.reps); break;
+    }
+}
+
+template <typename T, int OP>
+static void launch_arith_t(const pm_variant &v, void *const *b, hipStream_t s) {
+    dim3 gr((unsigned)(v.n[0] / v.wg[0])), bl(v.wg[0]);
+    const T *in = (const T *)b[0];
+    T *out = (T *)b[1];
+    switch (v.chains) {
+    case 1: hipLaunchKernelGGL((k_arith<T, 1, OP>), gr, bl, 0, s, in, out, v.reps); break;
+    case 2: hipLaunchKernelGGL((k_arith<T, 2, OP>), gr, bl, 0, s, in, out, v.reps); break;
+    case 4: hipLaunchKernelGGL((k_arith<T, 4, OP>), gr, bl, 0, s, in, out, v.reps); break;
+    default: hipLaunchKernelGGL((k_arith<T, 8, OP>), gr, bl, 0, s, in, out, v.reps); break;
     }
 }
 
@@ -452,6 +542,24 @@ int launch(const pm_variant &v, void *const *b, hipStream_t s) {
         if (v.dtype == PM_F64) launch_stencil_t<double>(v, b, s);
         else launch_stencil_t<float>(v, b, s);
         break;
+    case PM_FAM_ARITH:
+        if (v.dtype == PM_F64) {
+            if (v.op == PM_ARITH_DIV) launch_arith_t<double, PM_ARITH_DIV>(v, b, s);
+            else launch_arith_t<double, PM_ARITH_EXP>(v, b, s);
+        } else {
+            if (v.op == PM_ARITH_DIV) launch_arith_t<float, PM_ARITH_DIV>(v, b, s);
+            else launch_arith_t<float, PM_ARITH_EXP>(v, b, s);
+        }
+        break;
+    case PM_FAM_CONV: {
+        int n = (int)v.n[0], T = v.tile;
+        dim3 gr((unsigned)cdiv64(n, T), (unsigned)cdiv64(n, T), 9), bl(T, T);
+        const float *img = (const float *)b[0], *fl = (const float *)b[1];
+        float *o = (float *)b[2];
+        if (T == 8) hipLaunchKernelGGL(k_conv<8>, gr, bl, 0, s, img, fl, o, n);
+        else hipLaunchKernelGGL(k_conv<16>, gr, bl, 0, s, img, fl, o, n);
+        break;
+    }
     case PM_FAM_NBODY: {
         int N = (int)v.n[0], G = v.wg[0];
         hipLaunchKernelGGL(k_nbody, dim3((unsigned)cdiv64(N, G)), dim3(G), (size_t)12 * G, s, (const float *)b[0], (float *)b[1], N);

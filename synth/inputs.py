@@ -95,6 +95,17 @@ def suite_instructive(roofline_points: bool = True):
                           gs=1, vec=1, U=1))
         out.append(_v("stream", op="add4", dtype="f32", n=n, wg=256, s=1,
                       gs=1, vec=1, U=1))
+    # vector scale and add at strides 1, 2, 3
+    for dt in ("f32", "f64"):
+        for s in (1, 2, 3):
+            for n in (1 << 20, 1 << 24):
+                out.append(_v("stream", op="axpby", dtype=dt, n=n, wg=256, s=s,
+                              gs=1, vec=1, U=1))
+    # division and exponential chains
+    for dt in ("f32", "f64"):
+        for op in ("div", "exp"):
+            for F in (32, 128):
+                out.append(_v("arith", op=op, dtype=dt, n=1 << 20, wg=256, F=F, K=4))
     # matrix multiplication, tiled: shapes n=m=l, l=n/2, m=n/2, n=m/2
     for n in (384, 768, 1536):
         for (a, b, c) in ((n, n, n), (n, n, n // 2), (n, n // 2, n), (n // 2, n, n)):
@@ -138,19 +149,27 @@ def suite_instructive(roofline_points: bool = True):
 # workload 3: test-kernel suite whose run times the model predicts
 # ---------------------------------------------------------------------------
 def suite_test():
+    """Test kernels: the paper's four (finite differences = stencil, skinny
+    matmul n = l = m/8, n-body, convolution) and square matmul and
+    transpose.  `kernel` names the test kernel."""
     out = []
     for n in (512, 1024, 2048, 4096):
         for T in (8, 16, 32):
             for op in ("tiled", "naive"):
-                out.append(_v("matmul", op=op, n=n, m=n, l=n, T=T))
+                out.append(_v("matmul", op=op, n=n, m=n, l=n, T=T, kernel="matmul"))
+    for m in (1024, 2048, 4096, 8192):
+        out.append(_v("matmul", op="tiled", n=m // 8, m=m, l=m // 8, T=16,
+                      kernel="skinny_mm"))
+    for n in (256, 512, 1024, 2048):
+        out.append(_v("conv", n=n, T=16, kernel="convolution"))
     for n in (1024, 2048, 4096, 8192):
-        out.append(_v("transpose", op="naive_wc", n=n, T=16))
-        out.append(_v("transpose", op="tiled", n=n, T=32))
+        out.append(_v("transpose", op="naive_wc", n=n, T=16, kernel="transpose"))
+        out.append(_v("transpose", op="tiled", n=n, T=32, kernel="transpose"))
     for dt in ("f32", "f64"):
         for n in (1024, 2048, 4096, 8192):
-            out.append(_v("stencil", dtype=dt, n=n, T=16))
+            out.append(_v("stencil", dtype=dt, n=n, T=16, kernel="finite_difference"))
     for n in (4096, 8192, 16384, 32768, 65536):
-        out.append(_v("nbody", n=n, wg=256))
+        out.append(_v("nbody", n=n, wg=256, kernel="nbody"))
     for i, v in enumerate(out):
         v["seed"] = seed_for(3, i)
     return out

@@ -78,6 +78,9 @@ def stream(v):
         base["gst." + key] = n * U
     elif v["op"] == "copy":
         base.update({"gld." + key: n * U, "gst." + key: n * U})
+    elif v["op"] == "axpby":
+        base.update({"gld." + key: 2 * n * U, "gst." + key: n * U,
+                     "mul." + dt: 2 * n * U * vec, "add." + dt: n * U * vec})
     else:
         base.update({"gld." + key: 4 * n * U, "gst." + key: n * U,
                      "add." + dt: 3 * n * U * vec})
@@ -119,9 +122,36 @@ def empty(v):
     return {"wg": gx * gy, "wi": gx * gy * v["wx"] * v.get("wy", 1)}
 
 
+def conv(v):
+    n, T = v["n"], v["T"]
+    P, G, TT = n + 6, cdiv(n, T), T + 6
+    rows = sum(min(TT, P - gy * T) for gy in range(G))
+    img = 9 * rows * rows * 3
+    filt = 9 * G * G * 147
+    wi = 9 * G * G * T * T
+    return {"gld.4.1": filt, "gld.4.3/3": img, "lst.4": img + filt,
+            "lld.4": 9 * n * n * 294, "fma.f32": 9 * n * n * 147,
+            "gst.4.1": 9 * n * n, "bar.wi": wi, "bar.wg": 9 * G * G,
+            "wg": 9 * G * G, "wi": wi}
+
+
+def arith(v):
+    dt = v.get("dtype", "f32")
+    e = 4 if dt == "f32" else 8
+    n, F, K = v["n"], v["F"], v["K"]
+    out = {"gld.%d.1" % e: n, "gst.%d.1" % e: n, "mul." + dt: n * F,
+           "wg": n // v["wg"], "wi": n}
+    if v["op"] == "div":
+        out.update({"div." + dt: n * F, "add." + dt: n * F + n * (K - 1)})
+    else:
+        out.update({"exp." + dt: n * F, "add." + dt: n * (K - 1)})
+    return {k: x for k, x in out.items() if x}
+
+
 FORMS = {"matmul": matmul, "transpose": transpose, "stencil": stencil,
          "nbody": nbody, "stream": stream, "fma": chain, "rsqrt": chain,
-         "lds": lds, "barrier": barrier, "empty": empty}
+         "lds": lds, "barrier": barrier, "empty": empty, "conv": conv,
+         "arith": arith}
 
 
 def counts(v):

@@ -143,6 +143,11 @@ OUT_CASES = (
     + [dict(family="stencil", dtype=dt, n=n, T=T)
        for dt in ("f32", "f64") for n in (1, 2, 37, 100, 129) for T in (8, 16, 32)]
     + [dict(family="nbody", n=n, wg=wg) for n in (1, 2, 63, 300, 1000, 4099) for wg in (64, 256)]
+    + [dict(family="stream", op="axpby", dtype=dt, n=4096, wg=256, s=s, gs=gs, vec=vec, U=U)
+       for dt in ("f32", "f64") for (s, gs, vec, U) in ((1, 1, 1, 1), (3, 2, 2, 2))]
+    + [dict(family="arith", op=op, dtype=dt, n=8192, wg=256, F=F, K=K)
+       for op in ("div", "exp") for dt in ("f32", "f64") for (F, K) in ((8, 1), (64, 8))]
+    + [dict(family="conv", n=n, T=T) for n in (1, 5, 37, 100) for T in (8, 16)]
 )
 
 
@@ -159,6 +164,8 @@ def check_output(v, outs, host):
             np.testing.assert_array_equal(outs[1], O.stream_copy(v, host[0], host[1]))
         elif op == "add4":
             np.testing.assert_array_equal(outs[4], O.stream_add4(v, *host[:5]))
+        elif op == "axpby":
+            np.testing.assert_array_equal(outs[2], O.stream_axpby(v, *host[:3]))
         else:
             np.testing.assert_array_equal(outs[1], O.stream_filled(v, host[0]))
     elif fam == "lds":
@@ -169,6 +176,19 @@ def check_output(v, outs, host):
         ref = O.rsqrt_chain(v, host[0])
         # each step contracts errors (|d y'/d y| <= 0.385); a few ulp each
         np.testing.assert_allclose(outs[1], ref, rtol=16 * U32 * v["K"], atol=0)
+    elif fam == "arith":
+        if v["op"] == "div":
+            np.testing.assert_array_equal(outs[1], O.div_chain(v, host[0]))
+        else:
+            ref = O.exp_chain(v, host[0])
+            u = U32 if dt == "f32" else U64
+            # exp within a few ulp per step; |d exp(-y^2)/dy| <= 0.86 damps them
+            np.testing.assert_allclose(outs[1], ref, rtol=64 * u * v["K"], atol=0)
+    elif fam == "conv":
+        n = v["n"]
+        ref, scale = O.conv(host[0], host[1], n)
+        err = np.abs(outs[2].reshape(3, 3, n, n).astype(np.float64) - ref)
+        assert (err <= 1e-5 * scale).all(), float((err / np.maximum(scale, 1e-300)).max())
     elif fam == "barrier":
         np.testing.assert_array_equal(outs[0], O.barrier_out(v))
     elif fam == "matmul":

@@ -93,6 +93,14 @@ FAMILY_CASES = [
     for dt in ("f32", "f64") for n in (1, 2, 7, 16, 37) for T in (8, 16, 32)
 ] + [
     dict(family="nbody", n=n, wg=wg) for n in (1, 63, 300, 1000) for wg in (64, 256)
+] + [
+    dict(family="stream", op="axpby", dtype=dt, n=512, wg=64, s=s, gs=gs, vec=vec, U=U)
+    for dt in ("f32", "f64") for s in (1, 2, 3) for (gs, vec, U) in ((1, 1, 1), (2, 2, 3))
+] + [
+    dict(family="arith", op=op, dtype=dt, n=1024, wg=256, F=F, K=K)
+    for op in ("div", "exp") for dt in ("f32", "f64") for (F, K) in ((8, 1), (64, 8))
+] + [
+    dict(family="conv", n=n, T=T) for n in (1, 5, 16, 37) for T in (8, 16)
 ]
 
 

@@ -164,6 +164,56 @@ def test_nbody_closed_forms(N, G):
                    "bar.wg": 2 * B * B, "wg": B, "wi": wi}
 
 
+@pytest.mark.parametrize("n,T", [(16, 8), (20, 8), (37, 16), (7, 16)])
+def test_conv_closed_forms(n, T):
+    """Three 7x7 filters, three images: 147 FMAs and 294 LDS loads per
+    output; the filter fetched once per work-group; every image row and
+    column of the (T+6)-wide tiles that lies inside the padded image."""
+    P, G, TT = n + 6, cdiv(n, T), T + 6
+    rows = sum(min(TT, P - gy * T) for gy in range(G))
+    got = C.count(dict(family="conv", n=n, T=T))
+    assert got["fma.f32"] == 9 * 147 * n * n and got["lld.4"] == 9 * 294 * n * n
+    assert got["gld.4.1"] == 9 * G * G * 147
+    assert got["gld.4.3/3"] == 27 * rows * rows
+    assert got["gst.4.1"] == 9 * n * n and got["bar.wi"] == 9 * G * G * T * T
+
+
+@pytest.mark.parametrize("op", ["div", "exp"])
+def test_arith_and_axpby_closed_forms(op):
+    n, F, K = 2048, 32, 4
+    got = C.count(dict(family="arith", op=op, dtype="f32", n=n, wg=256, F=F, K=K))
+    assert got["mul.f32"] == n * F and got.get(op + ".f32") == n * F
+    assert got["add.f32"] == (n * F if op == "div" else 0) + n * (K - 1)
+    got = C.count(dict(family="stream", op="axpby", dtype="f64", n=n, wg=256, s=3,
+                       gs=1, vec=1, U=1))
+    assert got == {"gld.8.1/3": 2 * n, "gst.8.1/3": n, "mul.f64": 2 * n,
+                   "add.f64": n, "wg": n // 256, "wi": n}
+
+
+def test_div_chain_reference_exact_steps():
+    """One division-chain step is (k+1) / (a*a + 1), each operation
+    rounded once in float32: compare with rationals."""
+    x = np.random.default_rng(8).uniform(-1, 1, 32).astype(np.float32)
+    out = O.div_chain({"F": 1, "K": 1}, x)
+    for i in range(32):
+        sq = _round_f32(Fraction(float(x[i])) ** 2)
+        den = _round_f32(Fraction(float(sq)) + 1)
+        assert out[i] == _round_f32(Fraction(1) / Fraction(float(den)))
+
+
+def test_conv_reference_single_tap():
+    """With one non-zero filter tap (u, v, c) the convolution is a shifted
+    copy of one image channel."""
+    n = 5
+    img = np.random.default_rng(9).uniform(-1, 1, 9 * (n + 6) ** 2).astype(np.float32)
+    filt = np.zeros(3 * 147, dtype=np.float32)
+    filt[1 * 147 + (2 * 7 + 4) * 3 + 1] = 2.0  # filter j=1, u=2, v=4, c=1
+    r, _ = O.conv(img, filt, n)
+    I = img.reshape(3, n + 6, n + 6, 3).astype(np.float64)
+    np.testing.assert_array_equal(r[:, 1], 2.0 * I[:, 4:4 + n, 2:2 + n, 1])
+    assert not r[:, 0].any() and not r[:, 2].any()
+
+
 def test_counts_additive_over_a_domain_split():
     """Counts add when the launch is split: two half-size stream launches of
     a unit-stride kernel give the counts of the whole (Alg. 1 is a sum over
