@@ -94,7 +94,15 @@ def model_phase(ctx, P, proj_list=("p12", "full")):
                   ("finite_difference", "skinny_mm", "nbody", "convolution")]
         gm = float(math.exp(np.mean(np.log(np.maximum(err, 1e-12)))))
         fit_err = float(math.exp(np.mean(np.log(np.maximum(np.abs(resid), 1e-12)))))
+        table = {}
+        for i, v in enumerate(test):
+            if v["kernel"] in ("finite_difference", "skinny_mm", "nbody", "convolution") \
+                    and v.get("dtype", "f32") == "f32":
+                size = v["m"] if v["kernel"] == "skinny_mm" else v["n"]
+                table.setdefault(v["kernel"], []).append(
+                    [size, round(Tt[i] * 1e3, 4), round(float(pred[i]) * 1e3, 4)])
         out[proj] = {"geomean": round(gm, 4), "per_kernel": fam,
+                     "table1_ms_actual_predicted": table,
                      "geomean_paper_test_kernels": round(float(math.exp(np.mean(np.log(
                          np.maximum(paper4, 1e-12))))), 4), "rank": rank,
                      "cond": float("%.3g" % cond), "fit_geomean": round(fit_err, 4)}

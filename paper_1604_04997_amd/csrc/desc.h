@@ -748,8 +748,13 @@ PM_HD int fuse(int nv, int64_t *ext, int nf, int64_t (*f)[MAXVAR + 1],
                 if (a == bb) continue;
                 bool ok = true;
                 for (int q = 0; q < nf && ok; q++) {
+                    const int64_t ca = f[q][a], cb = f[q][bb];
+                    if (!ca) {  // then b must be absent too (ext >= 1)
+                        ok = cb == 0;
+                        continue;
+                    }
                     int64_t want;
-                    if (mul_ovf(f[q][a], ext[a], &want) || f[q][bb] != want) ok = false;
+                    if (!cb || mul_ovf(ca, ext[a], &want) || cb != want) ok = false;
                 }
                 if (!ok) continue;
                 int64_t e2;
