@@ -54,6 +54,81 @@ def domain_points(v):
     return v.get("n", 0)
 
 
+# Issue peak of plain vector ALU work: 256 CUs x 4 SIMDs x 16 lanes per
+# clock at 2.4 GHz = 3.93e13 lane operations/s (a wave64 instruction takes
+# four clocks on a 16-lane SIMD).
+ALU_PEAK = 256 * 4 * 16 * 2.4e9
+KERNEL_SOURCES = ("include/pm.h", "paper_1604_04997_amd/csrc/desc.h",
+                  "paper_1604_04997_amd/csrc/counter.h",
+                  "paper_1604_04997_amd/csrc/counter.hip")
+PMC_SUMMARY = "profiles/counter_batched4096_pmc.txt"
+COPY_BYTES = 2 * (1 << 26) * 4  # the calibration copy: 2^26 fp32 read + written
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_pmc():
+    """Per-dispatch hardware counters of the counter kernels on the batched
+    workload, from the committed rocprofv3 summary, or None when the kernel
+    sources have changed since it was taken."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    rows, h = {}, None
+    for line in open(path):
+        if line.startswith("# kernel sources sha256/16:"):
+            h = line.split(":")[1].strip()
+        if line.startswith("#") or not line.strip():
+            continue
+        name, rest = line.split(" grid=", 1)
+        kv = dict(x.split("=") for x in ("grid=" + rest).split())
+        kv = {k: float(x) for k, x in kv.items()}
+        name = name.split("::")[-1].split("<")[0]
+        if name not in rows or kv["grid"] > rows[name]["grid"]:
+            rows[name] = kv
+    if h != source_hash():
+        return None
+    return rows
+
+
+def counter_roofline(phase, ms, nv):
+    """Roofline of the dominant counter kernel.  Its work is integer
+    bookkeeping (descriptor expansion, interval arithmetic), bounded by the
+    vector ALU: achieved = VALU lane operations per launch (the rocprofv3
+    SQ_INSTS_VALU count per dispatch x 64 lanes) / the launch's live HIP-event
+    duration.  traffic = FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
+    by what it reads for a copy of known size."""
+    kern = "k_" + phase
+    roof = {"kernel": kern, "bound": "alu", "achieved": None, "peak": round(ALU_PEAK / 1e12, 2),
+            "unit": "TOP/s (int lane-ops)", "frac": None, "traffic": None,
+            "launch_ms": round(ms, 4), "variants_per_launch": nv}
+    pmc = read_pmc()
+    if not pmc or kern not in pmc:
+        roof["note"] = "no counter summary for the current kernel sources"
+        return roof
+    r = pmc[kern]
+    ops = r["SQ_INSTS_VALU"] * 64
+    ach = ops / (ms * 1e-3)
+    roof.update({"achieved": round(ach / 1e12, 3), "frac": round(ach / ALU_PEAK, 4),
+                 "valu_lane_ops_per_launch": ops,
+                 "valu_instr_per_variant": round(r["SQ_INSTS_VALU"] / nv, 1)})
+    cal = pmc.get("k_stream")
+    if cal and "FETCH_SIZE" in r and "WRITE_SIZE" in r:
+        fs = (COPY_BYTES / 2) / (cal["FETCH_SIZE"] * 1024)
+        ws = (COPY_BYTES / 2) / (cal["WRITE_SIZE"] * 1024)
+        roof["traffic"] = round((r["FETCH_SIZE"] * fs + r["WRITE_SIZE"] * ws) * 1024)
+        roof["traffic_scale"] = {"fetch": round(fs, 3), "write": round(ws, 3)}
+    return roof
+
+
+
 def measure_suite(ctx, P, variants, warmup=4, reps=26):
     import torch
     T = []
@@ -209,7 +284,8 @@ def main():
     if not args.skip_model:
         model_info, models, _ = model_phase(ctx, P)
         log("model:", json.dumps(model_info))
-    m = models.get("p12") or P.model_struct("p12", [1e-12] * 12)
+    # the paper's own property list (Sec. 2) drives prediction
+    m = models.get("full") or P.model_struct("full", [1e-12] * 154)
 
     # ------------------------------------------------------ batched step --
     vs = suite_batched(4096)
@@ -290,7 +366,7 @@ def main():
                 if k >= args.autotune_problems:
                     break
         log("autotune: %d problems, every configuration measured" % len(probs))
-        res = autotune.rank_and_measure(ctx, models["p12"], probs, measure_all=True)
+        res = autotune.rank_and_measure(ctx, m, probs, measure_all=True)
         tune = autotune.summary(res)
         tune["per_family"] = {}
         for fam in ("matmul", "stencil", "transpose"):
@@ -319,21 +395,9 @@ def main():
         log("serving:", json.dumps(serving))
 
     # ---------------------------------------------------------- roofline --
-    # the dominant kernel and its algorithmic bytes: clear writes the used
-    # bitmap words, fill reads F and B words of every strided array, count
-    # ORs footprint words (read-modify-write)
-    words = stats["bitmap_words"]
     dom = max(phase_ms, key=phase_ms.get)
-    alg_bytes = {"clear": 8 * words, "fill": 8 * words, "count": 16 * words}.get(dom) if words else None
-    roof = None
-    if alg_bytes:
-        ach = alg_bytes / (phase_ms[dom] * 1e-3)
-        roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(ach / 1e9, 2),
-                "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(ach / HBM_PEAK, 4),
-                "traffic": None, "alg_bytes_per_launch": alg_bytes}
-    else:
-        roof = {"kernel": "k_" + dom, "bound": "alu", "achieved": None, "peak": None,
-                "unit": None, "frac": None, "traffic": None}
+    roof = counter_roofline(dom, phase_ms[dom], nv)
+    log("roofline:", json.dumps(roof))
 
     # ------------------------------------------------- suite rooflines --
     suite_roof = None
@@ -356,7 +420,7 @@ def main():
         "config": {"workload": "batched autotune sweep: 4096 matmul/stencil/transpose "
                                "variants, main domains 2^16..2^30 points, counted + "
                                "predicted in one pass", "variants": nv,
-                   "domain_points": points, "model": "p12"},
+                   "domain_points": points, "model": "full (the paper's property list)"},
         "points_per_s": float("%.4g" % (points * value / nv)),
         "plain_variants_per_s": round(plain, 1), "plain_us_per_call": round(t_call * 1e6, 2),
         "batched_over_plain": round(value / plain, 2),

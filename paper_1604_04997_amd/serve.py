@@ -18,7 +18,8 @@ every step:
      timed runs (pm_launch bracketed by events) on the measure stream, so
      they overlap with the count batches.
 
-Latency of a request = time its result is on the host - its arrival time.
+Latency of a request = time its result is on the host - its arrival time
+(with realtime=False every request arrives at the start).
 `run_plain` processes the same trace one request at a time, synchronously.
 """
 from __future__ import annotations
@@ -118,6 +119,8 @@ class Server:
             # 1. arrivals
             while arrivals and (not realtime or arrivals[0][1][0] <= now):
                 rid, (ta, kind, v) = arrivals.popleft()
+                if not realtime:  # every request is queued at the start
+                    ta = 0.0
                 (wait_p if kind == "predict" else wait_m).append((rid, v, ta))
             # 2. retire finished batches (in stream order) and measures
             while batches and batches[0][0].query():
@@ -198,6 +201,8 @@ def run_plain(ctx: Context, model: Model, trace, realtime: bool = True,
         if realtime:
             while time.perf_counter() - t0 < ta:
                 pass
+        else:  # every request is queued at the start
+            ta = 0.0
         if kind == "predict":
             p = float(ctx.predict(model, [v])[0])
             rec.append({"id": rid, "kind": kind, "arrival": ta,
