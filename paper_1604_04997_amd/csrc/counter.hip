@@ -17,7 +17,7 @@
 //               the bitmaps
 //   k_fill      per array segment: |F| and |Fill| (F with every strided
 //               cell widened to its run of stride*vec cells)
-//   k_finalize  one thread per variant: count vector and prediction
+//   k_finalize  one wavefront per variant: count vector and prediction
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -72,6 +72,55 @@ __device__ int64_t block_sum(int64_t x, int64_t *red) {
     return t;
 }
 
+// Count vector and prediction of one variant by one work-group: every
+// thread calls this, the first wavefront does the work.  Lanes gather the
+// statement counts and the non-zero contributions (compacted by ballot),
+// then each lane owns the count slots k = lane (mod 64) and the features
+// i = lane (mod 64); the prediction's 64 partial sums meet in a butterfly,
+// the order predict() fixes.  st != PM_OK: zero counts, prediction 0.
+struct FinShared {
+    int64_t c[PM_NCOUNT];
+    int64_t sc[MAXSTMT];
+    Contrib list[MAXSTMT * NENT];
+    int bad;
+};
+
+__device__ int finalize_block(const Prog &p, const int64_t *jobres, const int64_t *F,
+                              const int64_t *Fill, int st, FinShared &sh, pm_counts *out,
+                              const pm_model &model, int has_model, double *pred) {
+    const int t = threadIdx.x, l = t & 63;
+    const bool w0 = t < 64;
+    const int nst = st == PM_OK ? p.nstmt : 0;
+    if (t == 0) sh.bad = 0;
+    __syncthreads();
+    if (w0 && l < nst && !stmt_count(p, l, jobres, &sh.sc[l])) sh.bad = 1;
+    int n = 0;
+    for (int e0 = 0; e0 < nst * NENT; e0 += 64) {
+        Contrib cc;
+        const int e = e0 + l;
+        const bool has = w0 && e < nst * NENT && contrib(p, e / NENT, e % NENT, F, Fill, &cc);
+        const uint64_t mask = __ballot(has);
+        if (has) sh.list[n + __popcll(mask & ((1ull << l) - 1))] = cc;
+        n += __popcll(mask);
+    }
+    __syncthreads();
+    if (w0 && st == PM_OK)
+        for (int k = l; k < PM_NCOUNT; k += 64)
+            if (k != C_BARWG && !slot_value(p, k, sh.list, n, sh.sc, &sh.c[k])) sh.bad = 1;
+    __syncthreads();
+    if (t == 0 && st == PM_OK) sh.c[C_BARWG] = p.wg_size ? sh.c[C_BARWI] / p.wg_size : 0;
+    __syncthreads();
+    const int st2 = st == PM_OK && sh.bad ? PM_EOVERFLOW : st;
+    if (out)
+        for (int k = t; k < PM_NCOUNT; k += blockDim.x) out->c[k] = st2 == PM_OK ? sh.c[k] : 0;
+    if (w0 && has_model && pred) {
+        double part = st2 == PM_OK ? predict_partial(sh.c, model, l) : 0.0;
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if (t == 0) *pred = st2 == PM_OK ? part : 0.0;
+    }
+    return st2;
+}
+
 __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
@@ -80,9 +129,9 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     __shared__ Prog P;
     __shared__ Job J[MAXJOB];
     __shared__ int64_t jr[MAXJOB];
-    __shared__ int64_t fs[MAXARR][2];
-    __shared__ int64_t cnt[PM_NCOUNT];
+    __shared__ int64_t fF[MAXARR], fFill[MAXARR];
     __shared__ int64_t red[FUSED_THREADS / 64];
+    __shared__ FinShared fin;
     __shared__ int st_sh;
     const int i = blockIdx.x;
     const int t = threadIdx.x;
@@ -96,7 +145,7 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         st_sh = st;
     }
     if (t < MAXJOB) jr[t] = 0;
-    if (t < 2 * MAXARR) fs[t / 2][t % 2] = 0;
+    if (t < MAXARR) fF[t] = fFill[t] = 0;
     __syncthreads();
     const int st = st_sh;
     if (t == 0) {
@@ -128,24 +177,9 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         }
         __syncthreads();
     }
-    if (t == 0) {
-        int64_t F[MAXARR], Fill[MAXARR];
-        for (int a = 0; a < MAXARR; a++) {
-            F[a] = fs[a][0];
-            Fill[a] = fs[a][1];
-        }
-        int s2 = st;
-        if (st == PM_OK) s2 = finalize(P, jr, F, Fill, cnt);
-        else
-            for (int k = 0; k < PM_NCOUNT; k++) cnt[k] = 0;
-        if (s2 != PM_OK)
-            for (int k = 0; k < PM_NCOUNT; k++) cnt[k] = 0;
-        status[i] = s2;
-        if (has_model && pred) pred[i] = s2 == PM_OK ? predict(cnt, model) : 0.0;
-    }
-    __syncthreads();
-    if (counts)
-        for (int k = t; k < PM_NCOUNT; k += FUSED_THREADS) counts[i].c[k] = cnt[k];
+    const int s2 = finalize_block(P, jr, fF, fFill, st, fin, counts ? &counts[i] : nullptr,
+                                  model, has_model, pred ? &pred[i] : nullptr);
+    if (t == 0) status[i] = s2;
 }
 
 // Block-wide inclusive scan of per-thread int64 values (SCAN_THREADS).
@@ -375,29 +409,26 @@ k_fill(int nv, const Prog *prog, const int64_t *varsegs, const int64_t *varoff,
     }
 }
 
-__global__ void k_finalize(int nv, const Prog *prog, const int64_t *jobres,
-                           const int64_t *foot, int32_t *status,
-                           pm_counts *counts, pm_model model, int has_model,
-                           double *pred) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(64)
+k_finalize(int nv, const Prog *prog, const int64_t *jobres, const int64_t *foot,
+           int32_t *status, pm_counts *counts, pm_model model, int has_model,
+           double *pred) {
+    __shared__ FinShared fin;
+    __shared__ int64_t F[MAXARR], Fill[MAXARR];
+    const int i = blockIdx.x, t = threadIdx.x;
     if (i >= nv) return;
-    int64_t c[PM_NCOUNT];
-    int64_t F[MAXARR], Fill[MAXARR];
-    for (int a = 0; a < MAXARR; a++) {
-        F[a] = foot[((int64_t)i * MAXARR + a) * 2];
-        Fill[a] = foot[((int64_t)i * MAXARR + a) * 2 + 1];
-    }
-    int st = status[i];
+    const int st = status[i];
     if (st == PM_OK) return;  // finished in k_fused
-    if (st == PM_DEFER) {
-        st = finalize(prog[i], jobres + (int64_t)i * MAXJOB, F, Fill, c);
-        status[i] = st;
+    if (t < MAXARR) {
+        F[t] = foot[((int64_t)i * MAXARR + t) * 2];
+        Fill[t] = foot[((int64_t)i * MAXARR + t) * 2 + 1];
     }
-    if (st != PM_OK)
-        for (int k = 0; k < PM_NCOUNT; k++) c[k] = 0;
-    if (counts)
-        for (int k = 0; k < PM_NCOUNT; k++) counts[i].c[k] = c[k];
-    if (has_model && pred) pred[i] = st == PM_OK ? predict(c, model) : 0.0;
+    __syncthreads();
+    const int s2 = finalize_block(prog[i], jobres + (int64_t)i * MAXJOB, F, Fill,
+                                  st == PM_DEFER ? PM_OK : st, fin,
+                                  counts ? &counts[i] : nullptr, model, has_model,
+                                  pred ? &pred[i] : nullptr);
+    if (t == 0 && st == PM_DEFER) status[i] = s2;
 }
 
 // ---------------------------------------------------------------- host ---
@@ -416,7 +447,6 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
                  int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev) {
     if (nv <= 0) return PM_OK;
     const int build_lanes = build_lanes_setting();
-    int tb = 64;
     int q = 0;
     auto mark = [&]() {
         if (ev) (void)hipEventRecord(ev[q++], s);
@@ -454,7 +484,7 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
                        (const int64_t *)ar.varoff, (const uint64_t *)ar.bitmap,
                        ar.foot, (const int64_t *)ar.meta);
     mark();
-    hipLaunchKernelGGL(k_finalize, dim3((nv + tb - 1) / tb), dim3(tb), 0, s, nv,
+    hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(64), 0, s, nv,
                        (const Prog *)ar.prog, (const int64_t *)ar.jobres,
                        (const int64_t *)ar.foot, d_status, d_counts, m, has, d_pred);
     mark();

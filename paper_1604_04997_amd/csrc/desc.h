@@ -1320,43 +1320,107 @@ PM_HD int class_index(int64_t s, int64_t F, int64_t Fill) {
     return base + (int)(k - 1);
 }
 
+// The count vector is assembled from a list of contributions: statement
+// `stmt` adds mult x (its number of executions) to slot `slot`.  Each
+// statement has NENT candidate entries -- its global accesses, LDS accesses
+// by direction and size, flops by kind and dtype, barriers -- of which only
+// the non-zero ones enter the list.  The same helpers serve the host loop
+// (finalize) and the 64-lane version on the device.
+constexpr int NENT = MAXACC + 6 + 12 + 1;
+struct Contrib {
+    int16_t slot, stmt;
+    int32_t mult;
+};
+
+// Executions of statement si: its free extents and closed-form components
+// (s.fixed) times the counts of its enumerated components.  False on
+// overflow.
+PM_HD bool stmt_count(const Prog &p, int si, const int64_t *jobres, int64_t *out) {
+    const Stmt &s = p.st[si];
+    int64_t cnt = s.fixed;
+    bool ok = true;
+    for (int q = 0; q < s.ncomp; q++)
+        if (mul_ovf(cnt, jobres[s.comp_job[q]], &cnt)) ok = false;
+    *out = cnt;
+    return ok;
+}
+
+// Entry e (0 <= e < NENT) of statement si: true with *c set when present.
+// A global access's slot follows from its size, direction and stride class
+// (Sec. 2, classes from Alg. 2's footprints F and Fill of its array).
+PM_HD bool contrib(const Prog &p, int si, int e, const int64_t *F, const int64_t *Fill,
+                   Contrib *c) {
+    const Stmt &s = p.st[si];
+    c->stmt = (int16_t)si;
+    if (e < MAXACC) {
+        if (e >= s.nacc) return false;
+        const GAcc &a = s.acc[e];
+        const int64_t st = lane_stride(s, a);
+        const int z = size_index(a.elem * a.vec);
+        const int cl = class_index(st, F[a.arr] + p.arr[a.arr].fixF,
+                                   Fill[a.arr] + p.arr[a.arr].fixFill);
+        c->slot = (int16_t)(C_GACC + (a.dir * 3 + z) * NCLS + cl);
+        c->mult = 1;
+        return true;
+    }
+    e -= MAXACC;
+    if (e < 6) {
+        c->slot = (int16_t)(C_LDS + e);
+        c->mult = s.lds[e / 3][e % 3];
+    } else if (e < 18) {
+        e -= 6;
+        c->slot = (int16_t)(C_FLOP + e);
+        c->mult = s.flop[e / 2][e % 2];
+    } else {
+        c->slot = (int16_t)C_BARWI;
+        c->mult = s.bar;
+    }
+    return c->mult != 0;
+}
+
+// Value of count slot k from the contribution list; false on overflow.
+// Slots without entries are 0; C_WG / C_WI come from the launch shape and
+// C_BARWG from C_BARWI (set by the caller).
+PM_HD bool slot_value(const Prog &p, int k, const Contrib *list, int n, const int64_t *sc,
+                      int64_t *out) {
+    if (k == C_WG) {
+        *out = p.n_wg;
+        return true;
+    }
+    if (k == C_WI) return !mul_ovf(p.n_wg, (int64_t)p.wg_size, out);
+    int64_t v = 0, t;
+    bool ok = true;
+    for (int i = 0; i < n; i++) {
+        if (list[i].slot != k) continue;
+        if (mul_ovf(sc[list[i].stmt], (int64_t)list[i].mult, &t) || add_ovf(v, t, &v)) ok = false;
+    }
+    *out = v;
+    return ok;
+}
+
 // Assemble the count vector from statement counts (component job results
 // `jobres`) and per-array footprint sizes F/Fill.  Returns a status.
 PM_HD int finalize(const Prog &p, const int64_t *jobres, const int64_t *F,
                    const int64_t *Fill, int64_t *c) {
     for (int i = 0; i < PM_NCOUNT; i++) c[i] = 0;
     if (p.status != PM_OK) return p.status;
-    bool ovf = false;
-    auto addm = [&](int slot, int64_t cnt, int64_t mult) {
-        int64_t t;
-        if (mul_ovf(cnt, mult, &t) || add_ovf(c[slot], t, &c[slot])) ovf = true;
-    };
+    bool ok = true;
+    int64_t sc[MAXSTMT];
+    Contrib list[MAXSTMT * NENT];
+    int n = 0;
     for (int si = 0; si < p.nstmt; si++) {
-        const Stmt &s = p.st[si];
-        int64_t cnt = s.fixed;
-        for (int q = 0; q < s.ncomp; q++)
-            if (mul_ovf(cnt, jobres[s.comp_job[q]], &cnt)) ovf = true;
-        if (cnt == 0) continue;
-        for (int q = 0; q < s.nacc; q++) {
-            const GAcc &a = s.acc[q];
-            int64_t st = lane_stride(s, a);
-            int z = size_index(a.elem * a.vec);
-            int cl = class_index(st, F[a.arr] + p.arr[a.arr].fixF,
-                                 Fill[a.arr] + p.arr[a.arr].fixFill);
-            addm(C_GACC + (a.dir * 3 + z) * NCLS + cl, cnt, 1);
-        }
-        for (int d = 0; d < 2; d++)
-            for (int z = 0; z < 3; z++)
-                if (s.lds[d][z]) addm(C_LDS + d * 3 + z, cnt, s.lds[d][z]);
-        for (int k = 0; k < 6; k++)
-            for (int d = 0; d < 2; d++)
-                if (s.flop[k][d]) addm(C_FLOP + k * 2 + d, cnt, s.flop[k][d]);
-        if (s.bar) addm(C_BARWI, cnt, s.bar);
+        if (!stmt_count(p, si, jobres, &sc[si])) ok = false;
+        for (int e = 0; e < NENT; e++)
+            if (contrib(p, si, e, F, Fill, &list[n])) n++;
     }
-    c[C_WG] = p.n_wg;
-    if (mul_ovf(p.n_wg, (int64_t)p.wg_size, &c[C_WI])) ovf = true;
+    for (int k = 0; k < PM_NCOUNT; k++)
+        if (k != C_BARWG && !slot_value(p, k, list, n, sc, &c[k])) ok = false;
     c[C_BARWG] = p.wg_size ? c[C_BARWI] / p.wg_size : 0;
-    return ovf ? PM_EOVERFLOW : PM_OK;
+    if (!ok) {
+        for (int i = 0; i < PM_NCOUNT; i++) c[i] = 0;
+        return PM_EOVERFLOW;
+    }
+    return PM_OK;
 }
 
 // ------------------------------------------------------------- features ---
@@ -1368,83 +1432,108 @@ PM_HD bool full_use_class(int cl) {  // '0', '1', '2/2', '3/3', '4/4'
     return cl == 0 || cl == 1 || cl == 3 || cl == 6 || cl == 10;
 }
 
-PM_HD int features(const int64_t *c, uint32_t proj, double *f) {
-    const int SZ[3] = {4, 8, 16};
+// Feature j of projection `proj` from count vector c.
+PM_HD double feature_one(const int64_t *c, uint32_t proj, int j) {
+    const double SZ[3] = {4, 8, 16};
     if (proj == PM_PROJ_P3) {
-        double gb = 0;
-        for (int d = 0; d < 2; d++)
-            for (int z = 0; z < 3; z++)
-                for (int cl = 0; cl < NCLS; cl++)
-                    gb += (double)SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + cl];
-        f[0] = gb;
-        f[1] = (double)c[C_FLOP + K_FMA * 2 + 0];
-        f[2] = (double)c[C_WG];
-        return 3;
+        if (j == 0) {  // global bytes, every class and direction
+            double gb = 0;
+            for (int d = 0; d < 2; d++)
+                for (int z = 0; z < 3; z++)
+                    for (int cl = 0; cl < NCLS; cl++)
+                        gb += SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + cl];
+            return gb;
+        }
+        return j == 1 ? (double)c[C_FLOP + K_FMA * 2 + 0] : (double)c[C_WG];
     }
     if (proj == PM_PROJ_P12) {
-        double full[2] = {0, 0}, part[2] = {0, 0}, s1[2] = {0, 0};
-        for (int d = 0; d < 2; d++)
+        switch (j) {
+        case 0: return 1.0;
+        case 1: return (double)c[C_WG];
+        case 2: return (double)c[C_BARWI];
+        case 3:
+        case 4: {
+            const int d = j - 3;
+            return (double)c[C_FLOP + K_ADD * 2 + d] + (double)c[C_FLOP + K_MUL * 2 + d] +
+                   2.0 * (double)c[C_FLOP + K_FMA * 2 + d];
+        }
+        case 5: {
+            double sp = 0;
+            for (int d = 0; d < 2; d++)
+                sp += (double)c[C_FLOP + K_SPEC * 2 + d] + (double)c[C_FLOP + K_DIV * 2 + d] +
+                      (double)c[C_FLOP + K_EXP * 2 + d];
+            return sp;
+        }
+        case 6: {
+            double ldsb = 0;
+            for (int d = 0; d < 2; d++)
+                for (int z = 0; z < 3; z++) ldsb += SZ[z] * (double)c[C_LDS + d * 3 + z];
+            return ldsb;
+        }
+        case 7: case 8: case 9: case 10: {  // full-use / partial-use bytes per direction
+            const int d = (j - 7) & 1;
+            const bool want_full = j < 9;
+            double x = 0;
             for (int z = 0; z < 3; z++)
-                for (int cl = 0; cl < NCLS; cl++) {
-                    double bytes = (double)SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + cl];
-                    if (full_use_class(cl)) full[d] += bytes;
-                    else part[d] += bytes;
-                    if (cl == 1) s1[d] += bytes;
-                }
-        double ldsb = 0;
-        for (int d = 0; d < 2; d++)
-            for (int z = 0; z < 3; z++) ldsb += (double)SZ[z] * (double)c[C_LDS + d * 3 + z];
-        f[0] = 1.0;
-        f[1] = (double)c[C_WG];
-        f[2] = (double)c[C_BARWI];
-        f[3] = (double)c[C_FLOP + K_ADD * 2] + (double)c[C_FLOP + K_MUL * 2] +
-               2.0 * (double)c[C_FLOP + K_FMA * 2];
-        f[4] = (double)c[C_FLOP + K_ADD * 2 + 1] + (double)c[C_FLOP + K_MUL * 2 + 1] +
-               2.0 * (double)c[C_FLOP + K_FMA * 2 + 1];
-        double sp = 0;
-        for (int d = 0; d < 2; d++)
-            sp += (double)c[C_FLOP + K_SPEC * 2 + d] + (double)c[C_FLOP + K_DIV * 2 + d] +
-                  (double)c[C_FLOP + K_EXP * 2 + d];
-        f[5] = sp;
-        f[6] = ldsb;
-        f[7] = full[0];
-        f[8] = full[1];
-        f[9] = part[0];
-        f[10] = part[1];
-        f[11] = s1[0] < s1[1] ? s1[0] : s1[1];
-        return 12;
+                for (int cl = 0; cl < NCLS; cl++)
+                    if (full_use_class(cl) == want_full)
+                        x += SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + cl];
+            return x;
+        }
+        default: {  // min(unit-stride load bytes, unit-stride store bytes)
+            double s1[2] = {0, 0};
+            for (int d = 0; d < 2; d++)
+                for (int z = 0; z < 3; z++) s1[d] += SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + 1];
+            return s1[0] < s1[1] ? s1[0] : s1[1];
+        }
+        }
     }
-    if (proj == PM_PROJ_FULL) {
-        int t = 0;
-        for (int i = 0; i < 90; i++) f[t++] = (double)c[C_GACC + i];
-        for (int i = 0; i < 6; i++) f[t++] = (double)c[C_LDS + i];
-        for (int k = 0; k < 5; k++)
-            for (int d = 0; d < 2; d++) {
-                double x = (double)c[C_FLOP + k * 2 + d];
-                if (k == K_ADD || k == K_MUL) x += (double)c[C_FLOP + K_FMA * 2 + d];
-                f[t++] = x;
-            }
-        f[t++] = (double)c[C_BARWI];
-        f[t++] = (double)c[C_WG];
-        f[t++] = 1.0;
-        for (int z = 0; z < 3; z++)
-            for (int cl = 0; cl < NCLS; cl++) {
-                int64_t ld = c[C_GACC + (0 * 3 + z) * NCLS + cl];
-                int64_t st = c[C_GACC + (1 * 3 + z) * NCLS + cl];
-                f[t++] = (double)(ld < st ? ld : st);
-            }
-        return t;
+    // PM_PROJ_FULL: every global class, LDS, flops (an FMA counts as one add
+    // and one mul), barriers, work-groups, a constant, min(load, store) per
+    // size and class
+    if (j < 90) return (double)c[C_GACC + j];
+    if (j < 96) return (double)c[C_LDS + j - 90];
+    if (j < 106) {
+        const int k = (j - 96) / 2, d = (j - 96) % 2;
+        double x = (double)c[C_FLOP + k * 2 + d];
+        if (k == K_ADD || k == K_MUL) x += (double)c[C_FLOP + K_FMA * 2 + d];
+        return x;
     }
-    return -1;
+    if (j == 106) return (double)c[C_BARWI];
+    if (j == 107) return (double)c[C_WG];
+    if (j == 108) return 1.0;
+    const int z = (j - 109) / NCLS, cl = (j - 109) % NCLS;
+    const int64_t ld = c[C_GACC + (0 * 3 + z) * NCLS + cl];
+    const int64_t st = c[C_GACC + (1 * 3 + z) * NCLS + cl];
+    return (double)(ld < st ? ld : st);
 }
 
-// T = sum_i alpha_i f_i, accumulated in feature order.
-PM_HD double predict(const int64_t *c, const pm_model &m) {
-    double f[PM_NFEAT_MAX];
-    int nf = features(c, m.proj, f);
+PM_HD int features(const int64_t *c, uint32_t proj, double *f) {
+    const int n = nfeat(proj);
+    for (int j = 0; j < n; j++) f[j] = feature_one(c, proj, j);
+    return n;
+}
+
+// T = sum_i alpha_i f_i.  The summation order is fixed so that every device
+// path gives the same bits: 64 partial sums, partial l over features
+// i = l, l+64, ... in increasing order, then combined pairwise at distances
+// 32, 16, ..., 1 (the order of a 64-lane butterfly reduction).
+PM_HD double predict_partial(const int64_t *c, const pm_model &m, int lane) {
+    const int nf = nfeat(m.proj) < (int)m.nfeat ? nfeat(m.proj) : (int)m.nfeat;
     double t = 0.0;
-    for (int i = 0; i < nf && i < (int)m.nfeat; i++) t += m.alpha[i] * f[i];
+    for (int i = lane; i < nf; i += 64) t += m.alpha[i] * feature_one(c, m.proj, i);
     return t;
+}
+
+PM_HD double predict(const int64_t *c, const pm_model &m) {
+    double part[64];
+    for (int l = 0; l < 64; l++) part[l] = predict_partial(c, m, l);
+    for (int off = 32; off > 0; off >>= 1) {
+        double nxt[64];
+        for (int l = 0; l < 64; l++) nxt[l] = part[l] + part[l ^ off];
+        for (int l = 0; l < 64; l++) part[l] = nxt[l];
+    }
+    return part[0];
 }
 
 }  // namespace pm
