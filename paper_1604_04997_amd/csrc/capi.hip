@@ -124,6 +124,7 @@ void free_arena(pm_ctx *c) {
     (void)hipFree(a.jobres);
     (void)hipFree(a.foot);
     (void)hipFree(a.meta);
+    (void)hipFree(a.order);
     (void)hipFree(c->d_var);
     (void)hipFree(c->d_counts);
     (void)hipFree(c->d_pred);
@@ -169,6 +170,7 @@ int grow_cap(pm_ctx *c, size_t nv) {
     HIPCHK(hipMalloc(&a.jobres, 8 * cap * pm::MAXJOB));
     HIPCHK(hipMalloc(&a.foot, 16 * cap * pm::MAXARR));
     HIPCHK(hipMalloc(&a.meta, 64));
+    HIPCHK(hipMalloc(&a.order, sizeof(int32_t) * cap));
     HIPCHK(hipMalloc(&c->d_var, sizeof(pm_variant) * cap));
     HIPCHK(hipMalloc(&c->d_counts, sizeof(pm_counts) * cap));
     HIPCHK(hipMalloc(&c->d_pred, sizeof(double) * cap));

@@ -25,6 +25,7 @@ struct Arena {
     int64_t *foot = nullptr;     // [cap * MAXARR * 2]
     int64_t *meta = nullptr;     // [8]: chunks, words used, fill segments, ticket, words requested
     uint64_t *bitmap = nullptr;  // [bitmap_words]
+    int32_t *order = nullptr;    // [cap]: build order (variants grouped by kind)
 };
 
 size_t arena_bytes_per_variant();

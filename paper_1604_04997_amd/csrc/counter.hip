@@ -20,6 +20,7 @@
 //   k_finalize  one wavefront per variant: count vector and prediction
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdlib>
 #include <vector>
 
@@ -36,29 +37,83 @@ constexpr int FUSED_THREADS = 256;
 constexpr int64_t FUSED_MAX_ITEMS = 1 << 20;
 constexpr int PM_DEFER = 1;  // internal status: finish in the general pipeline
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
-constexpr int BUILD_LANES = 16;        // variants built per wavefront in k_build
+constexpr int BUILD_LANES = 4;         // variants built per wavefront in k_build
 
-// One thread per variant (BUILD_LANES active lanes per wavefront): the
-// descriptor and jobs go to HBM and every valid variant continues in the
+// Batch order for k_build: variants grouped by (family, op), so that the
+// lanes of a wavefront expand alike descriptors.  One work-group; the order
+// within a group is immaterial (every result is indexed by variant).
+constexpr int ORDER_THREADS = 1024;
+constexpr int ORDER_KEYS = 16 * 8;
+__device__ inline int order_key(const pm_variant &v) {
+    const int f = v.family < 15 ? (int)v.family : 15, o = v.op < 7 ? (int)v.op : 7;
+    return f * 8 + o;
+}
+
+__global__ void __launch_bounds__(ORDER_THREADS)
+k_order(int nv, const pm_variant *__restrict__ var, int32_t *order) {
+    __shared__ int cnt[ORDER_KEYS];
+    const int t = threadIdx.x;
+    if (t < ORDER_KEYS) cnt[t] = 0;
+    __syncthreads();
+    for (int i = t; i < nv; i += ORDER_THREADS) atomicAdd(&cnt[order_key(var[i])], 1);
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int k = 0; k < ORDER_KEYS; k++) {
+            const int c = cnt[k];
+            cnt[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < nv; i += ORDER_THREADS) order[atomicAdd(&cnt[order_key(var[i])], 1)] = i;
+}
+
+// `lanes` variants per 64-wide work-group (one wavefront), one per lane,
+// each expanded in LDS (its Prog and the job being assembled) and copied to
+// HBM by the whole wavefront.  Every valid variant continues in the
 // general pipeline.
 __global__ void __launch_bounds__(64)
-k_build(int nv, int lanes, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
-        int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
-        int64_t *jobres, int64_t *foot) {
-    if ((int)threadIdx.x >= lanes) return;
-    const int64_t i = (int64_t)blockIdx.x * lanes + threadIdx.x;
-    if (i >= nv) return;
-    pm_variant v = var[i];
-    Prog *p = &prog[i];
-    int st = build_prog(v, p, &jobs[i * MAXJOB]);
-    if (st == PM_OK) st = PM_DEFER;
-    status[i] = st;
-    varwords[i] = st == PM_DEFER ? p->bitmap_words : 0;
-    varchunks[i] = st == PM_DEFER ? p->chunks : 0;
-    varsegs[i] = st == PM_DEFER ? p->segs : 0;
-    for (int j = 0; j < MAXJOB; j++) jobres[i * MAXJOB + j] = 0;
-    for (int a = 0; a < 2 * MAXARR; a++) foot[i * MAXARR * 2 + a] = 0;
+k_build(int nv, int lanes, const int32_t *__restrict__ order,
+        const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
+        int64_t *varwords, int64_t *varchunks, int64_t *varsegs, int64_t *jobres,
+        int64_t *foot) {
+    extern __shared__ uint64_t lds[];
+    __shared__ int vid[64];
+    Prog *LP = (Prog *)lds;
+    Job *LJ = (Job *)(lds + (size_t)lanes * (sizeof(Prog) / 8));
+    const int t = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * lanes + t;
+    int i = -1;
+    if (t < lanes && s < nv) {
+        i = order[s];
+        const pm_variant v = var[i];
+        Prog *p = &LP[t];
+        int st = build_prog(v, p, &jobs[(int64_t)i * MAXJOB], &LJ[t]);
+        if (st == PM_OK) st = PM_DEFER;
+        status[i] = st;
+        varwords[i] = st == PM_DEFER ? p->bitmap_words : 0;
+        varchunks[i] = st == PM_DEFER ? p->chunks : 0;
+        varsegs[i] = st == PM_DEFER ? p->segs : 0;
+        for (int j = 0; j < MAXJOB; j++) jobres[(int64_t)i * MAXJOB + j] = 0;
+        for (int a = 0; a < 2 * MAXARR; a++) foot[(int64_t)i * MAXARR * 2 + a] = 0;
+    }
+    vid[t] = i;
+    __syncthreads();
+    for (int k = 0; k < lanes; k++) {  // programs to HBM: header and used statements
+        const int vi = vid[k];
+        if (vi < 0) continue;
+        const Prog &p = LP[k];
+        const int ns = p.nstmt < MAXSTMT ? p.nstmt : MAXSTMT;
+        const size_t words = (offsetof(Prog, st) + (size_t)ns * sizeof(Stmt)) / 8;
+        const uint64_t *src = (const uint64_t *)&p;
+        uint64_t *dst = (uint64_t *)&prog[vi];
+        for (size_t w = t; w < words; w += 64) dst[w] = src[w];
+    }
 }
+
+// LDS bytes of a k_build work-group with `lanes` lanes.
+static size_t build_lds_bytes(int lanes) { return (size_t)lanes * (sizeof(Prog) + sizeof(Job)); }
 
 // Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
 __device__ int64_t block_sum(int64_t x, int64_t *red) {
@@ -432,12 +487,13 @@ k_finalize(int nv, const Prog *prog, const int64_t *jobres, const int64_t *foot,
 }
 
 // ---------------------------------------------------------------- host ---
-// Variants built per wavefront by k_build: PM_BUILD_LANES (1..64) if set.
+// Variants built per wavefront by k_build: PM_BUILD_LANES (1..4) if set;
+// four lanes hold 60 KB of LDS.
 static int build_lanes_setting() {
     static int lanes = [] {
         const char *e = getenv("PM_BUILD_LANES");
         int v = e ? atoi(e) : BUILD_LANES;
-        return v < 1 ? 1 : v > 64 ? 64 : v;
+        return v < 1 ? 1 : v > BUILD_LANES ? BUILD_LANES : v;
     }();
     return lanes;
 }
@@ -462,10 +518,13 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
         hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
                            ar.prog, ar.jobs, d_status, ar.varwords, ar.varchunks,
                            ar.varsegs, ar.jobres, ar.foot, d_counts, m, has, d_pred);
-    else
-        hipLaunchKernelGGL(k_build, dim3((nv + build_lanes - 1) / build_lanes), dim3(64), 0, s,
-                           nv, build_lanes, d_var, ar.prog, ar.jobs, d_status, ar.varwords,
-                           ar.varchunks, ar.varsegs, ar.jobres, ar.foot);
+    else {
+        hipLaunchKernelGGL(k_order, dim3(1), dim3(ORDER_THREADS), 0, s, nv, d_var, ar.order);
+        hipLaunchKernelGGL(k_build, dim3((nv + build_lanes - 1) / build_lanes), dim3(64),
+                           build_lds_bytes(build_lanes), s, nv, build_lanes,
+                           (const int32_t *)ar.order, d_var, ar.prog, ar.jobs, d_status,
+                           ar.varwords, ar.varchunks, ar.varsegs, ar.jobres, ar.foot);
+    }
     mark();
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
                        (const int64_t *)ar.varwords, ar.varoff, ar.varchunks,
@@ -492,7 +551,8 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
 }
 
 size_t arena_bytes_per_variant() {
-    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (4 + MAXJOB + 2 * MAXARR);
+    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (4 + MAXJOB + 2 * MAXARR) +
+           sizeof(int32_t);
 }
 
 // ------------------------------------------------------- host execution ---

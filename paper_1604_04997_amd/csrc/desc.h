@@ -132,6 +132,9 @@ struct Job {
     int64_t f_off, b_off;            // bitmap word offsets (variant-relative)
     int64_t words;                   // words of each of this array's bitmaps
     int64_t w;                       // interval mode: fill width of a strided access, else 0
+    // footprint jobs: interval-mode test and sizes, taken when the job is built
+    int64_t ivF, ivFill;
+    int32_t ivok, ivst;
 };
 
 // ------------------------------------------------------------- helpers ---
@@ -160,15 +163,23 @@ PM_HD bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 // -------------------------------------------------------------- builder ---
 struct B {
     Prog *p;
+    // counts of the statement being built, kept in registers so that the
+    // variable and guard indices of a builder are compile-time constants.
+    // Builders fill one statement at a time: additions go to the latest.
+    Stmt *cur = nullptr;
+    int nvar = 0, nguard = 0, nacc = 0;
     PM_HD void fail(int st) {
         if (p->status == PM_OK) p->status = st;
     }
     PM_HD Stmt *stmt(int lane) {
+        nvar = nguard = nacc = 0;
+        cur = nullptr;
         if (p->nstmt >= MAXSTMT) {
             fail(PM_EINVAL);
             return nullptr;
         }
         Stmt *s = &p->st[p->nstmt++];
+        cur = s;
         s->nvar = 0;
         s->lane = lane;
         s->nguard = 0;
@@ -182,21 +193,27 @@ struct B {
         s->fixed = 0;
         return s;
     }
-    // declare variables in order; returns their ids 0..
+    // declare variables in order; returns their ids 0..  (The id does not
+    // depend on the extent, so it stays a compile-time constant; a failed
+    // declaration marks the program invalid.)
     PM_HD int var(Stmt *s, int64_t ext) {
-        if (s->nvar >= MAXVAR || ext < 0) {
+        if (s != cur) fail(PM_EINVAL);
+        if (nvar >= MAXVAR) {
             fail(PM_EINVAL);
-            return 0;
+            return MAXVAR - 1;
         }
-        s->ext[s->nvar] = ext;
-        return s->nvar++;
+        if (ext < 0) fail(PM_EINVAL);
+        s->ext[nvar] = ext;
+        s->nvar = nvar + 1;
+        return nvar++;
     }
     PM_HD void ge0(Stmt *s, Aff a) {  // a >= 0
-        if (s->nguard >= MAXGUARD) {
+        if (s != cur || nguard >= MAXGUARD) {
             fail(PM_EINVAL);
             return;
         }
-        s->guard[s->nguard++] = a;
+        s->guard[nguard] = a;
+        s->nguard = ++nguard;
     }
     PM_HD void lt(Stmt *s, Aff a, int64_t b) {  // a < b  <=>  (b-1) - a >= 0
         Aff g = aff(b - 1 - a.k);
@@ -212,16 +229,17 @@ struct B {
         lt(s, a, b + 1);
     }
     PM_HD void acc(Stmt *s, int arr, int dir, int elem, int vec, Aff idx) {
-        if (s->nacc >= MAXACC || arr >= p->narr) {
+        if (s != cur || nacc >= MAXACC || arr >= p->narr) {
             fail(PM_EINVAL);
             return;
         }
-        GAcc &g = s->acc[s->nacc++];
+        GAcc &g = s->acc[nacc];
         g.arr = arr;
         g.dir = dir;
         g.elem = elem;
         g.vec = vec;
         g.idx = idx;
+        s->nacc = ++nacc;
     }
     PM_HD void array(int a, int64_t cells) {
         if (a >= MAXARR) {
@@ -919,9 +937,18 @@ PM_HD int ival_sizes(const Job &J, int64_t *F, int64_t *Fill) {
     return ovf ? PM_EOVERFLOW : PM_OK;
 }
 
+// Copy of a finished job into its slot.
+PM_HD void put_job(Job *dst, const Job &src) {
+    const uint64_t *a = (const uint64_t *)&src;
+    uint64_t *d = (uint64_t *)dst;
+    for (size_t k = 0; k < sizeof(Job) / 8; k++) d[k] = a[k];
+}
+
 // Expand a variant into its program and jobs.  `jobs` has MAXJOB slots.
-// Returns the status; sets per-array bitmap needs and prog->bitmap_words.
-PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
+// Each job is assembled in *jt when given (fast memory next to a slow
+// `jobs`), else in its slot.  Returns the status; sets per-array bitmap
+// needs and prog->bitmap_words.
+PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr) {
     p->status = PM_OK;
     p->nstmt = p->narr = p->njob = 0;
     p->wg_size = 1;
@@ -1008,7 +1035,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             while (par[rr] != rr) rr = par[rr];
             if (!guarded[root] || rr != root) continue;
             if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
-            Job &J = jobs[nj];  // built in place; kept only if it enumerates
+            Job &J = jt ? *jt : jobs[nj];  // kept only if it enumerates
             J.kind = JOB_COUNT;
             J.nv = 0;
             J.ng = 0;
@@ -1068,6 +1095,8 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             J.f_off = J.b_off = 0;
             J.words = 0;
             J.w = 0;
+            J.ivok = 0;
+            if (jt) put_job(&jobs[nj], J);
             s.comp_job[s.ncomp++] = nj++;
         }
         // footprint jobs for accesses to arrays with a strided access
@@ -1076,7 +1105,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             ArrInfo &A = p->arr[a.arr];
             if (!A.w) continue;
             if (nj >= MAXJOB) return b.fail(PM_EINVAL), p->status;
-            Job &J = jobs[nj];
+            Job &J = jt ? *jt : jobs[nj];
             J.kind = JOB_FOOT;
             J.nv = 0;
             J.ng = 0;
@@ -1138,6 +1167,11 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
             if (mul_ovf(J.outer, J.nseg, &J.items)) return b.fail(PM_EOVERFLOW), p->status;
             J.chunk_items = CHUNK_FOOT;
             J.chunks = cdiv(J.items, J.chunk_items);
+            J.ivok = ival_ok(J);
+            J.ivst = PM_OK;
+            J.ivF = J.ivFill = 0;
+            if (J.ivok) J.ivst = ival_sizes(J, &J.ivF, &J.ivFill);
+            if (jt) put_job(&jobs[nj], J);
             nj++;
         }
     }
@@ -1152,9 +1186,11 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs) {
         int nfj = 0, fj = -1;
         for (int j = 0; j < nj; j++)
             if (jobs[j].kind == JOB_FOOT && jobs[j].arr == ai) nfj++, fj = j;
-        if (nfj == 1 && !(v.flags & PM_FLAG_BITMAP) && ival_ok(jobs[fj])) {
+        if (nfj == 1 && !(v.flags & PM_FLAG_BITMAP) && jobs[fj].ivok) {
             Job &J = jobs[fj];
-            if (ival_sizes(J, &A.fixF, &A.fixFill) != PM_OK) return b.fail(PM_EOVERFLOW), p->status;
+            if (J.ivst != PM_OK) return b.fail(PM_EOVERFLOW), p->status;
+            A.fixF = J.ivF;
+            A.fixFill = J.ivFill;
             J.kind = JOB_NONE;  // nothing left to enumerate
             J.items = J.chunks = 0;
             A.words = 0;
