@@ -794,23 +794,75 @@ PM_HD int fuse(int nv, int64_t *ext, int nf, int64_t (*f)[MAXVAR + 1],
     return nv;
 }
 
-// Inclusive bounds of var x in [0, ext) under guards c*x + k >= 0 on a
-// single variable; returns the count.
+// Narrow [lo, hi) of one variable by the guard c*x + k >= 0.
+PM_HD void clip(int64_t c, int64_t k, int64_t &lo, int64_t &hi) {
+    if (c == 1) {
+        if (-k > lo) lo = -k;
+    } else if (c == -1) {
+        if (k + 1 < hi) hi = k + 1;
+    } else if (c > 0) {
+        const int64_t t = ceil_div(-k, c);
+        if (t > lo) lo = t;
+    } else if (c < 0) {
+        const int64_t t = fdiv(k, -c) + 1;
+        if (t < hi) hi = t;
+    } else if (k < 0) {
+        hi = lo;
+    }
+}
+
+// Points of var x in [0, ext) under guards c*x + k >= 0 on a single
+// variable (rows of g: coefficient in column 0, constant last).
 PM_HD int64_t interval_count(int64_t ext, int ng, const int64_t (*g)[MAXVAR + 1]) {
     int64_t lo = 0, hi = ext;  // [lo, hi)
-    for (int q = 0; q < ng; q++) {
-        int64_t a = g[q][0], r = g[q][MAXVAR];
-        if (a > 0) {
-            int64_t t = ceil_div(-r, a);
-            if (t > lo) lo = t;
-        } else if (a < 0) {
-            int64_t t = fdiv(r, -a) + 1;
-            if (t < hi) hi = t;
-        } else if (r < 0) {
-            return 0;
+    for (int q = 0; q < ng; q++) clip(g[q][0], g[q][MAXVAR], lo, hi);
+    return hi > lo ? hi - lo : 0;
+}
+
+// Closed-form count of a component of statement s with one variable, or
+// with two that fuse (as fuse() would fuse them: (a, b) tried before
+// (b, a)); guards `qs` (bit q: guard q touches the component).  Returns
+// false when the component needs enumeration; *ovf on overflow.
+PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt, bool *ovf) {
+    const int a = __builtin_ctz(M);
+    const uint32_t rest = M & (M - 1);
+    int64_t ext, lo = 0, hi;
+    int col;
+    if (!rest) {
+        ext = s.ext[a];
+        col = a;
+    } else {
+        if (rest & (rest - 1)) return false;  // three or more variables
+        const int b = __builtin_ctz(rest);
+        const int64_t ea = s.ext[a], eb = s.ext[b];
+        // (x, y) fuses when every form has c_y == c_x * ext_x (both zero, or
+        // both non-zero without overflow)
+        auto fuses = [&](int x, int y, int64_t ex) {
+            for (int q = 0; q < s.nguard; q++) {
+                if (!((qs >> q) & 1)) continue;
+                const int64_t cx = s.guard[q].c[x], cy = s.guard[q].c[y];
+                if (!cx) {
+                    if (cy) return false;
+                    continue;
+                }
+                int64_t want;
+                if (!cy || mul_ovf(cx, ex, &want) || cy != want) return false;
+            }
+            return true;
+        };
+        if (fuses(a, b, ea)) col = a;
+        else if (fuses(b, a, eb)) col = b;
+        else return false;
+        if (mul_ovf(ea, eb, &ext)) {
+            *ovf = true;
+            return true;
         }
     }
-    return hi > lo ? hi - lo : 0;
+    hi = ext;
+    for (int q = 0; q < s.nguard; q++)
+        if ((qs >> q) & 1) clip(s.guard[q].c[col], s.guard[q].k, lo, hi);
+    *cnt = hi > lo ? hi - lo : 0;
+    return true;
 }
 
 // Range [lo, hi) of the inner variable (var 0) for fixed outer values:
@@ -855,9 +907,13 @@ PM_HD void eval_outer(const Job &J, int64_t o, int64_t *r, int64_t *base) {
 
 // Lane stride of an access in units of the access size (-1: not whole).
 PM_HD int64_t lane_stride(const Stmt &s, const GAcc &a) {
-    int64_t d = iabs(a.idx.c[s.lane]);
-    if (d % a.vec) return -1;
-    return d / a.vec;
+    const int64_t d = iabs(a.idx.c[s.lane]);
+    switch (a.vec) {
+    case 1: return d;
+    case 2: return (d & 1) ? -1 : d >> 1;
+    case 4: return (d & 3) ? -1 : d >> 2;
+    default: return a.vec <= 0 || d % a.vec ? -1 : d / a.vec;
+    }
 }
 
 // ---------------------------------------------------------- interval mode
@@ -996,44 +1052,55 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
     for (int si = 0; si < p->nstmt; si++) {
         Stmt &s = p->st[si];
         s.ncomp = 0;
-        s.fixed = 1;
+        const int nvar = s.nvar, ng = s.nguard;
         bool empty = false;
-        for (int x = 0; x < s.nvar; x++)
+        for (int x = 0; x < nvar; x++)
             if (s.ext[x] == 0) empty = true;
-        bool guarded[MAXVAR];
-        int par[MAXVAR];
-        for (int x = 0; x < MAXVAR; x++) {
-            guarded[x] = false;
-            par[x] = x;
-        }
-        for (int q = 0; q < s.nguard; q++) {
-            int first = -1;
-            for (int x = 0; x < s.nvar; x++) {
-                if (!s.guard[q].c[x]) continue;
-                guarded[x] = true;
-                if (first < 0) {
-                    first = x;
-                } else {  // union(first, x)
-                    int ra = first, rb = x;
-                    while (par[ra] != ra) ra = par[ra];
-                    while (par[rb] != rb) rb = par[rb];
-                    if (ra != rb) par[rb] = ra;
-                }
-            }
-            if (first < 0 && s.guard[q].k < 0) empty = true;
+        // variables of each guard (8 bits per guard) and of all guards
+        uint64_t gm = 0;
+        uint32_t guarded = 0;
+        for (int q = 0; q < ng; q++) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int x = 0; x < MAXVAR; x++)
+                if (x < nvar && s.guard[q].c[x]) m |= 1u << x;
+            gm |= (uint64_t)m << (8 * q);
+            guarded |= m;
+            if (!m && s.guard[q].k < 0) empty = true;
         }
         if (empty) {
             s.fixed = 0;
             continue;
         }
-        for (int x = 0; x < s.nvar; x++)
-            if (!guarded[x] && mul_ovf(s.fixed, s.ext[x], &s.fixed))
+        int64_t fixed = 1;
+        for (int x = 0; x < nvar; x++)
+            if (!((guarded >> x) & 1) && mul_ovf(fixed, s.ext[x], &fixed))
                 return b.fail(PM_EOVERFLOW), p->status;
-        // one count per component
-        for (int root = 0; root < s.nvar; root++) {
-            int rr = root;
-            while (par[rr] != rr) rr = par[rr];
-            if (!guarded[root] || rr != root) continue;
+        // one count per component: variables linked through common guards
+        uint32_t done = 0;
+        for (int root = 0; root < nvar; root++) {
+            if (!((guarded >> root) & 1) || ((done >> root) & 1)) continue;
+            uint32_t M = 1u << root;
+            for (bool grow = true; grow;) {
+                grow = false;
+                for (int q = 0; q < ng; q++) {
+                    const uint32_t m = (uint32_t)(gm >> (8 * q)) & 0xffu;
+                    if ((m & M) && (m & ~M)) {
+                        M |= m;
+                        grow = true;
+                    }
+                }
+            }
+            done |= M;
+            uint32_t qs = 0;
+            for (int q = 0; q < ng; q++)
+                if ((gm >> (8 * q)) & M) qs |= 1u << q;
+            int64_t c;
+            bool ovf = false;
+            if (small_component(s, M, qs, &c, &ovf)) {  // closed form
+                if (ovf || mul_ovf(fixed, c, &fixed)) return b.fail(PM_EOVERFLOW), p->status;
+                continue;
+            }
             if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
             Job &J = jt ? *jt : jobs[nj];  // kept only if it enumerates
             J.kind = JOB_COUNT;
@@ -1043,30 +1110,22 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             J.vec = 1;
             J.mark_b = 0;
             int map[MAXVAR];
-            for (int x = 0; x < s.nvar; x++) {
-                int t = x;
-                while (par[t] != t) t = par[t];
-                map[x] = (guarded[x] && t == root) ? J.nv++ : -1;
-            }
-            for (int x = 0; x < s.nvar; x++)
+            for (int x = 0; x < nvar; x++) map[x] = ((M >> x) & 1) ? J.nv++ : -1;
+            for (int x = 0; x < nvar; x++)
                 if (map[x] >= 0) J.ext[map[x]] = s.ext[x];
-            for (int q = 0; q < s.nguard; q++) {
-                bool mine = false;
-                for (int x = 0; x < s.nvar; x++)
-                    if (s.guard[q].c[x] && map[x] >= 0) mine = true;
-                if (!mine) continue;
+            for (int q = 0; q < ng; q++) {
+                if (!((qs >> q) & 1)) continue;
                 for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;
-                for (int x = 0; x < s.nvar; x++)
+                for (int x = 0; x < nvar; x++)
                     if (map[x] >= 0) J.f[J.ng][map[x]] = s.guard[q].c[x];
                 J.f[J.ng][MAXVAR] = s.guard[q].k;
                 J.ng++;
             }
-            bool ovf = false;
             J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
             if (ovf) return b.fail(PM_EOVERFLOW), p->status;
             if (J.nv == 1) {  // an interval: closed form, the slot is reused
-                int64_t c = interval_count(J.ext[0], J.ng, J.f);
-                if (mul_ovf(s.fixed, c, &s.fixed)) return b.fail(PM_EOVERFLOW), p->status;
+                c = interval_count(J.ext[0], J.ng, J.f);
+                if (mul_ovf(fixed, c, &fixed)) return b.fail(PM_EOVERFLOW), p->status;
                 continue;
             }
             // inner variable: the largest extent
@@ -1091,7 +1150,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             J.nseg = 1;
             J.items = J.outer;
             J.chunk_items = CHUNK_COUNT;
-            J.chunks = cdiv(J.items, J.chunk_items);
+            J.chunks = cdiv(J.items, CHUNK_COUNT);
             J.f_off = J.b_off = 0;
             J.words = 0;
             J.w = 0;
@@ -1099,6 +1158,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             if (jt) put_job(&jobs[nj], J);
             s.comp_job[s.ncomp++] = nj++;
         }
+        s.fixed = fixed;
         // footprint jobs for accesses to arrays with a strided access
         for (int q = 0; q < s.nacc; q++) {
             GAcc &a = s.acc[q];
@@ -1117,7 +1177,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             J.w = J.mark_b ? A.w : 0;
             int map[MAXVAR];
             for (int x = 0; x < s.nvar; x++)
-                map[x] = (guarded[x] || a.idx.c[x]) ? J.nv++ : -1;
+                map[x] = (((guarded >> x) & 1) || a.idx.c[x]) ? J.nv++ : -1;
             for (int x = 0; x < s.nvar; x++)
                 if (map[x] >= 0) J.ext[map[x]] = s.ext[x];
             for (int g = 0; g < s.nguard; g++) {
@@ -1166,7 +1226,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             J.nseg = cdiv(J.ext[0], J.seg);
             if (mul_ovf(J.outer, J.nseg, &J.items)) return b.fail(PM_EOVERFLOW), p->status;
             J.chunk_items = CHUNK_FOOT;
-            J.chunks = cdiv(J.items, J.chunk_items);
+            J.chunks = cdiv(J.items, CHUNK_FOOT);
             J.ivok = ival_ok(J);
             J.ivst = PM_OK;
             J.ivF = J.ivFill = 0;
