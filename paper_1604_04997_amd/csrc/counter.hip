@@ -140,7 +140,7 @@ struct FinShared {
     int bad;
 };
 
-__device__ int finalize_block(const Prog &p, const int64_t *jobres, const int64_t *F,
+__device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobres, const int64_t *F,
                               const int64_t *Fill, int st, FinShared &sh, pm_counts *out,
                               const pm_model &model, int has_model, double *pred) {
     const int t = threadIdx.x, l = t & 63;

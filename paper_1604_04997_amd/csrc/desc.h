@@ -87,6 +87,7 @@ struct GAcc {
 
 struct Stmt {
     int32_t nvar, lane, nguard, nacc;
+    uint64_t gmask;  // bits 8q..8q+7: variables with a non-zero coefficient in guard q
     int64_t ext[MAXVAR];
     Aff guard[MAXGUARD];
     GAcc acc[MAXACC];
@@ -184,6 +185,7 @@ struct B {
         s->lane = lane;
         s->nguard = 0;
         s->nacc = 0;
+        s->gmask = 0;
         for (int i = 0; i < MAXVAR; i++) s->ext[i] = 1;
         for (int d = 0; d < 2; d++)
             for (int z = 0; z < 3; z++) s->lds[d][z] = 0;
@@ -213,6 +215,10 @@ struct B {
             return;
         }
         s->guard[nguard] = a;
+        uint64_t m = 0;
+        for (int x = 0; x < MAXVAR; x++)
+            if (a.c[x]) m |= 1ull << x;
+        s->gmask |= m << (8 * nguard);
         s->nguard = ++nguard;
     }
     PM_HD void lt(Stmt *s, Aff a, int64_t b) {  // a < b  <=>  (b-1) - a >= 0
@@ -826,41 +832,43 @@ PM_HD int64_t interval_count(int64_t ext, int ng, const int64_t (*g)[MAXVAR + 1]
 PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt, bool *ovf) {
     const int a = __builtin_ctz(M);
     const uint32_t rest = M & (M - 1);
-    int64_t ext, lo = 0, hi;
-    int col;
-    if (!rest) {
-        ext = s.ext[a];
-        col = a;
-    } else {
-        if (rest & (rest - 1)) return false;  // three or more variables
-        const int b = __builtin_ctz(rest);
-        const int64_t ea = s.ext[a], eb = s.ext[b];
+    if (rest & (rest - 1)) return false;  // three or more variables
+    const int b = rest ? __builtin_ctz(rest) : a;
+    // the component's coefficients and constants, every guard at once
+    int64_t ca[MAXGUARD], cb[MAXGUARD], kk[MAXGUARD];
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++) {
+        const bool on = (qs >> q) & 1;
+        ca[q] = on ? s.guard[q].c[a] : 0;
+        cb[q] = on ? s.guard[q].c[b] : 0;
+        kk[q] = on ? s.guard[q].k : 0;
+    }
+    int64_t ext = s.ext[a], lo = 0, hi;
+    bool use_b = false;
+    if (rest) {
+        const int64_t ea = ext, eb = s.ext[b];
         // (x, y) fuses when every form has c_y == c_x * ext_x (both zero, or
         // both non-zero without overflow)
-        auto fuses = [&](int x, int y, int64_t ex) {
-            for (int q = 0; q < s.nguard; q++) {
-                if (!((qs >> q) & 1)) continue;
-                const int64_t cx = s.guard[q].c[x], cy = s.guard[q].c[y];
-                if (!cx) {
-                    if (cy) return false;
-                    continue;
-                }
-                int64_t want;
-                if (!cy || mul_ovf(cx, ex, &want) || cy != want) return false;
-            }
-            return true;
-        };
-        if (fuses(a, b, ea)) col = a;
-        else if (fuses(b, a, eb)) col = b;
-        else return false;
+        bool fab = true, fba = true;
+#pragma unroll
+        for (int q = 0; q < MAXGUARD; q++) {
+            int64_t want;
+            if (ca[q] ? (!cb[q] || mul_ovf(ca[q], ea, &want) || cb[q] != want) : cb[q] != 0)
+                fab = false;
+            if (cb[q] ? (!ca[q] || mul_ovf(cb[q], eb, &want) || ca[q] != want) : ca[q] != 0)
+                fba = false;
+        }
+        if (!fab && !fba) return false;
+        use_b = !fab;
         if (mul_ovf(ea, eb, &ext)) {
             *ovf = true;
             return true;
         }
     }
     hi = ext;
-    for (int q = 0; q < s.nguard; q++)
-        if ((qs >> q) & 1) clip(s.guard[q].c[col], s.guard[q].k, lo, hi);
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++)
+        if ((qs >> q) & 1) clip(use_b ? cb[q] : ca[q], kk[q], lo, hi);
     *cnt = hi > lo ? hi - lo : 0;
     return true;
 }
@@ -1057,14 +1065,11 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
         for (int x = 0; x < nvar; x++)
             if (s.ext[x] == 0) empty = true;
         // variables of each guard (8 bits per guard) and of all guards
-        uint64_t gm = 0;
+        const uint64_t gm = s.gmask;
+        const uint32_t vmask = (1u << nvar) - 1;  // declared variables
         uint32_t guarded = 0;
         for (int q = 0; q < ng; q++) {
-            uint32_t m = 0;
-#pragma unroll
-            for (int x = 0; x < MAXVAR; x++)
-                if (x < nvar && s.guard[q].c[x]) m |= 1u << x;
-            gm |= (uint64_t)m << (8 * q);
+            const uint32_t m = (uint32_t)(gm >> (8 * q)) & vmask;
             guarded |= m;
             if (!m && s.guard[q].k < 0) empty = true;
         }
@@ -1084,7 +1089,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             for (bool grow = true; grow;) {
                 grow = false;
                 for (int q = 0; q < ng; q++) {
-                    const uint32_t m = (uint32_t)(gm >> (8 * q)) & 0xffu;
+                    const uint32_t m = (uint32_t)(gm >> (8 * q)) & vmask;
                     if ((m & M) && (m & ~M)) {
                         M |= m;
                         grow = true;
