@@ -23,6 +23,12 @@ extern "C" {
 
 pm_status pm_count_host(const pm_variant *v, pm_counts *out, int64_t *foot);
 
+/* The same with the descriptor expanded statement after statement in one
+ * pass (compact job slots) instead of statement by statement in two slots
+ * each, the layout the GPU's one-thread-per-statement expansion uses; the
+ * two must give identical counts. */
+pm_status pm_count_host_seq(const pm_variant *v, pm_counts *out, int64_t *foot);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,6 +96,7 @@ def lib():
             "pm_measure": (ctypes.c_int, [vp, P(Variant), P(vp), P(ctypes.c_size_t), ctypes.c_uint32, vp,
                                           ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]),
             "pm_count_host": (ctypes.c_int, [P(Variant), P(Counts), P(ctypes.c_int64)]),
+            "pm_count_host_seq": (ctypes.c_int, [P(Variant), P(Counts), P(ctypes.c_int64)]),
             "pm_profile": (ctypes.c_int, [vp, ctypes.c_int]),
             "pm_profile_read": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int)]),
             "pm_batch_stats": (ctypes.c_int, [vp, P(ctypes.c_int64)]),
@@ -225,12 +226,14 @@ def bitmap_bytes(d: dict) -> int:
     return out.value
 
 
-def count_host(d: dict, with_footprints: bool = False):
-    """Test hook: the library's descriptor/count code run on the host."""
+def count_host(d: dict, with_footprints: bool = False, sequential: bool = False):
+    """Test hook: the library's descriptor/count code run on the host
+    (`sequential`: the one-pass descriptor expansion)."""
     v = variant_struct(d)
     c = Counts()
     foot = (ctypes.c_int64 * 12)()
-    _check(lib().pm_count_host(ctypes.byref(v), ctypes.byref(c), foot))
+    fn = lib().pm_count_host_seq if sequential else lib().pm_count_host
+    _check(fn(ctypes.byref(v), ctypes.byref(c), foot))
     res = counts_dict(c)
     if with_footprints:
         for a in range(6):

@@ -124,7 +124,6 @@ void free_arena(pm_ctx *c) {
     (void)hipFree(a.jobres);
     (void)hipFree(a.foot);
     (void)hipFree(a.meta);
-    (void)hipFree(a.order);
     (void)hipFree(c->d_var);
     (void)hipFree(c->d_counts);
     (void)hipFree(c->d_pred);
@@ -170,7 +169,6 @@ int grow_cap(pm_ctx *c, size_t nv) {
     HIPCHK(hipMalloc(&a.jobres, 8 * cap * pm::MAXJOB));
     HIPCHK(hipMalloc(&a.foot, 16 * cap * pm::MAXARR));
     HIPCHK(hipMalloc(&a.meta, 64));
-    HIPCHK(hipMalloc(&a.order, sizeof(int32_t) * cap));
     HIPCHK(hipMalloc(&c->d_var, sizeof(pm_variant) * cap));
     HIPCHK(hipMalloc(&c->d_counts, sizeof(pm_counts) * cap));
     HIPCHK(hipMalloc(&c->d_pred, sizeof(double) * cap));
@@ -500,7 +498,14 @@ pm_status pm_measure(pm_ctx *c, const pm_variant *v, void *const *bufs, const si
 // ------------------------------------------------------------- testing ---
 pm_status pm_count_host(const pm_variant *v, pm_counts *out, int64_t *foot) {
     if (!v || !out) return (pm_status)set_err(PM_EINVAL, "null argument");
-    int st = pm::count_host(*v, out, foot);
+    int st = pm::count_host(*v, out, foot, false);
+    if (st) set_err(st, status_name(st));
+    return (pm_status)st;
+}
+
+pm_status pm_count_host_seq(const pm_variant *v, pm_counts *out, int64_t *foot) {
+    if (!v || !out) return (pm_status)set_err(PM_EINVAL, "null argument");
+    int st = pm::count_host(*v, out, foot, true);
     if (st) set_err(st, status_name(st));
     return (pm_status)st;
 }

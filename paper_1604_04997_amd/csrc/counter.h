@@ -25,7 +25,6 @@ struct Arena {
     int64_t *foot = nullptr;     // [cap * MAXARR * 2]
     int64_t *meta = nullptr;     // [8]: chunks, words used, fill segments, ticket, words requested
     uint64_t *bitmap = nullptr;  // [bitmap_words]
-    int32_t *order = nullptr;    // [cap]: build order (variants grouped by kind)
 };
 
 size_t arena_bytes_per_variant();
@@ -40,7 +39,8 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
 
 // Host execution of the same per-variant code (descriptor, jobs, items,
 // fill, finalize), one variant at a time; for unit tests on machines
-// without a GPU.  Returns a pm_status.
-int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out);
+// without a GPU.  `sequential`: the one-pass expansion instead of the
+// per-statement one.  Returns a pm_status.
+int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out, bool sequential);
 
 }  // namespace pm

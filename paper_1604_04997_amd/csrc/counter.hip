@@ -1,12 +1,15 @@
 // GPU counter: kernel properties of a batch of variants (Sec. 3.2).
 //
-// k_fused     one work-group per variant: builds the descriptor and its jobs
-//             in LDS (desc.h), runs the count jobs (guarded points per
-//             statement, Alg. 1) and interval-mode footprint jobs (Alg. 2)
-//             with all its threads, and writes the count vector (Eq.
+// Both first kernels expand a variant's descriptor in LDS with one thread
+// per statement (desc.h: build_head, analyze_stmt, build_tail).
+// k_fused     batches of up to FUSED_MAX_NV variants, one work-group each:
+//             also runs the count jobs (guarded points per statement, Alg.
+//             1) with all its threads and writes the count vector (Eq.
 //             opcount) and the FP64 prediction.  A variant whose footprints
 //             need bitmaps (or whose jobs exceed FUSED_MAX_ITEMS items) is
 //             handed on: its descriptor is copied to HBM, status PM_DEFER.
+// k_build     larger batches, one 64-wide work-group per variant: the
+//             descriptor and jobs go to HBM and every variant is handed on.
 // For handed-on variants only:
 //   k_scan      one work-group: prefix sums of bitmap words, work chunks and
 //               fill segments per variant; bitmaps that overflow the arena
@@ -37,83 +40,57 @@ constexpr int FUSED_THREADS = 256;
 constexpr int64_t FUSED_MAX_ITEMS = 1 << 20;
 constexpr int PM_DEFER = 1;  // internal status: finish in the general pipeline
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
-constexpr int BUILD_LANES = 4;         // variants built per wavefront in k_build
 
-// Batch order for k_build: variants grouped by (family, op), so that the
-// lanes of a wavefront expand alike descriptors.  One work-group; the order
-// within a group is immaterial (every result is indexed by variant).
-constexpr int ORDER_THREADS = 1024;
-constexpr int ORDER_KEYS = 16 * 8;
-__device__ inline int order_key(const pm_variant &v) {
-    const int f = v.family < 15 ? (int)v.family : 15, o = v.op < 7 ? (int)v.op : 7;
-    return f * 8 + o;
-}
-
-__global__ void __launch_bounds__(ORDER_THREADS)
-k_order(int nv, const pm_variant *__restrict__ var, int32_t *order) {
-    __shared__ int cnt[ORDER_KEYS];
+// Expansion of one variant by a work-group (at least MAXSTMT threads; all
+// call this): thread 0 lays out the statements, thread si analyses
+// statement si in job slots 2si and 2si+1, thread 0 finishes
+// (build_slots_finish).  p and jt (MAXSTMT job buffers) are in LDS; sh
+// holds 1 + MAXSTMT ints.
+__device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jobs, Job *jt,
+                                           int *sh) {
     const int t = threadIdx.x;
-    if (t < ORDER_KEYS) cnt[t] = 0;
+    if (t == 0) sh[0] = build_head(v, p, jobs);
     __syncthreads();
-    for (int i = t; i < nv; i += ORDER_THREADS) atomicAdd(&cnt[order_key(var[i])], 1);
-    __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int k = 0; k < ORDER_KEYS; k++) {
-            const int c = cnt[k];
-            cnt[k] = run;
-            run += c;
-        }
+    if (sh[0] != PM_OK) return sh[0];
+    if (t < p->nstmt) {
+        int made;
+        sh[1 + t] = analyze_stmt(p, t, jobs, &jt[t], 2 * t, 2 * t + 2, PM_SEQ, &made);
     }
     __syncthreads();
-    for (int i = t; i < nv; i += ORDER_THREADS) order[atomicAdd(&cnt[order_key(var[i])], 1)] = i;
+    if (t == 0) sh[0] = build_slots_finish(v, p, jobs, &jt[0], sh + 1);
+    __syncthreads();
+    return sh[0];
 }
 
-// `lanes` variants per 64-wide work-group (one wavefront), one per lane,
-// each expanded in LDS (its Prog and the job being assembled) and copied to
-// HBM by the whole wavefront.  Every valid variant continues in the
-// general pipeline.
+// One variant per 64-wide work-group, expanded in LDS and copied to HBM.
+// Every valid variant continues in the general pipeline.
 __global__ void __launch_bounds__(64)
-k_build(int nv, int lanes, const int32_t *__restrict__ order,
-        const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
+k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
         int64_t *varwords, int64_t *varchunks, int64_t *varsegs, int64_t *jobres,
         int64_t *foot) {
-    extern __shared__ uint64_t lds[];
-    __shared__ int vid[64];
-    Prog *LP = (Prog *)lds;
-    Job *LJ = (Job *)(lds + (size_t)lanes * (sizeof(Prog) / 8));
-    const int t = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * lanes + t;
-    int i = -1;
-    if (t < lanes && s < nv) {
-        i = order[s];
-        const pm_variant v = var[i];
-        Prog *p = &LP[t];
-        int st = build_prog(v, p, &jobs[(int64_t)i * MAXJOB], &LJ[t]);
-        if (st == PM_OK) st = PM_DEFER;
+    __shared__ Prog P;
+    __shared__ Job JT[MAXSTMT];
+    __shared__ int sh[1 + MAXSTMT];
+    const int i = blockIdx.x, t = threadIdx.x;
+    if (i >= nv) return;
+    const pm_variant v = var[i];
+    int st = build_block(v, &P, &jobs[(int64_t)i * MAXJOB], JT, sh);
+    if (st == PM_OK) st = PM_DEFER;
+    if (t == 0) {
         status[i] = st;
-        varwords[i] = st == PM_DEFER ? p->bitmap_words : 0;
-        varchunks[i] = st == PM_DEFER ? p->chunks : 0;
-        varsegs[i] = st == PM_DEFER ? p->segs : 0;
-        for (int j = 0; j < MAXJOB; j++) jobres[(int64_t)i * MAXJOB + j] = 0;
-        for (int a = 0; a < 2 * MAXARR; a++) foot[(int64_t)i * MAXARR * 2 + a] = 0;
+        varwords[i] = st == PM_DEFER ? P.bitmap_words : 0;
+        varchunks[i] = st == PM_DEFER ? P.chunks : 0;
+        varsegs[i] = st == PM_DEFER ? P.segs : 0;
     }
-    vid[t] = i;
-    __syncthreads();
-    for (int k = 0; k < lanes; k++) {  // programs to HBM: header and used statements
-        const int vi = vid[k];
-        if (vi < 0) continue;
-        const Prog &p = LP[k];
-        const int ns = p.nstmt < MAXSTMT ? p.nstmt : MAXSTMT;
-        const size_t words = (offsetof(Prog, st) + (size_t)ns * sizeof(Stmt)) / 8;
-        const uint64_t *src = (const uint64_t *)&p;
-        uint64_t *dst = (uint64_t *)&prog[vi];
-        for (size_t w = t; w < words; w += 64) dst[w] = src[w];
-    }
+    if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
+    if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
+    // the program to HBM: header and used statements
+    const int ns = P.nstmt < MAXSTMT ? P.nstmt : MAXSTMT;
+    const size_t words = (offsetof(Prog, st) + (size_t)ns * sizeof(Stmt)) / 8;
+    const uint64_t *src = (const uint64_t *)&P;
+    uint64_t *dst = (uint64_t *)&prog[i];
+    for (size_t w = t; w < words; w += 64) dst[w] = src[w];
 }
-
-// LDS bytes of a k_build work-group with `lanes` lanes.
-static size_t build_lds_bytes(int lanes) { return (size_t)lanes * (sizeof(Prog) + sizeof(Job)); }
 
 // Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
 __device__ int64_t block_sum(int64_t x, int64_t *red) {
@@ -183,19 +160,23 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int has_model, double *pred) {
     __shared__ Prog P;
     __shared__ Job J[MAXJOB];
+    __shared__ Job JT[MAXSTMT];
     __shared__ int64_t jr[MAXJOB];
     __shared__ int64_t fF[MAXARR], fFill[MAXARR];
     __shared__ int64_t red[FUSED_THREADS / 64];
     __shared__ FinShared fin;
+    __shared__ int bsh[1 + MAXSTMT];
     __shared__ int st_sh;
     const int i = blockIdx.x;
     const int t = threadIdx.x;
     if (i >= nv) return;
+    const pm_variant v = var[i];
+    const int sb = build_block(v, &P, J, JT, bsh);
     if (t == 0) {
-        pm_variant v = var[i];
-        int st = build_prog(v, &P, J);
+        int st = sb;
         int64_t items = 0;
-        for (int j = 0; j < P.njob; j++) items += J[j].items;
+        for (int j = 0; j < P.njob; j++)
+            if (J[j].kind != JOB_NONE) items += J[j].items;
         if (st == PM_OK && (P.bitmap_words > 0 || items > FUSED_MAX_ITEMS)) st = PM_DEFER;
         st_sh = st;
     }
@@ -487,22 +468,10 @@ k_finalize(int nv, const Prog *prog, const int64_t *jobres, const int64_t *foot,
 }
 
 // ---------------------------------------------------------------- host ---
-// Variants built per wavefront by k_build: PM_BUILD_LANES (1..4) if set;
-// four lanes hold 60 KB of LDS.
-static int build_lanes_setting() {
-    static int lanes = [] {
-        const char *e = getenv("PM_BUILD_LANES");
-        int v = e ? atoi(e) : BUILD_LANES;
-        return v < 1 ? 1 : v > BUILD_LANES ? BUILD_LANES : v;
-    }();
-    return lanes;
-}
-
 int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev) {
     if (nv <= 0) return PM_OK;
-    const int build_lanes = build_lanes_setting();
     int q = 0;
     auto mark = [&]() {
         if (ev) (void)hipEventRecord(ev[q++], s);
@@ -518,13 +487,10 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
         hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
                            ar.prog, ar.jobs, d_status, ar.varwords, ar.varchunks,
                            ar.varsegs, ar.jobres, ar.foot, d_counts, m, has, d_pred);
-    else {
-        hipLaunchKernelGGL(k_order, dim3(1), dim3(ORDER_THREADS), 0, s, nv, d_var, ar.order);
-        hipLaunchKernelGGL(k_build, dim3((nv + build_lanes - 1) / build_lanes), dim3(64),
-                           build_lds_bytes(build_lanes), s, nv, build_lanes,
-                           (const int32_t *)ar.order, d_var, ar.prog, ar.jobs, d_status,
-                           ar.varwords, ar.varchunks, ar.varsegs, ar.jobres, ar.foot);
-    }
+    else
+        hipLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, nv, d_var, ar.prog, ar.jobs,
+                           d_status, ar.varwords, ar.varchunks, ar.varsegs, ar.jobres,
+                           ar.foot);
     mark();
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
                        (const int64_t *)ar.varwords, ar.varoff, ar.varchunks,
@@ -551,8 +517,7 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
 }
 
 size_t arena_bytes_per_variant() {
-    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (4 + MAXJOB + 2 * MAXARR) +
-           sizeof(int32_t);
+    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (4 + MAXJOB + 2 * MAXARR);
 }
 
 // ------------------------------------------------------- host execution ---
@@ -560,11 +525,11 @@ struct HostOr {
     void operator()(uint64_t *p, uint64_t m) const { *p |= m; }
 };
 
-int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out) {
+int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out, bool sequential) {
     std::vector<Prog> P(1);
     std::vector<Job> J(MAXJOB);
     Prog &p = P[0];
-    int st = build_prog(v, &p, J.data());
+    int st = sequential ? build_prog(v, &p, J.data()) : build_prog_slots(v, &p, J.data());
     for (int i = 0; i < PM_NCOUNT; i++) out->c[i] = 0;
     if (st != PM_OK) return st;
     std::vector<uint64_t> bm((size_t)p.bitmap_words + 1, 0);

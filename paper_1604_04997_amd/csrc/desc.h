@@ -145,15 +145,21 @@ PM_HD bool mul_ovf(int64_t a, int64_t b, int64_t *r) {
 PM_HD bool add_ovf(int64_t a, int64_t b, int64_t *r) {
     return __builtin_add_overflow(a, b, r);
 }
-PM_HD int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// a / b rounded toward zero (b != 0); the 32-bit divide when both fit,
+// which is far shorter than the 64-bit sequence on the GPU.
+PM_HD int64_t tdiv(int64_t a, int64_t b) {
+    if (a == (int32_t)a && b == (int32_t)b && b != -1) return (int32_t)a / (int32_t)b;
+    return a / b;
+}
+PM_HD int64_t cdiv(int64_t a, int64_t b) { return tdiv(a + b - 1, b); }
 // floor(a / b) and ceil(a / b) for b > 0, any sign of a
 PM_HD int64_t fdiv(int64_t a, int64_t b) {
-    int64_t q = a / b;
-    return (a % b != 0 && a < 0) ? q - 1 : q;
+    const int64_t q = tdiv(a, b);
+    return (q * b != a && a < 0) ? q - 1 : q;
 }
 PM_HD int64_t ceil_div(int64_t a, int64_t b) {
-    int64_t q = a / b;
-    return (a % b != 0 && a > 0) ? q + 1 : q;
+    const int64_t q = tdiv(a, b);
+    return (q * b != a && a > 0) ? q + 1 : q;
 }
 PM_HD int64_t iabs(int64_t a) { return a < 0 ? -a : a; }
 PM_HD int size_index(int bytes) {
@@ -833,30 +839,20 @@ PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt,
     const int a = __builtin_ctz(M);
     const uint32_t rest = M & (M - 1);
     if (rest & (rest - 1)) return false;  // three or more variables
-    const int b = rest ? __builtin_ctz(rest) : a;
-    // the component's coefficients and constants, every guard at once
-    int64_t ca[MAXGUARD], cb[MAXGUARD], kk[MAXGUARD];
-#pragma unroll
-    for (int q = 0; q < MAXGUARD; q++) {
-        const bool on = (qs >> q) & 1;
-        ca[q] = on ? s.guard[q].c[a] : 0;
-        cb[q] = on ? s.guard[q].c[b] : 0;
-        kk[q] = on ? s.guard[q].k : 0;
-    }
     int64_t ext = s.ext[a], lo = 0, hi;
     bool use_b = false;
     if (rest) {
+        const int b = __builtin_ctz(rest);
         const int64_t ea = ext, eb = s.ext[b];
         // (x, y) fuses when every form has c_y == c_x * ext_x (both zero, or
         // both non-zero without overflow)
         bool fab = true, fba = true;
-#pragma unroll
-        for (int q = 0; q < MAXGUARD; q++) {
+        for (uint32_t r = qs; r; r &= r - 1) {
+            const int q = __builtin_ctz(r);
+            const int64_t ca = s.guard[q].c[a], cb = s.guard[q].c[b];
             int64_t want;
-            if (ca[q] ? (!cb[q] || mul_ovf(ca[q], ea, &want) || cb[q] != want) : cb[q] != 0)
-                fab = false;
-            if (cb[q] ? (!ca[q] || mul_ovf(cb[q], eb, &want) || ca[q] != want) : ca[q] != 0)
-                fba = false;
+            if (ca ? (!cb || mul_ovf(ca, ea, &want) || cb != want) : cb != 0) fab = false;
+            if (cb ? (!ca || mul_ovf(cb, eb, &want) || ca != want) : ca != 0) fba = false;
         }
         if (!fab && !fba) return false;
         use_b = !fab;
@@ -864,11 +860,21 @@ PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt,
             *ovf = true;
             return true;
         }
+        if (use_b) {
+            hi = ext;
+            for (uint32_t r = qs; r; r &= r - 1) {
+                const int q = __builtin_ctz(r);
+                clip(s.guard[q].c[b], s.guard[q].k, lo, hi);
+            }
+            *cnt = hi > lo ? hi - lo : 0;
+            return true;
+        }
     }
     hi = ext;
-#pragma unroll
-    for (int q = 0; q < MAXGUARD; q++)
-        if ((qs >> q) & 1) clip(use_b ? cb[q] : ca[q], kk[q], lo, hi);
+    for (uint32_t r = qs; r; r &= r - 1) {
+        const int q = __builtin_ctz(r);
+        clip(s.guard[q].c[a], s.guard[q].k, lo, hi);
+    }
     *cnt = hi > lo ? hi - lo : 0;
     return true;
 }
@@ -905,8 +911,8 @@ PM_HD void eval_outer(const Job &J, int64_t o, int64_t *r, int64_t *base) {
     int64_t b = J.f[J.ng][MAXVAR];
     for (int v = 1; v < J.nv; v++) {
         int64_t e = J.ext[v];
-        int64_t x = o % e;
-        o /= e;
+        const int64_t q = tdiv(o, e), x = o - q * e;
+        o = q;
         for (int q = 0; q < J.ng; q++) r[q] += J.f[q][v] * x;
         b += J.f[J.ng][v] * x;
     }
@@ -1008,11 +1014,14 @@ PM_HD void put_job(Job *dst, const Job &src) {
     for (size_t k = 0; k < sizeof(Job) / 8; k++) d[k] = a[k];
 }
 
-// Expand a variant into its program and jobs.  `jobs` has MAXJOB slots.
-// Each job is assembled in *jt when given (fast memory next to a slow
-// `jobs`), else in its slot.  Returns the status; sets per-array bitmap
-// needs and prog->bitmap_words.
-PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr) {
+// The expansion of a variant into its program and jobs runs in three
+// parts: build_head (statements, cleared job slots, fill widths),
+// analyze_stmt for every statement (independent of each other), and
+// build_tail (footprint modes, prefixes).  build_prog chains them.
+
+// Statements of the variant's family, MAXJOB cleared job slots, and the
+// fill width of every array with a strided access.  Returns the status.
+PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     p->status = PM_OK;
     p->nstmt = p->narr = p->njob = 0;
     p->wg_size = 1;
@@ -1056,190 +1065,248 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             }
         }
     }
-    int nj = 0;
-    for (int si = 0; si < p->nstmt; si++) {
-        Stmt &s = p->st[si];
-        s.ncomp = 0;
-        const int nvar = s.nvar, ng = s.nguard;
-        bool empty = false;
-        for (int x = 0; x < nvar; x++)
-            if (s.ext[x] == 0) empty = true;
-        // variables of each guard (8 bits per guard) and of all guards
-        const uint64_t gm = s.gmask;
-        const uint32_t vmask = (1u << nvar) - 1;  // declared variables
-        uint32_t guarded = 0;
-        for (int q = 0; q < ng; q++) {
-            const uint32_t m = (uint32_t)(gm >> (8 * q)) & vmask;
-            guarded |= m;
-            if (!m && s.guard[q].k < 0) empty = true;
+    return PM_OK;
+}
+
+// Counts of statement si (its fixed factor and components) and its jobs,
+// numbered from `base`: a job number reaching `cap` returns `over`.  Jobs
+// are assembled in *jt when given, else in their slots.  *made: jobs made.
+// Reads the program and writes only statement si and its job slots, so
+// statements may be analysed concurrently.  Returns a status.
+PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, Job *jt, int base, int cap, int over,
+                       int *made) {
+    int nj = base;
+    *made = 0;
+    Stmt &s = p->st[si];
+    s.ncomp = 0;
+    const int nvar = s.nvar, ng = s.nguard;
+    bool empty = false;
+    int64_t ext[MAXVAR];  // read at once
+#pragma unroll
+    for (int x = 0; x < MAXVAR; x++) {
+        ext[x] = x < nvar ? s.ext[x] : 1;
+        if (ext[x] == 0) empty = true;
+    }
+    // variables of each guard (8 bits per guard) and of all guards
+    const uint64_t gm = s.gmask;
+    const uint32_t vmask = (1u << nvar) - 1;  // declared variables
+    uint32_t guarded = 0;
+    for (int q = 0; q < ng; q++) {
+        const uint32_t m = (uint32_t)(gm >> (8 * q)) & vmask;
+        guarded |= m;
+        if (!m && s.guard[q].k < 0) empty = true;
+    }
+    if (empty) {
+        s.fixed = 0;
+        return PM_OK;
+    }
+    int64_t fixed = 1;
+    bool fovf = false;
+#pragma unroll
+    for (int x = 0; x < MAXVAR; x++)
+        if (x < nvar && !((guarded >> x) & 1) && mul_ovf(fixed, ext[x], &fixed)) fovf = true;
+    if (fovf) return PM_EOVERFLOW;
+    // one count per component: variables linked through common guards
+    uint32_t done = 0;
+    for (int root = 0; root < nvar; root++) {
+        if (!((guarded >> root) & 1) || ((done >> root) & 1)) continue;
+        uint32_t M = 1u << root;
+        for (bool grow = true; grow;) {
+            grow = false;
+            for (int q = 0; q < ng; q++) {
+                const uint32_t m = (uint32_t)(gm >> (8 * q)) & vmask;
+                if ((m & M) && (m & ~M)) {
+                    M |= m;
+                    grow = true;
+                }
+            }
         }
-        if (empty) {
-            s.fixed = 0;
+        done |= M;
+        uint32_t qs = 0;
+        for (int q = 0; q < ng; q++)
+            if ((gm >> (8 * q)) & M) qs |= 1u << q;
+        int64_t c;
+        bool ovf = false;
+        if (small_component(s, M, qs, &c, &ovf)) {  // closed form
+            if (ovf || mul_ovf(fixed, c, &fixed)) return PM_EOVERFLOW;
             continue;
         }
-        int64_t fixed = 1;
-        for (int x = 0; x < nvar; x++)
-            if (!((guarded >> x) & 1) && mul_ovf(fixed, s.ext[x], &fixed))
-                return b.fail(PM_EOVERFLOW), p->status;
-        // one count per component: variables linked through common guards
-        uint32_t done = 0;
-        for (int root = 0; root < nvar; root++) {
-            if (!((guarded >> root) & 1) || ((done >> root) & 1)) continue;
-            uint32_t M = 1u << root;
-            for (bool grow = true; grow;) {
-                grow = false;
-                for (int q = 0; q < ng; q++) {
-                    const uint32_t m = (uint32_t)(gm >> (8 * q)) & vmask;
-                    if ((m & M) && (m & ~M)) {
-                        M |= m;
-                        grow = true;
-                    }
-                }
+        if (nj >= cap) return over;
+        if (s.ncomp >= MAXCOMP) return PM_EINVAL;
+        Job &J = jt ? *jt : jobs[nj];  // kept only if it enumerates
+        J.kind = JOB_COUNT;
+        J.nv = 0;
+        J.ng = 0;
+        J.arr = -1;
+        J.vec = 1;
+        J.mark_b = 0;
+        // job column t: the component's t-th variable (increasing order)
+        int xt[MAXVAR];
+        const int ncol = __builtin_popcount(M);
+        {
+            uint32_t r = M;
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) {
+                xt[t] = r ? __builtin_ctz(r) : 0;
+                r &= r - 1;
             }
-            done |= M;
-            uint32_t qs = 0;
-            for (int q = 0; q < ng; q++)
-                if ((gm >> (8 * q)) & M) qs |= 1u << q;
-            int64_t c;
-            bool ovf = false;
-            if (small_component(s, M, qs, &c, &ovf)) {  // closed form
-                if (ovf || mul_ovf(fixed, c, &fixed)) return b.fail(PM_EOVERFLOW), p->status;
-                continue;
-            }
-            if (nj >= MAXJOB || s.ncomp >= MAXCOMP) return b.fail(PM_EINVAL), p->status;
-            Job &J = jt ? *jt : jobs[nj];  // kept only if it enumerates
-            J.kind = JOB_COUNT;
-            J.nv = 0;
-            J.ng = 0;
-            J.arr = -1;
-            J.vec = 1;
-            J.mark_b = 0;
-            int map[MAXVAR];
-            for (int x = 0; x < nvar; x++) map[x] = ((M >> x) & 1) ? J.nv++ : -1;
-            for (int x = 0; x < nvar; x++)
-                if (map[x] >= 0) J.ext[map[x]] = s.ext[x];
-            for (int q = 0; q < ng; q++) {
-                if (!((qs >> q) & 1)) continue;
-                for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;
-                for (int x = 0; x < nvar; x++)
-                    if (map[x] >= 0) J.f[J.ng][map[x]] = s.guard[q].c[x];
-                J.f[J.ng][MAXVAR] = s.guard[q].k;
-                J.ng++;
-            }
-            J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
-            if (ovf) return b.fail(PM_EOVERFLOW), p->status;
-            if (J.nv == 1) {  // an interval: closed form, the slot is reused
-                c = interval_count(J.ext[0], J.ng, J.f);
-                if (mul_ovf(fixed, c, &fixed)) return b.fail(PM_EOVERFLOW), p->status;
-                continue;
-            }
-            // inner variable: the largest extent
-            int in = 0;
-            for (int x = 1; x < J.nv; x++)
-                if (J.ext[x] > J.ext[in]) in = x;
-            if (in) {
-                int64_t te = J.ext[0];
-                J.ext[0] = J.ext[in];
-                J.ext[in] = te;
-                for (int q = 0; q < J.ng; q++) {
-                    int64_t tg = J.f[q][0];
-                    J.f[q][0] = J.f[q][in];
-                    J.f[q][in] = tg;
-                }
-            }
-            for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;  // no index map
-            J.outer = 1;
-            for (int x = 1; x < J.nv; x++)
-                if (mul_ovf(J.outer, J.ext[x], &J.outer)) return b.fail(PM_EOVERFLOW), p->status;
-            J.seg = J.ext[0];
-            J.nseg = 1;
-            J.items = J.outer;
-            J.chunk_items = CHUNK_COUNT;
-            J.chunks = cdiv(J.items, CHUNK_COUNT);
-            J.f_off = J.b_off = 0;
-            J.words = 0;
-            J.w = 0;
-            J.ivok = 0;
-            if (jt) put_job(&jobs[nj], J);
-            s.comp_job[s.ncomp++] = nj++;
         }
-        s.fixed = fixed;
-        // footprint jobs for accesses to arrays with a strided access
-        for (int q = 0; q < s.nacc; q++) {
-            GAcc &a = s.acc[q];
-            ArrInfo &A = p->arr[a.arr];
-            if (!A.w) continue;
-            if (nj >= MAXJOB) return b.fail(PM_EINVAL), p->status;
-            Job &J = jt ? *jt : jobs[nj];
-            J.kind = JOB_FOOT;
-            J.nv = 0;
-            J.ng = 0;
-            J.arr = a.arr;
-            J.vec = a.vec;
-            J.mark_b = lane_stride(s, a) >= 2;  // strided: its cells are widened
-            J.f_off = J.b_off = -1;             // set with the array's mode below
-            J.words = 0;
-            J.w = J.mark_b ? A.w : 0;
-            int map[MAXVAR];
-            for (int x = 0; x < s.nvar; x++)
-                map[x] = (((guarded >> x) & 1) || a.idx.c[x]) ? J.nv++ : -1;
-            for (int x = 0; x < s.nvar; x++)
-                if (map[x] >= 0) J.ext[map[x]] = s.ext[x];
-            for (int g = 0; g < s.nguard; g++) {
-                for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;
-                for (int x = 0; x < s.nvar; x++)
-                    if (map[x] >= 0) J.f[J.ng][map[x]] = s.guard[g].c[x];
-                J.f[J.ng][MAXVAR] = s.guard[g].k;
-                J.ng++;
-            }
-            int64_t *ic = J.f[J.ng];  // the index map after the guards
-            for (int t = 0; t <= MAXVAR; t++) ic[t] = 0;
-            for (int x = 0; x < s.nvar; x++)
-                if (map[x] >= 0) ic[map[x]] = a.idx.c[x];
-            ic[MAXVAR] = a.idx.k;
-            // fuse over guards and the index map together
-            bool ovf = false;
-            J.nv = fuse(J.nv, J.ext, J.ng + 1, J.f, &ovf);
-            if (ovf) return b.fail(PM_EOVERFLOW), p->status;
-            if (J.nv == 0) {  // a single access point
-                J.nv = 1;
-                J.ext[0] = 1;
-            }
-            // inner variable: smallest non-zero index coefficient
-            int in = -1;
-            for (int x = 0; x < J.nv; x++) {
-                if (!ic[x]) continue;
-                if (in < 0 || iabs(ic[x]) < iabs(ic[in]) ||
-                    (iabs(ic[x]) == iabs(ic[in]) && J.ext[x] > J.ext[in]))
-                    in = x;
-            }
-            if (in < 0) in = 0;
-            if (in) {
-                int64_t te = J.ext[0];
-                J.ext[0] = J.ext[in];
-                J.ext[in] = te;
-                for (int g = 0; g <= J.ng; g++) {
-                    int64_t tg = J.f[g][0];
-                    J.f[g][0] = J.f[g][in];
-                    J.f[g][in] = tg;
-                }
-            }
-            J.outer = 1;
-            for (int x = 1; x < J.nv; x++)
-                if (mul_ovf(J.outer, J.ext[x], &J.outer)) return b.fail(PM_EOVERFLOW), p->status;
-            J.seg = iabs(ic[0]) <= J.vec ? SEG_CONTIG : SEG_STRIDED;
-            J.nseg = cdiv(J.ext[0], J.seg);
-            if (mul_ovf(J.outer, J.nseg, &J.items)) return b.fail(PM_EOVERFLOW), p->status;
-            J.chunk_items = CHUNK_FOOT;
-            J.chunks = cdiv(J.items, CHUNK_FOOT);
-            J.ivok = ival_ok(J);
-            J.ivst = PM_OK;
-            J.ivF = J.ivFill = 0;
-            if (J.ivok) J.ivst = ival_sizes(J, &J.ivF, &J.ivFill);
-            if (jt) put_job(&jobs[nj], J);
-            nj++;
+        J.nv = ncol;
+#pragma unroll
+        for (int t = 0; t < MAXVAR; t++)
+            if (t < ncol) J.ext[t] = s.ext[xt[t]];
+        for (uint32_t r = qs; r; r &= r - 1) {
+            const int q = __builtin_ctz(r);
+            int64_t row[MAXVAR];
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? s.guard[q].c[xt[t]] : 0;
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) J.f[J.ng][t] = row[t];
+            J.f[J.ng][MAXVAR] = s.guard[q].k;
+            J.ng++;
         }
+        J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
+        if (ovf) return PM_EOVERFLOW;
+        if (J.nv == 1) {  // an interval: closed form, the slot is reused
+            c = interval_count(J.ext[0], J.ng, J.f);
+            if (mul_ovf(fixed, c, &fixed)) return PM_EOVERFLOW;
+            continue;
+        }
+        // inner variable: the largest extent
+        int in = 0;
+        for (int x = 1; x < J.nv; x++)
+            if (J.ext[x] > J.ext[in]) in = x;
+        if (in) {
+            int64_t te = J.ext[0];
+            J.ext[0] = J.ext[in];
+            J.ext[in] = te;
+            for (int q = 0; q < J.ng; q++) {
+                int64_t tg = J.f[q][0];
+                J.f[q][0] = J.f[q][in];
+                J.f[q][in] = tg;
+            }
+        }
+        for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;  // no index map
+        J.outer = 1;
+        for (int x = 1; x < J.nv; x++)
+            if (mul_ovf(J.outer, J.ext[x], &J.outer)) return PM_EOVERFLOW;
+        J.seg = J.ext[0];
+        J.nseg = 1;
+        J.items = J.outer;
+        J.chunk_items = CHUNK_COUNT;
+        J.chunks = cdiv(J.items, CHUNK_COUNT);
+        J.f_off = J.b_off = 0;
+        J.words = 0;
+        J.w = 0;
+        J.ivok = 0;
+        if (jt) put_job(&jobs[nj], J);
+        s.comp_job[s.ncomp++] = nj++;
     }
+    s.fixed = fixed;
+    // footprint jobs for accesses to arrays with a strided access
+    for (int q = 0; q < s.nacc; q++) {
+        GAcc &a = s.acc[q];
+        ArrInfo &A = p->arr[a.arr];
+        if (!A.w) continue;
+        if (nj >= cap) return over;
+        Job &J = jt ? *jt : jobs[nj];
+        J.kind = JOB_FOOT;
+        J.nv = 0;
+        J.ng = 0;
+        J.arr = a.arr;
+        J.vec = a.vec;
+        J.mark_b = lane_stride(s, a) >= 2;  // strided: its cells are widened
+        J.f_off = J.b_off = -1;             // set with the array's mode below
+        J.words = 0;
+        J.w = J.mark_b ? A.w : 0;
+        // variables: every guarded one and those of the index map, in
+        // increasing order (job column t = the t-th of them)
+        uint32_t Mf = guarded;
+#pragma unroll
+        for (int x = 0; x < MAXVAR; x++)
+            if (a.idx.c[x]) Mf |= 1u << x;
+        Mf &= vmask;
+        int xt[MAXVAR];
+        const int ncol = __builtin_popcount(Mf);
+        {
+            uint32_t r = Mf;
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) {
+                xt[t] = r ? __builtin_ctz(r) : 0;
+                r &= r - 1;
+            }
+        }
+        J.nv = ncol;
+#pragma unroll
+        for (int t = 0; t < MAXVAR; t++)
+            if (t < ncol) J.ext[t] = s.ext[xt[t]];
+        for (int g = 0; g < ng; g++) {
+            int64_t row[MAXVAR];
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? s.guard[g].c[xt[t]] : 0;
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) J.f[J.ng][t] = row[t];
+            J.f[J.ng][MAXVAR] = s.guard[g].k;
+            J.ng++;
+        }
+        int64_t *ic = J.f[J.ng];  // the index map after the guards
+        {
+            int64_t row[MAXVAR];
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? a.idx.c[xt[t]] : 0;
+#pragma unroll
+            for (int t = 0; t < MAXVAR; t++) ic[t] = row[t];
+            ic[MAXVAR] = a.idx.k;
+        }
+        // fuse over guards and the index map together
+        bool ovf = false;
+        J.nv = fuse(J.nv, J.ext, J.ng + 1, J.f, &ovf);
+        if (ovf) return PM_EOVERFLOW;
+        if (J.nv == 0) {  // a single access point
+            J.nv = 1;
+            J.ext[0] = 1;
+        }
+        // inner variable: smallest non-zero index coefficient
+        int in = -1;
+        for (int x = 0; x < J.nv; x++) {
+            if (!ic[x]) continue;
+            if (in < 0 || iabs(ic[x]) < iabs(ic[in]) ||
+                (iabs(ic[x]) == iabs(ic[in]) && J.ext[x] > J.ext[in]))
+                in = x;
+        }
+        if (in < 0) in = 0;
+        if (in) {
+            int64_t te = J.ext[0];
+            J.ext[0] = J.ext[in];
+            J.ext[in] = te;
+            for (int g = 0; g <= J.ng; g++) {
+                int64_t tg = J.f[g][0];
+                J.f[g][0] = J.f[g][in];
+                J.f[g][in] = tg;
+            }
+        }
+        J.outer = 1;
+        for (int x = 1; x < J.nv; x++)
+            if (mul_ovf(J.outer, J.ext[x], &J.outer)) return PM_EOVERFLOW;
+        J.seg = iabs(ic[0]) <= J.vec ? SEG_CONTIG : SEG_STRIDED;
+        J.nseg = cdiv(J.ext[0], J.seg);
+        if (mul_ovf(J.outer, J.nseg, &J.items)) return PM_EOVERFLOW;
+        J.chunk_items = CHUNK_FOOT;
+        J.chunks = cdiv(J.items, CHUNK_FOOT);
+        J.ivok = ival_ok(J);
+        J.ivst = PM_OK;
+        J.ivF = J.ivFill = 0;
+        if (J.ivok) J.ivst = ival_sizes(J, &J.ivF, &J.ivFill);
+        if (jt) put_job(&jobs[nj], J);
+        nj++;
+    }
+    *made = nj - base;
+    return PM_OK;
+}
+
+// Footprint mode of every strided array over job slots [0, nj), then the
+// chunk and segment prefixes.  Returns the status.
+PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj) {
     p->njob = nj;
 
     // Each strided array: interval mode when its footprint is a sequence of
@@ -1253,7 +1320,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
             if (jobs[j].kind == JOB_FOOT && jobs[j].arr == ai) nfj++, fj = j;
         if (nfj == 1 && !(v.flags & PM_FLAG_BITMAP) && jobs[fj].ivok) {
             Job &J = jobs[fj];
-            if (J.ivst != PM_OK) return b.fail(PM_EOVERFLOW), p->status;
+            if (J.ivst != PM_OK) return p->status = PM_EOVERFLOW;
             A.fixF = J.ivF;
             A.fixFill = J.ivFill;
             J.kind = JOB_NONE;  // nothing left to enumerate
@@ -1298,6 +1365,51 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
     }
     p->segs = cum;
     return p->status;
+}
+
+// Expand a variant into its program and jobs.  `jobs` has MAXJOB slots.
+// Each job is assembled in *jt when given (fast memory next to a slow
+// `jobs`), else in its slot.  Returns the status; sets per-array bitmap
+// needs and prog->bitmap_words.
+PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr) {
+    int st = build_head(v, p, jobs);
+    if (st != PM_OK) return st;
+    int nj = 0;
+    for (int si = 0; si < p->nstmt; si++) {
+        int k;
+        st = analyze_stmt(p, si, jobs, jt, nj, MAXJOB, PM_EINVAL, &k);
+        if (st != PM_OK) return p->status = st;
+        nj += k;
+    }
+    return build_tail(v, p, jobs, nj);
+}
+
+// The expansion with statements analysed independently: statement si
+// gets job slots 2si and 2si+1.  After analyze_stmt(p, si, jobs, ., 2si,
+// 2si+2, PM_SEQ, .) returned r[si] for every statement, build_slots_finish
+// completes it: the first failing statement's status, or the tail over
+// 2*nstmt slots; a statement that wanted more than two jobs sends the
+// variant through build_prog instead (compact slots, same counts).
+constexpr int PM_SEQ = 1000;  // internal: more than two jobs in a statement
+PM_HD int build_slots_finish(const pm_variant &v, Prog *p, Job *jobs, Job *jt, const int *r) {
+    const int ns = p->nstmt;
+    for (int si = 0; si < ns; si++) {
+        if (r[si] == PM_SEQ) return build_prog(v, p, jobs, jt);
+        if (r[si] != PM_OK) return p->status = r[si];
+    }
+    return build_tail(v, p, jobs, 2 * ns);
+}
+
+// Host form of the same: the statements one after another.
+PM_HD int build_prog_slots(const pm_variant &v, Prog *p, Job *jobs) {
+    int st = build_head(v, p, jobs);
+    if (st != PM_OK) return st;
+    int r[MAXSTMT];
+    for (int si = 0; si < p->nstmt; si++) {
+        int made;
+        r[si] = analyze_stmt(p, si, jobs, nullptr, 2 * si, 2 * si + 2, PM_SEQ, &made);
+    }
+    return build_slots_finish(v, p, jobs, nullptr, r);
 }
 
 // --------------------------------------------------- footprint marking ---
@@ -1354,7 +1466,7 @@ PM_HD void mark_run(uint64_t *bm, int64_t nwords, int64_t first, int64_t step,
 template <class ORF>
 PM_HD void foot_item(const Job &J, int64_t it, uint64_t *vbase, int ln, int nl,
                      ORF orf) {
-    int64_t o = it / J.nseg, sg = it % J.nseg;
+    const int64_t o = tdiv(it, J.nseg), sg = it - o * J.nseg;
     int64_t r[MAXGUARD], base, lo, hi;
     eval_outer(J, o, r, &base);
     inner_range(J, r, &lo, &hi);

@@ -110,6 +110,20 @@ def test_host_counts_match_oracle(v):
     _same(dict(v, bitmap=True))  # bitmap footprints instead of intervals
 
 
+@pytest.mark.parametrize("v", FAMILY_CASES, ids=lambda v: "-".join(str(x) for x in v.values()))
+def test_per_statement_expansion_matches_one_pass(v):
+    """Statements expanded one by one in two job slots each (the GPU's
+    layout, with its fall-back when a statement needs more jobs) give the
+    same counts and footprints as the one-pass expansion."""
+    for d in (v, dict(v, bitmap=True)):
+        assert P.count_host(d, True) == P.count_host(d, True, sequential=True)
+
+
+def test_per_statement_expansion_on_batched_workload():
+    for v in suite_batched(count=256):
+        assert P.count_host(v, True) == P.count_host(v, True, sequential=True)
+
+
 def test_host_counts_on_batched_workload_sample():
     """Small-domain draws of the batched sweep (same generator, smaller
     domains so the oracle finishes quickly): uneven extents that are not
