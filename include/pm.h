@@ -98,10 +98,13 @@ enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC 
  *             filt[j][u][v][c] for 3 images (n+6)^2 x 3 and 3 filters
  *             7 x 7 x 3, channel fastest; fp32
  * flags: PM_FLAG_BITMAP counts every footprint with bitmaps, also where
- * the interval form applies (same counts; for cross-checks).
+ * the interval form applies; PM_FLAG_ENUMERATE runs every count job in the
+ * chip-wide count kernel, also where the work-group that expanded the
+ * descriptor could count it itself (same counts; both for cross-checks).
  * Unused fields must be zero.  `seed` is carried for the caller's records.
  */
 #define PM_FLAG_BITMAP 1u
+#define PM_FLAG_ENUMERATE 2u
 typedef struct {
     uint32_t family, dtype, op, flags;
     int64_t n[3];

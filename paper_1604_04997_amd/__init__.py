@@ -137,7 +137,7 @@ def variant_struct(d: dict) -> Variant:
     v.dtype = 1 if d.get("dtype", "f32") == "f64" else 0
     v.op = OPS.get(fam, {}).get(d.get("op"), 0)
     v.seed = int(d.get("seed", 0)) & ((1 << 64) - 1)
-    v.flags = 1 if d.get("bitmap") else 0
+    v.flags = (1 if d.get("bitmap") else 0) | (2 if d.get("enumerate") else 0)
     if fam == "stream":
         v.n[0], v.wg[0] = d["n"], d["wg"]
         v.stride, v.gstride, v.vec, v.reps = d["s"], d.get("gs", 1), d.get("vec", 1), d.get("U", 1)

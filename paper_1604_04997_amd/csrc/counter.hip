@@ -8,8 +8,9 @@
 //             opcount) and the FP64 prediction.  A variant whose footprints
 //             need bitmaps (or whose jobs exceed FUSED_MAX_ITEMS items) is
 //             handed on: its descriptor is copied to HBM, status PM_DEFER.
-// k_build     larger batches, one 64-wide work-group per variant: the
-//             descriptor and jobs go to HBM and every variant is handed on.
+// k_build     larger batches, one 64-wide work-group per variant: counts
+//             small count jobs itself and finishes those variants, hands the
+//             others on with their descriptor and jobs in HBM.
 // For handed-on variants only:
 //   k_scan      one work-group: prefix sums of bitmap words, work chunks and
 //               fill segments per variant; bitmaps that overflow the arena
@@ -60,36 +61,6 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
     if (t == 0) sh[0] = build_slots_finish(v, p, jobs, &jt[0], sh + 1);
     __syncthreads();
     return sh[0];
-}
-
-// One variant per 64-wide work-group, expanded in LDS and copied to HBM.
-// Every valid variant continues in the general pipeline.
-__global__ void __launch_bounds__(64)
-k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
-        int64_t *varwords, int64_t *varchunks, int64_t *varsegs, int64_t *jobres,
-        int64_t *foot) {
-    __shared__ Prog P;
-    __shared__ Job JT[MAXSTMT];
-    __shared__ int sh[1 + MAXSTMT];
-    const int i = blockIdx.x, t = threadIdx.x;
-    if (i >= nv) return;
-    const pm_variant v = var[i];
-    int st = build_block(v, &P, &jobs[(int64_t)i * MAXJOB], JT, sh);
-    if (st == PM_OK) st = PM_DEFER;
-    if (t == 0) {
-        status[i] = st;
-        varwords[i] = st == PM_DEFER ? P.bitmap_words : 0;
-        varchunks[i] = st == PM_DEFER ? P.chunks : 0;
-        varsegs[i] = st == PM_DEFER ? P.segs : 0;
-    }
-    if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
-    if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
-    // the program to HBM: header and used statements
-    const int ns = P.nstmt < MAXSTMT ? P.nstmt : MAXSTMT;
-    const size_t words = (offsetof(Prog, st) + (size_t)ns * sizeof(Stmt)) / 8;
-    const uint64_t *src = (const uint64_t *)&P;
-    uint64_t *dst = (uint64_t *)&prog[i];
-    for (size_t w = t; w < words; w += 64) dst[w] = src[w];
 }
 
 // Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
@@ -153,6 +124,90 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
     return st2;
 }
 
+// One variant per 64-wide work-group, expanded in LDS.  A variant without
+// bitmaps whose count jobs hold at most BUILD_MAX_ITEMS items (and fit the
+// LDS staging slots) is finished here: its jobs are counted by the
+// work-group, then the count vector and prediction are written.  Any other
+// is handed on with its program and jobs in HBM (status PM_DEFER).
+constexpr int64_t BUILD_MAX_ITEMS = 4096;
+__global__ void __launch_bounds__(64)
+k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
+        int64_t *varwords, int64_t *varchunks, int64_t *varsegs, int64_t *jobres,
+        int64_t *foot, pm_counts *counts, pm_model model, int has_model, double *pred) {
+    __shared__ Prog P;
+    __shared__ union {
+        Job jt[MAXSTMT];  // during the expansion; then the count jobs
+        FinShared fin;    // for the count vector
+    } U;
+    __shared__ int64_t jr[MAXJOB];
+    __shared__ int64_t zero[MAXARR];
+    __shared__ int sh[1 + MAXSTMT];
+    __shared__ int jid[MAXSTMT];
+    __shared__ int64_t jitems[MAXJOB];  // items of count-job slots, -1 for others
+    const int i = blockIdx.x, t = threadIdx.x;
+    if (i >= nv) return;
+    if (t < MAXJOB) jr[t] = 0;
+    if (t < MAXARR) zero[t] = 0;
+    const pm_variant v = var[i];
+    Job *vj = &jobs[(int64_t)i * MAXJOB];
+    int st = build_block(v, &P, vj, U.jt, sh);
+    bool here = st == PM_OK && P.bitmap_words == 0 && !(P.flags & PM_FLAG_ENUMERATE);
+    if (here && t < P.njob) jitems[t] = vj[t].kind == JOB_COUNT ? vj[t].items : -1;
+    __syncthreads();
+    if (t == 0) {  // can this work-group finish the variant?
+        int ncj = 0;
+        int64_t items = 0;
+        for (int j = 0; j < P.njob && here; j++) {
+            if (jitems[j] < 0) continue;
+            if (ncj == MAXSTMT) here = false;
+            else jid[ncj++] = j;
+            items += jitems[j];
+        }
+        sh[0] = here && items <= BUILD_MAX_ITEMS ? ncj : -1;
+    }
+    __syncthreads();
+    const int ncj = sh[0];
+    if (ncj >= 0) {
+        for (int k = 0; k < ncj; k++) {  // stage the count jobs in LDS
+            const uint64_t *src = (const uint64_t *)&vj[jid[k]];
+            uint64_t *dst = (uint64_t *)&U.jt[k];
+            for (size_t w = t; w < sizeof(Job) / 8; w += 64) dst[w] = src[w];
+        }
+        __syncthreads();
+        for (int k = 0; k < ncj; k++) {
+            const Job &J = U.jt[k];
+            int64_t s0 = 0;
+            for (int64_t it = t; it < J.items; it += 64) s0 += count_item(J, it);
+            for (int off = 32; off > 0; off >>= 1) s0 += __shfl_xor(s0, off);
+            if (t == 0) jr[jid[k]] = s0;
+        }
+        __syncthreads();
+        const int s2 = finalize_block(P, jr, zero, zero, PM_OK, U.fin,
+                                      counts ? &counts[i] : nullptr, model, has_model,
+                                      pred ? &pred[i] : nullptr);
+        if (t == 0) {
+            status[i] = s2;
+            varwords[i] = varchunks[i] = varsegs[i] = 0;
+        }
+        return;
+    }
+    if (st == PM_OK) st = PM_DEFER;
+    if (t == 0) {
+        status[i] = st;
+        varwords[i] = st == PM_DEFER ? P.bitmap_words : 0;
+        varchunks[i] = st == PM_DEFER ? P.chunks : 0;
+        varsegs[i] = st == PM_DEFER ? P.segs : 0;
+    }
+    if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
+    if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
+    // the program to HBM: header and used statements
+    const int ns = P.nstmt < MAXSTMT ? P.nstmt : MAXSTMT;
+    const size_t words = (offsetof(Prog, st) + (size_t)ns * sizeof(Stmt)) / 8;
+    const uint64_t *src = (const uint64_t *)&P;
+    uint64_t *dst = (uint64_t *)&prog[i];
+    for (size_t w = t; w < words; w += 64) dst[w] = src[w];
+}
+
 __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
@@ -177,7 +232,9 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int64_t items = 0;
         for (int j = 0; j < P.njob; j++)
             if (J[j].kind != JOB_NONE) items += J[j].items;
-        if (st == PM_OK && (P.bitmap_words > 0 || items > FUSED_MAX_ITEMS)) st = PM_DEFER;
+        const bool enumerate = (P.flags & PM_FLAG_ENUMERATE) && items > 0;
+        if (st == PM_OK && (P.bitmap_words > 0 || items > FUSED_MAX_ITEMS || enumerate))
+            st = PM_DEFER;
         st_sh = st;
     }
     if (t < MAXJOB) jr[t] = 0;
@@ -218,85 +275,90 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     if (t == 0) status[i] = s2;
 }
 
-// Block-wide inclusive scan of per-thread int64 values (SCAN_THREADS).
-__device__ int64_t block_scan_incl(int64_t x, int64_t *sh) {
-    int t = threadIdx.x;
-    sh[t] = x;
-    __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        int64_t y = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += y;
-        __syncthreads();
+// Inclusive scan of per-thread int64 values over the work-group
+// (SCAN_THREADS threads): lanes by shuffles, then the wavefront totals.
+// ws: SCAN_THREADS / 64 slots; ws[last] ends as the total.
+__device__ int64_t block_incl_scan(int64_t x, int64_t *ws) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    constexpr int NW = SCAN_THREADS / 64;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    int64_t r = sh[t];
+    if (lane == 63) ws[w] = x;
     __syncthreads();
-    return r;
-}
-
-// In-place prefix sum of a[0, n) by one work-group (each thread a
-// contiguous slice); elements with !ok(i) count as 0.  Inclusive, or
-// exclusive if `excl`.  Returns the total.
-template <class OK>
-__device__ int64_t scan_inplace(int64_t n, int64_t *a, OK ok, bool excl,
-                                int64_t *sh) {
-    int t = threadIdx.x;
-    int64_t per = (n + SCAN_THREADS - 1) / SCAN_THREADS;
-    int64_t lo = t * per < n ? t * per : n;
-    int64_t hi = lo + per < n ? lo + per : n;
-    int64_t s = 0;
-    for (int64_t i = lo; i < hi; i++) s += ok(i) ? a[i] : 0;
-    int64_t incl = block_scan_incl(s, sh);
-    int64_t run = incl - s;
-    for (int64_t i = lo; i < hi; i++) {
-        int64_t x = ok(i) ? a[i] : 0;
-        if (excl) {
-            a[i] = run;
-            run += x;
-        } else {
-            run += x;
-            a[i] = run;
+    if (t < 64) {
+        int64_t v = t < NW ? ws[t] : 0;
+#pragma unroll
+        for (int off = 1; off < NW; off <<= 1) {
+            const int64_t y = __shfl_up(v, off);
+            if (lane >= off) v += y;
         }
+        if (t < NW) ws[t] = v;
     }
-    int64_t tot = sh[SCAN_THREADS - 1];
     __syncthreads();
-    return tot;
+    return w ? x + ws[w - 1] : x;
 }
 
+// One work-group: exclusive bitmap offsets (variants whose bitmaps would
+// pass the arena's end get PM_ENOMEM), then inclusive prefixes of the
+// chunks and fill segments of the variants still handed on.  Each thread
+// owns a contiguous slice of variants.
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
        int64_t *varchunks, int64_t *varsegs, int64_t *meta, int64_t arena_words) {
-    __shared__ int64_t sh[SCAN_THREADS];
-    for (int64_t i = threadIdx.x; i < nv; i += SCAN_THREADS) varoff[i] = varwords[i];
-    __syncthreads();
-    int64_t need = scan_inplace(nv, varoff, [](int64_t) { return true; }, true, sh);
+    constexpr int NW = SCAN_THREADS / 64;
+    __shared__ int64_t ws[3][NW];
+    __shared__ int64_t mx[NW];
+    const int t = threadIdx.x;
+    const int64_t per = ((int64_t)nv + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t lo = t * per < nv ? t * per : nv, hi = lo + per < nv ? lo + per : nv;
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; i++) s += varwords[i];
+    int64_t run = block_incl_scan(s, ws[0]) - s;
     int64_t used = 0;
     // only variants that hold bitmap words bound the region to clear: a
     // variant without bitmaps may sit at an offset past the arena's end
-    for (int64_t i = threadIdx.x; i < nv; i += SCAN_THREADS) {
-        if (varwords[i] == 0) continue;
-        int64_t end = varoff[i] + varwords[i];
-        if (end > arena_words) status[i] = PM_ENOMEM;
-        else if (end > used) used = end;
+    for (int64_t i = lo; i < hi; i++) {
+        const int64_t w = varwords[i];
+        varoff[i] = run;
+        if (w) {
+            const int64_t end = run + w;
+            if (end > arena_words) status[i] = PM_ENOMEM;
+            else if (end > used) used = end;
+        }
+        run += w;
     }
-    sh[threadIdx.x] = used;
-    __syncthreads();
-    for (int off = SCAN_THREADS / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off && sh[threadIdx.x + off] > sh[threadIdx.x])
-            sh[threadIdx.x] = sh[threadIdx.x + off];
-        __syncthreads();
+    int64_t c = 0, g = 0;
+    for (int64_t i = lo; i < hi; i++)
+        if (status[i] == PM_DEFER) {
+            c += varchunks[i];
+            g += varsegs[i];
+        }
+    int64_t rc = block_incl_scan(c, ws[1]) - c;
+    int64_t rg = block_incl_scan(g, ws[2]) - g;
+    for (int64_t i = lo; i < hi; i++) {
+        const bool ok = status[i] == PM_DEFER;
+        rc += ok ? varchunks[i] : 0;
+        rg += ok ? varsegs[i] : 0;
+        varchunks[i] = rc;
+        varsegs[i] = rg;
     }
-    used = sh[0];
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t y = __shfl_xor(used, off);
+        if (y > used) used = y;
+    }
+    if ((t & 63) == 0) mx[t >> 6] = used;
     __syncthreads();
-    auto ok = [&](int64_t i) { return status[i] == PM_DEFER; };
-    int64_t tc = scan_inplace(nv, varchunks, ok, false, sh);
-    int64_t ts = scan_inplace(nv, varsegs, ok, false, sh);
-    if (threadIdx.x == 0) {
-        meta[0] = tc;
+    if (t == 0) {
+        for (int k = 1; k < NW; k++)
+            if (mx[k] > used) used = mx[k];
+        meta[0] = ws[1][NW - 1];
         meta[1] = used;
-        meta[2] = ts;
+        meta[2] = ws[2][NW - 1];
         meta[3] = 0;  // ticket
-        meta[4] = need;
+        meta[4] = ws[0][NW - 1];
     }
 }
 
@@ -490,7 +552,7 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
     else
         hipLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, nv, d_var, ar.prog, ar.jobs,
                            d_status, ar.varwords, ar.varchunks, ar.varsegs, ar.jobres,
-                           ar.foot);
+                           ar.foot, d_counts, m, has, d_pred);
     mark();
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
                        (const int64_t *)ar.varwords, ar.varoff, ar.varchunks,

@@ -111,7 +111,8 @@ struct ArrInfo {
 
 struct Prog {
     int32_t status, nstmt, narr, njob;
-    int32_t wg_size, pad;
+    int32_t wg_size;
+    uint32_t flags;            // the variant's PM_FLAG_*
     int64_t n_wg;
     int64_t bitmap_words;
     int64_t chunks;            // work chunks of all jobs
@@ -1023,6 +1024,7 @@ PM_HD void put_job(Job *dst, const Job &src) {
 // fill width of every array with a strided access.  Returns the status.
 PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     p->status = PM_OK;
+    p->flags = v.flags;
     p->nstmt = p->narr = p->njob = 0;
     p->wg_size = 1;
     p->n_wg = 0;

@@ -42,7 +42,8 @@ def _strip(d):
 # ---------------------------------------------------------------- counts --
 def test_counts_match_oracle_in_one_batch(ctx):
     vs = FAMILY_CASES + suite_batched(count=64, lo_log2=8, hi_log2=13)
-    vs = vs + [dict(v, bitmap=True) for v in vs]  # both footprint methods
+    # both footprint methods; count jobs where components are enumerated
+    vs = vs + [dict(v, bitmap=True) for v in vs] + [dict(v, enumerate=True) for v in vs]
     print("counting %d variants in one batch" % len(vs), flush=True)
     got = ctx.count(vs)
     for v, g in zip(vs, got):
@@ -52,6 +53,7 @@ def test_counts_match_oracle_in_one_batch(ctx):
 def test_counts_full_size_closed_forms(ctx):
     vs = suite_batched(4096) + suite_instructive() + suite_test() + suite_tiny()
     vs = vs + [dict(v, bitmap=True) for v in suite_batched(512, seed=3)]
+    vs = vs + [dict(v, enumerate=True) for v in suite_batched(512, seed=5)]
     print("counting %d full-size variants" % len(vs), flush=True)
     got = ctx.count(vs)
     for v, g in zip(vs, got):

@@ -108,6 +108,7 @@ FAMILY_CASES = [
 def test_host_counts_match_oracle(v):
     _same(v)
     _same(dict(v, bitmap=True))  # bitmap footprints instead of intervals
+    _same(dict(v, enumerate=True))  # count jobs instead of inline enumeration
 
 
 @pytest.mark.parametrize("v", FAMILY_CASES, ids=lambda v: "-".join(str(x) for x in v.values()))
@@ -115,7 +116,7 @@ def test_per_statement_expansion_matches_one_pass(v):
     """Statements expanded one by one in two job slots each (the GPU's
     layout, with its fall-back when a statement needs more jobs) give the
     same counts and footprints as the one-pass expansion."""
-    for d in (v, dict(v, bitmap=True)):
+    for d in (v, dict(v, bitmap=True), dict(v, enumerate=True)):
         assert P.count_host(d, True) == P.count_host(d, True, sequential=True)
 
 
