@@ -45,34 +45,31 @@ constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 // Expansion of one variant by a work-group (at least MAXSTMT threads; all
 // call this): thread 0 lays out the statements, thread si analyses
 // statement si in job slots 2si and 2si+1, thread 0 finishes
-// (build_slots_finish).  p and jt (MAXSTMT job buffers) are in LDS; sh
-// holds 1 + MAXSTMT ints.
+// (build_slots_finish).  p and the NTEMP job buffers jt are in LDS, handed
+// to the first statements that make jobs (the others make theirs in
+// place); sh holds 2 + MAXSTMT ints.
+constexpr int NTEMP = 4;
 __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jobs, Job *jt,
                                            int *sh) {
     const int t = threadIdx.x;
-    if (t == 0) sh[0] = build_head(v, p, jobs);
+    if (t == 0) {
+        sh[0] = build_head(v, p, jobs);
+        sh[1 + MAXSTMT] = 0;  // temp buffers handed out
+    }
     __syncthreads();
     if (sh[0] != PM_OK) return sh[0];
     if (t < p->nstmt) {
         int made;
-        sh[1 + t] = analyze_stmt(p, t, jobs, &jt[t], 2 * t, 2 * t + 2, PM_SEQ, &made);
+        auto temp = [&]() -> Job * {
+            const int k = atomicAdd(&sh[1 + MAXSTMT], 1);
+            return k < NTEMP ? &jt[k] : nullptr;
+        };
+        sh[1 + t] = analyze_stmt(p, t, jobs, temp, 2 * t, 2 * t + 2, PM_SEQ, &made);
     }
     __syncthreads();
     if (t == 0) sh[0] = build_slots_finish(v, p, jobs, &jt[0], sh + 1);
     __syncthreads();
     return sh[0];
-}
-
-// Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
-__device__ int64_t block_sum(int64_t x, int64_t *red) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = x;
-    __syncthreads();
-    int64_t t = 0;
-    for (int k = 0; k < FUSED_THREADS / 64; k++) t += red[k];
-    return t;
 }
 
 // Count vector and prediction of one variant by one work-group: every
@@ -136,13 +133,13 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
         int64_t *foot, pm_counts *counts, pm_model model, int has_model, double *pred) {
     __shared__ Prog P;
     __shared__ union {
-        Job jt[MAXSTMT];  // during the expansion; then the count jobs
-        FinShared fin;    // for the count vector
+        Job jt[NTEMP];  // during the expansion; then the count jobs
+        FinShared fin;  // for the count vector
     } U;
     __shared__ int64_t jr[MAXJOB];
     __shared__ int64_t zero[MAXARR];
-    __shared__ int sh[1 + MAXSTMT];
-    __shared__ int jid[MAXSTMT];
+    __shared__ int sh[2 + MAXSTMT];
+    __shared__ int jid[NTEMP];
     __shared__ int64_t jitems[MAXJOB];  // items of count-job slots, -1 for others
     const int i = blockIdx.x, t = threadIdx.x;
     if (i >= nv) return;
@@ -159,7 +156,7 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
         int64_t items = 0;
         for (int j = 0; j < P.njob && here; j++) {
             if (jitems[j] < 0) continue;
-            if (ncj == MAXSTMT) here = false;
+            if (ncj == NTEMP) here = false;
             else jid[ncj++] = j;
             items += jitems[j];
         }
@@ -208,6 +205,18 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     for (size_t w = t; w < words; w += 64) dst[w] = src[w];
 }
 
+// Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
+__device__ int64_t block_sum(int64_t x, int64_t *red) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = x;
+    __syncthreads();
+    int64_t t = 0;
+    for (int k = 0; k < FUSED_THREADS / 64; k++) t += red[k];
+    return t;
+}
+
 __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
@@ -215,12 +224,12 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int has_model, double *pred) {
     __shared__ Prog P;
     __shared__ Job J[MAXJOB];
-    __shared__ Job JT[MAXSTMT];
+    __shared__ Job JT[NTEMP];
     __shared__ int64_t jr[MAXJOB];
     __shared__ int64_t fF[MAXARR], fFill[MAXARR];
     __shared__ int64_t red[FUSED_THREADS / 64];
     __shared__ FinShared fin;
-    __shared__ int bsh[1 + MAXSTMT];
+    __shared__ int bsh[2 + MAXSTMT];
     __shared__ int st_sh;
     const int i = blockIdx.x;
     const int t = threadIdx.x;

@@ -36,9 +36,9 @@
 namespace pm {
 
 constexpr int MAXVAR = 8;
-constexpr int MAXGUARD = 6;
-constexpr int MAXACC = 6;
-constexpr int MAXSTMT = 12;
+constexpr int MAXGUARD = 4;  // the most any family needs (stencil halo, convolution tile)
+constexpr int MAXACC = 5;    // the most any family needs (4 loads + 1 store)
+constexpr int MAXSTMT = 10;  // the largest family (the stencil) has 9 statements
 constexpr int MAXARR = 6;
 constexpr int MAXJOB = 24;
 constexpr int MAXCOMP = 4;
@@ -1072,13 +1072,17 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
 
 // Counts of statement si (its fixed factor and components) and its jobs,
 // numbered from `base`: a job number reaching `cap` returns `over`.  Jobs
-// are assembled in *jt when given, else in their slots.  *made: jobs made.
-// Reads the program and writes only statement si and its job slots, so
-// statements may be analysed concurrently.  Returns a status.
-PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, Job *jt, int base, int cap, int over,
+// are assembled in the buffer temp() gives when the first one is made
+// (fast memory next to a slow `jobs`), else (nullptr) in their slots.
+// *made: jobs made.  Reads the program and writes only statement si and its
+// job slots, so statements may be analysed concurrently.  Returns a status.
+template <class TEMP>
+PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap, int over,
                        int *made) {
     int nj = base;
     *made = 0;
+    Job *jt = nullptr;
+    bool asked = false;
     Stmt &s = p->st[si];
     s.ncomp = 0;
     const int nvar = s.nvar, ng = s.nguard;
@@ -1135,6 +1139,7 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, Job *jt, int base, int cap, i
         }
         if (nj >= cap) return over;
         if (s.ncomp >= MAXCOMP) return PM_EINVAL;
+        if (!asked) jt = temp(), asked = true;
         Job &J = jt ? *jt : jobs[nj];  // kept only if it enumerates
         J.kind = JOB_COUNT;
         J.nv = 0;
@@ -1211,6 +1216,7 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, Job *jt, int base, int cap, i
         ArrInfo &A = p->arr[a.arr];
         if (!A.w) continue;
         if (nj >= cap) return over;
+        if (!asked) jt = temp(), asked = true;
         Job &J = jt ? *jt : jobs[nj];
         J.kind = JOB_FOOT;
         J.nv = 0;
@@ -1379,7 +1385,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
     int nj = 0;
     for (int si = 0; si < p->nstmt; si++) {
         int k;
-        st = analyze_stmt(p, si, jobs, jt, nj, MAXJOB, PM_EINVAL, &k);
+        st = analyze_stmt(p, si, jobs, [jt]() { return jt; }, nj, MAXJOB, PM_EINVAL, &k);
         if (st != PM_OK) return p->status = st;
         nj += k;
     }
@@ -1393,6 +1399,7 @@ PM_HD int build_prog(const pm_variant &v, Prog *p, Job *jobs, Job *jt = nullptr)
 // 2*nstmt slots; a statement that wanted more than two jobs sends the
 // variant through build_prog instead (compact slots, same counts).
 constexpr int PM_SEQ = 1000;  // internal: more than two jobs in a statement
+static_assert(2 * MAXSTMT <= MAXJOB, "two job slots per statement");
 PM_HD int build_slots_finish(const pm_variant &v, Prog *p, Job *jobs, Job *jt, const int *r) {
     const int ns = p->nstmt;
     for (int si = 0; si < ns; si++) {
@@ -1409,7 +1416,8 @@ PM_HD int build_prog_slots(const pm_variant &v, Prog *p, Job *jobs) {
     int r[MAXSTMT];
     for (int si = 0; si < p->nstmt; si++) {
         int made;
-        r[si] = analyze_stmt(p, si, jobs, nullptr, 2 * si, 2 * si + 2, PM_SEQ, &made);
+        r[si] = analyze_stmt(p, si, jobs, []() { return (Job *)nullptr; }, 2 * si, 2 * si + 2,
+                             PM_SEQ, &made);
     }
     return build_slots_finish(v, p, jobs, nullptr, r);
 }
