@@ -139,8 +139,18 @@ typedef struct { int64_t c[PM_NCOUNT]; } pm_counts;
  *   PM_PROJ_FULL  the paper's property list: 90 global access counts,
  *                  6 LDS counts, 10 flop counts (FMA = one add and one mul),
  *                  barriers, work-groups, const 1, 45 min(load, store)
- *                  counts per (size, class) -- 154 features */
-enum { PM_PROJ_P3 = 0, PM_PROJ_P12 = 1, PM_PROJ_FULL = 2 };
+ *                  counts per (size, class) -- 154 features
+ *   PM_PROJ_EXT   PM_PROJ_FULL and three features for what the paper names
+ *                  as extensions (Sec. 6, future work): arithmetic
+ *                  instructions per resident work-item and global bytes per
+ *                  resident work-item (a grid smaller than the GPU holds at
+ *                  once runs as long as one work-item's chain:  x / min(WI,
+ *                  PM_RESIDENT_WI)), and min(arithmetic instructions, global
+ *                  bytes) for arithmetic overlapped with data motion --
+ *                  157 features.  Arithmetic instructions: the sum of the
+ *                  ten flop counts (an FMA once). */
+enum { PM_PROJ_P3 = 0, PM_PROJ_P12 = 1, PM_PROJ_FULL = 2, PM_PROJ_EXT = 3 };
+#define PM_RESIDENT_WI 524288 /* 256 CUs x 2048 work-items */
 #define PM_NFEAT_MAX 160
 typedef struct {
     uint32_t nfeat, proj;

@@ -19,6 +19,9 @@ Feature sets (projections of the count dict of oracle.count.count):
         (direction, size, class) count, per LDS (direction, size), per flop
         (kind, dtype) with an FMA counted as one add and one mul, barriers,
         work-groups, const 1, and min(loads, stores) per (size, class)
+  ext   full and the extensions the paper names as future work (Sec. 6):
+        arithmetic instructions and global bytes per resident work-item,
+        min(arithmetic instructions, global bytes)
 """
 from __future__ import annotations
 
@@ -109,7 +112,23 @@ def features_full(c):
     return out
 
 
-FEATURES = {"p3": features_p3, "p12": features_p12, "full": features_full}
+RESIDENT_WI = 256 * 2048  # work-items the GPU holds at once
+
+
+def features_ext(c):
+    """The paper's list plus its named extensions (Sec. 6): arithmetic
+    instructions and global bytes per resident work-item, and
+    min(arithmetic instructions, global bytes)."""
+    ops = sum(_g(c, "%s.%s" % (k, dt)) for k in ("add", "mul", "div", "exp", "spec", "fma")
+              for dt in ("f32", "f64"))
+    gb = _gbytes(c, "gld", lambda cl: True) + _gbytes(c, "gst", lambda cl: True)
+    wi = min(_g(c, "wi"), RESIDENT_WI)
+    return features_full(c) + [ops / wi if wi else 0.0, gb / wi if wi else 0.0,
+                               float(min(ops, gb))]
+
+
+FEATURES = {"p3": features_p3, "p12": features_p12, "full": features_full,
+            "ext": features_ext}
 
 
 def feature_matrix(counts, proj):

@@ -1648,7 +1648,8 @@ PM_HD int finalize(const Prog &p, const int64_t *jobres, const int64_t *F,
 
 // ------------------------------------------------------------- features ---
 PM_HD int nfeat(uint32_t proj) {
-    return proj == PM_PROJ_P3 ? 3 : proj == PM_PROJ_P12 ? 12 : proj == PM_PROJ_FULL ? 154 : -1;
+    return proj == PM_PROJ_P3 ? 3 : proj == PM_PROJ_P12 ? 12 : proj == PM_PROJ_FULL ? 154 :
+           proj == PM_PROJ_EXT ? 157 : -1;
 }
 
 PM_HD bool full_use_class(int cl) {  // '0', '1', '2/2', '3/3', '4/4'
@@ -1710,6 +1711,18 @@ PM_HD double feature_one(const int64_t *c, uint32_t proj, int j) {
             return s1[0] < s1[1] ? s1[0] : s1[1];
         }
         }
+    }
+    if (proj == PM_PROJ_EXT && j >= 154) {
+        double ops = 0, gb = 0;
+        for (int k = 0; k < 12; k++) ops += (double)c[C_FLOP + k];
+        for (int d = 0; d < 2; d++)
+            for (int z = 0; z < 3; z++)
+                for (int cl = 0; cl < NCLS; cl++)
+                    gb += SZ[z] * (double)c[C_GACC + (d * 3 + z) * NCLS + cl];
+        const double wi = (double)(c[C_WI] < PM_RESIDENT_WI ? c[C_WI] : PM_RESIDENT_WI);
+        if (j == 154) return wi > 0 ? ops / wi : 0.0;
+        if (j == 155) return wi > 0 ? gb / wi : 0.0;
+        return ops < gb ? ops : gb;
     }
     // PM_PROJ_FULL: every global class, LDS, flops (an FMA counts as one add
     // and one mul), barriers, work-groups, a constant, min(load, store) per

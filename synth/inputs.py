@@ -67,12 +67,13 @@ def suite_tiny():
 # ---------------------------------------------------------------------------
 # workload 2: full performance-instructive measurement suite
 # ---------------------------------------------------------------------------
-def suite_instructive(roofline_points: bool = True):
+def suite_instructive(roofline_points: bool = True, extended: bool = False):
     """Performance-instructive kernels: global stream access by dtype,
     direction, lane and group stride and size; stride-2/3 filled access;
     LDS by bank stride; FMA and rsqrt chains; barriers; empty kernels;
     tiled and naive matrix multiplication in four shapes; three transpose
-    configurations."""
+    configurations.  `extended` appends grids smaller than the GPU holds at
+    once (tagged "extension": True), the data for the extension features."""
     out = []
     ns = (1 << 20, 1 << 23, 1 << 26)
     for dt in ("f32", "f64"):
@@ -140,6 +141,23 @@ def suite_instructive(roofline_points: bool = True):
     for (wx, wy) in ((64, 1), (128, 1), (256, 1), (512, 1), (1024, 1)):
         for n in (1 << 10, 1 << 12, 1 << 14):
             out.append(_v("empty", n=n, wx=wx, wy=wy))
+    if extended:
+        # grids smaller than the GPU holds at once: long per-work-item chains
+        # of arithmetic and of global loads
+        ext = []
+        for F in (256, 1024, 4096):
+            for n in (1 << 12, 1 << 14, 1 << 16):
+                ext.append(_v("fma", dtype="f32", n=n, wg=256, F=F, K=8))
+        for F in (256, 1024):
+            for n in (1 << 12, 1 << 14):
+                ext.append(_v("rsqrt", n=n, wg=256, F=F, K=4))
+        for U in (16, 64):
+            for n in (1 << 14, 1 << 16):
+                ext.append(_v("stream", op="load", dtype="f32", n=n, wg=256, s=1, gs=1,
+                              vec=1, U=U))
+        for v in ext:
+            v["extension"] = True
+        out += ext
     for i, v in enumerate(out):
         v["seed"] = seed_for(2, i)
     return out

@@ -1,0 +1,123 @@
+"""GPU edge cases of the batched counter, through the C ABI: per-variant
+statuses in a batch that mixes valid, invalid and overflowing descriptors
+(on both expansion kernels: batches of up to 32 variants and larger ones),
+the empty batch, batch sizes around the switch between the two kernels,
+and the largest batch one call accepts."""
+import numpy as np
+import pytest
+
+import paper_1604_04997_amd as P
+from oracle import count as C
+
+from closed_forms import counts as closed_counts
+from test_lib_host import FAMILY_CASES
+
+pytestmark = pytest.mark.gpu
+
+PM_EINVAL, PM_EOVERFLOW = -1, -5
+
+BAD = dict(family="matmul", op="tiled", n=16, m=16, l=16, T=12)          # tile not 8/16/32
+HUGE = dict(family="stream", op="load", dtype="f32", n=1 << 40, wg=256,  # count > int64
+            s=1 << 20, gs=1 << 20, vec=1, U=1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _strip(d):
+    return {k: v for k, v in d.items() if not k.startswith("foot.")}
+
+
+def _device_count(ctx, vs, model=None):
+    import torch
+    va = P.variant_array(vs)
+    raw = bytes(memoryview(va).cast("B"))
+    nv = len(vs)
+    d_v = torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
+    d_c = torch.full((nv, P.PM_NCOUNT), 7, dtype=torch.int64, device="cuda")
+    d_t = torch.full((nv,), 7.0, dtype=torch.float64, device="cuda")
+    d_s = torch.full((nv,), 99, dtype=torch.int32, device="cuda")
+    ctx.reserve(nv, sum(P.bitmap_bytes(v) for v in vs if v is not BAD and v is not HUGE))
+    ctx.count_device(d_v.data_ptr(), nv, d_c.data_ptr(), model, d_t.data_ptr(),
+                     d_s.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return d_c.cpu().numpy(), d_t.cpu().numpy(), d_s.cpu().numpy()
+
+
+@pytest.mark.parametrize("nv", [5, 40])
+def test_per_variant_status_in_mixed_batch(ctx, nv):
+    good = [v for v in FAMILY_CASES if v["family"] in ("stencil", "transpose", "matmul")]
+    vs = []
+    for k in range(nv):
+        vs.append(BAD if k % 5 == 1 else HUGE if k % 5 == 3 else good[k % len(good)])
+    m = P.model_struct("p12", np.linspace(1e-12, 1e-11, 12))
+    print("mixed batch of %d variants" % nv, flush=True)
+    cnt, t, st = _device_count(ctx, vs, m)
+    names = P.count_names()
+    for k, v in enumerate(vs):
+        if v is BAD:
+            assert st[k] == PM_EINVAL
+        elif v is HUGE:
+            assert st[k] == PM_EOVERFLOW
+        else:
+            assert st[k] == 0
+            got = {names[i]: int(x) for i, x in enumerate(cnt[k]) if x}
+            assert got == _strip(C.count(v)), v
+            c = P.Counts()
+            c.c[:] = [int(x) for x in cnt[k]]
+            want = float(P.features(c, "p12") @ np.array(m.alpha[:m.nfeat]))
+            assert t[k] == pytest.approx(want, rel=1e-12)
+            continue
+        assert (cnt[k] == 0).all() and t[k] == 0.0
+
+
+def test_empty_batch(ctx):
+    import torch
+    assert ctx.count([]) == []
+    small = torch.zeros(64, dtype=torch.int64, device="cuda")
+    ctx.count_device(small.data_ptr(), 0, small.data_ptr(), None, small.data_ptr(),
+                     small.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert (small.cpu() == 0).all()
+
+
+@pytest.mark.parametrize("nv", [1, 32, 33, 65])
+def test_batch_sizes_around_the_kernel_switch(ctx, nv):
+    vs = [FAMILY_CASES[(7 * k) % len(FAMILY_CASES)] for k in range(nv)]
+    print("batch of %d variants" % nv, flush=True)
+    got = ctx.count(vs)
+    for v, g in zip(vs, got):
+        assert g == _strip(C.count(v)), v
+
+
+def test_largest_batch(ctx):
+    """PM_BATCH_MAX variants in one device call (closed forms check every
+    one); one more is refused before anything runs."""
+    kinds = [dict(family="transpose", op=op, n=n, T=16) for op in ("tiled", "naive_wc")
+             for n in (17, 100, 333)]
+    kinds += [dict(family="stencil", dtype="f32", n=n, T=16) for n in (31, 64, 250)]
+    vs = [kinds[k % len(kinds)] for k in range(P.PM_BATCH_MAX)]
+    print("batch of %d variants" % len(vs), flush=True)
+    cnt, _, st = _device_count(ctx, vs)
+    assert (st == 0).all()
+    names = P.count_names()
+    want = {}
+    for k, v in enumerate(kinds):
+        row = np.zeros(P.PM_NCOUNT, dtype=np.int64)
+        for name, x in closed_counts(v).items():
+            row[names.index(name)] = x
+        want[k] = row
+    for k in range(len(vs)):
+        np.testing.assert_array_equal(cnt[k], want[k % len(kinds)], err_msg=str(vs[k]))
+    import torch
+    small = torch.zeros(64, dtype=torch.int64, device="cuda")  # never read: refused first
+    with pytest.raises(P.PMError):
+        ctx.count_device(small.data_ptr(), P.PM_BATCH_MAX + 1, small.data_ptr(), None,
+                         small.data_ptr(), small.data_ptr(),
+                         torch.cuda.current_stream().cuda_stream)

@@ -201,7 +201,7 @@ def _small(v):
     return v
 
 
-@pytest.mark.parametrize("proj", ["p3", "p12", "full"])
+@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext"])
 def test_features_match_oracle(proj):
     vs = [_small(v) for v in suite_tiny() + suite_test()[::3]]
     arr = _lib_counts(vs)
@@ -211,9 +211,9 @@ def test_features_match_oracle(proj):
         np.testing.assert_array_equal(lib, np.array(orc, dtype=np.float64))
 
 
-@pytest.mark.parametrize("proj", ["p3", "p12", "full"])
+@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext"])
 def test_fit_matches_numpy_oracle(proj):
-    vs = [_small(v) for v in suite_instructive(roofline_points=False)
+    vs = [_small(v) for v in suite_instructive(roofline_points=False, extended=True)
           + suite_test()]
     arr = _lib_counts(vs)
     F = np.array([P.features(arr[i], proj) for i in range(len(vs))])
@@ -231,6 +231,17 @@ def test_fit_matches_numpy_oracle(proj):
     full_rank = rank == int(np.count_nonzero(np.any(F != 0, axis=0)))
     if full_rank and cond < 1e8:  # weights are unique only at full rank
         np.testing.assert_allclose(alpha, ao, rtol=1e-7, atol=1e-30)
+
+
+def test_extension_features_at_full_size():
+    """Full-size test kernels (grids above and below what the GPU holds at
+    once): the library's extension features against the oracle's, on
+    closed-form counts."""
+    from closed_forms import counts as closed_counts
+    for v in suite_test():
+        lib = P.features(_lib_counts([v])[0], "ext")
+        orc = M.features_ext(closed_counts(v))
+        np.testing.assert_array_equal(lib, np.array(orc, dtype=np.float64), err_msg=str(v))
 
 
 def test_fit_exact_recovery_and_errors():
