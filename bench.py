@@ -180,7 +180,16 @@ def model_phase(ctx, P, proj_list=("p12", "full", "ext")):
                 size = v["m"] if v["kernel"] == "skinny_mm" else v["n"]
                 table.setdefault(v["kernel"], []).append(
                     [size, round(Tt[i] * 1e3, 4), round(float(pred[i]) * 1e3, 4)])
-        out[proj] = {"geomean": round(gm, 4), "per_kernel": fam,
+        # work-group size sensitivity: error by tile (work-group T x T) and
+        # by n-body block size
+        by_wg = {}
+        for i, v in enumerate(test):
+            wg = v.get("T", v.get("wg"))
+            if wg:
+                by_wg.setdefault("%s.%d" % (v["kernel"], wg), []).append(err[i])
+        by_wg = {k: round(float(math.exp(np.mean(np.log(np.maximum(e, 1e-12))))), 4)
+                 for k, e in sorted(by_wg.items())}
+        out[proj] = {"geomean": round(gm, 4), "per_kernel": fam, "per_work_group": by_wg,
                      "table1_ms_actual_predicted": table,
                      "geomean_paper_test_kernels": round(float(math.exp(np.mean(np.log(
                          np.maximum(paper4, 1e-12))))), 4), "rank": rank,
