@@ -72,26 +72,103 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
     return sh[0];
 }
 
-// Count vector and prediction of one variant by one work-group: every
-// thread calls this, the first wavefront does the work.  Lanes gather the
-// statement counts and the non-zero contributions (compacted by ballot),
-// then each lane owns the count slots k = lane (mod 64) and the features
-// i = lane (mod 64); the prediction's 64 partial sums meet in a butterfly,
-// the order predict() fixes.  st != PM_OK: zero counts, prediction 0.
 struct FinShared {
     int64_t c[PM_NCOUNT];
     int64_t sc[MAXSTMT];
     Contrib list[MAXSTMT * NENT];
-    int bad;
+    int bad, big;
 };
 
+// Sums over a count vector that the projections use, by the 64 lanes (lane
+// l takes slots l and l + 64; a butterfly combines them).  Every term is an
+// integer, so while the sums stay below 2^53 they are exact and equal to
+// the serial sums of feature_one.
+struct Agg {
+    double gb, ops, sp, ldsb, full0, full1, part0, part1, s10, s11;
+};
+__device__ inline double wave_sum(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+__device__ Agg wave_aggregates(const int64_t *c, int l) {
+    Agg a{};
+    for (int k = l; k < PM_NCOUNT; k += 64) {
+        const double x = (double)c[k];
+        if (k < C_LDS) {
+            const int d = k / 45, z = (k % 45) / NCLS, cl = k % NCLS;
+            const double b = (z == 0 ? 4.0 : z == 1 ? 8.0 : 16.0) * x;
+            const bool fu = full_use_class(cl);
+            a.gb += b;
+            a.full0 += (d == 0 && fu) ? b : 0.0;
+            a.full1 += (d == 1 && fu) ? b : 0.0;
+            a.part0 += (d == 0 && !fu) ? b : 0.0;
+            a.part1 += (d == 1 && !fu) ? b : 0.0;
+            a.s10 += (d == 0 && cl == 1) ? b : 0.0;
+            a.s11 += (d == 1 && cl == 1) ? b : 0.0;
+        } else if (k < C_FLOP) {
+            const int z = (k - C_LDS) % 3;
+            a.ldsb += (z == 0 ? 4.0 : z == 1 ? 8.0 : 16.0) * x;
+        } else if (k < C_BARWI) {
+            a.ops += x;
+            const int kind = (k - C_FLOP) / 2;
+            if (kind == K_SPEC || kind == K_DIV || kind == K_EXP) a.sp += x;
+        }
+    }
+    a.gb = wave_sum(a.gb);
+    a.ops = wave_sum(a.ops);
+    a.sp = wave_sum(a.sp);
+    a.ldsb = wave_sum(a.ldsb);
+    a.full0 = wave_sum(a.full0);
+    a.full1 = wave_sum(a.full1);
+    a.part0 = wave_sum(a.part0);
+    a.part1 = wave_sum(a.part1);
+    a.s10 = wave_sum(a.s10);
+    a.s11 = wave_sum(a.s11);
+    return a;
+}
+
+// feature_one(c, proj, j), with the sums over many slots taken from `a`.
+__device__ double feature_dev(const int64_t *c, uint32_t proj, int j, const Agg &a) {
+    if (proj == PM_PROJ_P3) return j == 0 ? a.gb : feature_one(c, proj, j);
+    if (proj == PM_PROJ_P12) {
+        switch (j) {
+        case 5: return a.sp;
+        case 6: return a.ldsb;
+        case 7: return a.full0;
+        case 8: return a.full1;
+        case 9: return a.part0;
+        case 10: return a.part1;
+        case 11: return a.s10 < a.s11 ? a.s10 : a.s11;
+        default: return feature_one(c, proj, j);
+        }
+    }
+    if (proj == PM_PROJ_EXT && j >= 154) {
+        const double wi = (double)(c[C_WI] < PM_RESIDENT_WI ? c[C_WI] : PM_RESIDENT_WI);
+        if (j == 154) return wi > 0 ? a.ops / wi : 0.0;
+        if (j == 155) return wi > 0 ? a.gb / wi : 0.0;
+        return a.ops < a.gb ? a.ops : a.gb;
+    }
+    return feature_one(c, proj, j);
+}
+
+// Count vector and prediction of one variant by one work-group: every
+// thread calls this, the first wavefront does the work.  Lanes take the
+// statement counts and the non-zero contributions (compacted by ballot)
+// and add the contributions into the slots with LDS atomics (exact: while
+// every product is below 2^54 no sum of at most MAXSTMT*NENT of them can
+// pass int64; larger products take the per-slot sums with overflow
+// checks).  Lane l then owns the features i = l (mod 64); the
+// prediction's 64 partial sums meet in a butterfly, the order predict()
+// fixes.  st != PM_OK: zero counts, prediction 0.
 __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobres, const int64_t *F,
                               const int64_t *Fill, int st, FinShared &sh, pm_counts *out,
                               const pm_model &model, int has_model, double *pred) {
     const int t = threadIdx.x, l = t & 63;
     const bool w0 = t < 64;
     const int nst = st == PM_OK ? p.nstmt : 0;
-    if (t == 0) sh.bad = 0;
+    if (t == 0) sh.bad = sh.big = 0;
+    if (w0)
+        for (int k = l; k < PM_NCOUNT; k += 64) sh.c[k] = 0;
     __syncthreads();
     if (w0 && l < nst && !stmt_count(p, l, jobres, &sh.sc[l])) sh.bad = 1;
     int n = 0;
@@ -104,9 +181,25 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
         n += __popcll(mask);
     }
     __syncthreads();
-    if (w0 && st == PM_OK)
+    if (w0 && st == PM_OK) {
+        for (int i = l; i < n; i += 64) {
+            const Contrib cc = sh.list[i];
+            int64_t v;
+            if (mul_ovf(sh.sc[cc.stmt], (int64_t)cc.mult, &v)) sh.bad = 1;
+            else if (v >= (1ll << 54)) sh.big = 1;
+            else if (v) atomicAdd((unsigned long long *)&sh.c[cc.slot], (unsigned long long)v);
+        }
+        if (l == 0) {
+            sh.c[C_WG] = p.n_wg;
+            if (mul_ovf(p.n_wg, (int64_t)p.wg_size, &sh.c[C_WI])) sh.bad = 1;
+        }
+    }
+    __syncthreads();
+    if (w0 && st == PM_OK && sh.big)  // products this large: exact sums slot by slot
         for (int k = l; k < PM_NCOUNT; k += 64)
-            if (k != C_BARWG && !slot_value(p, k, sh.list, n, sh.sc, &sh.c[k])) sh.bad = 1;
+            if (k != C_BARWG && k != C_WG && k != C_WI &&
+                !slot_value(p, k, sh.list, n, sh.sc, &sh.c[k]))
+                sh.bad = 1;
     __syncthreads();
     if (t == 0 && st == PM_OK) sh.c[C_BARWG] = p.wg_size ? sh.c[C_BARWI] / p.wg_size : 0;
     __syncthreads();
@@ -114,7 +207,11 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
     if (out)
         for (int k = t; k < PM_NCOUNT; k += blockDim.x) out->c[k] = st2 == PM_OK ? sh.c[k] : 0;
     if (w0 && has_model && pred) {
-        double part = st2 == PM_OK ? predict_partial(sh.c, model, l) : 0.0;
+        const Agg a = wave_aggregates(sh.c, l);
+        const int nf = nfeat(model.proj) < (int)model.nfeat ? nfeat(model.proj) : (int)model.nfeat;
+        double part = 0.0;
+        if (st2 == PM_OK)
+            for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_dev(sh.c, model.proj, i, a);
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         if (t == 0) *pred = st2 == PM_OK ? part : 0.0;
     }

@@ -70,9 +70,10 @@ def test_batched_equals_one_at_a_time_and_any_order(ctx):
         np.testing.assert_array_equal(one, whole[i], err_msg=str(v))
 
 
-def test_device_resident_path_and_prediction(ctx):
+@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext"])
+def test_device_resident_path_and_prediction(ctx, proj):
     import torch
-    vs = suite_batched(512, seed=5)
+    vs = suite_batched(512, seed=5) + suite_test()
     va = P.variant_array(vs)
     raw = bytes(memoryview(va).cast("B"))
     d_v = torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
@@ -80,8 +81,8 @@ def test_device_resident_path_and_prediction(ctx):
     d_c = torch.zeros((nv, P.PM_NCOUNT), dtype=torch.int64, device="cuda")
     d_t = torch.zeros(nv, dtype=torch.float64, device="cuda")
     d_s = torch.full((nv,), 99, dtype=torch.int32, device="cuda")
-    alpha = np.linspace(1e-13, 1e-11, 12)
-    m = P.model_struct("p12", alpha)
+    alpha = np.linspace(1e-13, 1e-11, P.NFEAT[proj])
+    m = P.model_struct(proj, alpha)
     ctx.reserve(nv, sum(P.bitmap_bytes(v) for v in vs))
     s = torch.cuda.current_stream()
     ctx.count_device(d_v.data_ptr(), nv, d_c.data_ptr(), m, d_t.data_ptr(),
@@ -91,7 +92,7 @@ def test_device_resident_path_and_prediction(ctx):
     want = P.counts_numpy(ctx.count_raw(vs))
     np.testing.assert_array_equal(d_c.cpu().numpy(), want)
     arr = ctx.count_raw(vs)
-    pred = np.array([P.features(arr[i], "p12") @ alpha for i in range(nv)])
+    pred = np.array([P.features(arr[i], proj) @ alpha for i in range(nv)])
     np.testing.assert_allclose(d_t.cpu().numpy(), pred, rtol=1e-12)
     np.testing.assert_allclose(ctx.predict(m, vs), pred, rtol=1e-12)
 
