@@ -261,21 +261,33 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     }
     __syncthreads();
     const int ncj = sh[0];
+    if (ncj > 0) {
+        constexpr int JW = sizeof(Job) / 8;
+        for (int w = t; w < ncj * JW; w += 64)  // stage the count jobs in LDS
+            ((uint64_t *)U.jt)[w] = ((const uint64_t *)&vj[jid[w / JW]])[w % JW];
+        __syncthreads();
+        // the jobs' items as one range, spread over the lanes
+        int64_t pre[NTEMP + 1];
+        pre[0] = 0;
+#pragma unroll
+        for (int k = 0; k < NTEMP; k++) pre[k + 1] = pre[k] + (k < ncj ? U.jt[k].items : 0);
+        int64_t s0[NTEMP] = {};
+        for (int64_t x = t; x < pre[ncj]; x += 64) {
+            int k = 0;
+#pragma unroll
+            for (int q = 1; q < NTEMP; q++) k += x >= pre[q];
+            const int64_t c = count_item(U.jt[k], x - pre[k]);
+#pragma unroll
+            for (int q = 0; q < NTEMP; q++) s0[q] += q == k ? c : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < NTEMP; q++) {
+            for (int off = 32; off > 0; off >>= 1) s0[q] += __shfl_xor(s0[q], off);
+            if (t == 0 && q < ncj) jr[jid[q]] = s0[q];
+        }
+        __syncthreads();
+    }
     if (ncj >= 0) {
-        for (int k = 0; k < ncj; k++) {  // stage the count jobs in LDS
-            const uint64_t *src = (const uint64_t *)&vj[jid[k]];
-            uint64_t *dst = (uint64_t *)&U.jt[k];
-            for (size_t w = t; w < sizeof(Job) / 8; w += 64) dst[w] = src[w];
-        }
-        __syncthreads();
-        for (int k = 0; k < ncj; k++) {
-            const Job &J = U.jt[k];
-            int64_t s0 = 0;
-            for (int64_t it = t; it < J.items; it += 64) s0 += count_item(J, it);
-            for (int off = 32; off > 0; off >>= 1) s0 += __shfl_xor(s0, off);
-            if (t == 0) jr[jid[k]] = s0;
-        }
-        __syncthreads();
         const int s2 = finalize_block(P, jr, zero, zero, PM_OK, U.fin,
                                       counts ? &counts[i] : nullptr, model, has_model,
                                       pred ? &pred[i] : nullptr);

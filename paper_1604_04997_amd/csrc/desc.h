@@ -175,12 +175,14 @@ struct B {
     // variable and guard indices of a builder are compile-time constants.
     // Builders fill one statement at a time: additions go to the latest.
     Stmt *cur = nullptr;
-    int nvar = 0, nguard = 0, nacc = 0;
+    int nvar = 0, nguard = 0, nacc = 0, lane = 0;
+    bool werr = false;  // an access with no whole lane stride, or two widths on one array
     PM_HD void fail(int st) {
         if (p->status == PM_OK) p->status = st;
     }
-    PM_HD Stmt *stmt(int lane) {
+    PM_HD Stmt *stmt(int lane_var) {
         nvar = nguard = nacc = 0;
+        lane = lane_var;
         cur = nullptr;
         if (p->nstmt >= MAXSTMT) {
             fail(PM_EINVAL);
@@ -189,7 +191,7 @@ struct B {
         Stmt *s = &p->st[p->nstmt++];
         cur = s;
         s->nvar = 0;
-        s->lane = lane;
+        s->lane = lane_var;
         s->nguard = 0;
         s->nacc = 0;
         s->gmask = 0;
@@ -253,6 +255,19 @@ struct B {
         g.vec = vec;
         g.idx = idx;
         s->nacc = ++nacc;
+        // the array's fill width: lane stride (in accesses) times the width
+        // of a strided (stride >= 2) access
+        const int64_t d = idx.c[lane] < 0 ? -idx.c[lane] : idx.c[lane];
+        const int64_t st = vec == 1 ? d : vec == 2 ? ((d & 1) ? -1 : d >> 1)
+                         : vec == 4 ? ((d & 3) ? -1 : d >> 2) : -1;
+        if (st < 0 || size_index(elem * vec) < 0) {
+            werr = true;
+        } else if (st >= 2) {
+            ArrInfo &A = p->arr[arr];
+            const int64_t w = st * vec;
+            if (A.w && A.w != w) werr = true;
+            else A.w = w;
+        }
     }
     PM_HD void array(int a, int64_t cells) {
         if (a >= MAXARR) {
@@ -1050,24 +1065,9 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
         jobs[j].kind = JOB_NONE;
         jobs[j].chunks = 0;
     }
-    if (p->status != PM_OK) return p->status;
-
-    // arrays needing footprints and their fill widths
-    for (int si = 0; si < p->nstmt; si++) {
-        Stmt &s = p->st[si];
-        for (int q = 0; q < s.nacc; q++) {
-            GAcc &a = s.acc[q];
-            int64_t st = lane_stride(s, a);
-            if (st < 0 || size_index(a.elem * a.vec) < 0) return b.fail(PM_EINVAL), p->status;
-            if (st >= 2) {
-                ArrInfo &A = p->arr[a.arr];
-                int64_t w = st * a.vec;
-                if (A.w && A.w != w) return b.fail(PM_EINVAL), p->status;
-                A.w = w;
-            }
-        }
-    }
-    return PM_OK;
+    // arrays needing footprints got their fill widths as accesses were added
+    if (p->status == PM_OK && b.werr) b.fail(PM_EINVAL);
+    return p->status;
 }
 
 // Counts of statement si (its fixed factor and components) and its jobs,
