@@ -210,15 +210,17 @@ pm_status pm_reserve(pm_ctx *ctx, size_t nv, size_t bitmap_bytes);
 /* Per-kernel timing of the batched counter.  pm_profile(ctx, 1) starts a
  * timing window: every batch until pm_profile_read (at most
  * PM_PROFILE_MAX batches) records HIP events around each of its six
- * launches (fused per-variant build + count + finalize, then for variants
- * that need footprint bitmaps: prefix sums, clear, count, fill, finalize)
- * on the stream they run on.  pm_profile_read waits for the recorded
- * batches and writes the mean duration of each kernel in milliseconds to
- * ms[6] (host) and the number of batches to *nbatch; the window then
- * restarts.  pm_profile(ctx, 0) stops recording.
+ * phases (per-variant expansion, count and finish; a scan phase that is
+ * empty since work lists are claimed during the expansion; then for
+ * variants handed on: clear, count, fill, finish) on the stream they run
+ * on.  pm_profile_read waits for the recorded batches and writes the mean
+ * duration of each phase in milliseconds to ms[6] (host) and the number of
+ * batches to *nbatch; the window then restarts.  pm_profile(ctx, 0) stops
+ * recording.
  * pm_batch_stats writes, for the last batch, stats[0] work chunks,
- * stats[1] bitmap words cleared, stats[2] fill segments, stats[4] bitmap
- * words requested (host int64[8]); synchronous. */
+ * stats[1] bitmap words cleared, stats[2] fill segments, stats[3] variants
+ * handed on to the chip-wide kernels, stats[4] bitmap words requested
+ * (host int64[8]); synchronous. */
 #define PM_NPHASE 6
 #define PM_PROFILE_MAX 4096
 pm_status pm_profile(pm_ctx *ctx, int enable);

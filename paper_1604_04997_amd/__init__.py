@@ -294,7 +294,7 @@ class Context:
         st = (ctypes.c_int64 * 8)()
         _check(lib().pm_batch_stats(self._h, st))
         return {"chunks": st[0], "bitmap_words": st[1], "fill_segments": st[2],
-                "bitmap_words_requested": st[4]}
+                "handed_on": st[3], "bitmap_words_requested": st[4]}
 
     def reserve(self, nv: int, bitmap_bytes_: int):
         _check(lib().pm_reserve(self._h, nv, bitmap_bytes_))

@@ -117,10 +117,12 @@ void free_arena(pm_ctx *c) {
     pm::Arena &a = c->ar;
     (void)hipFree(a.prog);
     (void)hipFree(a.jobs);
-    (void)hipFree(a.varwords);
     (void)hipFree(a.varoff);
-    (void)hipFree(a.varchunks);
-    (void)hipFree(a.varsegs);
+    (void)hipFree(a.clist);
+    (void)hipFree(a.cend);
+    (void)hipFree(a.slist);
+    (void)hipFree(a.send);
+    (void)hipFree(a.dlist);
     (void)hipFree(a.jobres);
     (void)hipFree(a.foot);
     (void)hipFree(a.meta);
@@ -162,13 +164,18 @@ int grow_cap(pm_ctx *c, size_t nv) {
     pm::Arena &a = c->ar;
     HIPCHK(hipMalloc(&a.prog, sizeof(pm::Prog) * cap));
     HIPCHK(hipMalloc(&a.jobs, sizeof(pm::Job) * cap * pm::MAXJOB));
-    HIPCHK(hipMalloc(&a.varwords, 8 * cap));
     HIPCHK(hipMalloc(&a.varoff, 8 * cap));
-    HIPCHK(hipMalloc(&a.varchunks, 8 * cap));
-    HIPCHK(hipMalloc(&a.varsegs, 8 * cap));
+    HIPCHK(hipMalloc(&a.clist, 4 * cap));
+    HIPCHK(hipMalloc(&a.cend, 8 * cap));
+    HIPCHK(hipMalloc(&a.slist, 4 * cap));
+    HIPCHK(hipMalloc(&a.send, 8 * cap));
+    HIPCHK(hipMalloc(&a.dlist, 4 * cap));
     HIPCHK(hipMalloc(&a.jobres, 8 * cap * pm::MAXJOB));
     HIPCHK(hipMalloc(&a.foot, 16 * cap * pm::MAXARR));
-    HIPCHK(hipMalloc(&a.meta, 64));
+    HIPCHK(hipMalloc(&a.meta, 16 * pm::META_WORDS));
+    HIPCHK(hipMemset(a.meta, 0, 16 * pm::META_WORDS));  // both halves start clear
+    HIPCHK(hipDeviceSynchronize());
+    a.parity = 0;
     HIPCHK(hipMalloc(&c->d_var, sizeof(pm_variant) * cap));
     HIPCHK(hipMalloc(&c->d_counts, sizeof(pm_counts) * cap));
     HIPCHK(hipMalloc(&c->d_pred, sizeof(double) * cap));
@@ -211,7 +218,8 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
                               c->d_status, c->stream, c->n_cu, c->next_events());
         if (st) return set_err(st, "counter launch failed");
         HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_meta, c->ar.meta, 64, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_meta, c->ar.meta + pm::META_WORDS * (c->ar.parity ^ 1),
+                              8 * pm::META_WORDS, hipMemcpyDeviceToHost, c->stream));
         if (out) HIPCHK(hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(pm_counts) * nv, hipMemcpyDeviceToHost, c->stream));
         if (m) HIPCHK(hipMemcpyAsync(c->h_pred, c->d_pred, 8 * nv, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -219,7 +227,7 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
         for (size_t i = 0; i < nv; i++) nomem |= c->h_status[i] == PM_ENOMEM;
         if (!nomem) break;
         if (attempt == 1) return set_err(PM_ENOMEM, "footprint bitmaps do not fit");
-        st = grow_bitmap(c, (size_t)c->h_meta[4]);
+        st = grow_bitmap(c, (size_t)c->h_meta[pm::M_WORDS]);
         if (st) return st;
     }
     int first = PM_OK;
@@ -323,7 +331,7 @@ pm_status pm_create(pm_ctx **out, int device, size_t budget) {
         c->n_cu = 256;
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "stream creation failed");
-    if (hipHostMalloc(&c->h_meta, 64, 0) != hipSuccess)
+    if (hipHostMalloc(&c->h_meta, 8 * pm::META_WORDS, 0) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "pinned allocation failed");
     *out = c.release();
     return PM_OK;
@@ -439,9 +447,17 @@ pm_status pm_profile_read(pm_ctx *c, double *ms, int *nbatch) {
 pm_status pm_batch_stats(pm_ctx *c, int64_t *stats) {
     if (!c || !stats || !c->ar.meta) return (pm_status)set_err(PM_EINVAL, "no batch has run");
     DeviceGuard g(c->device);
+    int64_t m[pm::META_WORDS];
     if (hipStreamSynchronize(c->stream) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(stats, c->ar.meta, 64, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(m, c->ar.meta + pm::META_WORDS * (c->ar.parity ^ 1), sizeof m,
+                  hipMemcpyDeviceToHost) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "stats copy failed");
+    for (int k = 0; k < 8; k++) stats[k] = 0;
+    stats[0] = m[pm::M_CHUNKS] & pm::LIST_OFF_MASK;
+    stats[1] = m[pm::M_USED];
+    stats[2] = m[pm::M_SEGS] & pm::LIST_OFF_MASK;
+    stats[3] = m[pm::M_DEFER];
+    stats[4] = m[pm::M_WORDS];
     return PM_OK;
 }
 

@@ -12,27 +12,51 @@ struct Job;
 
 // Per-batch device buffers, sized for `cap` variants and `bitmap_words`
 // words of footprint bitmap.  Owned by a pm_ctx.
+//
+// Variants handed on by the expansion kernels claim their bitmap words and
+// their places in three work lists with atomics: every count or footprint
+// chunk, every fill segment and every variant left to finish.  A list
+// entry and its running chunk (segment) offset come from one 64-bit atomic
+// (entry number in the bits from LIST_POS up, offset below), so offsets
+// grow with the entry number and a chunk finds its entry by binary search.
+// meta holds two halves of META_WORDS: a batch uses half `parity` and its
+// last kernel clears the other for the next batch.
+constexpr int LIST_POS = 47;
+constexpr int64_t LIST_OFF_MASK = (1ll << LIST_POS) - 1;
+constexpr int64_t MAX_VARIANT_CHUNKS = 1ll << 30;  // 2^30 * 2048 outer points
+constexpr int META_WORDS = 8;
+enum {
+    M_CHUNKS = 0,  // packed: count-list entries, chunks
+    M_WORDS = 1,   // bitmap words claimed (requested)
+    M_SEGS = 2,    // packed: fill-list entries, segments
+    M_DEFER = 3,   // variants handed on
+    M_USED = 4,    // end of the last bitmap that fitted
+};
 struct Arena {
     size_t cap = 0;
     size_t bitmap_words = 0;
-    Prog *prog = nullptr;        // [cap]
-    Job *jobs = nullptr;         // [cap * MAXJOB]
-    int64_t *varwords = nullptr; // [cap]
-    int64_t *varoff = nullptr;   // [cap]
-    int64_t *varchunks = nullptr; // [cap]: chunks, then their inclusive prefix
-    int64_t *varsegs = nullptr;   // [cap]: fill segments, then their inclusive prefix
-    int64_t *jobres = nullptr;   // [cap * MAXJOB]
-    int64_t *foot = nullptr;     // [cap * MAXARR * 2]
-    int64_t *meta = nullptr;     // [8]: chunks, words used, fill segments, ticket, words requested
-    uint64_t *bitmap = nullptr;  // [bitmap_words]
+    int parity = 0;               // meta half of the next batch
+    Prog *prog = nullptr;         // [cap]
+    Job *jobs = nullptr;          // [cap * MAXJOB]
+    int64_t *varoff = nullptr;    // [cap]: bitmap word offset of each variant
+    int32_t *clist = nullptr;     // [cap]: variants with chunks, in claim order
+    int64_t *cend = nullptr;      // [cap]: their inclusive chunk prefix
+    int32_t *slist = nullptr;     // [cap]: variants with fill segments
+    int64_t *send = nullptr;      // [cap]: their inclusive segment prefix
+    int32_t *dlist = nullptr;     // [cap]: variants left to finish
+    int64_t *jobres = nullptr;    // [cap * MAXJOB]
+    int64_t *foot = nullptr;      // [cap * MAXARR * 2]
+    int64_t *meta = nullptr;      // [2 * META_WORDS]
+    uint64_t *bitmap = nullptr;   // [bitmap_words]
 };
 
 size_t arena_bytes_per_variant();
 
-// Enqueue the six counter launches for nv variants already in device
-// memory (d_var) on stream s.  d_counts / model / d_pred may be null.
-// ev: null, or 7 events recorded around the six launches.
-int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
+// Enqueue the counter launches for nv variants already in device memory
+// (d_var) on stream s; flips ar.parity.  d_counts / model / d_pred may be
+// null.  ev: null, or 7 events recorded around the six phases (build, an
+// empty scan phase, clear, count, fill, finalize).
+int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu,
                  hipEvent_t *ev = nullptr);

@@ -11,17 +11,17 @@
 // k_build     larger batches, one 64-wide work-group per variant: counts
 //             small count jobs itself and finishes those variants, hands the
 //             others on with their descriptor and jobs in HBM.
-// For handed-on variants only:
-//   k_scan      one work-group: prefix sums of bitmap words, work chunks and
-//               fill segments per variant; bitmaps that overflow the arena
-//               give PM_ENOMEM
+// A variant handed on claims, with atomics, its bitmap words (PM_ENOMEM
+// when they pass the arena's end) and entries in the chunk, segment and
+// finish lists (counter.h).  For handed-on variants only:
 //   k_clear     zero the used bitmap words
 //   k_count     every wavefront takes chunks round-robin: count chunks sum
 //               inner interval lengths, footprint chunks OR cell runs into
 //               the bitmaps
 //   k_fill      per array segment: |F| and |Fill| (F with every strided
 //               cell widened to its run of stride*vec cells)
-//   k_finalize  one wavefront per variant: count vector and prediction
+//   k_finalize  one wavefront per listed variant: count vector and
+//               prediction
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -33,7 +33,6 @@
 
 namespace pm {
 
-constexpr int SCAN_THREADS = 1024;
 constexpr int FILL_THREADS = 256;
 constexpr int FILL_WORDS_PER_THREAD = 16;  // 4096 words per segment
 constexpr int COUNT_THREADS = 256;
@@ -218,16 +217,64 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
     return st2;
 }
 
+// Device buffers a kernel that hands variants on writes to.
+struct HandOn {
+    int64_t *meta;  // this batch's half
+    int64_t *varoff;
+    int32_t *clist, *slist, *dlist;
+    int64_t *cend, *send;
+    int64_t arena_words;
+    int64_t cap;  // list capacity (variants the arena holds)
+};
+
+// Hand variant i, whose program and jobs are in HBM, on to the chip-wide
+// pipeline (one thread): claim its bitmap words and its work-list entries.
+// Returns PM_DEFER, PM_ENOMEM when its bitmaps pass the arena's end, or
+// PM_EOVERFLOW when it needs MAX_VARIANT_CHUNKS chunks or more.  (A list
+// entry past the capacity, which only a meta half left dirty by an
+// unfinished batch could give, is refused with PM_EDEVICE.)
+__device__ __forceinline__ int hand_on(const Prog &P, int i, const HandOn &h) {
+    if (P.chunks >= MAX_VARIANT_CHUNKS) return PM_EOVERFLOW;
+    if (P.bitmap_words > 0) {
+        const int64_t off = (int64_t)atomicAdd((unsigned long long *)&h.meta[M_WORDS],
+                                               (unsigned long long)P.bitmap_words);
+        if (off + P.bitmap_words > h.arena_words) return PM_ENOMEM;
+        h.varoff[i] = off;
+        atomicMax((unsigned long long *)&h.meta[M_USED], (unsigned long long)(off + P.bitmap_words));
+    }
+    if (P.chunks > 0) {
+        const unsigned long long old = atomicAdd((unsigned long long *)&h.meta[M_CHUNKS],
+                                                 (1ull << LIST_POS) + (unsigned long long)P.chunks);
+        const int64_t pos = (int64_t)(old >> LIST_POS);
+        if (pos >= h.cap) return PM_EDEVICE;
+        h.clist[pos] = i;
+        h.cend[pos] = (int64_t)(old & LIST_OFF_MASK) + P.chunks;
+    }
+    if (P.segs > 0) {
+        const unsigned long long old = atomicAdd((unsigned long long *)&h.meta[M_SEGS],
+                                                 (1ull << LIST_POS) + (unsigned long long)P.segs);
+        const int64_t pos = (int64_t)(old >> LIST_POS);
+        if (pos >= h.cap) return PM_EDEVICE;
+        h.slist[pos] = i;
+        h.send[pos] = (int64_t)(old & LIST_OFF_MASK) + P.segs;
+    }
+    const int64_t d = (int64_t)atomicAdd((unsigned long long *)&h.meta[M_DEFER], 1ull);
+    if (d >= h.cap) return PM_EDEVICE;
+    h.dlist[d] = i;
+    return PM_DEFER;
+}
+
 // One variant per 64-wide work-group, expanded in LDS.  A variant without
 // bitmaps whose count jobs hold at most BUILD_MAX_ITEMS items (and fit the
 // LDS staging slots) is finished here: its jobs are counted by the
 // work-group, then the count vector and prediction are written.  Any other
-// is handed on with its program and jobs in HBM (status PM_DEFER).
+// is handed on with its program and jobs in HBM (status PM_DEFER, or
+// PM_ENOMEM / PM_EOVERFLOW when it cannot be: zero outputs then).
 constexpr int64_t BUILD_MAX_ITEMS = 4096;
 __global__ void __launch_bounds__(64)
 k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
-        int64_t *varwords, int64_t *varchunks, int64_t *varsegs, int64_t *jobres,
-        int64_t *foot, pm_counts *counts, pm_model model, int has_model, double *pred) {
+        int64_t *jobres, int64_t *foot, HandOn h, pm_counts *counts, pm_model model,
+        int has_model, double *pred) {
     __shared__ Prog P;
     __shared__ union {
         Job jt[NTEMP];  // during the expansion; then the count jobs
@@ -287,22 +334,12 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
         }
         __syncthreads();
     }
-    if (ncj >= 0) {
-        const int s2 = finalize_block(P, jr, zero, zero, PM_OK, U.fin,
+    if (ncj >= 0 || st != PM_OK) {  // finished here (or failed: zero outputs)
+        const int s2 = finalize_block(P, jr, zero, zero, st, U.fin,
                                       counts ? &counts[i] : nullptr, model, has_model,
                                       pred ? &pred[i] : nullptr);
-        if (t == 0) {
-            status[i] = s2;
-            varwords[i] = varchunks[i] = varsegs[i] = 0;
-        }
+        if (t == 0) status[i] = s2;
         return;
-    }
-    if (st == PM_OK) st = PM_DEFER;
-    if (t == 0) {
-        status[i] = st;
-        varwords[i] = st == PM_DEFER ? P.bitmap_words : 0;
-        varchunks[i] = st == PM_DEFER ? P.chunks : 0;
-        varsegs[i] = st == PM_DEFER ? P.segs : 0;
     }
     if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
     if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
@@ -312,6 +349,13 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     const uint64_t *src = (const uint64_t *)&P;
     uint64_t *dst = (uint64_t *)&prog[i];
     for (size_t w = t; w < words; w += 64) dst[w] = src[w];
+    if (t == 0) sh[0] = hand_on(P, i, h);
+    __syncthreads();
+    const int sd = sh[0];
+    if (t == 0) status[i] = sd;
+    if (sd != PM_DEFER)
+        finalize_block(P, jr, zero, zero, sd, U.fin, counts ? &counts[i] : nullptr, model,
+                       has_model, pred ? &pred[i] : nullptr);
 }
 
 // Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
@@ -328,9 +372,8 @@ __device__ int64_t block_sum(int64_t x, int64_t *red) {
 
 __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
-        int32_t *status, int64_t *varwords, int64_t *varchunks, int64_t *varsegs,
-        int64_t *jobres, int64_t *foot, pm_counts *counts, pm_model model,
-        int has_model, double *pred) {
+        int32_t *status, int64_t *jobres, int64_t *foot, HandOn h, pm_counts *counts,
+        pm_model model, int has_model, double *pred) {
     __shared__ Prog P;
     __shared__ Job J[MAXJOB];
     __shared__ Job JT[NTEMP];
@@ -358,13 +401,7 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     if (t < MAXJOB) jr[t] = 0;
     if (t < MAXARR) fF[t] = fFill[t] = 0;
     __syncthreads();
-    const int st = st_sh;
-    if (t == 0) {
-        status[i] = st;
-        varwords[i] = st == PM_DEFER ? P.bitmap_words : 0;
-        varchunks[i] = st == PM_DEFER ? P.chunks : 0;
-        varsegs[i] = st == PM_DEFER ? P.segs : 0;
-    }
+    int st = st_sh;
     if (st == PM_DEFER) {  // hand the descriptor and zeroed sums on
         const uint64_t *src = (const uint64_t *)&P;
         uint64_t *dst = (uint64_t *)&prog[i];
@@ -375,7 +412,13 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         for (size_t k = t; k < nw; k += FUSED_THREADS) jd[k] = js[k];
         if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
         if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
-        return;
+        if (t == 0) st_sh = hand_on(P, i, h);
+        __syncthreads();
+        st = st_sh;
+        if (st == PM_DEFER) {
+            if (t == 0) status[i] = st;
+            return;
+        }
     }
     if (st == PM_OK) {
         for (int j = 0; j < P.njob; j++) {
@@ -393,95 +436,8 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     if (t == 0) status[i] = s2;
 }
 
-// Inclusive scan of per-thread int64 values over the work-group
-// (SCAN_THREADS threads): lanes by shuffles, then the wavefront totals.
-// ws: SCAN_THREADS / 64 slots; ws[last] ends as the total.
-__device__ int64_t block_incl_scan(int64_t x, int64_t *ws) {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    constexpr int NW = SCAN_THREADS / 64;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) ws[w] = x;
-    __syncthreads();
-    if (t < 64) {
-        int64_t v = t < NW ? ws[t] : 0;
-#pragma unroll
-        for (int off = 1; off < NW; off <<= 1) {
-            const int64_t y = __shfl_up(v, off);
-            if (lane >= off) v += y;
-        }
-        if (t < NW) ws[t] = v;
-    }
-    __syncthreads();
-    return w ? x + ws[w - 1] : x;
-}
-
-// One work-group: exclusive bitmap offsets (variants whose bitmaps would
-// pass the arena's end get PM_ENOMEM), then inclusive prefixes of the
-// chunks and fill segments of the variants still handed on.  Each thread
-// owns a contiguous slice of variants.
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan(int nv, int32_t *status, const int64_t *varwords, int64_t *varoff,
-       int64_t *varchunks, int64_t *varsegs, int64_t *meta, int64_t arena_words) {
-    constexpr int NW = SCAN_THREADS / 64;
-    __shared__ int64_t ws[3][NW];
-    __shared__ int64_t mx[NW];
-    const int t = threadIdx.x;
-    const int64_t per = ((int64_t)nv + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int64_t lo = t * per < nv ? t * per : nv, hi = lo + per < nv ? lo + per : nv;
-    int64_t s = 0;
-    for (int64_t i = lo; i < hi; i++) s += varwords[i];
-    int64_t run = block_incl_scan(s, ws[0]) - s;
-    int64_t used = 0;
-    // only variants that hold bitmap words bound the region to clear: a
-    // variant without bitmaps may sit at an offset past the arena's end
-    for (int64_t i = lo; i < hi; i++) {
-        const int64_t w = varwords[i];
-        varoff[i] = run;
-        if (w) {
-            const int64_t end = run + w;
-            if (end > arena_words) status[i] = PM_ENOMEM;
-            else if (end > used) used = end;
-        }
-        run += w;
-    }
-    int64_t c = 0, g = 0;
-    for (int64_t i = lo; i < hi; i++)
-        if (status[i] == PM_DEFER) {
-            c += varchunks[i];
-            g += varsegs[i];
-        }
-    int64_t rc = block_incl_scan(c, ws[1]) - c;
-    int64_t rg = block_incl_scan(g, ws[2]) - g;
-    for (int64_t i = lo; i < hi; i++) {
-        const bool ok = status[i] == PM_DEFER;
-        rc += ok ? varchunks[i] : 0;
-        rg += ok ? varsegs[i] : 0;
-        varchunks[i] = rc;
-        varsegs[i] = rg;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const int64_t y = __shfl_xor(used, off);
-        if (y > used) used = y;
-    }
-    if ((t & 63) == 0) mx[t >> 6] = used;
-    __syncthreads();
-    if (t == 0) {
-        for (int k = 1; k < NW; k++)
-            if (mx[k] > used) used = mx[k];
-        meta[0] = ws[1][NW - 1];
-        meta[1] = used;
-        meta[2] = ws[2][NW - 1];
-        meta[3] = 0;  // ticket
-        meta[4] = ws[0][NW - 1];
-    }
-}
-
 __global__ void k_clear(uint64_t *bitmap, const int64_t *meta, int64_t arena_words) {
-    int64_t words = meta[1] < arena_words ? meta[1] : arena_words;
+    int64_t words = meta[M_USED] < arena_words ? meta[M_USED] : arena_words;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t i = t; i < words; i += stride) bitmap[i] = 0;
@@ -505,17 +461,21 @@ struct DevOr {
 };
 
 __global__ void __launch_bounds__(COUNT_THREADS)
-k_count(int nv, const Prog *prog, const Job *jobs, const int64_t *varchunks,
-        const int64_t *varoff, uint64_t *bitmap, int64_t *jobres, int64_t *foot,
-        int64_t *meta) {
+k_count(const Prog *prog, const Job *jobs, const int32_t *clist, const int64_t *cend,
+        const int64_t *varoff, uint64_t *bitmap, int64_t *jobres, const int64_t *meta,
+        int64_t cap) {
     const int lane = threadIdx.x & 63;
-    const int64_t total = meta[0];
+    const int64_t total = meta[M_CHUNKS] & LIST_OFF_MASK;
+    int64_t nlist = (int64_t)((unsigned long long)meta[M_CHUNKS] >> LIST_POS);
+    if (nlist > cap) nlist = cap;
     const int64_t nwave = (int64_t)gridDim.x * (blockDim.x / 64);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    for (int64_t ch = wave; ch < total; ch += nwave) {
-        // chunk -> variant (prefix over variants) -> job (prefix inside it)
-        int64_t v = upper(varchunks, nv, ch);
-        int64_t local = ch - (v ? varchunks[v - 1] : 0);
+    const int64_t last = nlist ? cend[nlist - 1] : 0;  // chunks listed
+    for (int64_t ch = wave; ch < total && ch < last; ch += nwave) {
+        // chunk -> list entry (prefix over the list) -> variant -> job
+        const int64_t e = upper(cend, nlist, ch);
+        const int64_t v = clist[e];
+        int64_t local = ch - (e ? cend[e - 1] : 0);
         const int64_t *cum = prog[v].jobcum;
         int jl = 0;
         while (cum[jl] <= local) jl++;
@@ -538,15 +498,19 @@ k_count(int nv, const Prog *prog, const Job *jobs, const int64_t *varchunks,
 }
 
 __global__ void __launch_bounds__(FILL_THREADS)
-k_fill(int nv, const Prog *prog, const int64_t *varsegs, const int64_t *varoff,
-       const uint64_t *bitmap, int64_t *foot, const int64_t *meta) {
+k_fill(const Prog *prog, const int32_t *slist, const int64_t *send, const int64_t *varoff,
+       const uint64_t *bitmap, int64_t *foot, const int64_t *meta, int64_t cap) {
     __shared__ int64_t sh[FILL_THREADS];
     __shared__ unsigned long long red[2];
-    const int64_t total = meta[2];
+    const int64_t total = meta[M_SEGS] & LIST_OFF_MASK;
+    int64_t nlist = (int64_t)((unsigned long long)meta[M_SEGS] >> LIST_POS);
+    if (nlist > cap) nlist = cap;
+    const int64_t last = nlist ? send[nlist - 1] : 0;  // segments listed
     const int t = threadIdx.x;
-    for (int64_t sg = blockIdx.x; sg < total; sg += gridDim.x) {
-        int64_t v = upper(varsegs, nv, sg);
-        int64_t local = sg - (v ? varsegs[v - 1] : 0);
+    for (int64_t sg = blockIdx.x; sg < total && sg < last; sg += gridDim.x) {
+        const int64_t le = upper(send, nlist, sg);
+        const int64_t v = slist[le];
+        int64_t local = sg - (le ? send[le - 1] : 0);
         const int64_t *cum = prog[v].arrcum;
         int al = 0;
         while (cum[al] <= local) al++;
@@ -625,30 +589,35 @@ k_fill(int nv, const Prog *prog, const int64_t *varsegs, const int64_t *varoff,
     }
 }
 
+// One 64-wide work-group per variant left to finish (the dlist entries, in
+// a grid-stride loop); work-group 0 also clears the other meta half for
+// the next batch.
 __global__ void __launch_bounds__(64)
-k_finalize(int nv, const Prog *prog, const int64_t *jobres, const int64_t *foot,
-           int32_t *status, pm_counts *counts, pm_model model, int has_model,
-           double *pred) {
+k_finalize(const Prog *prog, const int64_t *jobres, const int64_t *foot,
+           const int32_t *dlist, int32_t *status, pm_counts *counts, pm_model model,
+           int has_model, double *pred, const int64_t *meta, int64_t *meta_next, int64_t cap) {
     __shared__ FinShared fin;
     __shared__ int64_t F[MAXARR], Fill[MAXARR];
-    const int i = blockIdx.x, t = threadIdx.x;
-    if (i >= nv) return;
-    const int st = status[i];
-    if (st == PM_OK) return;  // finished in k_fused
-    if (t < MAXARR) {
-        F[t] = foot[((int64_t)i * MAXARR + t) * 2];
-        Fill[t] = foot[((int64_t)i * MAXARR + t) * 2 + 1];
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0 && t < META_WORDS) meta_next[t] = 0;
+    const int64_t nd = meta[M_DEFER] < cap ? meta[M_DEFER] : cap;
+    for (int64_t d = blockIdx.x; d < nd; d += gridDim.x) {
+        const int i = dlist[d];
+        if (t < MAXARR) {
+            F[t] = foot[((int64_t)i * MAXARR + t) * 2];
+            Fill[t] = foot[((int64_t)i * MAXARR + t) * 2 + 1];
+        }
+        __syncthreads();
+        const int s2 = finalize_block(prog[i], jobres + (int64_t)i * MAXJOB, F, Fill, PM_OK,
+                                      fin, counts ? &counts[i] : nullptr, model, has_model,
+                                      pred ? &pred[i] : nullptr);
+        if (t == 0) status[i] = s2;
+        __syncthreads();
     }
-    __syncthreads();
-    const int s2 = finalize_block(prog[i], jobres + (int64_t)i * MAXJOB, F, Fill,
-                                  st == PM_DEFER ? PM_OK : st, fin,
-                                  counts ? &counts[i] : nullptr, model, has_model,
-                                  pred ? &pred[i] : nullptr);
-    if (t == 0 && st == PM_DEFER) status[i] = s2;
 }
 
 // ---------------------------------------------------------------- host ---
-int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
+int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev) {
     if (nv <= 0) return PM_OK;
@@ -662,42 +631,48 @@ int launch_batch(const Arena &ar, int nv, const pm_variant *d_var,
         m = *model;
         has = 1;
     }
+    int64_t *meta = ar.meta + META_WORDS * ar.parity;
+    int64_t *meta_next = ar.meta + META_WORDS * (ar.parity ^ 1);
+    ar.parity ^= 1;
+    const HandOn h{meta, ar.varoff, ar.clist, ar.slist, ar.dlist, ar.cend, ar.send,
+                   (int64_t)ar.bitmap_words, (int64_t)ar.cap};
     mark();
     if (nv <= FUSED_MAX_NV)
         hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
-                           ar.prog, ar.jobs, d_status, ar.varwords, ar.varchunks,
-                           ar.varsegs, ar.jobres, ar.foot, d_counts, m, has, d_pred);
+                           ar.prog, ar.jobs, d_status, ar.jobres, ar.foot, h, d_counts, m,
+                           has, d_pred);
     else
         hipLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, nv, d_var, ar.prog, ar.jobs,
-                           d_status, ar.varwords, ar.varchunks, ar.varsegs, ar.jobres,
-                           ar.foot, d_counts, m, has, d_pred);
+                           d_status, ar.jobres, ar.foot, h, d_counts, m, has, d_pred);
     mark();
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nv, d_status,
-                       (const int64_t *)ar.varwords, ar.varoff, ar.varchunks,
-                       ar.varsegs, ar.meta, (int64_t)ar.bitmap_words);
+    mark();  // the scan phase: work lists are claimed by atomics in the kernel above
+    hipLaunchKernelGGL(k_clear, dim3(n_cu * 4), dim3(256), 0, s, ar.bitmap,
+                       (const int64_t *)meta, (int64_t)ar.bitmap_words);
     mark();
-    hipLaunchKernelGGL(k_clear, dim3(n_cu * 8), dim3(256), 0, s, ar.bitmap,
-                       (const int64_t *)ar.meta, (int64_t)ar.bitmap_words);
-    mark();
-    hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s, nv,
+    hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s,
                        (const Prog *)ar.prog, (const Job *)ar.jobs,
-                       (const int64_t *)ar.varchunks, (const int64_t *)ar.varoff,
-                       ar.bitmap, ar.jobres, ar.foot, ar.meta);
+                       (const int32_t *)ar.clist, (const int64_t *)ar.cend,
+                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, (const int64_t *)meta,
+                       (int64_t)ar.cap);
     mark();
-    hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s, nv,
-                       (const Prog *)ar.prog, (const int64_t *)ar.varsegs,
-                       (const int64_t *)ar.varoff, (const uint64_t *)ar.bitmap,
-                       ar.foot, (const int64_t *)ar.meta);
+    hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s,
+                       (const Prog *)ar.prog, (const int32_t *)ar.slist,
+                       (const int64_t *)ar.send, (const int64_t *)ar.varoff,
+                       (const uint64_t *)ar.bitmap, ar.foot, (const int64_t *)meta,
+                       (int64_t)ar.cap);
     mark();
-    hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(64), 0, s, nv,
-                       (const Prog *)ar.prog, (const int64_t *)ar.jobres,
-                       (const int64_t *)ar.foot, d_status, d_counts, m, has, d_pred);
+    const int nfin = nv < n_cu * 4 ? nv : n_cu * 4;
+    hipLaunchKernelGGL(k_finalize, dim3(nfin), dim3(64), 0, s, (const Prog *)ar.prog,
+                       (const int64_t *)ar.jobres, (const int64_t *)ar.foot,
+                       (const int32_t *)ar.dlist, d_status, d_counts, m, has, d_pred,
+                       (const int64_t *)meta, meta_next, (int64_t)ar.cap);
     mark();
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
 size_t arena_bytes_per_variant() {
-    return sizeof(Prog) + sizeof(Job) * MAXJOB + sizeof(int64_t) * (4 + MAXJOB + 2 * MAXARR);
+    return sizeof(Prog) + sizeof(Job) * MAXJOB +
+           sizeof(int64_t) * (1 + 2 + MAXJOB + 2 * MAXARR) + sizeof(int32_t) * 3;
 }
 
 // ------------------------------------------------------- host execution ---
