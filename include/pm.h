@@ -208,7 +208,9 @@ pm_status pm_count_device(pm_ctx *ctx, const pm_variant *d_v, size_t nv,
 pm_status pm_reserve(pm_ctx *ctx, size_t nv, size_t bitmap_bytes);
 
 /* Per-kernel timing of the batched counter.  pm_profile(ctx, 1) starts a
- * timing window: every batch until pm_profile_read (at most
+ * timing window (pm_profile(ctx, 2): the same with events around the
+ * expansion kernel only, ms[0]; every recorded event adds a few
+ * microseconds to a batch): every batch until pm_profile_read (at most
  * PM_PROFILE_MAX batches) records HIP events around each of its six
  * phases (per-variant expansion, count and finish; a scan phase that is
  * empty since work lists are claimed during the expansion; then for

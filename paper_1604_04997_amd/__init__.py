@@ -280,8 +280,10 @@ class Context:
 
     PHASES = ("build", "scan", "clear", "count", "fill", "finalize")
 
-    def profile(self, enable: bool = True):
-        _check(lib().pm_profile(self._h, 1 if enable else 0))
+    def profile(self, enable=True):
+        """True / 1: events around every phase; 2: around the expansion
+        kernel only (the lightest); False / 0: off."""
+        _check(lib().pm_profile(self._h, int(enable)))
 
     def profile_read(self):
         """({kernel: mean milliseconds}, batches) since profiling started."""

@@ -96,9 +96,10 @@ struct pm_ctx {
     int32_t *h_status = nullptr;
     int64_t *h_meta = nullptr;
     std::vector<hipEvent_t> events;
-    bool profile = false;
+    int profile = 0;  // 0 off, 1 every phase, 2 the expansion kernel only
     std::vector<hipEvent_t> pev;  // (PM_NPHASE + 1) per recorded batch
     int pcount = 0;
+    int nmarks() const { return profile == 2 ? 2 : PM_NPHASE + 1; }
     hipEvent_t *next_events() {
         if (!profile || pcount >= PM_PROFILE_MAX) return nullptr;
         size_t need = (size_t)(pcount + 1) * (PM_NPHASE + 1);
@@ -215,7 +216,7 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
     for (int attempt = 0; attempt < 2; attempt++) {
         HIPCHK(hipMemcpyAsync(c->d_var, c->h_var, sizeof(pm_variant) * nv, hipMemcpyHostToDevice, c->stream));
         st = pm::launch_batch(c->ar, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
-                              c->d_status, c->stream, c->n_cu, c->next_events());
+                              c->d_status, c->stream, c->n_cu, c->next_events(), c->nmarks());
         if (st) return set_err(st, "counter launch failed");
         HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(c->h_meta, c->ar.meta + pm::META_WORDS * (c->ar.parity ^ 1),
@@ -400,7 +401,7 @@ pm_status pm_count_device(pm_ctx *c, const pm_variant *d_v, size_t nv, pm_counts
     if (st) return (pm_status)st;
     hipStream_t s = (hipStream_t)stream;  // NULL: HIP's null stream
     st = pm::launch_batch(c->ar, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu,
-                          c->next_events());
+                          c->next_events(), c->nmarks());
     if (st) return (pm_status)set_err(st, "counter launch failed");
     return PM_OK;
 }
@@ -416,7 +417,8 @@ pm_status pm_reserve(pm_ctx *c, size_t nv, size_t bitmap_bytes) {
 
 pm_status pm_profile(pm_ctx *c, int enable) {
     if (!c) return (pm_status)set_err(PM_EINVAL, "null context");
-    c->profile = enable != 0;
+    if (enable < 0 || enable > 2) return (pm_status)set_err(PM_EINVAL, "profile mode is 0, 1 or 2");
+    c->profile = enable;
     c->pcount = 0;
     return PM_OK;
 }
@@ -426,11 +428,12 @@ pm_status pm_profile_read(pm_ctx *c, double *ms, int *nbatch) {
     DeviceGuard g(c->device);
     int n = c->pcount;
     for (int i = 0; i < PM_NPHASE; i++) ms[i] = 0;
+    const int nph = c->nmarks() - 1;  // phases recorded
     for (int b = 0; b < n; b++) {
         hipEvent_t *e = &c->pev[(size_t)b * (PM_NPHASE + 1)];
-        if (hipEventSynchronize(e[PM_NPHASE]) != hipSuccess)
+        if (hipEventSynchronize(e[nph]) != hipSuccess)
             return (pm_status)set_err(PM_EDEVICE, "event wait failed");
-        for (int i = 0; i < PM_NPHASE; i++) {
+        for (int i = 0; i < nph; i++) {
             float t = 0;
             if (hipEventElapsedTime(&t, e[i], e[i + 1]) != hipSuccess)
                 return (pm_status)set_err(PM_EDEVICE, "no timing recorded");

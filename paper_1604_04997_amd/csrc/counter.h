@@ -54,12 +54,13 @@ size_t arena_bytes_per_variant();
 
 // Enqueue the counter launches for nv variants already in device memory
 // (d_var) on stream s; flips ar.parity.  d_counts / model / d_pred may be
-// null.  ev: null, or 7 events recorded around the six phases (build, an
-// empty scan phase, clear, count, fill, finalize).
+// null.  ev: null, or events recorded around the six phases (build, an
+// empty scan phase, clear, count, fill, finalize); the first `nmark` of the
+// seven are recorded (2: around the expansion kernel only).
 int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu,
-                 hipEvent_t *ev = nullptr);
+                 hipEvent_t *ev = nullptr, int nmark = 7);
 
 // Host execution of the same per-variant code (descriptor, jobs, items,
 // fill, finalize), one variant at a time; for unit tests on machines

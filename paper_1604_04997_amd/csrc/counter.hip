@@ -619,11 +619,12 @@ k_finalize(const Prog *prog, const int64_t *jobres, const int64_t *foot,
 // ---------------------------------------------------------------- host ---
 int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
-                 int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev) {
+                 int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev, int nmark) {
     if (nv <= 0) return PM_OK;
     int q = 0;
     auto mark = [&]() {
-        if (ev) (void)hipEventRecord(ev[q++], s);
+        if (ev && q < nmark) (void)hipEventRecord(ev[q], s);
+        q++;
     };
     pm_model m{};
     int has = 0;
