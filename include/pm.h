@@ -218,7 +218,10 @@ pm_status pm_reserve(pm_ctx *ctx, size_t nv, size_t bitmap_bytes);
  * on.  pm_profile_read waits for the recorded batches and writes the mean
  * duration of each phase in milliseconds to ms[6] (host) and the number of
  * batches to *nbatch; the window then restarts.  pm_profile(ctx, 0) stops
- * recording.
+ * recording.  In the synchronous host calls (pm_count, pm_predict) the
+ * chip-wide phases run only when the expansion handed variants on: the
+ * host's read of the expansion's results then falls in the scan phase, and
+ * phases that did not run read zero.
  * pm_batch_stats writes, for the last batch, stats[0] work chunks,
  * stats[1] bitmap words cleared, stats[2] fill segments, stats[3] variants
  * handed on to the chip-wide kernels, stats[4] bitmap words requested

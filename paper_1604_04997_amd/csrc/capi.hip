@@ -213,23 +213,45 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
     int st = grow_cap(c, nv);
     if (st) return st;
     std::memcpy(c->h_var, v, sizeof(pm_variant) * nv);
+    // The expansion kernel finishes most variants by itself; the chip-wide
+    // kernels run only when it handed some on, after the host has read its
+    // meta half (one more round trip then, four launches fewer otherwise).
+    hipEvent_t *ev = c->next_events();
+    const int nmark = c->nmarks();
     for (int attempt = 0; attempt < 2; attempt++) {
         HIPCHK(hipMemcpyAsync(c->d_var, c->h_var, sizeof(pm_variant) * nv, hipMemcpyHostToDevice, c->stream));
-        st = pm::launch_batch(c->ar, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
-                              c->d_status, c->stream, c->n_cu, c->next_events(), c->nmarks());
+        st = pm::launch_expand(c->ar, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
+                               c->d_status, c->stream, ev, nmark);
         if (st) return set_err(st, "counter launch failed");
         HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_meta, c->ar.meta + pm::META_WORDS * (c->ar.parity ^ 1),
-                              8 * pm::META_WORDS, hipMemcpyDeviceToHost, c->stream));
         if (out) HIPCHK(hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(pm_counts) * nv, hipMemcpyDeviceToHost, c->stream));
         if (m) HIPCHK(hipMemcpyAsync(c->h_pred, c->d_pred, 8 * nv, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        bool nomem = false;
-        for (size_t i = 0; i < nv; i++) nomem |= c->h_status[i] == PM_ENOMEM;
-        if (!nomem) break;
-        if (attempt == 1) return set_err(PM_ENOMEM, "footprint bitmaps do not fit");
-        st = grow_bitmap(c, (size_t)c->h_meta[pm::M_WORDS]);
-        if (st) return st;
+        bool nomem = false, deferred = false;
+        for (size_t i = 0; i < nv; i++) {
+            nomem |= c->h_status[i] == PM_ENOMEM;
+            deferred |= c->h_status[i] == pm::PM_DEFER;
+        }
+        if (nomem) {  // grow the bitmap arena to what the batch asked for, expand again
+            if (attempt == 1) return set_err(PM_ENOMEM, "footprint bitmaps do not fit");
+            HIPCHK(hipMemcpy(c->h_meta, c->ar.meta + pm::META_WORDS * (c->ar.parity ^ 1),
+                             8 * pm::META_WORDS, hipMemcpyDeviceToHost));
+            st = grow_bitmap(c, (size_t)c->h_meta[pm::M_WORDS]);
+            if (st) return st;
+            continue;
+        }
+        if (deferred) {
+            st = pm::launch_rest(c->ar, (int)nv, c->d_counts, m, m ? c->d_pred : nullptr,
+                                 c->d_status, c->stream, c->n_cu, ev, nmark);
+            if (st) return set_err(st, "counter launch failed");
+            HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
+            if (out) HIPCHK(hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(pm_counts) * nv, hipMemcpyDeviceToHost, c->stream));
+            if (m) HIPCHK(hipMemcpyAsync(c->h_pred, c->d_pred, 8 * nv, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        } else if (ev) {  // phases that did not run take no time
+            for (int q = 2; q < nmark; q++) (void)hipEventRecord(ev[q], c->stream);
+        }
+        break;
     }
     int first = PM_OK;
     for (size_t i = 0; i < nv; i++) {

@@ -19,11 +19,14 @@ struct Job;
 // entry and its running chunk (segment) offset come from one 64-bit atomic
 // (entry number in the bits from LIST_POS up, offset below), so offsets
 // grow with the entry number and a chunk finds its entry by binary search.
-// meta holds two halves of META_WORDS: a batch uses half `parity` and its
-// last kernel clears the other for the next batch.
 constexpr int LIST_POS = 47;
 constexpr int64_t LIST_OFF_MASK = (1ll << LIST_POS) - 1;
 constexpr int64_t MAX_VARIANT_CHUNKS = 1ll << 30;  // 2^30 * 2048 outer points
+// Internal status of a variant the expansion kernel handed on to the
+// chip-wide kernels (they replace it with the variant's final status).
+constexpr int PM_DEFER = 1;
+// meta holds two halves of META_WORDS: a batch uses half `parity` and its
+// expansion kernel clears the other for the next batch.
 constexpr int META_WORDS = 8;
 enum {
     M_CHUNKS = 0,  // packed: count-list entries, chunks
@@ -61,6 +64,15 @@ int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu,
                  hipEvent_t *ev = nullptr, int nmark = 7);
+// The same in two parts: the expansion kernel (events 0 and 1; flips
+// ar.parity) and the chip-wide kernels for the variants it handed on
+// (events 2..6), which a caller that has read the expansion's meta half
+// may skip when it handed none on.
+int launch_expand(Arena &ar, int nv, const pm_variant *d_var, pm_counts *d_counts,
+                  const pm_model *model, double *d_pred, int32_t *d_status, hipStream_t s,
+                  hipEvent_t *ev, int nmark);
+int launch_rest(Arena &ar, int nv, pm_counts *d_counts, const pm_model *model, double *d_pred,
+                int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev, int nmark);
 
 // Host execution of the same per-variant code (descriptor, jobs, items,
 // fill, finalize), one variant at a time; for unit tests on machines

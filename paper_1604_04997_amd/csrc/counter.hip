@@ -38,7 +38,6 @@ constexpr int FILL_WORDS_PER_THREAD = 16;  // 4096 words per segment
 constexpr int COUNT_THREADS = 256;
 constexpr int FUSED_THREADS = 256;
 constexpr int64_t FUSED_MAX_ITEMS = 1 << 20;
-constexpr int PM_DEFER = 1;  // internal status: finish in the general pipeline
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 
 // Expansion of one variant by a work-group (at least MAXSTMT threads; all
@@ -219,7 +218,8 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
 
 // Device buffers a kernel that hands variants on writes to.
 struct HandOn {
-    int64_t *meta;  // this batch's half
+    int64_t *meta;       // this batch's half
+    int64_t *meta_next;  // the other half, cleared for the next batch by work-group 0
     int64_t *varoff;
     int32_t *clist, *slist, *dlist;
     int64_t *cend, *send;
@@ -286,6 +286,7 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     __shared__ int jid[NTEMP];
     __shared__ int64_t jitems[MAXJOB];  // items of count-job slots, -1 for others
     const int i = blockIdx.x, t = threadIdx.x;
+    if (i == 0 && t < META_WORDS) h.meta_next[t] = 0;
     if (i >= nv) return;
     if (t < MAXJOB) jr[t] = 0;
     if (t < MAXARR) zero[t] = 0;
@@ -385,6 +386,7 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     __shared__ int st_sh;
     const int i = blockIdx.x;
     const int t = threadIdx.x;
+    if (i == 0 && t < META_WORDS) h.meta_next[t] = 0;
     if (i >= nv) return;
     const pm_variant v = var[i];
     const int sb = build_block(v, &P, J, JT, bsh);
@@ -590,16 +592,14 @@ k_fill(const Prog *prog, const int32_t *slist, const int64_t *send, const int64_
 }
 
 // One 64-wide work-group per variant left to finish (the dlist entries, in
-// a grid-stride loop); work-group 0 also clears the other meta half for
-// the next batch.
+// a grid-stride loop).
 __global__ void __launch_bounds__(64)
 k_finalize(const Prog *prog, const int64_t *jobres, const int64_t *foot,
            const int32_t *dlist, int32_t *status, pm_counts *counts, pm_model model,
-           int has_model, double *pred, const int64_t *meta, int64_t *meta_next, int64_t cap) {
+           int has_model, double *pred, const int64_t *meta, int64_t cap) {
     __shared__ FinShared fin;
     __shared__ int64_t F[MAXARR], Fill[MAXARR];
     const int t = threadIdx.x;
-    if (blockIdx.x == 0 && t < META_WORDS) meta_next[t] = 0;
     const int64_t nd = meta[M_DEFER] < cap ? meta[M_DEFER] : cap;
     for (int64_t d = blockIdx.x; d < nd; d += gridDim.x) {
         const int i = dlist[d];
@@ -620,8 +620,42 @@ k_finalize(const Prog *prog, const int64_t *jobres, const int64_t *foot,
 int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev, int nmark) {
+    int st = launch_expand(ar, nv, d_var, d_counts, model, d_pred, d_status, s, ev, nmark);
+    if (st) return st;
+    return launch_rest(ar, nv, d_counts, model, d_pred, d_status, s, n_cu, ev, nmark);
+}
+
+int launch_expand(Arena &ar, int nv, const pm_variant *d_var, pm_counts *d_counts,
+                  const pm_model *model, double *d_pred, int32_t *d_status, hipStream_t s,
+                  hipEvent_t *ev, int nmark) {
     if (nv <= 0) return PM_OK;
-    int q = 0;
+    pm_model m{};
+    int has = 0;
+    if (model) {
+        m = *model;
+        has = 1;
+    }
+    int64_t *meta = ar.meta + META_WORDS * ar.parity;
+    int64_t *meta_next = ar.meta + META_WORDS * (ar.parity ^ 1);
+    ar.parity ^= 1;
+    const HandOn h{meta, meta_next, ar.varoff, ar.clist, ar.slist, ar.dlist, ar.cend, ar.send,
+                   (int64_t)ar.bitmap_words, (int64_t)ar.cap};
+    if (ev && nmark > 0) (void)hipEventRecord(ev[0], s);
+    if (nv <= FUSED_MAX_NV)
+        hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
+                           ar.prog, ar.jobs, d_status, ar.jobres, ar.foot, h, d_counts, m,
+                           has, d_pred);
+    else
+        hipLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, nv, d_var, ar.prog, ar.jobs,
+                           d_status, ar.jobres, ar.foot, h, d_counts, m, has, d_pred);
+    if (ev && nmark > 1) (void)hipEventRecord(ev[1], s);
+    return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+int launch_rest(Arena &ar, int nv, pm_counts *d_counts, const pm_model *model, double *d_pred,
+                int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev, int nmark) {
+    if (nv <= 0) return PM_OK;
+    int q = 2;
     auto mark = [&]() {
         if (ev && q < nmark) (void)hipEventRecord(ev[q], s);
         q++;
@@ -632,41 +666,26 @@ int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
         m = *model;
         has = 1;
     }
-    int64_t *meta = ar.meta + META_WORDS * ar.parity;
-    int64_t *meta_next = ar.meta + META_WORDS * (ar.parity ^ 1);
-    ar.parity ^= 1;
-    const HandOn h{meta, ar.varoff, ar.clist, ar.slist, ar.dlist, ar.cend, ar.send,
-                   (int64_t)ar.bitmap_words, (int64_t)ar.cap};
-    mark();
-    if (nv <= FUSED_MAX_NV)
-        hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
-                           ar.prog, ar.jobs, d_status, ar.jobres, ar.foot, h, d_counts, m,
-                           has, d_pred);
-    else
-        hipLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, nv, d_var, ar.prog, ar.jobs,
-                           d_status, ar.jobres, ar.foot, h, d_counts, m, has, d_pred);
-    mark();
-    mark();  // the scan phase: work lists are claimed by atomics in the kernel above
-    hipLaunchKernelGGL(k_clear, dim3(n_cu * 4), dim3(256), 0, s, ar.bitmap,
-                       (const int64_t *)meta, (int64_t)ar.bitmap_words);
+    const int64_t *meta = ar.meta + META_WORDS * (ar.parity ^ 1);  // the last expansion's
+    mark();  // the scan phase: work lists are claimed by atomics during the expansion
+    hipLaunchKernelGGL(k_clear, dim3(n_cu * 4), dim3(256), 0, s, ar.bitmap, meta,
+                       (int64_t)ar.bitmap_words);
     mark();
     hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s,
                        (const Prog *)ar.prog, (const Job *)ar.jobs,
                        (const int32_t *)ar.clist, (const int64_t *)ar.cend,
-                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, (const int64_t *)meta,
-                       (int64_t)ar.cap);
+                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, meta, (int64_t)ar.cap);
     mark();
     hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s,
                        (const Prog *)ar.prog, (const int32_t *)ar.slist,
                        (const int64_t *)ar.send, (const int64_t *)ar.varoff,
-                       (const uint64_t *)ar.bitmap, ar.foot, (const int64_t *)meta,
-                       (int64_t)ar.cap);
+                       (const uint64_t *)ar.bitmap, ar.foot, meta, (int64_t)ar.cap);
     mark();
     const int nfin = nv < n_cu * 4 ? nv : n_cu * 4;
     hipLaunchKernelGGL(k_finalize, dim3(nfin), dim3(64), 0, s, (const Prog *)ar.prog,
                        (const int64_t *)ar.jobres, (const int64_t *)ar.foot,
-                       (const int32_t *)ar.dlist, d_status, d_counts, m, has, d_pred,
-                       (const int64_t *)meta, meta_next, (int64_t)ar.cap);
+                       (const int32_t *)ar.dlist, d_status, d_counts, m, has, d_pred, meta,
+                       (int64_t)ar.cap);
     mark();
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
 }
