@@ -207,17 +207,23 @@ def suite_roofline(ctx, P):
         for dt, esz in (("f32", 4), ("f64", 8)):
             for vec, U in ((1, 1), (1, 4), (4 if dt == "f32" else 2, 1),
                            (4 if dt == "f32" else 2, 4)):
-                elems = (1 << 28) if dt == "f32" else (1 << 27)
-                v = dict(family="stream", op=op, dtype=dt, n=elems // (vec * U), wg=256,
-                         s=1, gs=1, vec=vec, U=U)
-                ts, _ = P.device_buffers(v, 11, fast=True)
-                t, _ = ctx.measure(v, ts, warmup=3, reps=20)
-                del ts
-                gbs = mult * elems * esz / t
-                res["stream"].append({"op": op, "dtype": dt, "vec": vec, "U": U,
-                                      "bytes": mult * elems * esz, "ms": round(t * 1e3, 4),
-                                      "GB/s": round(gbs / 1e9, 1),
-                                      "frac_8TBs": round(gbs / HBM_PEAK, 4)})
+                for nt in (False, True):
+                    elems = (1 << 28) if dt == "f32" else (1 << 27)
+                    v = dict(family="stream", op=op, dtype=dt, n=elems // (vec * U), wg=256,
+                             s=1, gs=1, vec=vec, U=U, streaming=nt)
+                    ts, _ = P.device_buffers(v, 11, fast=True)
+                    t, _ = ctx.measure(v, ts, warmup=3, reps=20)
+                    del ts
+                    gbs = mult * elems * esz / t
+                    res["stream"].append({"op": op, "dtype": dt, "vec": vec, "U": U,
+                                          "streaming_hint": nt,
+                                          "bytes": mult * elems * esz,
+                                          "ms": round(t * 1e3, 4), "GB/s": round(gbs / 1e9, 1),
+                                          "frac_8TBs": round(gbs / HBM_PEAK, 4)})
+    for op in ("load", "copy"):
+        best = max((r for r in res["stream"] if r["op"] == op), key=lambda r: r["frac_8TBs"])
+        res["best_" + op] = {k: best[k] for k in ("dtype", "vec", "U", "streaming_hint",
+                                                   "GB/s", "frac_8TBs")}
     for dt, peak_pub in (("f32", 157.3e12), ("f64", 78.6e12)):
         v = dict(family="fma", dtype=dt, n=1 << 24, wg=256, F=1024, K=16)
         ts, _ = P.device_buffers(v, 12, fast=True)

@@ -101,10 +101,14 @@ enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC 
  * the interval form applies; PM_FLAG_ENUMERATE runs every count job in the
  * chip-wide count kernel, also where the work-group that expanded the
  * descriptor could count it itself (same counts; both for cross-checks).
+ * PM_FLAG_STREAMING (STREAM only, ignored elsewhere): every access of the
+ * measured kernel carries the non-temporal cache hint; the counts do not
+ * change (the properties of Sec. 3 do not see cache hints).
  * Unused fields must be zero.  `seed` is carried for the caller's records.
  */
 #define PM_FLAG_BITMAP 1u
 #define PM_FLAG_ENUMERATE 2u
+#define PM_FLAG_STREAMING 4u
 typedef struct {
     uint32_t family, dtype, op, flags;
     int64_t n[3];

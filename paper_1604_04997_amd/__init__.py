@@ -75,6 +75,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libpm.so not built: run "
                               "`python -m paper_1604_04997_amd.build`")
+        # torch's wheel ships a HIP runtime under the same soname as the one
+        # libpm.so links: whichever loads first serves the whole process, and
+        # torch does not run on another release's.  Load torch's first (device
+        # buffers and streams come from torch); without torch, ROCm's serves.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         vp = ctypes.c_void_p
@@ -137,7 +145,8 @@ def variant_struct(d: dict) -> Variant:
     v.dtype = 1 if d.get("dtype", "f32") == "f64" else 0
     v.op = OPS.get(fam, {}).get(d.get("op"), 0)
     v.seed = int(d.get("seed", 0)) & ((1 << 64) - 1)
-    v.flags = (1 if d.get("bitmap") else 0) | (2 if d.get("enumerate") else 0)
+    v.flags = ((1 if d.get("bitmap") else 0) | (2 if d.get("enumerate") else 0)
+               | (4 if d.get("streaming") else 0))
     if fam == "stream":
         v.n[0], v.wg[0] = d["n"], d["wg"]
         v.stride, v.gstride, v.vec, v.reps = d["s"], d.get("gs", 1), d.get("vec", 1), d.get("U", 1)

@@ -26,6 +26,41 @@ __device__ inline float comp(float2 v, int c) { return c ? v.y : v.x; }
 __device__ inline float comp(float4 v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
 __device__ inline double comp(double2 v, int c) { return c ? v.y : v.x; }
 
+// Streaming accesses: the non-temporal cache hint on a load or store whose
+// line no later access of the kernel touches.
+template <typename T> __device__ inline T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T> __device__ inline void st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
+typedef float nf2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+template <> __device__ inline float2 ld_nt(const float2 *p) {
+    const nf2 r = __builtin_nontemporal_load((const nf2 *)p);
+    return make_float2(r[0], r[1]);
+}
+template <> __device__ inline float4 ld_nt(const float4 *p) {
+    const nf4 r = __builtin_nontemporal_load((const nf4 *)p);
+    return make_float4(r[0], r[1], r[2], r[3]);
+}
+template <> __device__ inline double2 ld_nt(const double2 *p) {
+    const nd2 r = __builtin_nontemporal_load((const nd2 *)p);
+    return make_double2(r[0], r[1]);
+}
+template <> __device__ inline void st_nt(float2 v, float2 *p) {
+    __builtin_nontemporal_store(nf2{v.x, v.y}, (nf2 *)p);
+}
+template <> __device__ inline void st_nt(float4 v, float4 *p) {
+    __builtin_nontemporal_store(nf4{v.x, v.y, v.z, v.w}, (nf4 *)p);
+}
+template <> __device__ inline void st_nt(double2 v, double2 *p) {
+    __builtin_nontemporal_store(nd2{v.x, v.y}, (nd2 *)p);
+}
+// A plain or (NT) streaming access.
+template <bool NT, typename T> __device__ inline T ld(const T *p) { return NT ? ld_nt(p) : *p; }
+template <bool NT, typename T> __device__ inline void st(T v, T *p) {
+    if (NT) st_nt(v, p);
+    else *p = v;
+}
+
 template <typename VT, typename T> __device__ inline VT vset(T *a);
 template <> __device__ inline float vset<float, float>(float *a) { return a[0]; }
 template <> __device__ inline float2 vset<float2, float>(float *a) { return make_float2(a[0], a[1]); }
@@ -35,8 +70,9 @@ template <> __device__ inline double2 vset<double2, double>(double *a) { return 
 
 // ----------------------------------------------------------------- stream
 // Access u of work-item (g, l) is element vector number
-// ((g*gs)*wg + l)*s + u*G*gs*wg*s (units of VEC elements).
-template <typename T, int VEC, int OP>
+// ((g*gs)*wg + l)*s + u*G*gs*wg*s (units of VEC elements).  NT: every
+// access carries the streaming hint (no element is touched twice).
+template <typename T, int VEC, int OP, bool NT>
 __global__ void k_stream(T *x0, T *x1, T *x2, T *x3, T *x4, int64_t G,
                          int64_t s, int64_t gs, int U, T sentinel) {
     using VT = typename Vec<T, VEC>::t;
@@ -48,31 +84,31 @@ __global__ void k_stream(T *x0, T *x1, T *x2, T *x3, T *x4, int64_t G,
     for (int u = 0; u < U; u++) {
         int64_t e = base + u * ust;
         if (OP == PM_STREAM_LOAD) {
-            VT a = ((const VT *)x0)[e];
+            VT a = ld<NT>((const VT *)x0 + e);
 #pragma unroll
             for (int c = 0; c < VEC; c++) acc += comp(a, c);
         } else if (OP == PM_STREAM_STORE) {
             T t[VEC];
 #pragma unroll
             for (int c = 0; c < VEC; c++) t[c] = (T)(e * VEC + c);
-            ((VT *)x0)[e] = vset<VT, T>(t);
+            st<NT>(vset<VT, T>(t), (VT *)x0 + e);
         } else if (OP == PM_STREAM_COPY) {
-            ((VT *)x1)[e] = ((const VT *)x0)[e];
+            st<NT>(ld<NT>((const VT *)x0 + e), (VT *)x1 + e);
         } else if (OP == PM_STREAM_AXPBY) {
-            VT a = ((const VT *)x0)[e], b = ((const VT *)x1)[e];
+            VT a = ld<NT>((const VT *)x0 + e), b = ld<NT>((const VT *)x1 + e);
             T t[VEC];
 #pragma unroll
             for (int q = 0; q < VEC; q++)
                 t[q] = (T)0.75 * comp(a, q) + (T)(-1.25) * comp(b, q);
-            ((VT *)x2)[e] = vset<VT, T>(t);
+            st<NT>(vset<VT, T>(t), (VT *)x2 + e);
         } else {  // add4
-            VT a = ((const VT *)x0)[e], b = ((const VT *)x1)[e];
-            VT c = ((const VT *)x2)[e], d = ((const VT *)x3)[e];
+            VT a = ld<NT>((const VT *)x0 + e), b = ld<NT>((const VT *)x1 + e);
+            VT c = ld<NT>((const VT *)x2 + e), d = ld<NT>((const VT *)x3 + e);
             T t[VEC];
 #pragma unroll
             for (int q = 0; q < VEC; q++)
                 t[q] = (comp(a, q) + comp(b, q)) + (comp(c, q) + comp(d, q));
-            ((VT *)x4)[e] = vset<VT, T>(t);
+            st<NT>(vset<VT, T>(t), (VT *)x4 + e);
         }
     }
     // never true (sentinel is NaN): keeps the loads without storing
@@ -397,29 +433,40 @@ int buffers(const pm_variant &v, size_t *bytes, uint32_t *role, uint32_t *nb) {
     return PM_OK;
 }
 
-template <typename T, int VEC>
-static void launch_stream_t(const pm_variant &v, void *const *b, hipStream_t s) {
+template <typename T, int VEC, bool NT>
+static void launch_stream_nt(const pm_variant &v, void *const *b, hipStream_t s) {
     int64_t G = v.n[0] / v.wg[0];
+    // the op's buffers (load 2, store 1, copy 2, axpby 3, add4 5); the
+    // caller's array holds no more
+    const int nb = v.op == PM_STREAM_STORE ? 1 : v.op == PM_STREAM_AXPBY ? 3
+                 : v.op == PM_STREAM_ADD4 ? 5 : 2;
     T *p[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    for (int i = 0; i < 5; i++) p[i] = i < 5 ? (T *)b[i] : nullptr;
+    for (int i = 0; i < nb; i++) p[i] = (T *)b[i];
     T nan = (T)__builtin_nan("");
     dim3 gr((unsigned)G), bl(v.wg[0]);
+    const int64_t st = v.stride, gst = v.gstride;
     switch (v.op) {
     case PM_STREAM_LOAD:
-        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_LOAD>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
+        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_LOAD, NT>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, st, gst, v.reps, nan);
         break;
     case PM_STREAM_STORE:
-        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_STORE>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
+        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_STORE, NT>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, st, gst, v.reps, nan);
         break;
     case PM_STREAM_COPY:
-        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_COPY>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
+        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_COPY, NT>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, st, gst, v.reps, nan);
         break;
     case PM_STREAM_AXPBY:
-        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_AXPBY>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
+        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_AXPBY, NT>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, st, gst, v.reps, nan);
         break;
     default:
-        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_ADD4>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, (int64_t)v.stride, (int64_t)v.gstride, v.reps, nan);
+        hipLaunchKernelGGL((k_stream<T, VEC, PM_STREAM_ADD4, NT>), gr, bl, 0, s, p[0], p[1], p[2], p[3], p[4], G, st, gst, v.reps, nan);
     }
+}
+
+template <typename T, int VEC>
+static void launch_stream_t(const pm_variant &v, void *const *b, hipStream_t s) {
+    if (v.flags & PM_FLAG_STREAMING) launch_stream_nt<T, VEC, true>(v, b, s);
+    else launch_stream_nt<T, VEC, false>(v, b, s);
 }
 
 template <typename T>

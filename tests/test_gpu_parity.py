@@ -151,6 +151,11 @@ OUT_CASES = (
     + [dict(family="arith", op=op, dtype=dt, n=8192, wg=256, F=F, K=K)
        for op in ("div", "exp") for dt in ("f32", "f64") for (F, K) in ((8, 1), (64, 8))]
     + [dict(family="conv", n=n, T=T) for n in (1, 5, 37, 100) for T in (8, 16)]
+    # the streaming (non-temporal) hint changes no output
+    + [dict(family="stream", op=op, dtype=dt, n=4096, wg=256, s=s, gs=gs, vec=vec, U=U,
+            streaming=True)
+       for op in ("load", "store", "copy", "add4", "axpby") for dt in ("f32", "f64")
+       for (s, gs, vec, U) in ((1, 1, 1, 1), (3, 2, 2, 2), (1, 1, 4 if dt == "f32" else 2, 3))]
 )
 
 

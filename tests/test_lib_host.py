@@ -109,6 +109,8 @@ def test_host_counts_match_oracle(v):
     _same(v)
     _same(dict(v, bitmap=True))  # bitmap footprints instead of intervals
     _same(dict(v, enumerate=True))  # count jobs instead of inline enumeration
+    if v["family"] == "stream":  # the streaming cache hint changes no count
+        _same(dict(v, streaming=True))
 
 
 @pytest.mark.parametrize("v", FAMILY_CASES, ids=lambda v: "-".join(str(x) for x in v.values()))
