@@ -271,7 +271,7 @@ __device__ __forceinline__ int hand_on(const Prog &P, int i, const HandOn &h) {
 // is handed on with its program and jobs in HBM (status PM_DEFER, or
 // PM_ENOMEM / PM_EOVERFLOW when it cannot be: zero outputs then).
 constexpr int64_t BUILD_MAX_ITEMS = 4096;
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
         int64_t *jobres, int64_t *foot, HandOn h, pm_counts *counts, pm_model model,
         int has_model, double *pred) {

@@ -37,7 +37,8 @@ namespace pm {
 
 constexpr int MAXVAR = 8;
 constexpr int MAXGUARD = 4;  // the most any family needs (stencil halo, convolution tile)
-constexpr int MAXACC = 5;    // the most any family needs (4 loads + 1 store)
+constexpr int MAXACC = 5;    // per statement: the most any family needs (4 loads + 1 store)
+constexpr int MAXACC_ALL = 12;  // per program (the stencil has 8)
 constexpr int MAXSTMT = 10;  // the largest family (the stencil) has 9 statements
 constexpr int MAXARR = 6;
 constexpr int MAXJOB = 24;
@@ -90,7 +91,7 @@ struct Stmt {
     uint64_t gmask;  // bits 8q..8q+7: variables with a non-zero coefficient in guard q
     int64_t ext[MAXVAR];
     Aff guard[MAXGUARD];
-    GAcc acc[MAXACC];
+    int32_t acc0;  // its accesses are Prog::acc[acc0, acc0 + nacc)
     int32_t lds[2][3];
     int32_t flop[6][2];
     int32_t bar;
@@ -120,8 +121,13 @@ struct Prog {
     int64_t jobcum[MAXJOB];    // inclusive prefix of job chunks
     int64_t arrcum[MAXARR];    // inclusive prefix of array fill segments
     ArrInfo arr[MAXARR];
+    int32_t nacc_all, pad;
+    GAcc acc[MAXACC_ALL];      // global accesses of all statements, in order
     Stmt st[MAXSTMT];
 };
+
+// Access q of statement s.
+PM_HD const GAcc &stmt_acc(const Prog &p, const Stmt &s, int q) { return p.acc[s.acc0 + q]; }
 
 struct Job {
     int32_t kind, nv, ng, arr;
@@ -194,6 +200,7 @@ struct B {
         s->lane = lane_var;
         s->nguard = 0;
         s->nacc = 0;
+        s->acc0 = p->nacc_all;
         s->gmask = 0;
         for (int i = 0; i < MAXVAR; i++) s->ext[i] = 1;
         for (int d = 0; d < 2; d++)
@@ -244,11 +251,11 @@ struct B {
         lt(s, a, b + 1);
     }
     PM_HD void acc(Stmt *s, int arr, int dir, int elem, int vec, Aff idx) {
-        if (s != cur || nacc >= MAXACC || arr >= p->narr) {
+        if (s != cur || nacc >= MAXACC || p->nacc_all >= MAXACC_ALL || arr >= p->narr) {
             fail(PM_EINVAL);
             return;
         }
-        GAcc &g = s->acc[nacc];
+        GAcc &g = p->acc[p->nacc_all++];
         g.arr = arr;
         g.dir = dir;
         g.elem = elem;
@@ -1041,6 +1048,7 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     p->status = PM_OK;
     p->flags = v.flags;
     p->nstmt = p->narr = p->njob = 0;
+    p->nacc_all = p->pad = 0;
     p->wg_size = 1;
     p->n_wg = 0;
     p->bitmap_words = 0;
@@ -1212,7 +1220,7 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
     s.fixed = fixed;
     // footprint jobs for accesses to arrays with a strided access
     for (int q = 0; q < s.nacc; q++) {
-        GAcc &a = s.acc[q];
+        const GAcc &a = stmt_acc(*p, s, q);
         ArrInfo &A = p->arr[a.arr];
         if (!A.w) continue;
         if (nj >= cap) return over;
@@ -1577,7 +1585,7 @@ PM_HD bool contrib(const Prog &p, int si, int e, const int64_t *F, const int64_t
     c->stmt = (int16_t)si;
     if (e < MAXACC) {
         if (e >= s.nacc) return false;
-        const GAcc &a = s.acc[e];
+        const GAcc &a = stmt_acc(p, s, e);
         const int64_t st = lane_stride(s, a);
         const int z = size_index(a.elem * a.vec);
         const int cl = class_index(st, F[a.arr] + p.arr[a.arr].fixF,
