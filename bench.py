@@ -374,6 +374,15 @@ def main():
         step()
     torch.cuda.synchronize()
     assert int((d_s != 0).sum()) == 0, "variants failed: %s" % d_s.unique()
+    # the counter's own schedule, tuned on this workload before the timed steps
+    from paper_1604_04997_amd import autotune as AT
+    default_sched = ctx.schedule()
+    sched, sched_table = AT.tune_counter(ctx, step)
+    torch.cuda.synchronize()
+    assert int((d_s != 0).sum()) == 0
+    log("counter schedule: chose %s (default %s); %s" % (
+        sched, default_sched, ["%s/%s: %.4f ms" % (c["inblock_items"], c["tail_wgs_per_cu"], t)
+                               for c, t in sched_table]))
     # the timed steps carry HIP events around the expansion kernel only (the
     # dominant kernel's live duration for the roofline; each event costs a
     # few microseconds on the stream)
@@ -504,6 +513,12 @@ def main():
         "geomean_rel_err": model_info,
         "kernel_ms": {k: round(x, 4) for k, x in phase_ms.items()},
         "expansion_kernel_ms_timed": round(build_ms, 4),
+        "counter_schedule": {
+            "chosen": sched, "default": default_sched,
+            "tried_ms": [[c["inblock_items"], c["tail_wgs_per_cu"], round(t, 4)]
+                         for c, t in sched_table],
+            "note": "tried_ms rows: in-block item limit, chip-wide work-groups per CU, "
+                    "best pass time (HIP events, min of 10)"},
         "batch_stats": stats,
         "autotune": tune, "serving": serving, "suite_roofline": suite_roof,
         "roofline": roof, "cpu_baseline": cpu,

@@ -211,6 +211,28 @@ pm_status pm_count_device(pm_ctx *ctx, const pm_variant *d_v, size_t nv,
  * the HBM budget. */
 pm_status pm_reserve(pm_ctx *ctx, size_t nv, size_t bitmap_bytes);
 
+/* Schedule of the batched counter: how a batch's work is split between
+ * the work-group that expands each variant and the chip-wide kernels.
+ * inblock_items: a variant (batches over 32) whose count jobs hold at most
+ *   this many outer points is counted by its own 64-wide work-group; larger
+ *   ones are handed on (0..2^20, default 4096);
+ * fused_items: the same limit for batches of up to 32 variants, whose
+ *   work-groups are 256 wide (0..2^24, default 2^20);
+ * tail_wgs_per_cu: work-groups per compute unit of the chip-wide kernels
+ *   (1..32, default 4).
+ * Counts and predictions do not depend on it (integer sums); only the time
+ * does.  pm_set_schedule returns PM_EINVAL for a value outside its range
+ * and leaves the schedule unchanged; pm_get_schedule writes the current
+ * one.  Both host calls; batches already launched keep their schedule. */
+typedef struct {
+    int64_t inblock_items;
+    int64_t fused_items;
+    int32_t tail_wgs_per_cu;
+    int32_t reserved;  /* zero */
+} pm_schedule;
+pm_status pm_set_schedule(pm_ctx *ctx, const pm_schedule *s);
+pm_status pm_get_schedule(pm_ctx *ctx, pm_schedule *s);
+
 /* Per-kernel timing of the batched counter.  pm_profile(ctx, 1) starts a
  * timing window (pm_profile(ctx, 2): the same with events around the
  * expansion kernel only, ms[0]; every recorded event adds a few

@@ -59,6 +59,11 @@ class Model(ctypes.Structure):
                 ("alpha", ctypes.c_double * PM_NFEAT_MAX)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("inblock_items", ctypes.c_int64), ("fused_items", ctypes.c_int64),
+                ("tail_wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class PMError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (STATUS.get(code, code), msg))
@@ -108,6 +113,8 @@ def lib():
             "pm_profile": (ctypes.c_int, [vp, ctypes.c_int]),
             "pm_profile_read": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int)]),
             "pm_batch_stats": (ctypes.c_int, [vp, P(ctypes.c_int64)]),
+            "pm_set_schedule": (ctypes.c_int, [vp, P(Schedule)]),
+            "pm_get_schedule": (ctypes.c_int, [vp, P(Schedule)]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -300,6 +307,24 @@ class Context:
         nb = ctypes.c_int()
         _check(lib().pm_profile_read(self._h, ms, ctypes.byref(nb)))
         return dict(zip(self.PHASES, ms[:])), nb.value
+
+    def schedule(self) -> dict:
+        """The batched counter's schedule (pm_get_schedule)."""
+        sc = Schedule()
+        _check(lib().pm_get_schedule(self._h, ctypes.byref(sc)))
+        return {"inblock_items": sc.inblock_items, "fused_items": sc.fused_items,
+                "tail_wgs_per_cu": sc.tail_wgs_per_cu}
+
+    def set_schedule(self, **kw):
+        """Change fields of the schedule (pm_set_schedule); returns the new one."""
+        cur = self.schedule()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise KeyError("no schedule field %s" % sorted(unknown))
+        cur.update(kw)
+        sc = Schedule(cur["inblock_items"], cur["fused_items"], cur["tail_wgs_per_cu"], 0)
+        _check(lib().pm_set_schedule(self._h, ctypes.byref(sc)))
+        return self.schedule()
 
     def batch_stats(self) -> dict:
         st = (ctypes.c_int64 * 8)()

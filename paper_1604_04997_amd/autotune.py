@@ -1,5 +1,6 @@
 """Model-ranked configuration selection (the paper's Sec. 6.2 use: pick the
-fastest of several equivalent kernel configurations from predictions).
+fastest of several equivalent kernel configurations from predictions), and
+the schedule tuner of the batched counter itself.
 
 A *problem* is one computation at one size (family, op-independent sizes,
 dtype); its *configurations* are the kernel variants that compute it
@@ -92,3 +93,36 @@ def summary(results):
             "geomean_slowdown": float(math.exp(np.mean(np.log(sl)))),
             "max_slowdown": float(max(sl)),
             "mean_spearman": float(np.mean(sp)) if sp else None}
+
+
+# Schedules of the batched counter tried by tune_counter: the in-block item
+# limit decides which variants the expanding work-group counts itself and
+# which go to the chip-wide kernels; the chip-wide kernels' work-groups per
+# CU trade parallelism against launch cost.
+COUNTER_SCHEDULES = [dict(inblock_items=i, tail_wgs_per_cu=w)
+                     for i in (0, 1024, 4096, 16384, 65536) for w in (1, 2, 4, 8)]
+
+
+def tune_counter(ctx, step, candidates=None, warmup: int = 2, reps: int = 10):
+    """Time one batched counter pass `step()` (launched on torch's current
+    stream) under each candidate schedule: HIP events around each pass,
+    minimum over `reps` passes after `warmup`.  Sets the fastest on `ctx`
+    and returns (chosen, [(schedule, ms), ...])."""
+    import torch
+    cands = candidates or COUNTER_SCHEDULES
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    table = []
+    for sc in cands:
+        cur = ctx.set_schedule(**sc)
+        for _ in range(warmup):
+            step()
+        for e0, e1 in ev:
+            e0.record()
+            step()
+            e1.record()
+        torch.cuda.synchronize()
+        table.append((cur, min(e0.elapsed_time(e1) for e0, e1 in ev)))
+    chosen = min(table, key=lambda r: r[1])[0]
+    ctx.set_schedule(**chosen)
+    return chosen, table

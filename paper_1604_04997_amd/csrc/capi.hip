@@ -81,6 +81,7 @@ struct pm_ctx {
     int device = 0;
     size_t budget = 0;
     int n_cu = 256;
+    pm::Sched sched;
     hipStream_t stream = nullptr;
     pm::Arena ar;
     size_t arena_alloc = 0;  // bytes held by ar (without bitmap)
@@ -220,7 +221,7 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
     const int nmark = c->nmarks();
     for (int attempt = 0; attempt < 2; attempt++) {
         HIPCHK(hipMemcpyAsync(c->d_var, c->h_var, sizeof(pm_variant) * nv, hipMemcpyHostToDevice, c->stream));
-        st = pm::launch_expand(c->ar, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
+        st = pm::launch_expand(c->ar, c->sched, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
                                c->d_status, c->stream, ev, nmark);
         if (st) return set_err(st, "counter launch failed");
         HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
@@ -241,7 +242,7 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
             continue;
         }
         if (deferred) {
-            st = pm::launch_rest(c->ar, (int)nv, c->d_counts, m, m ? c->d_pred : nullptr,
+            st = pm::launch_rest(c->ar, c->sched, (int)nv, c->d_counts, m, m ? c->d_pred : nullptr,
                                  c->d_status, c->stream, c->n_cu, ev, nmark);
             if (st) return set_err(st, "counter launch failed");
             HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
@@ -422,7 +423,7 @@ pm_status pm_count_device(pm_ctx *c, const pm_variant *d_v, size_t nv, pm_counts
     int st = grow_cap(c, nv);
     if (st) return (pm_status)st;
     hipStream_t s = (hipStream_t)stream;  // NULL: HIP's null stream
-    st = pm::launch_batch(c->ar, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu,
+    st = pm::launch_batch(c->ar, c->sched, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu,
                           c->next_events(), c->nmarks());
     if (st) return (pm_status)set_err(st, "counter launch failed");
     return PM_OK;
@@ -442,6 +443,27 @@ pm_status pm_profile(pm_ctx *c, int enable) {
     if (enable < 0 || enable > 2) return (pm_status)set_err(PM_EINVAL, "profile mode is 0, 1 or 2");
     c->profile = enable;
     c->pcount = 0;
+    return PM_OK;
+}
+
+pm_status pm_set_schedule(pm_ctx *c, const pm_schedule *s) {
+    if (!c || !s) return (pm_status)set_err(PM_EINVAL, "null argument");
+    if (s->inblock_items < 0 || s->inblock_items > (1 << 20) || s->fused_items < 0 ||
+        s->fused_items > (1 << 24) || s->tail_wgs_per_cu < 1 || s->tail_wgs_per_cu > 32 ||
+        s->reserved != 0)
+        return (pm_status)set_err(PM_EINVAL, "schedule value out of range");
+    c->sched.inblock_items = s->inblock_items;
+    c->sched.fused_items = s->fused_items;
+    c->sched.tail_wgs_per_cu = s->tail_wgs_per_cu;
+    return PM_OK;
+}
+
+pm_status pm_get_schedule(pm_ctx *c, pm_schedule *s) {
+    if (!c || !s) return (pm_status)set_err(PM_EINVAL, "null argument");
+    s->inblock_items = c->sched.inblock_items;
+    s->fused_items = c->sched.fused_items;
+    s->tail_wgs_per_cu = c->sched.tail_wgs_per_cu;
+    s->reserved = 0;
     return PM_OK;
 }
 

@@ -60,7 +60,17 @@ size_t arena_bytes_per_variant();
 // null.  ev: null, or events recorded around the six phases (build, an
 // empty scan phase, clear, count, fill, finalize); the first `nmark` of the
 // seven are recorded (2: around the expansion kernel only).
-int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
+// Schedule of the batched counter (pm_schedule): the most items a
+// variant's count jobs may hold to be counted by the work-group that
+// expands it (k_build; k_fused), and the work-groups per CU of the
+// chip-wide kernels.
+struct Sched {
+    int64_t inblock_items = 4096;
+    int64_t fused_items = 1 << 20;
+    int tail_wgs_per_cu = 4;
+};
+
+int launch_batch(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu,
                  hipEvent_t *ev = nullptr, int nmark = 7);
@@ -68,11 +78,12 @@ int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
 // ar.parity) and the chip-wide kernels for the variants it handed on
 // (events 2..6), which a caller that has read the expansion's meta half
 // may skip when it handed none on.
-int launch_expand(Arena &ar, int nv, const pm_variant *d_var, pm_counts *d_counts,
+int launch_expand(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var, pm_counts *d_counts,
                   const pm_model *model, double *d_pred, int32_t *d_status, hipStream_t s,
                   hipEvent_t *ev, int nmark);
-int launch_rest(Arena &ar, int nv, pm_counts *d_counts, const pm_model *model, double *d_pred,
-                int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev, int nmark);
+int launch_rest(Arena &ar, const Sched &sc, int nv, pm_counts *d_counts, const pm_model *model,
+                double *d_pred, int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev,
+                int nmark);
 
 // Host execution of the same per-variant code (descriptor, jobs, items,
 // fill, finalize), one variant at a time; for unit tests on machines

@@ -6,7 +6,7 @@
 //             also runs the count jobs (guarded points per statement, Alg.
 //             1) with all its threads and writes the count vector (Eq.
 //             opcount) and the FP64 prediction.  A variant whose footprints
-//             need bitmaps (or whose jobs exceed FUSED_MAX_ITEMS items) is
+//             need bitmaps (or whose jobs exceed the schedule's item limit) is
 //             handed on: its descriptor is copied to HBM, status PM_DEFER.
 // k_build     larger batches, one 64-wide work-group per variant: counts
 //             small count jobs itself and finishes those variants, hands the
@@ -37,7 +37,6 @@ constexpr int FILL_THREADS = 256;
 constexpr int FILL_WORDS_PER_THREAD = 16;  // 4096 words per segment
 constexpr int COUNT_THREADS = 256;
 constexpr int FUSED_THREADS = 256;
-constexpr int64_t FUSED_MAX_ITEMS = 1 << 20;
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 
 // Expansion of one variant by a work-group (at least MAXSTMT threads; all
@@ -265,16 +264,17 @@ __device__ __forceinline__ int hand_on(const Prog &P, int i, const HandOn &h) {
 }
 
 // One variant per 64-wide work-group, expanded in LDS.  A variant without
-// bitmaps whose count jobs hold at most BUILD_MAX_ITEMS items (and fit the
-// LDS staging slots) is finished here: its jobs are counted by the
-// work-group, then the count vector and prediction are written.  Any other
-// is handed on with its program and jobs in HBM (status PM_DEFER, or
-// PM_ENOMEM / PM_EOVERFLOW when it cannot be: zero outputs then).
-constexpr int64_t BUILD_MAX_ITEMS = 4096;
+// bitmaps whose count jobs hold at most `max_items` items (the schedule's
+// in-block limit; and fit the LDS staging slots) is finished here: its jobs
+// are counted by the work-group, then the count vector and prediction are
+// written.  Any other is handed on with its program and jobs in HBM (status
+// PM_DEFER, or PM_ENOMEM / PM_EOVERFLOW when it cannot be: zero outputs
+// then).  The work-group's 10 KB of LDS allows 16 per CU; asking for four
+// waves per SIMD keeps the registers within that occupancy too.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32_t *status,
         int64_t *jobres, int64_t *foot, HandOn h, pm_counts *counts, pm_model model,
-        int has_model, double *pred) {
+        int has_model, double *pred, int64_t max_items) {
     __shared__ Prog P;
     __shared__ union {
         Job jt[NTEMP];  // during the expansion; then the count jobs
@@ -305,7 +305,7 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
             else jid[ncj++] = j;
             items += jitems[j];
         }
-        sh[0] = here && items <= BUILD_MAX_ITEMS ? ncj : -1;
+        sh[0] = here && items <= max_items ? ncj : -1;
     }
     __syncthreads();
     const int ncj = sh[0];
@@ -374,7 +374,7 @@ __device__ int64_t block_sum(int64_t x, int64_t *red) {
 __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         int32_t *status, int64_t *jobres, int64_t *foot, HandOn h, pm_counts *counts,
-        pm_model model, int has_model, double *pred) {
+        pm_model model, int has_model, double *pred, int64_t max_items) {
     __shared__ Prog P;
     __shared__ Job J[MAXJOB];
     __shared__ Job JT[NTEMP];
@@ -396,7 +396,7 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
         for (int j = 0; j < P.njob; j++)
             if (J[j].kind != JOB_NONE) items += J[j].items;
         const bool enumerate = (P.flags & PM_FLAG_ENUMERATE) && items > 0;
-        if (st == PM_OK && (P.bitmap_words > 0 || items > FUSED_MAX_ITEMS || enumerate))
+        if (st == PM_OK && (P.bitmap_words > 0 || items > max_items || enumerate))
             st = PM_DEFER;
         st_sh = st;
     }
@@ -617,15 +617,15 @@ k_finalize(const Prog *prog, const int64_t *jobres, const int64_t *foot,
 }
 
 // ---------------------------------------------------------------- host ---
-int launch_batch(Arena &ar, int nv, const pm_variant *d_var,
+int launch_batch(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev, int nmark) {
-    int st = launch_expand(ar, nv, d_var, d_counts, model, d_pred, d_status, s, ev, nmark);
+    int st = launch_expand(ar, sc, nv, d_var, d_counts, model, d_pred, d_status, s, ev, nmark);
     if (st) return st;
-    return launch_rest(ar, nv, d_counts, model, d_pred, d_status, s, n_cu, ev, nmark);
+    return launch_rest(ar, sc, nv, d_counts, model, d_pred, d_status, s, n_cu, ev, nmark);
 }
 
-int launch_expand(Arena &ar, int nv, const pm_variant *d_var, pm_counts *d_counts,
+int launch_expand(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var, pm_counts *d_counts,
                   const pm_model *model, double *d_pred, int32_t *d_status, hipStream_t s,
                   hipEvent_t *ev, int nmark) {
     if (nv <= 0) return PM_OK;
@@ -644,17 +644,20 @@ int launch_expand(Arena &ar, int nv, const pm_variant *d_var, pm_counts *d_count
     if (nv <= FUSED_MAX_NV)
         hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
                            ar.prog, ar.jobs, d_status, ar.jobres, ar.foot, h, d_counts, m,
-                           has, d_pred);
+                           has, d_pred, sc.fused_items);
     else
         hipLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, nv, d_var, ar.prog, ar.jobs,
-                           d_status, ar.jobres, ar.foot, h, d_counts, m, has, d_pred);
+                           d_status, ar.jobres, ar.foot, h, d_counts, m, has, d_pred,
+                           sc.inblock_items);
     if (ev && nmark > 1) (void)hipEventRecord(ev[1], s);
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
-int launch_rest(Arena &ar, int nv, pm_counts *d_counts, const pm_model *model, double *d_pred,
-                int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev, int nmark) {
+int launch_rest(Arena &ar, const Sched &sc, int nv, pm_counts *d_counts, const pm_model *model,
+                double *d_pred, int32_t *d_status, hipStream_t s, int n_cu, hipEvent_t *ev,
+                int nmark) {
     if (nv <= 0) return PM_OK;
+    const int grid = n_cu * sc.tail_wgs_per_cu;
     int q = 2;
     auto mark = [&]() {
         if (ev && q < nmark) (void)hipEventRecord(ev[q], s);
@@ -668,20 +671,20 @@ int launch_rest(Arena &ar, int nv, pm_counts *d_counts, const pm_model *model, d
     }
     const int64_t *meta = ar.meta + META_WORDS * (ar.parity ^ 1);  // the last expansion's
     mark();  // the scan phase: work lists are claimed by atomics during the expansion
-    hipLaunchKernelGGL(k_clear, dim3(n_cu * 4), dim3(256), 0, s, ar.bitmap, meta,
+    hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, s, ar.bitmap, meta,
                        (int64_t)ar.bitmap_words);
     mark();
-    hipLaunchKernelGGL(k_count, dim3(n_cu * 4), dim3(COUNT_THREADS), 0, s,
+    hipLaunchKernelGGL(k_count, dim3(grid), dim3(COUNT_THREADS), 0, s,
                        (const Prog *)ar.prog, (const Job *)ar.jobs,
                        (const int32_t *)ar.clist, (const int64_t *)ar.cend,
                        (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, meta, (int64_t)ar.cap);
     mark();
-    hipLaunchKernelGGL(k_fill, dim3(n_cu * 4), dim3(FILL_THREADS), 0, s,
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(FILL_THREADS), 0, s,
                        (const Prog *)ar.prog, (const int32_t *)ar.slist,
                        (const int64_t *)ar.send, (const int64_t *)ar.varoff,
                        (const uint64_t *)ar.bitmap, ar.foot, meta, (int64_t)ar.cap);
     mark();
-    const int nfin = nv < n_cu * 4 ? nv : n_cu * 4;
+    const int nfin = nv < grid ? nv : grid;
     hipLaunchKernelGGL(k_finalize, dim3(nfin), dim3(64), 0, s, (const Prog *)ar.prog,
                        (const int64_t *)ar.jobres, (const int64_t *)ar.foot,
                        (const int32_t *)ar.dlist, d_status, d_counts, m, has, d_pred, meta,

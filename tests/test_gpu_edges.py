@@ -2,7 +2,8 @@
 statuses in a batch that mixes valid, invalid and overflowing descriptors
 (on both expansion kernels: batches of up to 32 variants and larger ones),
 the empty batch, batch sizes around the switch between the two kernels,
-and the largest batch one call accepts."""
+the largest batch one call accepts, and the counter's schedule (counts do
+not depend on it)."""
 import numpy as np
 import pytest
 
@@ -121,3 +122,37 @@ def test_largest_batch(ctx):
         ctx.count_device(small.data_ptr(), P.PM_BATCH_MAX + 1, small.data_ptr(), None,
                          small.data_ptr(), small.data_ptr(),
                          torch.cuda.current_stream().cuda_stream)
+
+
+@pytest.mark.parametrize("nv", [12, 150])
+def test_counts_do_not_depend_on_the_schedule(ctx, nv):
+    """Every schedule the tuner tries, on a batch that mixes bitmap
+    footprints, count jobs of every size and closed forms, gives the same
+    counts (both expansion kernels: up to 32 variants and more)."""
+    from paper_1604_04997_amd import autotune as AT
+    from synth import suite_batched
+    base = suite_batched(count=64, lo_log2=8, hi_log2=16, seed=21) + FAMILY_CASES[::9]
+    vs = [dict(v, bitmap=True) if k % 4 == 1 else v for k, v in enumerate(base)][:nv]
+    want = [_strip(C.count(v)) for v in vs]
+    default = ctx.schedule()
+    try:
+        for sc in AT.COUNTER_SCHEDULES[::3] + [dict(inblock_items=0, fused_items=0,
+                                                     tail_wgs_per_cu=32)]:
+            ctx.set_schedule(**sc)
+            print("schedule %s, %d variants" % (sc, nv), flush=True)
+            got = ctx.count(vs)
+            for v, g, w in zip(vs, got, want):
+                assert g == w, (sc, v)
+    finally:
+        ctx.set_schedule(**default)
+    assert ctx.schedule() == default
+
+
+def test_schedule_range_checks(ctx):
+    cur = ctx.schedule()
+    for bad in (dict(inblock_items=-1), dict(inblock_items=(1 << 20) + 1),
+                dict(fused_items=1 << 25), dict(tail_wgs_per_cu=0),
+                dict(tail_wgs_per_cu=33)):
+        with pytest.raises(P.PMError):
+            ctx.set_schedule(**bad)
+        assert ctx.schedule() == cur
