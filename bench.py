@@ -329,6 +329,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 2^26 fp32 once (a kernel of "
                          "known traffic for scaling hardware byte counters)")
+    ap.add_argument("--suite-roofline-only", action="store_true",
+                    help="only the stream and FMA roofline measurements (one JSON "
+                         "line of them; for profiling those kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the counter's work is per variant and "
@@ -345,6 +348,9 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     log("device:", dev.name, "CUs:", dev.multi_processor_count)
     ctx = P.Context(0, hbm_budget=128 << 30)
+    if args.suite_roofline_only:
+        print(json.dumps(suite_roofline(ctx, P)), flush=True)
+        return
 
     # ------------------------------------------------------------- model --
     model_info, models = None, {}
