@@ -77,6 +77,9 @@ struct DeviceGuard {
 
 }  // namespace
 
+// Host-call batches up to this size get mapped-memory outputs.
+constexpr int ZC_MAX = 32;
+
 struct pm_ctx {
     int device = 0;
     size_t budget = 0;
@@ -96,6 +99,14 @@ struct pm_ctx {
     double *h_pred = nullptr;
     int32_t *h_status = nullptr;
     int64_t *h_meta = nullptr;
+    // outputs of small host-call batches, written by the kernels straight
+    // into pinned host memory (fine-grained: visible once the kernel ends)
+    pm_counts *z_counts = nullptr;
+    double *z_pred = nullptr;
+    int32_t *z_status = nullptr;
+    pm_counts *zd_counts = nullptr;  // the same memory, device addresses
+    double *zd_pred = nullptr;
+    int32_t *zd_status = nullptr;
     std::vector<hipEvent_t> events;
     int profile = 0;  // 0 off, 1 every phase, 2 the expansion kernel only
     std::vector<hipEvent_t> pev;  // (PM_NPHASE + 1) per recorded batch
@@ -209,29 +220,44 @@ int grow_bitmap(pm_ctx *c, size_t words) {
 }
 
 // Count (and optionally predict) nv <= cap variants from host memory.
+// Batches of up to ZC_MAX variants have their outputs written by the
+// kernels into mapped host memory (no device-to-host copies); larger ones
+// are copied back.
 int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
                    const pm_model *m, double *t) {
     int st = grow_cap(c, nv);
     if (st) return st;
     std::memcpy(c->h_var, v, sizeof(pm_variant) * nv);
+    const bool zc = nv <= (size_t)ZC_MAX;
+    pm_counts *dc = zc ? c->zd_counts : c->d_counts;
+    double *dp = m ? (zc ? c->zd_pred : c->d_pred) : nullptr;
+    int32_t *ds = zc ? c->zd_status : c->d_status;
+    const int32_t *hs = zc ? c->z_status : c->h_status;
+    // read back what the kernels wrote (copies only for large batches)
+    auto fetch = [&]() -> int {
+        if (!zc) {
+            HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
+            if (out) HIPCHK(hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(pm_counts) * nv, hipMemcpyDeviceToHost, c->stream));
+            if (m) HIPCHK(hipMemcpyAsync(c->h_pred, c->d_pred, 8 * nv, hipMemcpyDeviceToHost, c->stream));
+        }
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return PM_OK;
+    };
     // The expansion kernel finishes most variants by itself; the chip-wide
-    // kernels run only when it handed some on, after the host has read its
-    // meta half (one more round trip then, four launches fewer otherwise).
+    // kernels run only when it handed some on, after the host has read the
+    // statuses (one more round trip then, four launches fewer otherwise).
     hipEvent_t *ev = c->next_events();
     const int nmark = c->nmarks();
     for (int attempt = 0; attempt < 2; attempt++) {
         HIPCHK(hipMemcpyAsync(c->d_var, c->h_var, sizeof(pm_variant) * nv, hipMemcpyHostToDevice, c->stream));
-        st = pm::launch_expand(c->ar, c->sched, (int)nv, c->d_var, c->d_counts, m, m ? c->d_pred : nullptr,
-                               c->d_status, c->stream, ev, nmark);
+        st = pm::launch_expand(c->ar, c->sched, (int)nv, c->d_var, dc, m, dp, ds, c->stream, ev,
+                               nmark);
         if (st) return set_err(st, "counter launch failed");
-        HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
-        if (out) HIPCHK(hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(pm_counts) * nv, hipMemcpyDeviceToHost, c->stream));
-        if (m) HIPCHK(hipMemcpyAsync(c->h_pred, c->d_pred, 8 * nv, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
+        if ((st = fetch())) return st;
         bool nomem = false, deferred = false;
         for (size_t i = 0; i < nv; i++) {
-            nomem |= c->h_status[i] == PM_ENOMEM;
-            deferred |= c->h_status[i] == pm::PM_DEFER;
+            nomem |= hs[i] == PM_ENOMEM;
+            deferred |= hs[i] == pm::PM_DEFER;
         }
         if (nomem) {  // grow the bitmap arena to what the batch asked for, expand again
             if (attempt == 1) return set_err(PM_ENOMEM, "footprint bitmaps do not fit");
@@ -242,13 +268,10 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
             continue;
         }
         if (deferred) {
-            st = pm::launch_rest(c->ar, c->sched, (int)nv, c->d_counts, m, m ? c->d_pred : nullptr,
-                                 c->d_status, c->stream, c->n_cu, ev, nmark);
+            st = pm::launch_rest(c->ar, c->sched, (int)nv, dc, m, dp, ds, c->stream, c->n_cu, ev,
+                                 nmark);
             if (st) return set_err(st, "counter launch failed");
-            HIPCHK(hipMemcpyAsync(c->h_status, c->d_status, 4 * nv, hipMemcpyDeviceToHost, c->stream));
-            if (out) HIPCHK(hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(pm_counts) * nv, hipMemcpyDeviceToHost, c->stream));
-            if (m) HIPCHK(hipMemcpyAsync(c->h_pred, c->d_pred, 8 * nv, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
+            if ((st = fetch())) return st;
         } else if (ev) {  // phases that did not run take no time
             for (int q = 2; q < nmark; q++) (void)hipEventRecord(ev[q], c->stream);
         }
@@ -256,13 +279,13 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
     }
     int first = PM_OK;
     for (size_t i = 0; i < nv; i++) {
-        if (c->h_status[i] != PM_OK && first == PM_OK) {
-            first = c->h_status[i];
+        if (hs[i] != PM_OK && first == PM_OK) {
+            first = hs[i];
             set_err(first, "variant " + std::to_string(i) + ": " + status_name(first));
         }
     }
-    if (out) std::memcpy(out, c->h_counts, sizeof(pm_counts) * nv);
-    if (m && t) std::memcpy(t, c->h_pred, 8 * nv);
+    if (out) std::memcpy(out, zc ? c->z_counts : c->h_counts, sizeof(pm_counts) * nv);
+    if (m && t) std::memcpy(t, zc ? c->z_pred : c->h_pred, 8 * nv);
     return first;
 }
 
@@ -357,6 +380,14 @@ pm_status pm_create(pm_ctx **out, int device, size_t budget) {
         return (pm_status)set_err(PM_EDEVICE, "stream creation failed");
     if (hipHostMalloc(&c->h_meta, 8 * pm::META_WORDS, 0) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "pinned allocation failed");
+    const unsigned zf = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc(&c->z_counts, sizeof(pm_counts) * ZC_MAX, zf) != hipSuccess ||
+        hipHostMalloc(&c->z_pred, sizeof(double) * ZC_MAX, zf) != hipSuccess ||
+        hipHostMalloc(&c->z_status, sizeof(int32_t) * ZC_MAX, zf) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->zd_counts, c->z_counts, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->zd_pred, c->z_pred, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->zd_status, c->z_status, 0) != hipSuccess)
+        return (pm_status)set_err(PM_EDEVICE, "mapped pinned allocation failed");
     *out = c.release();
     return PM_OK;
 }
@@ -368,6 +399,9 @@ void pm_destroy(pm_ctx *c) {
     free_arena(c);
     (void)hipFree(c->ar.bitmap);
     (void)hipHostFree(c->h_meta);
+    (void)hipHostFree(c->z_counts);
+    (void)hipHostFree(c->z_pred);
+    (void)hipHostFree(c->z_status);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);

@@ -40,7 +40,8 @@ constexpr int FUSED_THREADS = 256;
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 
 // Expansion of one variant by a work-group (at least MAXSTMT threads; all
-// call this): thread 0 lays out the statements, thread si analyses
+// call this): the first wavefront lays out the statements (affine forms
+// spread over its lanes), thread si analyses
 // statement si in job slots 2si and 2si+1, thread 0 finishes
 // (build_slots_finish).  p and the NTEMP job buffers jt are in LDS, handed
 // to the first statements that make jobs (the others make theirs in
@@ -49,9 +50,12 @@ constexpr int NTEMP = 4;
 __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jobs, Job *jt,
                                            int *sh) {
     const int t = threadIdx.x;
-    if (t == 0) {
-        sh[0] = build_head(v, p, jobs);
-        sh[1 + MAXSTMT] = 0;  // temp buffers handed out
+    if (t < 64) {  // the first wavefront lays out the statements, all lanes together
+        const int st = build_head<LaneAff>(v, p, jobs);
+        if (t == 0) {
+            sh[0] = st;
+            sh[1 + MAXSTMT] = 0;  // temp buffers handed out
+        }
     }
     __syncthreads();
     if (sh[0] != PM_OK) return sh[0];

@@ -175,7 +175,65 @@ PM_HD int size_index(int bytes) {
 PM_HD bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // -------------------------------------------------------------- builder ---
-struct B {
+// Affine forms while a descriptor is built.  RowAff: a whole form per
+// thread (the host, or one device lane).  LaneAff (device): a wavefront
+// holds one form, coefficient x in lane x and the constant in lane MAXVAR,
+// so an update is one instruction and storing a row one store by nine
+// lanes; every lane of the wavefront must run the builder together, with
+// the same arguments.
+struct RowAff {
+    using V = Aff;
+    static PM_HD V mk(int64_t k) { return aff(k); }
+    static PM_HD V add(V a, int x, int64_t c) {
+        a.c[x] += c;
+        return a;
+    }
+    static PM_HD V add_k(V a, int64_t d) {
+        a.k += d;
+        return a;
+    }
+    static PM_HD V neg(V a) {
+        for (int i = 0; i < MAXVAR; i++) a.c[i] = -a.c[i];
+        a.k = -a.k;
+        return a;
+    }
+    static PM_HD int64_t coef(const V &a, int x) { return a.c[x]; }
+    static PM_HD uint64_t vars(const V &a) {  // bit x: coefficient x non-zero
+        uint64_t m = 0;
+        for (int x = 0; x < MAXVAR; x++)
+            if (a.c[x]) m |= 1ull << x;
+        return m;
+    }
+    static PM_HD void put(Aff *dst, const V &a) { *dst = a; }
+};
+
+struct LaneAff {
+    struct V {
+        int64_t v;
+    };
+    static __device__ int lane() { return (int)(threadIdx.x & 63); }
+    static __device__ V mk(int64_t k) { return V{lane() == MAXVAR ? k : 0}; }
+    static __device__ V add(V a, int x, int64_t c) { return V{a.v + (lane() == x ? c : 0)}; }
+    static __device__ V add_k(V a, int64_t d) { return V{a.v + (lane() == MAXVAR ? d : 0)}; }
+    static __device__ V neg(V a) { return V{-a.v}; }
+    static __device__ int64_t coef(const V &a, int x) {
+        const uint64_t u = (uint64_t)a.v;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, x);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), x);
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    }
+    static __device__ uint64_t vars(const V &a) {
+        return __ballot(lane() < MAXVAR && a.v != 0) & ((1ull << MAXVAR) - 1);
+    }
+    static __device__ void put(Aff *dst, const V &a) {
+        if (lane() <= MAXVAR) ((int64_t *)dst)[lane()] = a.v;  // c[0..MAXVAR), then k
+    }
+};
+static_assert(offsetof(Aff, k) == MAXVAR * sizeof(int64_t), "row layout: c then k");
+
+template <class AP>
+struct BT {
+    using V = typename AP::V;
     Prog *p;
     // counts of the statement being built, kept in registers so that the
     // variable and guard indices of a builder are compile-time constants.
@@ -225,32 +283,29 @@ struct B {
         s->nvar = nvar + 1;
         return nvar++;
     }
-    PM_HD void ge0(Stmt *s, Aff a) {  // a >= 0
+    // affine forms of this builder
+    PM_HD V mk(int64_t k) const { return AP::mk(k); }
+    PM_HD V av(V a, int x, int64_t c) const { return AP::add(a, x, c); }
+    PM_HD void ge0(Stmt *s, V a) {  // a >= 0
         if (s != cur || nguard >= MAXGUARD) {
             fail(PM_EINVAL);
             return;
         }
-        s->guard[nguard] = a;
-        uint64_t m = 0;
-        for (int x = 0; x < MAXVAR; x++)
-            if (a.c[x]) m |= 1ull << x;
-        s->gmask |= m << (8 * nguard);
+        AP::put(&s->guard[nguard], a);
+        s->gmask |= AP::vars(a) << (8 * nguard);
         s->nguard = ++nguard;
     }
-    PM_HD void lt(Stmt *s, Aff a, int64_t b) {  // a < b  <=>  (b-1) - a >= 0
-        Aff g = aff(b - 1 - a.k);
-        for (int i = 0; i < MAXVAR; i++) g.c[i] = -a.c[i];
-        ge0(s, g);
+    PM_HD void lt(Stmt *s, V a, int64_t b) {  // a < b  <=>  (b-1) - a >= 0
+        ge0(s, AP::add_k(AP::neg(a), b - 1));
     }
-    PM_HD void ge(Stmt *s, Aff a, int64_t b) {  // a >= b
-        a.k -= b;
-        ge0(s, a);
+    PM_HD void ge(Stmt *s, V a, int64_t b) {  // a >= b
+        ge0(s, AP::add_k(a, -b));
     }
-    PM_HD void eq(Stmt *s, Aff a, int64_t b) {
+    PM_HD void eq(Stmt *s, V a, int64_t b) {
         ge(s, a, b);
         lt(s, a, b + 1);
     }
-    PM_HD void acc(Stmt *s, int arr, int dir, int elem, int vec, Aff idx) {
+    PM_HD void acc(Stmt *s, int arr, int dir, int elem, int vec, V idx) {
         if (s != cur || nacc >= MAXACC || p->nacc_all >= MAXACC_ALL || arr >= p->narr) {
             fail(PM_EINVAL);
             return;
@@ -260,11 +315,12 @@ struct B {
         g.dir = dir;
         g.elem = elem;
         g.vec = vec;
-        g.idx = idx;
+        AP::put(&g.idx, idx);
         s->nacc = ++nacc;
         // the array's fill width: lane stride (in accesses) times the width
         // of a strided (stride >= 2) access
-        const int64_t d = idx.c[lane] < 0 ? -idx.c[lane] : idx.c[lane];
+        const int64_t cl = AP::coef(idx, lane);
+        const int64_t d = cl < 0 ? -cl : cl;
         const int64_t st = vec == 1 ? d : vec == 2 ? ((d & 1) ? -1 : d >> 1)
                          : vec == 4 ? ((d & 3) ? -1 : d >> 2) : -1;
         if (st < 0 || size_index(elem * vec) < 0) {
@@ -291,7 +347,8 @@ struct B {
     }
 };
 
-PM_HD int64_t prod3(B &b, int64_t x, int64_t y, int64_t z) {
+template <class BB>
+PM_HD int64_t prod3(BB &b, int64_t x, int64_t y, int64_t z) {
     int64_t r;
     if (mul_ovf(x, y, &r) || mul_ovf(r, z, &r)) {
         b.fail(PM_EOVERFLOW);
@@ -301,7 +358,8 @@ PM_HD int64_t prod3(B &b, int64_t x, int64_t y, int64_t z) {
 }
 
 // --- stream: global-memory accesses at a lane stride and group stride ---
-PM_HD void build_stream(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_stream(BB &b, const pm_variant &v) {
     int64_t N = v.n[0], wg = v.wg[0], s = v.stride, gs = v.gstride,
             vec = v.vec, U = v.reps;
     int e = v.dtype == PM_F64 ? 8 : 4;
@@ -327,13 +385,13 @@ PM_HD void build_stream(B &b, const pm_variant &v) {
         if (!S) return;
         int g = b.var(S, G), l = b.var(S, wg), u = b.var(S, U);
         for (int c = 0; c < k; c++)
-            b.acc(S, 0, D_LD, e, 1, av(av(av(aff(c), g, k * wg), l, k), u, k * G * wg));
+            b.acc(S, 0, D_LD, e, 1, b.av(b.av(b.av(b.mk(c), g, k * wg), l, k), u, k * G * wg));
         S->flop[K_ADD][dt] = (int32_t)k;
         Stmt *T = b.stmt(1);
         if (!T) return;
         g = b.var(T, G);
         l = b.var(T, wg);
-        b.acc(T, 1, D_ST, e, 1, av(av(aff(0), g, wg), l, 1));
+        b.acc(T, 1, D_ST, e, 1, b.av(b.av(b.mk(0), g, wg), l, 1));
         return;
     }
     int64_t span = prod3(b, G * gs, wg * s, U * vec);
@@ -343,7 +401,7 @@ PM_HD void build_stream(B &b, const pm_variant &v) {
     Stmt *S = b.stmt(1);
     if (!S) return;
     int g = b.var(S, G), l = b.var(S, wg), u = b.var(S, U);
-    Aff x = av(av(av(aff(0), g, vec * gs * wg * s), l, vec * s), u, vec * G * gs * wg * s);
+    auto x = b.av(b.av(b.av(b.mk(0), g, vec * gs * wg * s), l, vec * s), u, vec * G * gs * wg * s);
     switch (v.op) {
     case PM_STREAM_LOAD:  // summed in a register; the sentinel store never runs
         b.acc(S, 0, D_LD, e, (int)vec, x);
@@ -371,7 +429,8 @@ PM_HD void build_stream(B &b, const pm_variant &v) {
 }
 
 // --- LDS: R accesses per work-item at bank stride b ---
-PM_HD void build_lds(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_lds(BB &b, const pm_variant &v) {
     int64_t G = v.n[0], wg = v.wg[0], R = v.reps, W = v.words;
     if (G <= 0 || wg <= 0 || wg > 1024 || R < 0 || v.stride < 1 ||
         !pow2(W) || W > 16384 || W % wg || v.op > PM_LDS_WRITE) {
@@ -384,7 +443,7 @@ PM_HD void build_lds(B &b, const pm_variant &v) {
     Stmt *S = b.stmt(1);
     if (!S) return;
     int g = b.var(S, G), l = b.var(S, wg);
-    b.acc(S, 0, D_ST, 4, 1, av(av(aff(0), g, wg), l, 1));
+    b.acc(S, 0, D_ST, 4, 1, b.av(b.av(b.mk(0), g, wg), l, 1));
     S->bar = 1;
     Stmt *L = b.stmt(1);
     if (!L) return;
@@ -403,7 +462,8 @@ PM_HD void build_lds(B &b, const pm_variant &v) {
 
 // --- FMA / rsqrt chains: 1 load, F ops, 1 store per work-item ---
 // kind 0: FMA, 1: rsqrt, 2: division, 3: exponential
-PM_HD void build_chain(B &b, const pm_variant &v, int kind) {
+template <class BB>
+PM_HD void build_chain(BB &b, const pm_variant &v, int kind) {
     int64_t N = v.n[0], wg = v.wg[0], F = v.reps, K = v.chains;
     int e = v.dtype == PM_F64 ? 8 : 4;
     int dt = v.dtype == PM_F64 ? 1 : 0;
@@ -422,7 +482,7 @@ PM_HD void build_chain(B &b, const pm_variant &v, int kind) {
     Stmt *S = b.stmt(1);
     if (!S) return;
     int g = b.var(S, N / wg), l = b.var(S, wg);
-    Aff i = av(av(aff(0), g, wg), l, 1);
+    auto i = b.av(b.av(b.mk(0), g, wg), l, 1);
     b.acc(S, 0, D_LD, e, 1, i);
     b.acc(S, 1, D_ST, e, 1, i);
     if (rsq) {  // y = rsqrt(y*y + d)
@@ -443,7 +503,8 @@ PM_HD void build_chain(B &b, const pm_variant &v, int kind) {
     }
 }
 
-PM_HD void build_barrier(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_barrier(BB &b, const pm_variant &v) {
     int64_t G = v.n[0], wg = v.wg[0], Bn = v.reps;
     if (G <= 0 || wg <= 0 || wg > 1024 || Bn < 0 || Bn > (1 << 20)) {
         b.fail(PM_EINVAL);
@@ -456,10 +517,11 @@ PM_HD void build_barrier(B &b, const pm_variant &v) {
     if (!S) return;
     int g = b.var(S, G), l = b.var(S, wg);
     S->bar = (int32_t)Bn;
-    b.acc(S, 0, D_ST, 4, 1, av(av(aff(0), g, wg), l, 1));
+    b.acc(S, 0, D_ST, 4, 1, b.av(b.av(b.mk(0), g, wg), l, 1));
 }
 
-PM_HD void build_empty(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_empty(BB &b, const pm_variant &v) {
     int64_t n = v.n[0], wx = v.wg[0], wy = v.wg[1] ? v.wg[1] : 1;
     if (n <= 0 || wx <= 0 || wy <= 0 || wx * wy > 1024) {
         b.fail(PM_EINVAL);
@@ -472,7 +534,8 @@ PM_HD void build_empty(B &b, const pm_variant &v) {
 PM_HD bool tile_ok(int T) { return T == 8 || T == 16 || T == 32; }
 
 // --- matmul: C[n,l] = A[n,m] B[m,l], T x T work-groups ---
-PM_HD void build_matmul(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_matmul(BB &b, const pm_variant &v) {
     int64_t n = v.n[0], m = v.n[1], L = v.n[2], T = v.tile;
     if (n <= 0 || m <= 0 || L <= 0 || !tile_ok((int)T) || v.dtype != PM_F32 ||
         v.op > PM_MATMUL_NAIVE || n > (1 << 24) || m > (1 << 24) || L > (1 << 24)) {
@@ -492,22 +555,22 @@ PM_HD void build_matmul(B &b, const pm_variant &v) {
         b.var(S, T);
         b.var(S, T);
     };
-    Aff row = av(av(aff(0), 0, T), 2, 1), col = av(av(aff(0), 1, T), 3, 1);
+    auto row = b.av(b.av(b.mk(0), 0, T), 2, 1), col = b.av(b.av(b.mk(0), 1, T), 3, 1);
     if (v.op == PM_MATMUL_TILED) {
         Stmt *S = b.stmt(3);  // A tile element -> LDS
         if (!S) return;
         head(S);
         int kt = b.var(S, KT);
         b.lt(S, row, n);
-        b.lt(S, av(av(aff(0), kt, T), 3, 1), m);
-        b.acc(S, 0, D_LD, 4, 1, av(av(av(av(aff(0), 0, T * m), 2, m), kt, T), 3, 1));
+        b.lt(S, b.av(b.av(b.mk(0), kt, T), 3, 1), m);
+        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 0, T * m), 2, m), kt, T), 3, 1));
         Stmt *Sb = b.stmt(3);  // B tile element -> LDS
         if (!Sb) return;
         head(Sb);
         kt = b.var(Sb, KT);
-        b.lt(Sb, av(av(aff(0), kt, T), 2, 1), m);
+        b.lt(Sb, b.av(b.av(b.mk(0), kt, T), 2, 1), m);
         b.lt(Sb, col, L);
-        b.acc(Sb, 1, D_LD, 4, 1, av(av(av(av(aff(0), kt, T * L), 2, L), 1, T), 3, 1));
+        b.acc(Sb, 1, D_LD, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), kt, T * L), 2, L), 1, T), 3, 1));
         Stmt *Sl = b.stmt(3);  // LDS stores (zero-padded outside) + 2 barriers
         if (!Sl) return;
         head(Sl);
@@ -528,8 +591,8 @@ PM_HD void build_matmul(B &b, const pm_variant &v) {
         int k = b.var(S, m);
         b.lt(S, row, n);
         b.lt(S, col, L);
-        b.acc(S, 0, D_LD, 4, 1, av(av(av(aff(0), 0, T * m), 2, m), k, 1));
-        b.acc(S, 1, D_LD, 4, 1, av(av(av(aff(0), k, L), 1, T), 3, 1));
+        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.av(b.mk(0), 0, T * m), 2, m), k, 1));
+        b.acc(S, 1, D_LD, 4, 1, b.av(b.av(b.av(b.mk(0), k, L), 1, T), 3, 1));
         S->flop[K_FMA][0] = 1;
     }
     Stmt *Sc = b.stmt(3);
@@ -537,11 +600,12 @@ PM_HD void build_matmul(B &b, const pm_variant &v) {
     head(Sc);
     b.lt(Sc, row, n);
     b.lt(Sc, col, L);
-    b.acc(Sc, 2, D_ST, 4, 1, av(av(av(av(aff(0), 0, T * L), 2, L), 1, T), 3, 1));
+    b.acc(Sc, 2, D_ST, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 0, T * L), 2, L), 1, T), 3, 1));
 }
 
 // --- transpose: out[c][r] = in[r][c], n x n ---
-PM_HD void build_transpose(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_transpose(BB &b, const pm_variant &v) {
     int64_t n = v.n[0], T = v.tile;
     if (n <= 0 || n > (1 << 24) || !tile_ok((int)T) || v.dtype != PM_F32 ||
         v.op > PM_TRANSPOSE_NAIVE_RC) {
@@ -559,9 +623,9 @@ PM_HD void build_transpose(B &b, const pm_variant &v) {
         b.var(S, T);  // 2 ly
         b.var(S, T);  // 3 lx
     };
-    Aff r = av(av(aff(0), 0, T), 2, 1), c = av(av(aff(0), 1, T), 3, 1);
-    Aff rn_c = av(av(av(av(aff(0), 0, T * n), 2, n), 1, T), 3, 1);  // r*n + c
-    Aff cn_r = av(av(av(av(aff(0), 1, T * n), 3, n), 0, T), 2, 1);  // c*n + r
+    auto r = b.av(b.av(b.mk(0), 0, T), 2, 1), c = b.av(b.av(b.mk(0), 1, T), 3, 1);
+    auto rn_c = b.av(b.av(b.av(b.av(b.mk(0), 0, T * n), 2, n), 1, T), 3, 1);  // r*n + c
+    auto cn_r = b.av(b.av(b.av(b.av(b.mk(0), 1, T * n), 3, n), 0, T), 2, 1);  // c*n + r
     if (v.op == PM_TRANSPOSE_TILED) {
         Stmt *S = b.stmt(3);
         if (!S) return;
@@ -577,10 +641,10 @@ PM_HD void build_transpose(B &b, const pm_variant &v) {
         Stmt *St = b.stmt(3);  // r2 = gx*T + ly, c2 = gy*T + lx
         if (!St) return;
         head(St);
-        b.lt(St, av(av(aff(0), 1, T), 2, 1), n);
-        b.lt(St, av(av(aff(0), 0, T), 3, 1), n);
+        b.lt(St, b.av(b.av(b.mk(0), 1, T), 2, 1), n);
+        b.lt(St, b.av(b.av(b.mk(0), 0, T), 3, 1), n);
         St->lds[D_LD][0] = 1;
-        b.acc(St, 1, D_ST, 4, 1, av(av(av(av(aff(0), 1, T * n), 2, n), 0, T), 3, 1));
+        b.acc(St, 1, D_ST, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 1, T * n), 2, n), 0, T), 3, 1));
     } else {
         Stmt *S = b.stmt(3);
         if (!S) return;
@@ -598,7 +662,8 @@ PM_HD void build_transpose(B &b, const pm_variant &v) {
 }
 
 // --- 5-point stencil on an (n+2)^2 input with halo, T x T tiles in LDS ---
-PM_HD void build_stencil(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_stencil(BB &b, const pm_variant &v) {
     int64_t n = v.n[0], T = v.tile;
     if (n <= 0 || n > (1 << 24) || !tile_ok((int)T)) {
         b.fail(PM_EINVAL);
@@ -612,12 +677,12 @@ PM_HD void build_stencil(B &b, const pm_variant &v) {
     b.p->wg_size = (int32_t)(T * T);
     b.array(0, P * P);
     b.array(1, n * n);
-    Aff i = av(av(aff(0), 0, T), 2, 1), j = av(av(aff(0), 1, T), 3, 1);
+    auto i = b.av(b.av(b.mk(0), 0, T), 2, 1), j = b.av(b.av(b.mk(0), 1, T), 3, 1);
     // flat index of input cell (i + di, j + dj)
     auto at = [&](int64_t di, int64_t dj) {
-        return av(av(av(av(aff(di * P + dj), 0, T * P), 2, P), 1, T), 3, 1);
+        return b.av(b.av(b.av(b.av(b.mk(di * P + dj), 0, T * P), 2, P), 1, T), 3, 1);
     };
-    Aff ly = av(aff(0), 2, 1), lx = av(aff(0), 3, 1);
+    auto ly = b.av(b.mk(0), 2, 1), lx = b.av(b.mk(0), 3, 1);
     for (int q = 0; q < 7; q++) {
         Stmt *S = b.stmt(3);
         if (!S) return;
@@ -667,11 +732,12 @@ PM_HD void build_stencil(B &b, const pm_variant &v) {
     Sc->lds[D_LD][z] = 5;
     Sc->flop[K_ADD][dt] = 4;  // N+S, +W, +E, + h^2 c^2
     Sc->flop[K_MUL][dt] = 3;  // c*c, h^2*(.), 0.25*(.)
-    b.acc(Sc, 1, D_ST, e, 1, av(av(av(av(aff(0), 0, T * n), 2, n), 1, T), 3, 1));
+    b.acc(Sc, 1, D_ST, e, 1, b.av(b.av(b.av(b.av(b.mk(0), 0, T * n), 2, n), 1, T), 3, 1));
 }
 
 // --- all-pairs n-body: out[i] = sum_{j != i} rsqrt(|x_i - x_j|^2) ---
-PM_HD void build_nbody(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_nbody(BB &b, const pm_variant &v) {
     int64_t N = v.n[0], Gs = v.wg[0];
     if (N <= 0 || N > (1 << 26) || Gs < 64 || Gs > 1024 || Gs % 64 ||
         v.dtype != PM_F32) {
@@ -686,17 +752,17 @@ PM_HD void build_nbody(B &b, const pm_variant &v) {
     Stmt *S = b.stmt(1);  // own position
     if (!S) return;
     int g = b.var(S, GB), l = b.var(S, Gs);
-    Aff i = av(av(aff(0), g, Gs), l, 1);
+    auto i = b.av(b.av(b.mk(0), g, Gs), l, 1);
     b.lt(S, i, N);
     for (int c = 0; c < 3; c++)
-        b.acc(S, 0, D_LD, 4, 1, av(av(aff(c), g, 3 * Gs), l, 3));
+        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.mk(c), g, 3 * Gs), l, 3));
     Stmt *Sk = b.stmt(1);  // a block of positions -> LDS
     if (!Sk) return;
     g = b.var(Sk, GB), l = b.var(Sk, Gs);
     int jb = b.var(Sk, GB);
-    b.lt(Sk, av(av(aff(0), jb, Gs), l, 1), N);
+    b.lt(Sk, b.av(b.av(b.mk(0), jb, Gs), l, 1), N);
     for (int c = 0; c < 3; c++)
-        b.acc(Sk, 0, D_LD, 4, 1, av(av(aff(c), jb, 3 * Gs), l, 3));
+        b.acc(Sk, 0, D_LD, 4, 1, b.av(b.av(b.mk(c), jb, 3 * Gs), l, 3));
     Sk->lds[D_ST][0] = 3;
     Stmt *Sb = b.stmt(1);
     if (!Sb) return;
@@ -707,7 +773,7 @@ PM_HD void build_nbody(B &b, const pm_variant &v) {
     b.var(Sp, GB), b.var(Sp, Gs);
     jb = b.var(Sp, GB);
     int jj = b.var(Sp, Gs);
-    b.lt(Sp, av(av(aff(0), jb, Gs), jj, 1), N);
+    b.lt(Sp, b.av(b.av(b.mk(0), jb, Gs), jj, 1), N);
     Sp->lds[D_LD][0] = 3;
     Sp->flop[K_ADD][0] = 6;   // 3 differences, 2 adds in r^2, 1 accumulate
     Sp->flop[K_MUL][0] = 3;
@@ -715,14 +781,15 @@ PM_HD void build_nbody(B &b, const pm_variant &v) {
     Stmt *So = b.stmt(1);
     if (!So) return;
     g = b.var(So, GB), l = b.var(So, Gs);
-    b.lt(So, av(av(aff(0), g, Gs), l, 1), N);
-    b.acc(So, 1, D_ST, 4, 1, av(av(aff(0), g, Gs), l, 1));
+    b.lt(So, b.av(b.av(b.mk(0), g, Gs), l, 1), N);
+    b.acc(So, 1, D_ST, 4, 1, b.av(b.av(b.mk(0), g, Gs), l, 1));
 }
 
 // --- convolution: three 7x7 filters over three RGB images ---
 // Work-group (gx, gy, image zi, filter zj), T x T work-items; the filter and
 // the (T+6)^2 x 3 image tile are staged through LDS.
-PM_HD void build_conv(B &b, const pm_variant &v) {
+template <class BB>
+PM_HD void build_conv(BB &b, const pm_variant &v) {
     int64_t n = v.n[0], T = v.tile;
     if (n <= 0 || n > (1 << 20) || !(T == 8 || T == 16) || v.dtype != PM_F32) {
         b.fail(PM_EINVAL);
@@ -748,21 +815,21 @@ PM_HD void build_conv(B &b, const pm_variant &v) {
     if (!Sf) return;
     head(Sf);
     int k = b.var(Sf, KF);
-    Aff t = av(av(av(aff(0), k, T * T), 4, T), 5, 1);
+    auto t = b.av(b.av(b.av(b.mk(0), k, T * T), 4, T), 5, 1);
     b.lt(Sf, t, 147);
-    b.acc(Sf, 1, D_LD, 4, 1, av(av(av(av(aff(0), 3, 147), k, T * T), 4, T), 5, 1));
+    b.acc(Sf, 1, D_LD, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 3, 147), k, T * T), 4, T), 5, 1));
     Sf->lds[D_ST][0] = 1;
     Stmt *Si = b.stmt(5);  // image tile cell (a*T + ly, b*T + lx), 3 channels
     if (!Si) return;
     head(Si);
     int a = b.var(Si, KA), bb = b.var(Si, KA);
-    b.lt(Si, av(av(aff(0), a, T), 4, 1), TT);
-    b.lt(Si, av(av(aff(0), bb, T), 5, 1), TT);
-    b.lt(Si, av(av(av(aff(0), 0, T), a, T), 4, 1), P);
-    b.lt(Si, av(av(av(aff(0), 1, T), bb, T), 5, 1), P);
+    b.lt(Si, b.av(b.av(b.mk(0), a, T), 4, 1), TT);
+    b.lt(Si, b.av(b.av(b.mk(0), bb, T), 5, 1), TT);
+    b.lt(Si, b.av(b.av(b.av(b.mk(0), 0, T), a, T), 4, 1), P);
+    b.lt(Si, b.av(b.av(b.av(b.mk(0), 1, T), bb, T), 5, 1), P);
     for (int c = 0; c < 3; c++)  // ((zi*P + X)*P + Y)*3 + c
         b.acc(Si, 0, D_LD, 4, 1,
-              av(av(av(av(av(av(av(aff(c), 2, P * P * 3), 0, T * P * 3), a, T * P * 3),
+              b.av(b.av(b.av(b.av(b.av(b.av(b.av(b.mk(c), 2, P * P * 3), 0, T * P * 3), a, T * P * 3),
                              4, P * 3), 1, T * 3), bb, T * 3), 5, 3));
     Si->lds[D_ST][0] = 3;
     Stmt *Sb = b.stmt(5);
@@ -774,7 +841,7 @@ PM_HD void build_conv(B &b, const pm_variant &v) {
     head(Sm);
     b.var(Sm, 7);
     b.var(Sm, 7);
-    Aff x = av(av(aff(0), 0, T), 4, 1), y = av(av(aff(0), 1, T), 5, 1);
+    auto x = b.av(b.av(b.mk(0), 0, T), 4, 1), y = b.av(b.av(b.mk(0), 1, T), 5, 1);
     b.lt(Sm, x, n);
     b.lt(Sm, y, n);
     Sm->lds[D_LD][0] = 6;
@@ -785,7 +852,7 @@ PM_HD void build_conv(B &b, const pm_variant &v) {
     b.lt(So, x, n);
     b.lt(So, y, n);  // ((zi*3 + zj)*n + x)*n + y
     b.acc(So, 2, D_ST, 4, 1,
-          av(av(av(av(av(av(aff(0), 2, 3 * n * n), 3, n * n), 0, T * n), 4, n), 1, T), 5, 1));
+          b.av(b.av(b.av(b.av(b.av(b.av(b.mk(0), 2, 3 * n * n), 3, n * n), 0, T * n), 4, n), 1, T), 5, 1));
 }
 
 // ------------------------------------------------------ job preparation ---
@@ -1044,6 +1111,7 @@ PM_HD void put_job(Job *dst, const Job &src) {
 
 // Statements of the variant's family, MAXJOB cleared job slots, and the
 // fill width of every array with a strided access.  Returns the status.
+template <class AP = RowAff>
 PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     p->status = PM_OK;
     p->flags = v.flags;
@@ -1053,7 +1121,7 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     p->n_wg = 0;
     p->bitmap_words = 0;
     p->chunks = p->segs = 0;
-    B b{p};
+    BT<AP> b{p};
     switch (v.family) {
     case PM_FAM_STREAM: build_stream(b, v); break;
     case PM_FAM_LDS: build_lds(b, v); break;
