@@ -205,6 +205,10 @@ struct RowAff {
         return m;
     }
     static PM_HD void put(Aff *dst, const V &a) { *dst = a; }
+    template <class F>
+    static PM_HD void each(int n, F f) {  // f(i) for i < n
+        for (int i = 0; i < n; i++) f(i);
+    }
 };
 
 struct LaneAff {
@@ -228,8 +232,13 @@ struct LaneAff {
     static __device__ void put(Aff *dst, const V &a) {
         if (lane() <= MAXVAR) ((int64_t *)dst)[lane()] = a.v;  // c[0..MAXVAR), then k
     }
+    template <class F>
+    static __device__ void each(int n, F f) {  // f(i) for i < n (n <= 64), lane i
+        if (lane() < n) f(lane());
+    }
 };
 static_assert(offsetof(Aff, k) == MAXVAR * sizeof(int64_t), "row layout: c then k");
+static_assert(MAXJOB <= 64 && MAXVAR < 64, "LaneAff::each covers one wavefront");
 
 template <class AP>
 struct BT {
@@ -260,10 +269,9 @@ struct BT {
         s->nacc = 0;
         s->acc0 = p->nacc_all;
         s->gmask = 0;
-        for (int i = 0; i < MAXVAR; i++) s->ext[i] = 1;
-        for (int d = 0; d < 2; d++)
-            for (int z = 0; z < 3; z++) s->lds[d][z] = 0;
-        for (int k = 0; k < 6; k++) s->flop[k][0] = s->flop[k][1] = 0;
+        AP::each(MAXVAR, [&](int i) { s->ext[i] = 1; });
+        AP::each(6, [&](int i) { (&s->lds[0][0])[i] = 0; });
+        AP::each(12, [&](int i) { (&s->flop[0][0])[i] = 0; });
         s->bar = 0;
         s->ncomp = 0;
         s->fixed = 0;
@@ -1137,10 +1145,10 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     case PM_FAM_NBODY: build_nbody(b, v); break;
     default: b.fail(PM_EINVAL);
     }
-    for (int j = 0; j < MAXJOB; j++) {
+    AP::each(MAXJOB, [&](int j) {
         jobs[j].kind = JOB_NONE;
         jobs[j].chunks = 0;
-    }
+    });
     // arrays needing footprints got their fill widths as accesses were added
     if (p->status == PM_OK && b.werr) b.fail(PM_EINVAL);
     return p->status;
