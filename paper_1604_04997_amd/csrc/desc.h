@@ -868,21 +868,26 @@ PM_HD void build_conv(BB &b, const pm_variant &v) {
 // mixed-radix digit pair; returns the new variable count.
 PM_HD int fuse(int nv, int64_t *ext, int nf, int64_t (*f)[MAXVAR + 1],
                bool *ovf) {
+    // rows in which each variable appears: only variables with the same
+    // rows can fuse, so the coefficients are compared for those pairs only
+    uint32_t sig[MAXVAR];
+    for (int x = 0; x < nv; x++) {
+        uint32_t m = 0;
+        for (int q = 0; q < nf; q++)
+            if (f[q][x]) m |= 1u << q;
+        sig[x] = m;
+    }
     bool again = true;
     while (again && nv > 1) {
         again = false;
         for (int a = 0; a < nv && !again; a++)
             for (int bb = 0; bb < nv && !again; bb++) {
-                if (a == bb) continue;
+                if (a == bb || sig[a] != sig[bb]) continue;
                 bool ok = true;
-                for (int q = 0; q < nf && ok; q++) {
-                    const int64_t ca = f[q][a], cb = f[q][bb];
-                    if (!ca) {  // then b must be absent too (ext >= 1)
-                        ok = cb == 0;
-                        continue;
-                    }
+                for (uint32_t r = sig[a]; r && ok; r &= r - 1) {
+                    const int q = __builtin_ctz(r);
                     int64_t want;
-                    if (!cb || mul_ovf(ca, ext[a], &want) || cb != want) ok = false;
+                    if (mul_ovf(f[q][a], ext[a], &want) || f[q][bb] != want) ok = false;
                 }
                 if (!ok) continue;
                 int64_t e2;
@@ -894,6 +899,7 @@ PM_HD int fuse(int nv, int64_t *ext, int nf, int64_t (*f)[MAXVAR + 1],
                 // remove bb
                 for (int t = bb; t < nv - 1; t++) {
                     ext[t] = ext[t + 1];
+                    sig[t] = sig[t + 1];
                     for (int q = 0; q < nf; q++) f[q][t] = f[q][t + 1];
                 }
                 for (int q = 0; q < nf; q++) f[q][nv - 1] = 0;
