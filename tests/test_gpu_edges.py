@@ -156,3 +156,43 @@ def test_schedule_range_checks(ctx):
         with pytest.raises(P.PMError):
             ctx.set_schedule(**bad)
         assert ctx.schedule() == cur
+
+
+def test_profile_and_batch_stats(ctx):
+    """Phase timing windows (every phase, then the expansion kernel only)
+    and the last batch's statistics: a batch with bitmap footprints hands
+    variants on, one without hands none on."""
+    import torch
+    vs = [dict(v, bitmap=True) for v in FAMILY_CASES if v["family"] == "transpose"][:40]
+    marked = sum(P.bitmap_bytes(v) > 0 for v in vs)  # these are handed on
+    assert marked > 0
+    va = P.variant_array(vs)
+    nv = len(vs)
+    d_v = torch.frombuffer(bytearray(bytes(memoryview(va).cast("B"))), dtype=torch.uint8).cuda()
+    d_c = torch.zeros((nv, P.PM_NCOUNT), dtype=torch.int64, device="cuda")
+    d_t = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    d_s = torch.zeros(nv, dtype=torch.int32, device="cuda")
+    ctx.reserve(nv, sum(P.bitmap_bytes(v) for v in vs))
+    stream = torch.cuda.current_stream().cuda_stream
+    for mode, nph in ((1, len(P.Context.PHASES)), (2, 1)):
+        ctx.profile(mode)
+        for _ in range(3):
+            ctx.count_device(d_v.data_ptr(), nv, d_c.data_ptr(), None, d_t.data_ptr(),
+                             d_s.data_ptr(), stream)
+        torch.cuda.synchronize()
+        ms, nb = ctx.profile_read()
+        ctx.profile(False)
+        assert nb == 3
+        assert ms["build"] > 0
+        assert all(x >= 0 for x in ms.values())
+        assert sum(x > 0 for x in ms.values()) <= nph
+    st = ctx.batch_stats()
+    assert st["handed_on"] == marked and st["chunks"] > 0 and st["fill_segments"] > 0
+    assert st["bitmap_words"] > 0 and st["bitmap_words_requested"] >= st["bitmap_words"]
+    got = d_c.cpu().numpy()
+    names = P.count_names()
+    for k, v in enumerate(vs):
+        assert {names[i]: int(x) for i, x in enumerate(got[k]) if x} == _strip(C.count(v)), v
+    plain = [v for v in FAMILY_CASES if v["family"] == "matmul"][:40]
+    ctx.count(plain)
+    assert ctx.batch_stats()["handed_on"] == 0
