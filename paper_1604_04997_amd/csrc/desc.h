@@ -269,9 +269,9 @@ struct BT {
         s->nacc = 0;
         s->acc0 = p->nacc_all;
         s->gmask = 0;
-        AP::each(MAXVAR, [&](int i) { s->ext[i] = 1; });
-        AP::each(6, [&](int i) { (&s->lds[0][0])[i] = 0; });
-        AP::each(12, [&](int i) { (&s->flop[0][0])[i] = 0; });
+        AP::each(MAXVAR, [=](int i) { s->ext[i] = 1; });
+        AP::each(6, [=](int i) { (&s->lds[0][0])[i] = 0; });
+        AP::each(12, [=](int i) { (&s->flop[0][0])[i] = 0; });
         s->bar = 0;
         s->ncomp = 0;
         s->fixed = 0;
@@ -1151,7 +1151,7 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     case PM_FAM_NBODY: build_nbody(b, v); break;
     default: b.fail(PM_EINVAL);
     }
-    AP::each(MAXJOB, [&](int j) {
+    AP::each(MAXJOB, [=](int j) {
         jobs[j].kind = JOB_NONE;
         jobs[j].chunks = 0;
     });
