@@ -60,6 +60,56 @@ def test_counts_full_size_closed_forms(ctx):
         assert g == closed_counts(v), v
 
 
+def test_bench_workload_on_the_device_path(ctx):
+    """The timed configuration itself: the 4096-variant sweep through
+    pm_count_device in one launch sequence with the extension model, under
+    the default schedule and the one the tuner picks on it; every count
+    vector against the closed forms, every prediction against the host's
+    features of those counts."""
+    import torch
+    from paper_1604_04997_amd import autotune as AT
+    vs = suite_batched(4096)
+    nv = len(vs)
+    d_v = torch.frombuffer(bytearray(bytes(memoryview(P.variant_array(vs)).cast("B"))),
+                           dtype=torch.uint8).cuda()
+    d_c = torch.zeros((nv, P.PM_NCOUNT), dtype=torch.int64, device="cuda")
+    d_t = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    d_s = torch.full((nv,), 99, dtype=torch.int32, device="cuda")
+    alpha = np.linspace(1e-13, 1e-11, P.NFEAT["ext"])
+    m = P.model_struct("ext", alpha)
+    ctx.reserve(nv, sum(P.bitmap_bytes(v) for v in vs))
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        ctx.count_device(d_v.data_ptr(), nv, d_c.data_ptr(), m, d_t.data_ptr(),
+                         d_s.data_ptr(), stream)
+
+    names = P.count_names()
+    want = np.zeros((nv, P.PM_NCOUNT), dtype=np.int64)
+    for k, v in enumerate(vs):
+        for name, x in closed_counts(v).items():
+            want[k, names.index(name)] = x
+    pred = None
+    default = ctx.schedule()
+    try:
+        for tune in (False, True):
+            if tune:
+                AT.tune_counter(ctx, step, candidates=AT.COUNTER_SCHEDULES[4:], reps=2)
+            print("sweep on the device path, schedule %s" % ctx.schedule(), flush=True)
+            d_c.zero_()
+            step()
+            torch.cuda.synchronize()
+            assert (d_s.cpu() == 0).all()
+            got = d_c.cpu().numpy()
+            np.testing.assert_array_equal(got, want)
+            if pred is None:
+                arr = ctx.count_raw(vs)
+                pred = np.array([P.features(arr[i], "ext") @ alpha for i in range(nv)])
+            np.testing.assert_allclose(d_t.cpu().numpy(), pred, rtol=1e-12)
+    finally:
+        ctx.set_schedule(**default)
+
+
 def test_batched_equals_one_at_a_time_and_any_order(ctx):
     vs = suite_batched(192, seed=11) + FAMILY_CASES[::7]
     whole = P.counts_numpy(ctx.count_raw(vs))
