@@ -438,6 +438,17 @@ def main():
     plain = ns / (tp1 - tp0)
     t_call = (tp1 - tp0) / ns
     log("plain: %.0f variants/s (%.1f us per call, %d-variant sample)" % (plain, t_call * 1e6, ns))
+    # the whole sweep through the host-memory call (variants in, count
+    # vectors out over PCIe): one pm_count of 4096 variants, best of three
+    va_host = P.variant_array(vs)
+    t_host = []
+    for _ in range(3):
+        th0 = time.perf_counter()
+        ctx.count_raw(va_host)
+        t_host.append(time.perf_counter() - th0)
+    host_batched = nv / min(t_host)
+    log("batched through host memory: %.0f variants/s (%.3f ms per call)" % (
+        host_batched, min(t_host) * 1e3))
 
     # ---------------------------------------------------------- autotune --
     tune = None
@@ -515,6 +526,7 @@ def main():
                    "model": "ext (the paper's property list and its named extensions)"},
         "points_per_s": float("%.4g" % (points * value / nv)),
         "plain_variants_per_s": round(plain, 1), "plain_us_per_call": round(t_call * 1e6, 2),
+        "host_memory_batched_variants_per_s": round(host_batched, 1),
         "batched_over_plain": round(value / plain, 2),
         "geomean_rel_err": model_info,
         "kernel_ms": {k: round(x, 4) for k, x in phase_ms.items()},
