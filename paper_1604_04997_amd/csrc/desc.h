@@ -147,6 +147,12 @@ struct Job {
 
 // ------------------------------------------------------------- helpers ---
 PM_HD bool mul_ovf(int64_t a, int64_t b, int64_t *r) {
+    // both factors within 32 bits (the usual case): the product fits
+    if ((uint64_t)a + 0x80000000ull < 0x100000000ull &&
+        (uint64_t)b + 0x80000000ull < 0x100000000ull) {
+        *r = a * b;
+        return false;
+    }
     return __builtin_mul_overflow(a, b, r);
 }
 PM_HD bool add_ovf(int64_t a, int64_t b, int64_t *r) {
@@ -943,20 +949,31 @@ PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt,
     const int a = __builtin_ctz(M);
     const uint32_t rest = M & (M - 1);
     if (rest & (rest - 1)) return false;  // three or more variables
+    const int b = rest ? __builtin_ctz(rest) : a;
+    // both variables' coefficients and the constant of every guard row,
+    // read at once (rows outside qs take no part)
+    int64_t ca[MAXGUARD], cb[MAXGUARD], kq[MAXGUARD];
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++) {
+        ca[q] = s.guard[q].c[a];
+        cb[q] = s.guard[q].c[b];
+        kq[q] = s.guard[q].k;
+    }
     int64_t ext = s.ext[a], lo = 0, hi;
     bool use_b = false;
     if (rest) {
-        const int b = __builtin_ctz(rest);
         const int64_t ea = ext, eb = s.ext[b];
         // (x, y) fuses when every form has c_y == c_x * ext_x (both zero, or
         // both non-zero without overflow)
         bool fab = true, fba = true;
-        for (uint32_t r = qs; r; r &= r - 1) {
-            const int q = __builtin_ctz(r);
-            const int64_t ca = s.guard[q].c[a], cb = s.guard[q].c[b];
+#pragma unroll
+        for (int q = 0; q < MAXGUARD; q++) {
+            if (!((qs >> q) & 1)) continue;
             int64_t want;
-            if (ca ? (!cb || mul_ovf(ca, ea, &want) || cb != want) : cb != 0) fab = false;
-            if (cb ? (!ca || mul_ovf(cb, eb, &want) || ca != want) : ca != 0) fba = false;
+            if (ca[q] ? (!cb[q] || mul_ovf(ca[q], ea, &want) || cb[q] != want) : cb[q] != 0)
+                fab = false;
+            if (cb[q] ? (!ca[q] || mul_ovf(cb[q], eb, &want) || ca[q] != want) : ca[q] != 0)
+                fba = false;
         }
         if (!fab && !fba) return false;
         use_b = !fab;
@@ -964,21 +981,11 @@ PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt,
             *ovf = true;
             return true;
         }
-        if (use_b) {
-            hi = ext;
-            for (uint32_t r = qs; r; r &= r - 1) {
-                const int q = __builtin_ctz(r);
-                clip(s.guard[q].c[b], s.guard[q].k, lo, hi);
-            }
-            *cnt = hi > lo ? hi - lo : 0;
-            return true;
-        }
     }
     hi = ext;
-    for (uint32_t r = qs; r; r &= r - 1) {
-        const int q = __builtin_ctz(r);
-        clip(s.guard[q].c[a], s.guard[q].k, lo, hi);
-    }
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++)
+        if ((qs >> q) & 1) clip(use_b ? cb[q] : ca[q], kq[q], lo, hi);
     *cnt = hi > lo ? hi - lo : 0;
     return true;
 }
@@ -1177,20 +1184,26 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
     s.ncomp = 0;
     const int nvar = s.nvar, ng = s.nguard;
     bool empty = false;
-    int64_t ext[MAXVAR];  // read at once
+    // the statement's extents (undeclared ones are 1) and guard constants,
+    // read at once (rows past nguard are not used)
+    int64_t ext[MAXVAR], kq[MAXGUARD];
 #pragma unroll
-    for (int x = 0; x < MAXVAR; x++) {
-        ext[x] = x < nvar ? s.ext[x] : 1;
+    for (int x = 0; x < MAXVAR; x++) ext[x] = s.ext[x];
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++) kq[q] = s.guard[q].k;
+#pragma unroll
+    for (int x = 0; x < MAXVAR; x++)
         if (ext[x] == 0) empty = true;
-    }
     // variables of each guard (8 bits per guard) and of all guards
     const uint64_t gm = s.gmask;
     const uint32_t vmask = (1u << nvar) - 1;  // declared variables
     uint32_t guarded = 0;
-    for (int q = 0; q < ng; q++) {
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++) {
+        if (q >= ng) break;
         const uint32_t m = (uint32_t)(gm >> (8 * q)) & vmask;
         guarded |= m;
-        if (!m && s.guard[q].k < 0) empty = true;
+        if (!m && kq[q] < 0) empty = true;
     }
     if (empty) {
         s.fixed = 0;
