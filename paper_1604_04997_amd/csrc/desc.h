@@ -1275,7 +1275,9 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
             J.f[J.ng][MAXVAR] = s.guard[q].k;
             J.ng++;
         }
-        J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
+        // two variables reach here only when small_component found that
+        // they fuse in neither order, which is fuse()'s test on these rows
+        if (ncol > 2) J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
         if (ovf) return PM_EOVERFLOW;
         if (J.nv == 1) {  // an interval: closed form, the slot is reused
             c = interval_count(J.ext[0], J.ng, J.f);
