@@ -1243,75 +1243,85 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
         if (nj >= cap) return over;
         if (s.ncomp >= MAXCOMP) return PM_EINVAL;
         if (!asked) jt = temp(), asked = true;
-        Job &J = jt ? *jt : jobs[nj];  // kept only if it enumerates
-        J.kind = JOB_COUNT;
-        J.nv = 0;
-        J.ng = 0;
-        J.arr = -1;
-        J.vec = 1;
-        J.mark_b = 0;
-        // job column t: the component's t-th variable (increasing order)
-        int xt[MAXVAR];
-        const int ncol = __builtin_popcount(M);
-        {
-            uint32_t r = M;
+        // the job, assembled in a fast buffer when one was given (a call per
+        // memory, so each knows where J lives): 1 made, 0 an interval (its
+        // count in c), < 0 a status
+        auto count_job = [&](Job &J) __attribute__((always_inline)) -> int {
+            J.kind = JOB_COUNT;
+            J.nv = 0;
+            J.ng = 0;
+            J.arr = -1;
+            J.vec = 1;
+            J.mark_b = 0;
+            // job column t: the component's t-th variable (increasing order)
+            int xt[MAXVAR];
+            const int ncol = __builtin_popcount(M);
+            {
+                uint32_t r = M;
 #pragma unroll
-            for (int t = 0; t < MAXVAR; t++) {
-                xt[t] = r ? __builtin_ctz(r) : 0;
-                r &= r - 1;
+                for (int t = 0; t < MAXVAR; t++) {
+                    xt[t] = r ? __builtin_ctz(r) : 0;
+                    r &= r - 1;
+                }
             }
-        }
-        J.nv = ncol;
+            J.nv = ncol;
 #pragma unroll
-        for (int t = 0; t < MAXVAR; t++)
-            if (t < ncol) J.ext[t] = s.ext[xt[t]];
-        for (uint32_t r = qs; r; r &= r - 1) {
-            const int q = __builtin_ctz(r);
-            int64_t row[MAXVAR];
+            for (int t = 0; t < MAXVAR; t++)
+                if (t < ncol) J.ext[t] = s.ext[xt[t]];
+            for (uint32_t r = qs; r; r &= r - 1) {
+                const int q = __builtin_ctz(r);
+                int64_t row[MAXVAR];
 #pragma unroll
-            for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? s.guard[q].c[xt[t]] : 0;
+                for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? s.guard[q].c[xt[t]] : 0;
 #pragma unroll
-            for (int t = 0; t < MAXVAR; t++) J.f[J.ng][t] = row[t];
-            J.f[J.ng][MAXVAR] = s.guard[q].k;
-            J.ng++;
-        }
-        // two variables reach here only when small_component found that
-        // they fuse in neither order, which is fuse()'s test on these rows
-        if (ncol > 2) J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
-        if (ovf) return PM_EOVERFLOW;
-        if (J.nv == 1) {  // an interval: closed form, the slot is reused
-            c = interval_count(J.ext[0], J.ng, J.f);
+                for (int t = 0; t < MAXVAR; t++) J.f[J.ng][t] = row[t];
+                J.f[J.ng][MAXVAR] = s.guard[q].k;
+                J.ng++;
+            }
+            // two variables reach here only when small_component found that
+            // they fuse in neither order, which is fuse()'s test on these rows
+            if (ncol > 2) J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
+            if (ovf) return PM_EOVERFLOW;
+            if (J.nv == 1) {  // an interval: closed form, the slot is reused
+                c = interval_count(J.ext[0], J.ng, J.f);
+                return 0;
+            }
+            // inner variable: the largest extent
+            int in = 0;
+            for (int x = 1; x < J.nv; x++)
+                if (J.ext[x] > J.ext[in]) in = x;
+            if (in) {
+                int64_t te = J.ext[0];
+                J.ext[0] = J.ext[in];
+                J.ext[in] = te;
+                for (int q = 0; q < J.ng; q++) {
+                    int64_t tg = J.f[q][0];
+                    J.f[q][0] = J.f[q][in];
+                    J.f[q][in] = tg;
+                }
+            }
+            for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;  // no index map
+            J.outer = 1;
+            for (int x = 1; x < J.nv; x++)
+                if (mul_ovf(J.outer, J.ext[x], &J.outer)) return PM_EOVERFLOW;
+            J.seg = J.ext[0];
+            J.nseg = 1;
+            J.items = J.outer;
+            J.chunk_items = CHUNK_COUNT;
+            J.chunks = cdiv(J.items, CHUNK_COUNT);
+            J.f_off = J.b_off = 0;
+            J.words = 0;
+            J.w = 0;
+            J.ivok = 0;
+            return 1;
+        };
+        const int rj = jt ? count_job(*jt) : count_job(jobs[nj]);
+        if (rj < 0) return rj;
+        if (rj == 0) {
             if (mul_ovf(fixed, c, &fixed)) return PM_EOVERFLOW;
             continue;
         }
-        // inner variable: the largest extent
-        int in = 0;
-        for (int x = 1; x < J.nv; x++)
-            if (J.ext[x] > J.ext[in]) in = x;
-        if (in) {
-            int64_t te = J.ext[0];
-            J.ext[0] = J.ext[in];
-            J.ext[in] = te;
-            for (int q = 0; q < J.ng; q++) {
-                int64_t tg = J.f[q][0];
-                J.f[q][0] = J.f[q][in];
-                J.f[q][in] = tg;
-            }
-        }
-        for (int t = 0; t <= MAXVAR; t++) J.f[J.ng][t] = 0;  // no index map
-        J.outer = 1;
-        for (int x = 1; x < J.nv; x++)
-            if (mul_ovf(J.outer, J.ext[x], &J.outer)) return PM_EOVERFLOW;
-        J.seg = J.ext[0];
-        J.nseg = 1;
-        J.items = J.outer;
-        J.chunk_items = CHUNK_COUNT;
-        J.chunks = cdiv(J.items, CHUNK_COUNT);
-        J.f_off = J.b_off = 0;
-        J.words = 0;
-        J.w = 0;
-        J.ivok = 0;
-        if (jt) put_job(&jobs[nj], J);
+        if (jt) put_job(&jobs[nj], *jt);
         s.comp_job[s.ncomp++] = nj++;
     }
     s.fixed = fixed;
@@ -1322,95 +1332,100 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
         if (!A.w) continue;
         if (nj >= cap) return over;
         if (!asked) jt = temp(), asked = true;
-        Job &J = jt ? *jt : jobs[nj];
-        J.kind = JOB_FOOT;
-        J.nv = 0;
-        J.ng = 0;
-        J.arr = a.arr;
-        J.vec = a.vec;
-        J.mark_b = lane_stride(s, a) >= 2;  // strided: its cells are widened
-        J.f_off = J.b_off = -1;             // set with the array's mode below
-        J.words = 0;
-        J.w = J.mark_b ? A.w : 0;
-        // variables: every guarded one and those of the index map, in
-        // increasing order (job column t = the t-th of them)
-        uint32_t Mf = guarded;
+        // assembled like the count jobs: 1 made, < 0 a status
+        auto foot_job = [&](Job &J) __attribute__((always_inline)) -> int {
+            J.kind = JOB_FOOT;
+            J.nv = 0;
+            J.ng = 0;
+            J.arr = a.arr;
+            J.vec = a.vec;
+            J.mark_b = lane_stride(s, a) >= 2;  // strided: its cells are widened
+            J.f_off = J.b_off = -1;             // set with the array's mode below
+            J.words = 0;
+            J.w = J.mark_b ? A.w : 0;
+            // variables: every guarded one and those of the index map, in
+            // increasing order (job column t = the t-th of them)
+            uint32_t Mf = guarded;
 #pragma unroll
-        for (int x = 0; x < MAXVAR; x++)
-            if (a.idx.c[x]) Mf |= 1u << x;
-        Mf &= vmask;
-        int xt[MAXVAR];
-        const int ncol = __builtin_popcount(Mf);
-        {
-            uint32_t r = Mf;
+            for (int x = 0; x < MAXVAR; x++)
+                if (a.idx.c[x]) Mf |= 1u << x;
+            Mf &= vmask;
+            int xt[MAXVAR];
+            const int ncol = __builtin_popcount(Mf);
+            {
+                uint32_t r = Mf;
 #pragma unroll
-            for (int t = 0; t < MAXVAR; t++) {
-                xt[t] = r ? __builtin_ctz(r) : 0;
-                r &= r - 1;
+                for (int t = 0; t < MAXVAR; t++) {
+                    xt[t] = r ? __builtin_ctz(r) : 0;
+                    r &= r - 1;
+                }
             }
-        }
-        J.nv = ncol;
+            J.nv = ncol;
 #pragma unroll
-        for (int t = 0; t < MAXVAR; t++)
-            if (t < ncol) J.ext[t] = s.ext[xt[t]];
-        for (int g = 0; g < ng; g++) {
-            int64_t row[MAXVAR];
+            for (int t = 0; t < MAXVAR; t++)
+                if (t < ncol) J.ext[t] = s.ext[xt[t]];
+            for (int g = 0; g < ng; g++) {
+                int64_t row[MAXVAR];
 #pragma unroll
-            for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? s.guard[g].c[xt[t]] : 0;
+                for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? s.guard[g].c[xt[t]] : 0;
 #pragma unroll
-            for (int t = 0; t < MAXVAR; t++) J.f[J.ng][t] = row[t];
-            J.f[J.ng][MAXVAR] = s.guard[g].k;
-            J.ng++;
-        }
-        int64_t *ic = J.f[J.ng];  // the index map after the guards
-        {
-            int64_t row[MAXVAR];
-#pragma unroll
-            for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? a.idx.c[xt[t]] : 0;
-#pragma unroll
-            for (int t = 0; t < MAXVAR; t++) ic[t] = row[t];
-            ic[MAXVAR] = a.idx.k;
-        }
-        // fuse over guards and the index map together
-        bool ovf = false;
-        J.nv = fuse(J.nv, J.ext, J.ng + 1, J.f, &ovf);
-        if (ovf) return PM_EOVERFLOW;
-        if (J.nv == 0) {  // a single access point
-            J.nv = 1;
-            J.ext[0] = 1;
-        }
-        // inner variable: smallest non-zero index coefficient
-        int in = -1;
-        for (int x = 0; x < J.nv; x++) {
-            if (!ic[x]) continue;
-            if (in < 0 || iabs(ic[x]) < iabs(ic[in]) ||
-                (iabs(ic[x]) == iabs(ic[in]) && J.ext[x] > J.ext[in]))
-                in = x;
-        }
-        if (in < 0) in = 0;
-        if (in) {
-            int64_t te = J.ext[0];
-            J.ext[0] = J.ext[in];
-            J.ext[in] = te;
-            for (int g = 0; g <= J.ng; g++) {
-                int64_t tg = J.f[g][0];
-                J.f[g][0] = J.f[g][in];
-                J.f[g][in] = tg;
+                for (int t = 0; t < MAXVAR; t++) J.f[J.ng][t] = row[t];
+                J.f[J.ng][MAXVAR] = s.guard[g].k;
+                J.ng++;
             }
-        }
-        J.outer = 1;
-        for (int x = 1; x < J.nv; x++)
-            if (mul_ovf(J.outer, J.ext[x], &J.outer)) return PM_EOVERFLOW;
-        J.seg = iabs(ic[0]) <= J.vec ? SEG_CONTIG : SEG_STRIDED;
-        J.nseg = cdiv(J.ext[0], J.seg);
-        if (mul_ovf(J.outer, J.nseg, &J.items)) return PM_EOVERFLOW;
-        J.chunk_items = CHUNK_FOOT;
-        J.chunks = cdiv(J.items, CHUNK_FOOT);
-        J.ivok = ival_ok(J);
-        J.ivst = PM_OK;
-        J.ivF = J.ivFill = 0;
-        if (J.ivok) J.ivst = ival_sizes(J, &J.ivF, &J.ivFill);
-        if (jt) put_job(&jobs[nj], J);
+            int64_t *ic = J.f[J.ng];  // the index map after the guards
+            {
+                int64_t row[MAXVAR];
+#pragma unroll
+                for (int t = 0; t < MAXVAR; t++) row[t] = t < ncol ? a.idx.c[xt[t]] : 0;
+#pragma unroll
+                for (int t = 0; t < MAXVAR; t++) ic[t] = row[t];
+                ic[MAXVAR] = a.idx.k;
+            }
+            // fuse over guards and the index map together
+            bool ovf = false;
+            J.nv = fuse(J.nv, J.ext, J.ng + 1, J.f, &ovf);
+            if (ovf) return PM_EOVERFLOW;
+            if (J.nv == 0) {  // a single access point
+                J.nv = 1;
+                J.ext[0] = 1;
+            }
+            // inner variable: smallest non-zero index coefficient
+            int in = -1;
+            for (int x = 0; x < J.nv; x++) {
+                if (!ic[x]) continue;
+                if (in < 0 || iabs(ic[x]) < iabs(ic[in]) ||
+                    (iabs(ic[x]) == iabs(ic[in]) && J.ext[x] > J.ext[in]))
+                    in = x;
+            }
+            if (in < 0) in = 0;
+            if (in) {
+                int64_t te = J.ext[0];
+                J.ext[0] = J.ext[in];
+                J.ext[in] = te;
+                for (int g = 0; g <= J.ng; g++) {
+                    int64_t tg = J.f[g][0];
+                    J.f[g][0] = J.f[g][in];
+                    J.f[g][in] = tg;
+                }
+            }
+            J.outer = 1;
+            for (int x = 1; x < J.nv; x++)
+                if (mul_ovf(J.outer, J.ext[x], &J.outer)) return PM_EOVERFLOW;
+            J.seg = iabs(ic[0]) <= J.vec ? SEG_CONTIG : SEG_STRIDED;
+            J.nseg = cdiv(J.ext[0], J.seg);
+            if (mul_ovf(J.outer, J.nseg, &J.items)) return PM_EOVERFLOW;
+            J.chunk_items = CHUNK_FOOT;
+            J.chunks = cdiv(J.items, CHUNK_FOOT);
+            J.ivok = ival_ok(J);
+            J.ivst = PM_OK;
+            J.ivF = J.ivFill = 0;
+            if (J.ivok) J.ivst = ival_sizes(J, &J.ivF, &J.ivFill);
+            return 1;
+        };
+        const int rf = jt ? foot_job(*jt) : foot_job(jobs[nj]);
+        if (rf < 0) return rf;
+        if (jt) put_job(&jobs[nj], *jt);
         nj++;
     }
     *made = nj - base;
