@@ -17,14 +17,17 @@
 //     by a common guard); the count is the product of component counts;
 //   * two variables a, b fuse into one of extent ext_a*ext_b when every
 //     affine form of the component has coef_b == coef_a*ext_a;
-//   * a one-variable component is an interval, counted in closed form;
-//     larger components become GPU jobs that enumerate all variables but
-//     one and intersect the guards for the last (inner) one.
-// Footprints (Alg. 2) of arrays with a lane stride >= 2 are marked in
-// bitmaps by footprint jobs over the same fused domains.
+//   * a one-variable component (or two that fuse) is an interval, counted
+//     in closed form; larger components become jobs that enumerate all
+//     variables but one and intersect the guards for the last (inner) one.
+// Footprints (Alg. 2) of arrays with a lane stride >= 2 are sized in closed
+// form when they are equally spaced runs, else marked in bitmaps by
+// footprint jobs over the same fused domains.
 //
-// Everything here is __host__ __device__: the build and finalize kernels
-// run it on the GPU, and a host entry point runs it for unit tests.
+// Everything here is __host__ __device__ (the expansion and finalize
+// kernels run it on the GPU, and a host entry point runs it for unit tests)
+// except LaneAff, the affine forms spread over a wavefront's lanes, which
+// only the device's descriptor layout uses.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
