@@ -71,10 +71,17 @@ enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC 
 /*
  * One kernel variant: family + parameters (all sizes in elements).
  *   STREAM    n[0] work-items (multiple of wg[0]), wg[0], stride = lane
- *             stride s (FILLED: k in {2,3}), gstride = group stride,
+ *             stride s, gstride = group stride,
  *             vec = elements per access (1,2,4; 16 bytes max),
  *             reps = accesses per work-item U.  Element of access u of
  *             work-item (g,l): vec*(((g*gs)*wg + l)*s + u*G*gs*wg*s).
+ *             FILLED (Sec. 4.1 stride-2/-3 "filled" access, generalised):
+ *             of every s cells (2 <= s <= 64) the first c = chains are
+ *             read (1 <= c <= min(s, 5); 0 means c = s), group j = i +
+ *             u*n of work-item i reading cells s*j .. s*j + c - 1, summed
+ *             left to right into a running sum stored at out[i]; vec = 1,
+ *             gstride = 1.  Utilization about c/s reaches every stride class
+ *             of Sec. 2.1 ('k/q' with q = min(s, 4)).
  *   LDS       n[0] groups, wg[0], stride = bank stride b, reps = R,
  *             words = W (power of two, multiple of wg, <= 16384)
  *   FMA       dtype, n[0] work-items, wg[0], reps = F, chains = K (F%K==0,

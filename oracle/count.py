@@ -92,10 +92,12 @@ def params(v: dict) -> list:
     reps = {"stream": v.get("U", 1), "lds": v.get("R", 0),
             "fma": v.get("F", 0), "rsqrt": v.get("F", 0), "arith": v.get("F", 0),
             "barrier": v.get("B", 0)}.get(fam, 0)
+    K = v.get("K", 1)
+    if fam == "stream" and v.get("op") == "filled":
+        K = v.get("c", v["s"])  # cells read of every s
     return [FAMILIES[fam], eb, op, n, v.get("m", 0), v.get("l", 0), wgx, wgy,
             v.get("T", 0), v.get("s", v.get("b", 1)), v.get("gs", 1),
-            v.get("vec", 1), reps, v.get("K", 1), v.get("W", 0),
-            v.get("groups", 0)]
+            v.get("vec", 1), reps, K, v.get("W", 0), v.get("groups", 0)]
 
 
 def count(v: dict, with_footprints: bool = False) -> dict:

@@ -101,17 +101,21 @@ static int size_index(int bytes) {
     return bytes == 4 ? 0 : bytes == 8 ? 1 : bytes == 16 ? 2 : -1;
 }
 
+/* The gap-filling difference array is allocated when the array's first
+ * access of stride >= 2 arrives (most arrays never need one): memory only,
+ * the counts do not depend on it. */
 static void new_array(sim_t *S, int a, int64_t cells) {
     S->arr[a].cells = cells;
     S->arr[a].touched = (uint8_t *)calloc((size_t)(cells > 0 ? cells : 1), 1);
-    S->arr[a].difflen = cells + 2;
-    S->arr[a].diff = (int64_t *)calloc((size_t)S->arr[a].difflen, 8);
+    S->arr[a].difflen = 0;
+    S->arr[a].diff = NULL;
     if (a + 1 > S->narr) S->narr = a + 1;
 }
 
 static void grow_diff(arr_t *A, int64_t need) {
     if (need < A->difflen) return;
-    int64_t nl = 2 * need + 16;
+    int64_t nl = A->diff ? A->difflen + A->difflen / 8 + 1024 : A->cells + 1024;
+    if (nl <= need) nl = need + 1024;
     A->diff = (int64_t *)realloc(A->diff, (size_t)nl * 8);
     memset(A->diff + A->difflen, 0, (size_t)(nl - A->difflen) * 8);
     A->difflen = nl;
@@ -179,19 +183,26 @@ static void sim_stream(sim_t *S, const oparams *p) {
     if (wg <= 0 || N % wg) { fail(S, "n must be a multiple of wg"); return; }
     int64_t G = N / wg;
     if (p->op == ST_FILLED) {
-        int64_t k = s;
-        new_array(S, 0, k * G * wg * U);
+        /* of every s cells the first c are read and summed left to right,
+         * then added to the work-item's running sum */
+        int64_t c = p->K;
+        if (s < 2 || c < 1 || c > s || c >= O_MAXSITE) {
+            fail(S, "filled needs 1 <= c <= s, s >= 2");
+            return;
+        }
+        new_array(S, 0, s * G * wg * U);
         new_array(S, 1, N);
         for (int64_t g = 0; g < G; g++)
             for (int64_t l = 0; l < wg; l++) {
                 for (int64_t u = 0; u < U; u++) {
                     int64_t j = (g * wg + l) + u * G * wg;
                     int64_t jn = (g * wg + l + 1) + u * G * wg;
-                    for (int64_t c = 0; c < k; c++)
-                        gacc(S, (int)c, 0, D_LD, e, 1, k * j + c, k * jn + c);
-                    flop(S, K_ADD, e, k); /* (x0 + x1) [+ x2] then acc += */
+                    for (int64_t q = 0; q < c; q++)
+                        gacc(S, (int)q, 0, D_LD, e, 1, s * j + q, s * jn + q);
+                    flop(S, K_ADD, e, c - 1); /* x0 + x1 + ... + x_{c-1} */
+                    flop(S, K_ADD, e, 1);     /* acc += */
                 }
-                gacc(S, (int)k, 1, D_ST, e, 1, g * wg + l, g * wg + l + 1);
+                gacc(S, O_MAXSITE - 1, 1, D_ST, e, 1, g * wg + l, g * wg + l + 1);
             }
     } else {
         int64_t span = G * gs * wg * s * U * vec;
@@ -472,10 +483,11 @@ static void sim_nbody(sim_t *S, const oparams *p) {
                 for (int64_t jj = 0; jj < Gs; jj++)
                     if (jb * Gs + jj < N) {
                         lds(S, D_LD, 4, 3);
-                        flop(S, K_ADD, 4, 6); /* 3 sub, 2 add in r^2, 1 accumulate */
+                        flop(S, K_ADD, 4, 6); /* 3 sub, 2 add in r^2, 1 into the block's partial */
                         flop(S, K_MUL, 4, 3);
                         flop(S, K_SPEC, 4, 1); /* rsqrt, self pair masked by select */
                     }
+                flop(S, K_ADD, 4, 1); /* the block's partial added to the total */
                 bar(S, l == 0);
             }
             if (i < N) gacc(S, 6, 1, D_ST, 4, 1, i, i + 1);

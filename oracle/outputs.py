@@ -81,17 +81,19 @@ def stream_axpby(v, x, y, o0):
 
 
 def stream_filled(v, x):
-    """filled (k = s): work-item i sums, for u = 0..U-1 and j = i + u*N,
-    the k consecutive cells x[k*j .. k*j+k-1] as ((x0 + x1) + x2) and adds
-    that to a running sum started at 0 (in the kernel dtype)."""
-    N, U, k = v["n"], v["U"], v["s"]
+    """filled (lane stride s, c = v["c"] cells read of every s, c = s when
+    absent): work-item i, for u = 0..U-1 and j = i + u*N, sums the cells
+    x[s*j .. s*j+c-1] left to right, ((x0 + x1) + x2) + ..., and adds that
+    to a running sum started at 0 (in the kernel dtype)."""
+    N, U, s = v["n"], v["U"], v["s"]
+    c = v.get("c", s)
     acc = np.zeros(N, dtype=x.dtype)
     i = np.arange(N, dtype=np.int64)
     for u in range(U):
         j = i + u * N
-        t = x[k * j] + x[k * j + 1]
-        for c in range(2, k):
-            t = t + x[k * j + c]
+        t = x[s * j]
+        for q in range(1, c):
+            t = t + x[s * j + q]
         acc = acc + t
     return acc
 
@@ -192,6 +194,24 @@ def conv(img, filt, n):
             win = I[:, 6 - u:6 - u + n, 6 - v:6 - v + n, :]  # (3, n, n, 3)
             r += np.einsum("ixyc,jc->ijxy", win, Fw[:, u, v, :])
             a += np.einsum("ixyc,jc->ijxy", np.abs(win), np.abs(Fw[:, u, v, :]))
+    return r, a
+
+
+def conv_at(img, filt, n, idx):
+    """The convolution of `conv` at sampled outputs only: idx is an array of
+    (image i, filter j, x, y) rows; returns (r, sum of |terms|) for them,
+    each the 147-term sum over u, v < 7 and c < 3 of
+    img[i][x+6-u][y+6-v][c] * filt[j][u][v][c] in float64."""
+    P = n + 6
+    I = img.reshape(3, P, P, 3).astype(np.float64)
+    Fw = filt.reshape(3, 7, 7, 3).astype(np.float64)
+    idx = np.asarray(idx, dtype=np.int64)
+    r = np.zeros(len(idx))
+    a = np.zeros(len(idx))
+    for t, (i, j, x, y) in enumerate(idx):
+        win = I[i, x:x + 7, y:y + 7, :][::-1, ::-1, :]  # win[u, v] = img[x+6-u, y+6-v]
+        r[t] = (win * Fw[j]).sum()
+        a[t] = (np.abs(win) * np.abs(Fw[j])).sum()
     return r, a
 
 

@@ -157,6 +157,8 @@ def variant_struct(d: dict) -> Variant:
     if fam == "stream":
         v.n[0], v.wg[0] = d["n"], d["wg"]
         v.stride, v.gstride, v.vec, v.reps = d["s"], d.get("gs", 1), d.get("vec", 1), d.get("U", 1)
+        if d.get("op") == "filled":
+            v.chains = d.get("c", 0)  # cells read of every s (0: all s)
     elif fam == "lds":
         v.n[0], v.wg[0] = d["groups"], d["wg"]
         v.stride, v.reps, v.words = d["b"], d["R"], d["W"]

@@ -391,19 +391,20 @@ PM_HD void build_stream(BB &b, const pm_variant &v) {
     b.p->n_wg = G;
     b.p->wg_size = (int32_t)wg;
     if (v.op == PM_STREAM_FILLED) {
-        int64_t k = s;
-        if (!(k == 2 || k == 3) || vec != 1 || gs != 1) {
+        // of every s cells the first c are read: c accesses at lane stride s
+        const int64_t c = v.chains ? v.chains : s;
+        if (s < 2 || s > 64 || c < 1 || c > s || c > MAXACC || vec != 1 || gs != 1) {
             b.fail(PM_EINVAL);
             return;
         }
-        b.array(0, prod3(b, k, N, U));
+        b.array(0, prod3(b, s, N, U));
         b.array(1, N);
         Stmt *S = b.stmt(1);
         if (!S) return;
         int g = b.var(S, G), l = b.var(S, wg), u = b.var(S, U);
-        for (int c = 0; c < k; c++)
-            b.acc(S, 0, D_LD, e, 1, b.av(b.av(b.av(b.mk(c), g, k * wg), l, k), u, k * G * wg));
-        S->flop[K_ADD][dt] = (int32_t)k;
+        for (int q = 0; q < c; q++)
+            b.acc(S, 0, D_LD, e, 1, b.av(b.av(b.av(b.mk(q), g, s * wg), l, s), u, s * G * wg));
+        S->flop[K_ADD][dt] = (int32_t)c;  // c - 1 in the group's sum, 1 into the running sum
         Stmt *T = b.stmt(1);
         if (!T) return;
         g = b.var(T, G);
@@ -792,9 +793,13 @@ PM_HD void build_nbody(BB &b, const pm_variant &v) {
     int jj = b.var(Sp, Gs);
     b.lt(Sp, b.av(b.av(b.mk(0), jb, Gs), jj, 1), N);
     Sp->lds[D_LD][0] = 3;
-    Sp->flop[K_ADD][0] = 6;   // 3 differences, 2 adds in r^2, 1 accumulate
+    Sp->flop[K_ADD][0] = 6;   // 3 differences, 2 adds in r^2, 1 into the block's partial
     Sp->flop[K_MUL][0] = 3;
     Sp->flop[K_SPEC][0] = 1;  // rsqrt; the self pair is masked by a select
+    Stmt *Sa = b.stmt(1);  // the block's partial sum added to the total
+    if (!Sa) return;
+    b.var(Sa, GB), b.var(Sa, Gs), b.var(Sa, GB);
+    Sa->flop[K_ADD][0] = 1;
     Stmt *So = b.stmt(1);
     if (!So) return;
     g = b.var(So, GB), l = b.var(So, Gs);

@@ -73,8 +73,9 @@ template <> __device__ inline double2 vset<double2, double>(double *a) { return 
 // ((g*gs)*wg + l)*s + u*G*gs*wg*s (units of VEC elements).  NT: every
 // access carries the streaming hint (no element is touched twice).
 template <typename T, int VEC, int OP, bool NT>
-__global__ void k_stream(T *x0, T *x1, T *x2, T *x3, T *x4, int64_t G,
-                         int64_t s, int64_t gs, int U, T sentinel) {
+__global__ void k_stream(T *__restrict__ x0, T *__restrict__ x1, T *__restrict__ x2,
+                         T *__restrict__ x3, T *__restrict__ x4, int64_t G, int64_t s,
+                         int64_t gs, int U, T sentinel) {
     using VT = typename Vec<T, VEC>::t;
     const int64_t wg = blockDim.x, g = blockIdx.x, l = threadIdx.x;
     const int64_t base = ((g * gs) * wg + l) * s;
@@ -115,16 +116,19 @@ __global__ void k_stream(T *x0, T *x1, T *x2, T *x3, T *x4, int64_t G,
     if (OP == PM_STREAM_LOAD && acc == sentinel) x1[g * wg + l] = acc;
 }
 
-// filled: k consecutive cells per access group, summed ((x0 + x1) + x2)
-template <typename T, int K>
-__global__ void k_filled(const T *x, T *out, int64_t G, int U) {
+// filled: of every s consecutive cells the first c are read (lane stride
+// s, c accesses per group of s cells) and summed left to right,
+// ((x0 + x1) + x2) + ..., into a running sum.
+template <typename T>
+__global__ void k_filled(const T *__restrict__ x, T *__restrict__ out, int64_t G, int U,
+                         int s, int c) {
     const int64_t wg = blockDim.x;
     const int64_t i = (int64_t)blockIdx.x * wg + threadIdx.x;
     T acc = 0;
     for (int u = 0; u < U; u++) {
-        int64_t j = i + (int64_t)u * G * wg;
-        T t = x[K * j] + x[K * j + 1];
-        if (K == 3) t = t + x[K * j + 2];
+        const T *p = x + (i + (int64_t)u * G * wg) * s;
+        T t = p[0];
+        for (int q = 1; q < c; q++) t = t + p[q];
         acc = acc + t;
     }
     out[i] = acc;
@@ -348,8 +352,10 @@ k_stencil(const T *u, T *out, int n, T h2) {
 }
 
 // ------------------------------------------------------------------ nbody
-// positions pos[c + 3 i]; blocks of G positions staged through LDS
-__global__ void k_nbody(const float *pos, float *out, int N) {
+// positions pos[c + 3 i]; blocks of G positions staged through LDS.  The
+// terms of one block are summed into a partial, which is then added to the
+// running total: an fp32 sum over N terms in two levels, G then N/G long.
+__global__ void k_nbody(const float *__restrict__ pos, float *__restrict__ out, int N) {
     extern __shared__ float sh[];
     const int G = blockDim.x, l = threadIdx.x;
     const int i = blockIdx.x * G + l;
@@ -370,12 +376,14 @@ __global__ void k_nbody(const float *pos, float *out, int N) {
         }
         __syncthreads();
         const int lim = N - jb * G < G ? N - jb * G : G;
+        float part = 0.f;
         for (int jj = 0; jj < lim; jj++) {
             const float dx = xi - sh[jj], dy = yi - sh[G + jj], dz = zi - sh[2 * G + jj];
             const float r2 = (dx * dx + dy * dy) + dz * dz;
             const float t = rsqrtf(r2);
-            acc += (jb * G + jj != i) ? t : 0.f;
+            part += (jb * G + jj != i) ? t : 0.f;
         }
+        acc += part;
         __syncthreads();
     }
     if (i < N) out[i] = acc;
@@ -515,13 +523,11 @@ int launch(const pm_variant &v, void *const *b, hipStream_t s) {
         if (v.op == PM_STREAM_FILLED) {
             int64_t G = v.n[0] / v.wg[0];
             dim3 gr((unsigned)G), bl(v.wg[0]);
-            if (v.dtype == PM_F64) {
-                if (v.stride == 2) hipLaunchKernelGGL((k_filled<double, 2>), gr, bl, 0, s, (const double *)b[0], (double *)b[1], G, v.reps);
-                else hipLaunchKernelGGL((k_filled<double, 3>), gr, bl, 0, s, (const double *)b[0], (double *)b[1], G, v.reps);
-            } else {
-                if (v.stride == 2) hipLaunchKernelGGL((k_filled<float, 2>), gr, bl, 0, s, (const float *)b[0], (float *)b[1], G, v.reps);
-                else hipLaunchKernelGGL((k_filled<float, 3>), gr, bl, 0, s, (const float *)b[0], (float *)b[1], G, v.reps);
-            }
+            const int c = v.chains ? v.chains : v.stride;
+            if (v.dtype == PM_F64)
+                hipLaunchKernelGGL(k_filled<double>, gr, bl, 0, s, (const double *)b[0], (double *)b[1], G, v.reps, v.stride, c);
+            else
+                hipLaunchKernelGGL(k_filled<float>, gr, bl, 0, s, (const float *)b[0], (float *)b[1], G, v.reps, v.stride, c);
         } else if (v.dtype == PM_F64) {
             if (v.vec == 1) launch_stream_t<double, 1>(v, b, s);
             else launch_stream_t<double, 2>(v, b, s);

@@ -55,7 +55,7 @@ def nbody(v):
     B = cdiv(N, G)
     wi = B * G
     return {"gld.4.3/3": 3 * N + 3 * N * B, "gst.4.1": N, "lst.4": 3 * N * B,
-            "lld.4": 3 * wi * N, "add.f32": 6 * wi * N, "mul.f32": 3 * wi * N,
+            "lld.4": 3 * wi * N, "add.f32": 6 * wi * N + wi * B, "mul.f32": 3 * wi * N,
             "spec.f32": wi * N, "bar.wi": 2 * wi * B, "bar.wg": 2 * B * B,
             "wg": B, "wi": wi}
 
@@ -66,9 +66,15 @@ def stream(v):
     n, wg, s, U, vec = v["n"], v["wg"], v["s"], v.get("U", 1), v.get("vec", 1)
     base = {"wg": n // wg, "wi": n}
     if v["op"] == "filled":
-        cl = {2: "2/2", 3: "3/3"}[s]
-        base.update({"gld.%d.%s" % (e, cl): s * n * U, "gst.%d.1" % e: n,
-                     "add." + dt: s * n * U})
+        # c of every s cells read: |F| = c*J cells for J = n*U groups; each
+        # read cell opens a run of s cells, so Fill = [0, s*(J-1) + c-1 + s)
+        c = v.get("c", s)
+        J = n * U
+        q = min(s, 4)
+        k = min(max(-(-(q * c * J) // (s * J + c - 1)), 1), q)
+        cl = "%d/%s" % (k, q if s <= 4 else ">4")
+        base.update({"gld.%d.%s" % (e, cl): c * J, "gst.%d.1" % e: n,
+                     "add." + dt: c * J})
         return base
     cl = {1: "1", 2: "1/2", 3: "1/3", 4: "1/4"}.get(s, "1/>4")
     key = "%d.%s" % (e * vec, cl)

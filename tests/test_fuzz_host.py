@@ -23,7 +23,9 @@ def _draw(rng):
         wg = int(rng.choice([64, 128, 256]))
         n = wg * r(1, 6)
         if op == "filled":
-            return dict(family=fam, op=op, dtype=dt, n=n, wg=wg, s=r(2, 3), gs=1, vec=1, U=r(1, 3))
+            s = r(2, 12)
+            return dict(family=fam, op=op, dtype=dt, n=n, wg=wg, s=s, c=r(1, min(s, 5)), gs=1,
+                        vec=1, U=r(1, 3))
         vec = int(rng.choice([1, 2] if dt == "f64" else [1, 2, 4]))
         return dict(family=fam, op=op, dtype=dt, n=n, wg=wg, s=r(1, 9), gs=r(1, 4), vec=vec,
                     U=r(1, 3))

@@ -18,7 +18,7 @@ from oracle import outputs as O
 from synth import suite_batched, suite_instructive, suite_test, suite_tiny, uniform
 
 from closed_forms import counts as closed_counts
-from test_lib_host import FAMILY_CASES
+from test_lib_host import FAMILY_CASES, FILLED_SC
 
 pytestmark = pytest.mark.gpu
 
@@ -180,6 +180,8 @@ OUT_CASES = (
      for (s, gs, vec, U) in ((1, 1, 1, 1), (3, 2, 2, 2), (8, 1, 1, 3))]
     + [dict(family="stream", op="filled", dtype=dt, n=4096, wg=128, s=k, gs=1, vec=1, U=2)
        for dt in ("f32", "f64") for k in (2, 3)]
+    + [dict(family="stream", op="filled", dtype=dt, n=2048, wg=64, s=s, c=c, gs=1, vec=1, U=3)
+       for dt in ("f32", "f64") for (s, c) in FILLED_SC]
     + [dict(family="lds", op=op, groups=8, wg=wg, b=b, R=R, W=W)
        for op in ("read", "write") for (wg, b, R, W) in ((256, 1, 256, 4096), (64, 5, 33, 1024),
                                                         (1024, 32, 17, 16384))]
@@ -262,14 +264,10 @@ def check_output(v, outs, host):
         n = v["n"]
         np.testing.assert_array_equal(outs[1].reshape(n, n), O.stencil(host[0], n, dt))
     elif fam == "nbody":
-        N = v["n"]
-        ref, _ = O.nbody(host[0])
-        # per term: a few roundings in dx, r^2 and rsqrt (<= 8u relative);
-        # the fp32 running sum adds rounding errors modelled as independent:
-        # 4 sqrt(N) u of the sum of the (positive) terms
-        tol = (8 + 4 * math.sqrt(N)) * U32 * np.abs(ref) + 1e-30
+        ref, scale = O.nbody(host[0])
+        # the bar of the test kernel: 1e-5 of sum_j |1/r_ij| per body
         err = np.abs(outs[1].astype(np.float64) - ref)
-        assert (err <= tol).all(), float((err / tol).max())
+        assert (err <= 1e-5 * scale).all(), float((err / np.maximum(scale, 1e-300)).max())
 
 
 @pytest.mark.parametrize("v", OUT_CASES, ids=lambda v: "-".join(str(x) for x in v.values()))
@@ -279,27 +277,35 @@ def test_outputs_match_oracle(ctx, v):
 
 
 def test_outputs_full_size_sampled(ctx):
-    """Test-suite sizes: every transpose and stencil element compared, and
-    sampled matmul entries and n-body rows computed by the oracle one by one."""
+    """Every test-suite variant at its full size: every transpose and
+    stencil element compared; sampled matmul entries (square and skinny),
+    convolution outputs and n-body rows computed by the oracle one by one."""
     import torch
     rng = np.random.default_rng(0)
     for v in suite_test():
         fam, n = v["family"], v["n"]
-        if n < 4096 and fam != "nbody":
-            continue
         print("full-size output check", v, flush=True)
         ts, host = P.device_buffers(v, v["seed"])
         ctx.launch(v, ts)
         torch.cuda.synchronize()
         if fam == "matmul":
-            out = ts[2].cpu().numpy().reshape(n, n)
-            A, B = host[0].reshape(n, n), host[1].reshape(n, n)
-            rows = rng.integers(0, n, 16)
-            cols = rng.integers(0, n, 64)
+            m, l = v["m"], v["l"]
+            out = ts[2].cpu().numpy().reshape(n, l)
+            A, B = host[0].reshape(n, m), host[1].reshape(m, l)
+            rows = np.concatenate([[0, n - 1], rng.integers(0, n, 14)])
+            cols = np.concatenate([[0, l - 1], rng.integers(0, l, 62)])
             ref = A[rows].astype(np.float64) @ B[:, cols].astype(np.float64)
             scale = np.abs(A[rows]).astype(np.float64) @ np.abs(B[:, cols]).astype(np.float64)
             err = np.abs(out[np.ix_(rows, cols)] - ref)
             assert (err <= 1e-5 * scale).all(), v
+        elif fam == "conv":
+            out = ts[2].cpu().numpy().reshape(3, 3, n, n)
+            idx = np.stack([rng.integers(0, 3, 256), rng.integers(0, 3, 256),
+                            rng.integers(0, n, 256), rng.integers(0, n, 256)], axis=1)
+            idx[:4, 2:] = [[0, 0], [n - 1, n - 1], [0, n - 1], [n - 1, 0]]
+            ref, scale = O.conv_at(host[0], host[1], n, idx)
+            got = out[idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3]].astype(np.float64)
+            assert (np.abs(got - ref) <= 1e-5 * scale).all(), v
         elif fam == "transpose":
             np.testing.assert_array_equal(ts[1].cpu().numpy().reshape(n, n),
                                           host[0].reshape(n, n).T)
@@ -307,13 +313,23 @@ def test_outputs_full_size_sampled(ctx):
             np.testing.assert_array_equal(ts[1].cpu().numpy().reshape(n, n),
                                           O.stencil(host[0], n, v["dtype"]))
         elif fam == "nbody":
-            rows = rng.integers(0, n, 32)
-            ref, _ = O.nbody(host[0], rows)
+            rows = np.concatenate([[0, n - 1], rng.integers(0, n, 30)])
+            ref, scale = O.nbody(host[0], rows)
             got = ts[1].cpu().numpy()[rows].astype(np.float64)
-            tol = (8 + 4 * math.sqrt(n)) * U32 * np.abs(ref)
-            assert (np.abs(got - ref) <= tol).all(), v
+            assert (np.abs(got - ref) <= 1e-5 * scale).all(), v
         del ts
         torch.cuda.empty_cache()
+
+
+def test_every_stride_class_counted_on_the_gpu(ctx):
+    """The family cases counted on the GPU in one batch reach all 15 stride
+    classes of Sec. 2.1, each count equal to the oracle's."""
+    got = ctx.count(FAMILY_CASES)
+    seen = set()
+    for v, g in zip(FAMILY_CASES, got):
+        assert g == _strip(C.count(v)), v
+        seen |= {k.split(".", 2)[2] for k in g if k.startswith(("gld.", "gst."))}
+    assert len(seen) == 15, sorted(seen)
 
 
 # --------------------------------------------------------------- measure --

@@ -60,6 +60,11 @@ def _same(v):
             assert orc[k] == x, (v, k)
 
 
+# (s, c) pairs of the generalised filled access that between them reach the
+# stride classes 1/2, 1/3, 2/3, 1/4..4/4 and 1/>4..4/>4
+FILLED_SC = ((2, 1), (3, 1), (3, 2), (4, 1), (4, 2), (4, 3), (4, 4), (5, 2), (5, 3),
+             (5, 4), (8, 1), (8, 4), (8, 5), (16, 5))
+
 FAMILY_CASES = [
     dict(family="stream", op=op, dtype=dt, n=512, wg=64, s=s, gs=gs, vec=vec, U=U)
     for op in ("load", "store", "copy", "add4")
@@ -69,6 +74,10 @@ FAMILY_CASES = [
 ] + [
     dict(family="stream", op="filled", dtype=dt, n=1024, wg=128, s=k, gs=1, vec=1, U=U)
     for dt in ("f32", "f64") for k in (2, 3) for U in (1, 3)
+] + [
+    # c of every s cells read: the classes k/q below q
+    dict(family="stream", op="filled", dtype=dt, n=512, wg=64, s=s, c=c, gs=1, vec=1, U=U)
+    for dt in ("f32", "f64") for (s, c) in FILLED_SC for U in (1, 2)
 ] + [
     dict(family="lds", op=op, groups=3, wg=wg, b=b, R=R, W=1024)
     for op in ("read", "write") for wg in (64, 256) for b in (1, 3, 32) for R in (0, 5)
@@ -127,6 +136,20 @@ def test_per_statement_expansion_on_batched_workload():
         assert P.count_host(v, True) == P.count_host(v, True, sequential=True)
 
 
+def _classes(counts):
+    return {k.split(".", 2)[2] for k in counts if k.startswith(("gld.", "gst."))}
+
+
+def test_family_cases_reach_every_stride_class():
+    """Between them the family cases give every one of the 15 classes of
+    Sec. 2.1 (counted by the library on the host, checked against the
+    oracle in test_host_counts_match_oracle)."""
+    seen = set()
+    for v in FAMILY_CASES:
+        seen |= _classes(P.count_host(v))
+    assert seen == set(M.CLASSES), set(M.CLASSES) - seen
+
+
 def test_host_counts_on_batched_workload_sample():
     """Small-domain draws of the batched sweep (same generator, smaller
     domains so the oracle finishes quickly): uneven extents that are not
@@ -144,7 +167,9 @@ def test_suites_are_valid_descriptors():
     dict(family="stream", op="load", dtype="f32", n=1000, wg=256, s=1, gs=1, vec=1, U=1),
     dict(family="stream", op="load", dtype="f64", n=1024, wg=256, s=1, gs=1, vec=4, U=1),
     dict(family="stream", op="load", dtype="f32", n=1024, wg=256, s=0, gs=1, vec=1, U=1),
-    dict(family="stream", op="filled", dtype="f32", n=1024, wg=256, s=4, gs=1, vec=1, U=1),
+    dict(family="stream", op="filled", dtype="f32", n=1024, wg=256, s=8, gs=1, vec=1, U=1),
+    dict(family="stream", op="filled", dtype="f32", n=1024, wg=256, s=4, c=5, gs=1, vec=1, U=1),
+    dict(family="stream", op="filled", dtype="f32", n=1024, wg=256, s=1, c=1, gs=1, vec=1, U=1),
     dict(family="lds", op="read", groups=1, wg=256, b=1, R=1, W=1000),
     dict(family="fma", dtype="f32", n=1024, wg=256, F=10, K=4),
     dict(family="fma", dtype="f32", n=1024, wg=2048, F=16, K=4),

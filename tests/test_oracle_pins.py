@@ -67,6 +67,26 @@ def test_filled_closed_forms(k, cls):
                    "add.f32": k * n * U, "wg": 4, "wi": n}
 
 
+# c of every s cells read: the utilization c/s (just under it: the last run
+# reaches s - 1 cells past the array's used part) picks the class k/q of
+# Sec. 2.1 with q = min(s, 4) quarters for s > 4 -- listed by hand here.
+@pytest.mark.parametrize("s,c,cls", [
+    (2, 1, "1/2"), (3, 1, "1/3"), (3, 2, "2/3"), (4, 1, "1/4"), (4, 2, "2/4"),
+    (4, 3, "3/4"), (4, 4, "4/4"), (8, 1, "1/>4"), (8, 4, "2/>4"), (5, 2, "2/>4"),
+    (8, 5, "3/>4"), (5, 3, "3/>4"), (5, 4, "4/>4"), (5, 5, "4/>4")])
+def test_filled_c_of_s_classes(s, c, cls):
+    n, U = 512, 3
+    got = C.count(dict(family="stream", op="filled", dtype="f64", n=n, wg=128,
+                       s=s, c=c, gs=1, vec=1, U=U), with_footprints=True)
+    J = n * U
+    assert got == {"gld.8.%s" % cls: c * J, "gst.8.1": n, "add.f64": c * J,
+                   "wg": 4, "wi": n,
+                   # |F|: c cells per group; Fill: up to the last read
+                   # cell's run end, s*(J-1) + (c-1) + s
+                   "foot.F.0": c * J, "foot.fill.0": s * J + c - 1,
+                   "foot.F.1": n, "foot.fill.1": n}
+
+
 @pytest.mark.parametrize("op", ["read", "write"])
 def test_lds_closed_forms(op):
     G, wg, R, W = 3, 128, 17, 512
@@ -157,9 +177,11 @@ def test_nbody_closed_forms(N, G):
     B = cdiv(N, G)
     wi = B * G
     got = C.count(dict(family="nbody", n=N, wg=G))
+    # per pair 3 differences, 2 adds in r^2 and 1 add into the block's
+    # partial; per (work-item, block) 1 add of the partial into the total
     assert got == {"gld.4.3/3": 3 * N + 3 * N * B, "gst.4.1": N,
                    "lst.4": 3 * N * B, "lld.4": 3 * wi * N,
-                   "add.f32": 6 * wi * N, "mul.f32": 3 * wi * N,
+                   "add.f32": 6 * wi * N + wi * B, "mul.f32": 3 * wi * N,
                    "spec.f32": wi * N, "bar.wi": 2 * wi * B,
                    "bar.wg": 2 * B * B, "wg": B, "wi": wi}
 
@@ -212,6 +234,22 @@ def test_conv_reference_single_tap():
     I = img.reshape(3, n + 6, n + 6, 3).astype(np.float64)
     np.testing.assert_array_equal(r[:, 1], 2.0 * I[:, 4:4 + n, 2:2 + n, 1])
     assert not r[:, 0].any() and not r[:, 2].any()
+
+
+def test_conv_sampled_reference_single_tap():
+    """The sampled convolution reference on one non-zero filter tap (filter
+    j = 2, u = 5, v = 1, channel 0, weight -0.5): each output is that tap
+    times img[i][x+1][y+5][0], and the other filters give 0."""
+    n = 9
+    img = np.random.default_rng(10).uniform(-1, 1, 9 * (n + 6) ** 2).astype(np.float32)
+    filt = np.zeros(3 * 147, dtype=np.float32)
+    filt[2 * 147 + (5 * 7 + 1) * 3 + 0] = -0.5
+    I = img.reshape(3, n + 6, n + 6, 3).astype(np.float64)
+    idx = [(i, j, x, y) for i in range(3) for j in (0, 2) for (x, y) in ((0, 0), (8, 3), (4, 8))]
+    r, a = O.conv_at(img, filt, n, idx)
+    for t, (i, j, x, y) in enumerate(idx):
+        want = -0.5 * I[i, x + 1, y + 5, 0] if j == 2 else 0.0
+        assert r[t] == want and a[t] == abs(want)
 
 
 def test_counts_additive_over_a_domain_split():
@@ -342,6 +380,24 @@ def test_features_of_a_known_count_dict():
     assert f["const"] == 1 and f["gst.4.4/>4"] == 2
 
 
+@pytest.mark.parametrize("wi,div", [(1000, 1000), (1 << 20, 256 * 2048)])
+def test_features_ext_of_a_known_count_dict(wi, div):
+    """The three extension features on a hand-written count dict, once with
+    a grid smaller than the GPU holds at once (256 CUs x 2048 work-items)
+    and once larger: arithmetic instructions (an FMA once) and global bytes
+    per resident work-item, and min(arithmetic instructions, global bytes)."""
+    c = {"fma.f32": 100, "add.f32": 20, "mul.f64": 5, "spec.f32": 3,
+         "div.f64": 2, "exp.f32": 1, "gld.4.1": 10, "gst.8.1/2": 3,
+         "lld.4": 50, "bar.wi": 7, "wg": 4, "wi": wi}
+    ops, gb = 131, 4 * 10 + 8 * 3
+    f = M.features_ext(c)
+    assert len(f) == 157 and f[:154] == M.features_full(c)
+    assert f[154] == ops / div and f[155] == gb / div and f[156] == min(ops, gb)
+    # arithmetic dominates the byte count the other way round
+    c2 = dict(c, **{"gld.4.1": 1000})
+    assert M.features_ext(c2)[156] == ops
+
+
 # -------------------------------------------------------------- outputs ---
 def _round_f32(q: Fraction) -> np.float32:
     """Correctly rounded (to nearest, ties to even) float32 of a rational."""
@@ -388,6 +444,41 @@ def test_nbody_known_geometry():
     out, _ = O.nbody(pos)
     np.testing.assert_allclose(out, [1 / 5 + 1 / 12, 1 / 5 + 1 / math.sqrt(9 + 16 + 144),
                                      1 / 12 + 1 / math.sqrt(9 + 16 + 144)])
+
+
+def test_rsqrt_chain_from_zero():
+    """a = 0: chain k runs y <- 1/sqrt(y^2 + (k+1)) from 0, so chain 0 gives
+    1, 1/sqrt 2, sqrt(2/3) and chain 1 gives 1/sqrt 2, sqrt(2/5); the chains
+    are summed."""
+    x = np.zeros(4)
+    np.testing.assert_allclose(O.rsqrt_chain({"F": 1, "K": 1}, x), 1.0, rtol=1e-15)
+    np.testing.assert_allclose(O.rsqrt_chain({"F": 2, "K": 1}, x), 1 / math.sqrt(2), rtol=1e-15)
+    np.testing.assert_allclose(O.rsqrt_chain({"F": 3, "K": 1}, x), math.sqrt(2 / 3), rtol=1e-15)
+    np.testing.assert_allclose(O.rsqrt_chain({"F": 4, "K": 2}, x),
+                               1 / math.sqrt(2) + math.sqrt(2 / 5), rtol=1e-15)
+    # from a = 1 one step gives 1/sqrt(1 + 1)
+    np.testing.assert_allclose(O.rsqrt_chain({"F": 1, "K": 1}, np.ones(2)),
+                               1 / math.sqrt(2), rtol=1e-15)
+
+
+def test_exp_chain_from_zero():
+    """a = 0: y <- exp(-y^2) gives 1, exp(-1), exp(-exp(-2)); with two
+    chains (no dependence on k) the sum is twice one chain."""
+    x = np.zeros(3)
+    np.testing.assert_allclose(O.exp_chain({"F": 1, "K": 1}, x), 1.0, rtol=1e-15)
+    np.testing.assert_allclose(O.exp_chain({"F": 2, "K": 1}, x), math.exp(-1), rtol=1e-15)
+    np.testing.assert_allclose(O.exp_chain({"F": 3, "K": 1}, x), math.exp(-math.exp(-2)),
+                               rtol=1e-15)
+    np.testing.assert_allclose(O.exp_chain({"F": 6, "K": 2}, x), 2 * math.exp(-math.exp(-2)),
+                               rtol=1e-15)
+
+
+def test_filled_reference_small():
+    """s = 4, c = 3, U = 2, 2 work-items: work-item i adds x[4j]+x[4j+1]+x[4j+2]
+    for j = i and j = i + 2 (integers: exact)."""
+    x = np.arange(16, dtype=np.float32)
+    out = O.stream_filled(dict(n=2, U=2, s=4, c=3), x)
+    np.testing.assert_array_equal(out, [(0 + 1 + 2) + (8 + 9 + 10), (4 + 5 + 6) + (12 + 13 + 14)])
 
 
 def test_matmul_reference_exact_small():
