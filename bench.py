@@ -130,18 +130,47 @@ def counter_roofline(phase, ms, nv):
 
 
 def measure_suite(ctx, P, variants, warmup=4, reps=26):
+    """Minimum of `reps` timed runs after `warmup` (Sec. 4.2) per variant;
+    also which ones fall below twice the context's launch floor."""
     import torch
-    T = []
+    T, low = [], []
     for i, v in enumerate(variants):
         ts, _ = P.device_buffers(v, v.get("seed", i), fast=True)
-        t, _ = ctx.measure(v, ts, warmup=warmup, reps=reps)
-        T.append(t)
+        r = ctx.measure_until(v, ts, warmup=warmup, reps=reps)
+        assert r["status"] == 0
+        T.append(r["t_min"])
+        low.append(r["below_floor"])
         del ts
         if i % 25 == 0:
-            log("  measured %d/%d (%s: %.3g ms)" % (i + 1, len(variants), v["family"], t * 1e3))
+            log("  measured %d/%d (%s: %.3g ms)" % (i + 1, len(variants), v["family"],
+                                                    r["t_min"] * 1e3))
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    return np.array(T)
+    return np.array(T), np.array(low, dtype=bool)
+
+
+def geomean(e):
+    return float(math.exp(np.mean(np.log(np.maximum(np.asarray(e, dtype=np.float64), 1e-12)))))
+
+
+def c1_phase(ctx, P):
+    """The plain method on the tiny suite (4 fp32 stream loads at lane
+    stride 1/2/4/8, 2 fp32 FMA loops): 4 untimed and 10 timed runs each,
+    counts on the GPU, the 3-feature fit [global bytes, fp32 FMAs,
+    work-groups] in FP64 (pm_fit), predictions through pm_predict; the
+    geometric mean of the relative errors of the six."""
+    from synth import suite_tiny
+    vs = suite_tiny()
+    T, low = measure_suite(ctx, P, vs, warmup=4, reps=10)
+    cnt = ctx.count_raw(vs)
+    m, cond, resid, rank = P.fit(cnt, T, "p3")
+    pred = ctx.predict(m, vs)
+    err = np.abs(pred - T) / T
+    return {"geomean": float("%.3g" % geomean(err)), "rank": rank, "cond": float("%.3g" % cond),
+            "alpha": [float("%.4g" % a) for a in P.model_alpha(m)],
+            "ms_measured": [round(t * 1e3, 5) for t in T],
+            "ms_predicted": [round(float(t) * 1e3, 5) for t in pred],
+            "below_launch_floor": int(low.sum())}
 
 
 def model_phase(ctx, P, proj_list=("p12", "full", "ext")):
@@ -151,18 +180,17 @@ def model_phase(ctx, P, proj_list=("p12", "full", "ext")):
     meas = suite_instructive(extended=True)
     test = suite_test()
     log("model: measuring %d instructive variants" % len(meas))
-    Tm = measure_suite(ctx, P, meas)
+    Tm, low_m = measure_suite(ctx, P, meas)
     cm = ctx.count_raw(meas)
     log("model: measuring %d test variants" % len(test))
-    Tt = measure_suite(ctx, P, test)
-    ct = ctx.count_raw(test)
+    Tt, low_t = measure_suite(ctx, P, test)
     out = {}
     models = {}
     for proj in proj_list:
         rows = [i for i, v in enumerate(meas) if proj == "ext" or not v.get("extension")]
         sub = (P.Counts * len(rows))(*[cm[i] for i in rows])
         m, cond, resid, rank = P.fit(sub, Tm[rows], proj)
-        pred = np.array([P.features(ct[i], proj) @ P.model_alpha(m) for i in range(len(test))])
+        pred = ctx.predict(m, test)  # counted and predicted on the GPU
         err = np.abs(pred - Tt) / Tt
         fam = {}
         for f in ("finite_difference", "skinny_mm", "nbody", "convolution",
@@ -195,7 +223,53 @@ def model_phase(ctx, P, proj_list=("p12", "full", "ext")):
                          np.maximum(paper4, 1e-12))))), 4), "rank": rank,
                      "cond": float("%.3g" % cond), "fit_geomean": round(fit_err, 4)}
         models[proj] = m
+    out["below_launch_floor"] = {
+        "instructive": int(low_m.sum()), "test": int(low_t.sum()),
+        "instructive_families": sorted({v["family"] for v, f in zip(meas, low_m) if f}),
+        "test_kernels": sorted({v["kernel"] for v, f in zip(test, low_t) if f})}
     return out, models, (meas, Tm, test, Tt)
+
+
+def c4_phase(ctx, P, vs, pred, per_family=8):
+    """Model ranking of the batched sweep: every variant's FP64 prediction
+    comes from the counted pass; per family the `per_family` variants with
+    the highest predicted rate (domain points per predicted second, the
+    autotuning objective) are measured (4 untimed + 26 timed runs, minimum).
+    Reported per family: the rank correlation of predicted and measured rate
+    among them, whether the predicted-best is the measured-best, and the
+    geometric-mean relative error of their predictions."""
+    import torch
+    out, errs = {}, []
+    for fam in ("matmul", "stencil", "transpose"):
+        idx = [i for i, v in enumerate(vs) if v["family"] == fam]
+        rate = {i: domain_points(vs[i]) / pred[i] for i in idx}
+        top = sorted(idx, key=lambda i: -rate[i])[:per_family]
+        T = []
+        for i in top:
+            ts, _ = P.device_buffers(vs[i], vs[i].get("seed", i), fast=True)
+            r = ctx.measure_until(vs[i], ts, warmup=4, reps=26)
+            assert r["status"] == 0
+            T.append(r["t_min"])
+            del ts
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        T = np.array(T)
+        pr = np.array([rate[i] for i in top])
+        mr = np.array([domain_points(vs[i]) for i in top]) / T
+        rp, rm = np.argsort(np.argsort(-pr)), np.argsort(np.argsort(-mr))
+        e = np.abs(np.array([pred[i] for i in top]) - T) / T
+        errs += list(e)
+        out[fam] = {"spearman": round(float(np.corrcoef(rp, rm)[0, 1]), 4),
+                    "predicted_best_is_measured_best": bool(rm[0] == 0),
+                    "geomean_rel_err": round(geomean(e), 4),
+                    "measured": [[vs[i].get("op"), vs[i].get("T"), int(domain_points(vs[i])),
+                                  round(float(pred[i]) * 1e3, 4), round(float(t) * 1e3, 4)]
+                                 for i, t in zip(top, T)]}
+    out["geomean_rel_err"] = round(geomean(errs), 4)
+    out["mean_spearman"] = round(float(np.mean([out[f]["spearman"] for f in
+                                                ("matmul", "stencil", "transpose")])), 4)
+    out["note"] = "measured rows: op, tile, domain points, predicted ms, measured ms"
+    return out
 
 
 def suite_roofline(ctx, P):
@@ -205,7 +279,7 @@ def suite_roofline(ctx, P):
     res = {"stream": [], "fma": []}
     for op, mult in (("load", 1), ("copy", 2)):
         for dt, esz in (("f32", 4), ("f64", 8)):
-            for vec, U in ((1, 1), (1, 4), (4 if dt == "f32" else 2, 1),
+            for vec, U in ((1, 1), (1, 4), (1, 8), (1, 16), (4 if dt == "f32" else 2, 1),
                            (4 if dt == "f32" else 2, 4)):
                 for nt in (False, True):
                     elems = (1 << 28) if dt == "f32" else (1 << 27)
@@ -224,6 +298,11 @@ def suite_roofline(ctx, P):
         best = max((r for r in res["stream"] if r["op"] == op), key=lambda r: r["frac_8TBs"])
         res["best_" + op] = {k: best[k] for k in ("dtype", "vec", "U", "streaming_hint",
                                                    "GB/s", "frac_8TBs")}
+        # the 32-bit access class alone (fp32, one element per access)
+        b4 = max((r for r in res["stream"] if r["op"] == op and r["dtype"] == "f32"
+                  and r["vec"] == 1), key=lambda r: r["frac_8TBs"])
+        res["best_%s_4B" % op] = {k: b4[k] for k in ("U", "streaming_hint", "GB/s",
+                                                     "frac_8TBs")}
     for dt, peak_pub in (("f32", 157.3e12), ("f64", 78.6e12)):
         v = dict(family="fma", dtype=dt, n=1 << 24, wg=256, F=1024, K=16)
         ts, _ = P.device_buffers(v, 12, fast=True)
@@ -251,25 +330,36 @@ def host_cpu():
     return model, os.cpu_count() or 1
 
 
-def cpu_baseline(workload, gpu_counts, budget_s=15.0, par_budget_s=8.0, max_threads=16):
+def cpu_baseline(workload, gpu_counts, names, budget_s=15.0, par_budget_s=8.0,
+                 max_threads=16):
     """Simulated-execution oracle on a bounded random sample of the workload:
     variants in random order until ~budget_s of oracle time; its event rate
     (events = sum of a variant's count vector) extrapolates the whole
     workload.  Then the same oracle on every core the host offers (threads
     calling the C oracle, which runs without the interpreter lock; at most
-    max_threads) for ~par_budget_s of wall time, reported beside it."""
+    max_threads) for ~par_budget_s of wall time, reported beside it.  Every
+    oracle result is compared with the GPU's count vector of the same
+    variant; a mismatch fails the run."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import count as OC
     rng = np.random.default_rng(42)
     order = rng.permutation(len(workload))
     ev_all = gpu_counts.sum(axis=1).astype(np.float64)
     t_used, ev_used, done = 0.0, 0.0, 0
+
+    def check(i, got):
+        want = {names[k]: int(x) for k, x in enumerate(gpu_counts[i]) if x}
+        if got != want:
+            raise AssertionError("oracle and GPU counts differ for variant %d: %s" %
+                                 (i, workload[i]))
+
     for i in order:
         if ev_all[i] > 3e8:  # one oracle call must stay a few seconds
             continue
         t0 = time.perf_counter()
-        OC.count(workload[i])
+        got = OC.count(workload[i])
         t_used += time.perf_counter() - t0
+        check(i, got)
         ev_used += ev_all[i]
         done += 1
         if t_used > budget_s:
@@ -281,8 +371,10 @@ def cpu_baseline(workload, gpu_counts, budget_s=15.0, par_budget_s=8.0, max_thre
            "cores": 1, "kind": "oracle",
            "sample": "%d of %d workload variants (random order, those under "
                      "3e8 events), %.1f s, %.3g events/s; value = 4096 / "
-                     "(all variants' events / that rate); host: %s, %d logical CPUs"
-                     % (done, len(workload), t_used, rate, model, ncpu)}
+                     "(all variants' events / that rate); every sampled count "
+                     "vector equal to the GPU's; host: %s, %d logical CPUs"
+                     % (done, len(workload), t_used, rate, model, ncpu),
+           "sample_variants_per_s": round(done / t_used, 3), "checked_vs_gpu": done}
     # all cores: the next variants of the same order, one per thread
     nthr = max(1, min(ncpu, max_threads))
     rest = [i for i in order if ev_all[i] <= 3e8][done:]
@@ -297,7 +389,7 @@ def cpu_baseline(workload, gpu_counts, budget_s=15.0, par_budget_s=8.0, max_thre
                 pending.append((i, ex.submit(OC.count, workload[i])))
         while pending:
             i, fu = pending.pop(0)
-            fu.result()
+            check(i, fu.result())
             ev_par += ev_all[i]
             n_par += 1
             if time.perf_counter() - t0 < par_budget_s:
@@ -311,7 +403,7 @@ def cpu_baseline(workload, gpu_counts, budget_s=15.0, par_budget_s=8.0, max_thre
             "value": round(len(workload) / (ev_all.sum() / prate), 4), "unit": "variants/s",
             "cores": nthr,
             "sample": "%d further variants on %d threads, %.1f s wall, %.3g events/s"
-                      % (n_par, nthr, wall, prate)}
+                      % (n_par, nthr, wall, prate), "checked_vs_gpu": n_par}
     return res
 
 
@@ -352,9 +444,16 @@ def main():
         print(json.dumps(suite_roofline(ctx, P)), flush=True)
         return
 
+    # launch overhead first (Sec. 4.2): the empty kernel's minimum time;
+    # measurements below twice it are flagged
+    floor = ctx.launch_floor()
+    log("launch floor: %.2f us" % (floor * 1e6))
+
     # ------------------------------------------------------------- model --
-    model_info, models = None, {}
+    model_info, models, c1 = None, {}, None
     if not args.skip_model:
+        c1 = c1_phase(ctx, P)
+        log("tiny plain-method suite:", json.dumps(c1))
         model_info, models, _ = model_phase(ctx, P)
         log("model:", json.dumps(model_info))
     # prediction: the paper's property list with its named extensions
@@ -424,6 +523,12 @@ def main():
         torch.cuda.synchronize()
         del cts
 
+    c4 = None
+    if models:
+        log("model ranking of the sweep: measuring the top-8 per family")
+        c4 = c4_phase(ctx, P, vs, d_t.cpu().numpy())
+        log("sweep ranking:", json.dumps(c4))
+
     # -------------------------------------------------------- plain path --
     ns = min(args.plain_sample, nv)
     rng = np.random.default_rng(1)
@@ -487,6 +592,10 @@ def main():
         srv = serve.Server(ctx, m)
         _, st_b = srv.run(trace)
         _, st_p = serve.run_plain(ctx, m, trace)
+        # a rate at which requests overlap and batches form
+        fast = serving_trace(rate=20000.0, duration=min(args.serve_seconds, 2.0), seed=11)
+        _, f_b = srv.run(fast)
+        _, f_p = serve.run_plain(ctx, m, fast)
         # capacity: the same requests all queued at once
         _, cap_b = srv.run(trace, realtime=False)
         _, cap_p = serve.run_plain(ctx, m, trace, realtime=False)
@@ -494,6 +603,7 @@ def main():
                          for k, x in d.items()}
         serving = {"requests": len(trace), "rate_per_s": 2000.0,
                    "batched": rnd(st_b), "plain": rnd(st_p),
+                   "requests_20k": len(fast), "batched_20k": rnd(f_b), "plain_20k": rnd(f_p),
                    "saturated_batched": rnd(cap_b), "saturated_plain": rnd(cap_p)}
         log("serving:", json.dumps(serving))
 
@@ -510,9 +620,32 @@ def main():
     # ----------------------------------------------------------- CPU leg --
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(vs, counts, args.cpu_seconds)
+        cpu = cpu_baseline(vs, counts, P.count_names(), args.cpu_seconds)
         log("cpu oracle:", cpu)
 
+    detail = {"model": model_info, "tiny_suite": c1, "sweep_ranking": c4,
+              "autotune": tune, "serving": serving, "suite_roofline": suite_roof,
+              "counter_schedule": {
+                  "chosen": sched, "default": default_sched,
+                  "tried_ms": [[c["inblock_items"], c["tail_wgs_per_cu"], round(t, 4)]
+                               for c, t in sched_table]},
+              "batch_stats": stats, "kernel_ms": phase_ms, "roofline": roof,
+              "cpu_baseline": cpu}
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", "bench_detail.json"), "w") as fh:
+        json.dump(detail, fh, indent=1, default=float)
+    gm = None
+    if model_info:
+        gm = {p: model_info[p]["geomean"] for p in ("ext", "full", "p12")}
+        gm["ext_paper_test_kernels"] = model_info["ext"]["geomean_paper_test_kernels"]
+        gm["tiny_p3"] = c1["geomean"] if c1 else None
+        gm["sweep_top8"] = c4["geomean_rel_err"] if c4 else None
+    srv = None
+    if serving:
+        srv = {k: {x: serving[k][x] for x in ("p50_ms", "p99_ms", "mean_batch",
+                                               "variants_per_s") if x in serving[k]}
+               for k in ("batched", "plain", "batched_20k", "plain_20k",
+                         "saturated_batched", "saturated_plain")}
     line = {
         "metric": "geomean rel. prediction error; variants counted+predicted/sec, batched vs plain",
         "value": round(value, 1), "unit": "variants/s", "n_gpus": 1,
@@ -522,24 +655,24 @@ def main():
         "config": {"workload": "batched autotune sweep: 4096 matmul/stencil/transpose "
                                "variants, main domains 2^16..2^30 points, counted + "
                                "predicted in one pass", "variants": nv,
-                   "domain_points": points,
                    "model": "ext (the paper's property list and its named extensions)"},
-        "points_per_s": float("%.4g" % (points * value / nv)),
-        "plain_variants_per_s": round(plain, 1), "plain_us_per_call": round(t_call * 1e6, 2),
-        "host_memory_batched_variants_per_s": round(host_batched, 1),
+        "geomean_rel_err": gm,
         "batched_over_plain": round(value / plain, 2),
-        "geomean_rel_err": model_info,
+        "plain_variants_per_s": round(plain, 1), "plain_us_per_call": round(t_call * 1e6, 2),
+        "points_per_s": float("%.4g" % (points * value / nv)),
+        "host_memory_batched_variants_per_s": round(host_batched, 1),
+        "launch_floor_us": round(floor * 1e6, 2),
         "kernel_ms": {k: round(x, 4) for k, x in phase_ms.items()},
-        "expansion_kernel_ms_timed": round(build_ms, 4),
-        "counter_schedule": {
-            "chosen": sched, "default": default_sched,
-            "tried_ms": [[c["inblock_items"], c["tail_wgs_per_cu"], round(t, 4)]
-                         for c, t in sched_table],
-            "note": "tried_ms rows: in-block item limit, chip-wide work-groups per CU, "
-                    "best pass time (HIP events, min of 10)"},
-        "batch_stats": stats,
-        "autotune": tune, "serving": serving, "suite_roofline": suite_roof,
+        "sweep_ranking": {k: c4[k] for k in ("mean_spearman", "geomean_rel_err")} if c4 else None,
+        "autotune": {k: round(tune[k], 4) for k in ("choice_is_best", "geomean_slowdown",
+                                                    "mean_spearman")} if tune else None,
+        "serving": srv,
+        "hbm": {k: suite_roof[k]["frac_8TBs"] for k in
+                ("best_load", "best_copy", "best_load_4B", "best_copy_4B")} if suite_roof else None,
+        "fma_frac_peak": {r["dtype"]: r["frac_published_peak"] for r in suite_roof["fma"]}
+        if suite_roof else None,
         "roofline": roof, "cpu_baseline": cpu,
+        "detail": "gpurun_out/bench_detail.json",
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -200,13 +200,19 @@ pm_status pm_predict(pm_ctx *ctx, const pm_model *m, const pm_variant *v,
                      size_t nv, double *t_sec);
 
 /*
- * Device-resident batched path: d_v[nv] (device) -> d_counts[nv] (device,
- * may be NULL), d_t[nv] (device, FP64 predictions with model m; ignored if
- * m or d_t is NULL), d_status[nv] (device int32: 0 or a pm_status per
- * variant).  Enqueued on `hip_stream` (a hipStream_t, used as given: NULL
- * is HIP's null stream); returns without waiting.  Variants whose footprint bitmaps do
- * not fit in the context's bitmap arena get status PM_ENOMEM and are not
- * counted; pm_reserve() sizes the arena.  At most PM_BATCH_MAX variants.
+ * Device-resident batched path of pm_count / pm_predict (Sec. 3.2, Alg. 1
+ * and 2, Eq. opcount; the prediction of Sec. 2): d_v[nv] (device) ->
+ * d_counts[nv] (device, may be NULL), d_t[nv] (device, FP64 predictions
+ * with model m; ignored if m or d_t is NULL), d_status[nv] (device int32: 0
+ * or a pm_status per variant).  Enqueued on `hip_stream` (a hipStream_t,
+ * used as given: NULL is HIP's null stream); returns without waiting.
+ * Variants whose footprint bitmaps do not fit in the context's bitmap arena
+ * get status PM_ENOMEM and are not counted; pm_reserve() sizes the arena.
+ * At most PM_BATCH_MAX variants.  Batches of one context share its device
+ * arena: a batch enqueued on another stream than the context's previous
+ * batch first waits (hipStreamWaitEvent) for that batch, so calls on
+ * different streams, and pm_count / pm_predict between them, are ordered
+ * in the order they were made.
  */
 #define PM_BATCH_MAX 65536
 pm_status pm_count_device(pm_ctx *ctx, const pm_variant *d_v, size_t nv,
@@ -268,7 +274,14 @@ pm_status pm_batch_stats(pm_ctx *ctx, int64_t *stats);
 /* Bytes of footprint bitmap one variant needs (host computation). */
 pm_status pm_bitmap_bytes(const pm_variant *v, size_t *bytes);
 
-/* Derived features of one count vector (host): f[*nfeat]. */
+/* Derived features of one count vector (host): f[*nfeat], the properties
+ * p_i of Sec. 2 formed from the counts as in Sec. 4.2 (last paragraph):
+ * global access counts by size, direction and stride class (Sec. 2.1), LDS
+ * accesses and flops by kind and precision (Sec. 2.2), barriers (Sec. 2.3),
+ * work-groups and the constant (Sec. 2.4), and the min(load, store) pairs
+ * of Sec. 2.1, projected as `proj` describes (PM_PROJ_*).  *nfeat
+ * (nullable) receives the number written.  PM_EINVAL for an unknown
+ * projection. */
 pm_status pm_features(const pm_counts *c, uint32_t proj, double *f,
                       uint32_t *nfeat);
 
@@ -307,6 +320,37 @@ pm_status pm_launch(pm_ctx *ctx, const pm_variant *v, void *const *bufs,
 pm_status pm_measure(pm_ctx *ctx, const pm_variant *v, void *const *bufs,
                      const size_t *bytes, uint32_t nbufs, void *hip_stream,
                      int warmup, int reps, double *t_reps, double *t_min);
+
+/*
+ * Launch overhead (Sec. 4.2: the empty kernel is run first on each GPU to
+ * find it): the minimum over 26 timed launches, after 4 untimed ones, of
+ * the empty kernel with one work-group of 64 work-items, on `hip_stream`.
+ * *t_sec receives it in seconds and the context keeps it as its launch
+ * floor for pm_measure_until.  Synchronous.
+ */
+pm_status pm_launch_floor(pm_ctx *ctx, void *hip_stream, double *t_sec);
+
+/*
+ * pm_measure with a deadline and the launch floor check.  Timed launches
+ * are enqueued at most 4 ahead of the last one that completed.
+ * deadline_s >= 0: once that much host wall time has passed since the
+ * call began, no further launch is enqueued and the call returns
+ * PM_ETIMEDOUT; launches already enqueued still run to completion on the
+ * stream (the caller keeps its buffers alive until the stream reaches
+ * them; the next measurement on the context waits for them).  deadline_s
+ * < 0: no deadline.  *reps_done (nullable) receives the number of timed
+ * launches that completed, t_reps[0 .. *reps_done) their times and *t_min
+ * their minimum (0 if none).  *flags (nullable) receives
+ * PM_MEASURE_BELOW_FLOOR when the context has a launch floor
+ * (pm_launch_floor) and *t_min is below twice it: the kernel's own work
+ * then takes less time than launching it, the regime Sec. 4.2 keeps
+ * measurement and test sizes out of.
+ */
+#define PM_MEASURE_BELOW_FLOOR 1u
+pm_status pm_measure_until(pm_ctx *ctx, const pm_variant *v, void *const *bufs,
+                           const size_t *bytes, uint32_t nbufs, void *hip_stream,
+                           int warmup, int reps, double deadline_s, double *t_reps,
+                           double *t_min, int32_t *reps_done, uint32_t *flags);
 
 #ifdef __cplusplus
 }

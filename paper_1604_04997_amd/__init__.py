@@ -108,6 +108,11 @@ def lib():
             "pm_launch": (ctypes.c_int, [vp, P(Variant), P(vp), P(ctypes.c_size_t), ctypes.c_uint32, vp]),
             "pm_measure": (ctypes.c_int, [vp, P(Variant), P(vp), P(ctypes.c_size_t), ctypes.c_uint32, vp,
                                           ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]),
+            "pm_measure_until": (ctypes.c_int, [vp, P(Variant), P(vp), P(ctypes.c_size_t), ctypes.c_uint32, vp,
+                                                ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                P(ctypes.c_double), P(ctypes.c_double),
+                                                P(ctypes.c_int32), P(ctypes.c_uint32)]),
+            "pm_launch_floor": (ctypes.c_int, [vp, vp, P(ctypes.c_double)]),
             "pm_count_host": (ctypes.c_int, [P(Variant), P(Counts), P(ctypes.c_int64)]),
             "pm_count_host_seq": (ctypes.c_int, [P(Variant), P(Counts), P(ctypes.c_int64)]),
             "pm_profile": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -380,6 +385,34 @@ class Context:
                                 self._stream(stream_ptr), warmup, reps, tr,
                                 ctypes.byref(tmin)))
         return tmin.value, list(tr[:])
+
+    def launch_floor(self, stream_ptr=None) -> float:
+        """Launch overhead in seconds: the empty kernel's minimum time
+        (Sec. 4.2); the context keeps it for measure_until's floor check."""
+        t = ctypes.c_double()
+        _check(lib().pm_launch_floor(self._h, self._stream(stream_ptr), ctypes.byref(t)))
+        return t.value
+
+    def measure_until(self, d: dict, tensors, warmup: int = 4, reps: int = 26,
+                      deadline_s: float = -1.0, stream_ptr=None) -> dict:
+        """pm_measure_until: like measure, with a host deadline (seconds
+        from the call, < 0: none).  Returns {"status", "t_min", "t_reps",
+        "below_floor"}; status is 0 or PM_ETIMEDOUT (-6), other errors
+        raise."""
+        v = variant_struct(d)
+        ptrs, sizes, n = self._bufs(tensors)
+        tr = (ctypes.c_double * reps)()
+        tmin = ctypes.c_double()
+        done = ctypes.c_int32()
+        flags = ctypes.c_uint32()
+        rc = lib().pm_measure_until(self._h, ctypes.byref(v), ptrs, sizes, n,
+                                    self._stream(stream_ptr), warmup, reps,
+                                    float(deadline_s), tr, ctypes.byref(tmin),
+                                    ctypes.byref(done), ctypes.byref(flags))
+        if rc not in (0, -6):
+            _check(rc)
+        return {"status": rc, "t_min": tmin.value, "t_reps": list(tr[:done.value]),
+                "below_floor": bool(flags.value & 1)}
 
 
 def device_buffers(d: dict, seed: int, device: str = "cuda:0",

@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "counter.h"
@@ -108,6 +110,16 @@ struct pm_ctx {
     double *zd_pred = nullptr;
     int32_t *zd_status = nullptr;
     std::vector<hipEvent_t> events;
+    // Order of batches on the shared arena: every batch waits for the event
+    // the previous batch recorded on its stream (when that stream differs)
+    // and records it again after its last kernel.
+    hipEvent_t arena_done = nullptr;
+    hipStream_t arena_stream = nullptr;
+    bool arena_used = false;
+    // measurement: the last timed launch of a call that timed out (a later
+    // call waits for it before reusing the events), the launch floor
+    hipEvent_t measure_pending = nullptr;
+    double launch_floor = 0.0;
     int profile = 0;  // 0 off, 1 every phase, 2 the expansion kernel only
     std::vector<hipEvent_t> pev;  // (PM_NPHASE + 1) per recorded batch
     int pcount = 0;
@@ -219,6 +231,20 @@ int grow_bitmap(pm_ctx *c, size_t words) {
     return PM_OK;
 }
 
+// Make stream s wait for the previous batch on the shared arena when that
+// batch ran on another stream.
+int arena_enter(pm_ctx *c, hipStream_t s) {
+    if (c->arena_used && c->arena_stream != s) HIPCHK(hipStreamWaitEvent(s, c->arena_done, 0));
+    return PM_OK;
+}
+// The batch on stream s has enqueued its last kernel.
+int arena_leave(pm_ctx *c, hipStream_t s) {
+    HIPCHK(hipEventRecord(c->arena_done, s));
+    c->arena_stream = s;
+    c->arena_used = true;
+    return PM_OK;
+}
+
 // Count (and optionally predict) nv <= cap variants from host memory.
 // Batches of up to ZC_MAX variants have their outputs written by the
 // kernels into mapped host memory (no device-to-host copies); larger ones
@@ -249,10 +275,12 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
     hipEvent_t *ev = c->next_events();
     const int nmark = c->nmarks();
     for (int attempt = 0; attempt < 2; attempt++) {
+        if ((st = arena_enter(c, c->stream))) return st;
         HIPCHK(hipMemcpyAsync(c->d_var, c->h_var, sizeof(pm_variant) * nv, hipMemcpyHostToDevice, c->stream));
         st = pm::launch_expand(c->ar, c->sched, (int)nv, c->d_var, dc, m, dp, ds, c->stream, ev,
                                nmark);
         if (st) return set_err(st, "counter launch failed");
+        if ((st = arena_leave(c, c->stream))) return st;
         if ((st = fetch())) return st;
         bool nomem = false, deferred = false;
         for (size_t i = 0; i < nv; i++) {
@@ -271,6 +299,7 @@ int run_host_batch(pm_ctx *c, const pm_variant *v, size_t nv, pm_counts *out,
             st = pm::launch_rest(c->ar, c->sched, (int)nv, dc, m, dp, ds, c->stream, c->n_cu, ev,
                                  nmark);
             if (st) return set_err(st, "counter launch failed");
+            if ((st = arena_leave(c, c->stream))) return st;
             if ((st = fetch())) return st;
         } else if (ev) {  // phases that did not run take no time
             for (int q = 2; q < nmark; q++) (void)hipEventRecord(ev[q], c->stream);
@@ -323,38 +352,106 @@ int check_bufs(const pm_variant *v, void *const *bufs, const size_t *bytes, uint
     return PM_OK;
 }
 
+// Timed launches in flight at once: enough that the next launch is always
+// queued behind the running one, few enough that a deadline stops the call
+// soon after it passes.
+constexpr int MEASURE_INFLIGHT = 4;
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Sec. 4.2 timing: `warmup` untimed launches, then `reps` launches between
+// HIP events, at most MEASURE_INFLIGHT of them enqueued ahead of the last
+// one that completed.  deadline_s >= 0: once that much host wall time has
+// passed since the call began, nothing more is enqueued and the call
+// returns PM_ETIMEDOUT; what was enqueued runs to completion on the stream
+// (the next measurement on this context waits for it).
 int measure_impl(pm_ctx *c, const pm_variant *v, void *const *bufs, const size_t *bytes,
-                     uint32_t nbufs, void *stream, int warmup, int reps, double *t_reps,
-                     double *t_min) {
+                 uint32_t nbufs, void *stream, int warmup, int reps, double deadline_s,
+                 double *t_reps, double *t_min, int32_t *reps_done, uint32_t *flags) {
     if (!c || !t_min || reps < 1 || warmup < 0) return set_err(PM_EINVAL, "bad argument");
     int st = validate(v);
     if (st) return st;
     st = check_bufs(v, bufs, bytes, nbufs);
     if (st) return st;
     DeviceGuard g(c->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto late = [&]() { return deadline_s >= 0 && seconds_since(t0) > deadline_s; };
     hipStream_t s = (hipStream_t)stream;  // NULL: HIP's null stream
-    while ((int)c->events.size() < 2 * reps) {
+    if (c->measure_pending) {  // launches of a call that timed out
+        HIPCHK(hipEventSynchronize(c->measure_pending));
+        c->measure_pending = nullptr;
+    }
+    while ((int)c->events.size() < 2 * reps + 1) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         c->events.push_back(e);
     }
-    for (int w = 0; w < warmup; w++)
-        if ((st = pm::launch(*v, bufs, s))) return set_err(st, "kernel launch failed");
-    for (int r = 0; r < reps; r++) {
-        HIPCHK(hipEventRecord(c->events[2 * r], s));
-        if ((st = pm::launch(*v, bufs, s))) return set_err(st, "kernel launch failed");
-        HIPCHK(hipEventRecord(c->events[2 * r + 1], s));
+    *t_min = 0;
+    if (reps_done) *reps_done = 0;
+    if (flags) *flags = 0;
+    int enq = 0, done = 0;  // timed launches enqueued, completed
+    bool timed_out = false;
+    // polls the end event of timed launch `done`; false on a HIP error
+    auto poll = [&](hipError_t *err) -> bool {
+        const hipError_t q = hipEventQuery(c->events[2 * done + 1]);
+        if (q == hipSuccess) {
+            done++;
+            return true;
+        }
+        if (q != hipErrorNotReady) {
+            *err = q;
+            return false;
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        return true;
+    };
+    hipError_t herr = hipSuccess;
+    for (int w = 0; w < warmup && !timed_out; w++) {
+        if (late()) timed_out = true;
+        else if ((st = pm::launch(*v, bufs, s))) return set_err(st, "kernel launch failed");
     }
-    HIPCHK(hipEventSynchronize(c->events[2 * reps - 1]));
-    double best = 1e300;
-    for (int r = 0; r < reps; r++) {
+    while (enq < reps && !timed_out) {
+        if (enq - done >= MEASURE_INFLIGHT) {
+            if (!poll(&herr)) return set_err(PM_EDEVICE, std::string("event query: ") + hipGetErrorString(herr));
+            if (late()) timed_out = true;
+            continue;
+        }
+        if (late()) {
+            timed_out = true;
+            break;
+        }
+        HIPCHK(hipEventRecord(c->events[2 * enq], s));
+        if ((st = pm::launch(*v, bufs, s))) return set_err(st, "kernel launch failed");
+        HIPCHK(hipEventRecord(c->events[2 * enq + 1], s));
+        enq++;
+    }
+    while (done < enq && !timed_out) {
+        if (!poll(&herr)) return set_err(PM_EDEVICE, std::string("event query: ") + hipGetErrorString(herr));
+        if (done < enq && late()) timed_out = true;
+    }
+    // times of the completed launches (the first `done`, in order)
+    double best = 0;
+    for (int r = 0; r < done; r++) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, c->events[2 * r], c->events[2 * r + 1]));
-        double sec = (double)ms * 1e-3;
+        const double sec = (double)ms * 1e-3;
         if (t_reps) t_reps[r] = sec;
-        best = std::min(best, sec);
+        best = r == 0 ? sec : std::min(best, sec);
     }
     *t_min = best;
+    if (reps_done) *reps_done = done;
+    if (flags && done > 0 && c->launch_floor > 0 && best < 2.0 * c->launch_floor)
+        *flags |= PM_MEASURE_BELOW_FLOOR;
+    if (timed_out) {
+        // whatever was enqueued still runs; mark its end for the next call
+        HIPCHK(hipEventRecord(c->events[2 * reps], s));
+        c->measure_pending = c->events[2 * reps];
+        return set_err(PM_ETIMEDOUT, "measurement deadline of " + std::to_string(deadline_s) +
+                                         " s passed after " + std::to_string(done) + " of " +
+                                         std::to_string(reps) + " timed launches");
+    }
     return PM_OK;
 }
 
@@ -378,6 +475,8 @@ pm_status pm_create(pm_ctx **out, int device, size_t budget) {
         c->n_cu = 256;
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "stream creation failed");
+    if (hipEventCreateWithFlags(&c->arena_done, hipEventDisableTiming) != hipSuccess)
+        return (pm_status)set_err(PM_EDEVICE, "event creation failed");
     if (hipHostMalloc(&c->h_meta, 8 * pm::META_WORDS, 0) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "pinned allocation failed");
     const unsigned zf = hipHostMallocMapped | hipHostMallocCoherent;
@@ -402,7 +501,10 @@ void pm_destroy(pm_ctx *c) {
     (void)hipHostFree(c->z_counts);
     (void)hipHostFree(c->z_pred);
     (void)hipHostFree(c->z_status);
+    if (c->measure_pending) (void)hipEventSynchronize(c->measure_pending);
+    (void)hipDeviceSynchronize();  // batches on caller streams
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    if (c->arena_done) (void)hipEventDestroy(c->arena_done);
     for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
     delete c;
@@ -457,10 +559,11 @@ pm_status pm_count_device(pm_ctx *c, const pm_variant *d_v, size_t nv, pm_counts
     int st = grow_cap(c, nv);
     if (st) return (pm_status)st;
     hipStream_t s = (hipStream_t)stream;  // NULL: HIP's null stream
+    if ((st = arena_enter(c, s))) return (pm_status)st;
     st = pm::launch_batch(c->ar, c->sched, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr, d_t, d_status, s, c->n_cu,
                           c->next_events(), c->nmarks());
     if (st) return (pm_status)set_err(st, "counter launch failed");
-    return PM_OK;
+    return (pm_status)arena_leave(c, s);
 }
 
 pm_status pm_reserve(pm_ctx *c, size_t nv, size_t bitmap_bytes) {
@@ -589,7 +692,36 @@ pm_status pm_launch(pm_ctx *c, const pm_variant *v, void *const *bufs, const siz
 pm_status pm_measure(pm_ctx *c, const pm_variant *v, void *const *bufs, const size_t *bytes,
                      uint32_t nbufs, void *stream, int warmup, int reps, double *t_reps,
                      double *t_min) {
-    return (pm_status)measure_impl(c, v, bufs, bytes, nbufs, stream, warmup, reps, t_reps, t_min);
+    return (pm_status)measure_impl(c, v, bufs, bytes, nbufs, stream, warmup, reps, -1.0, t_reps,
+                                   t_min, nullptr, nullptr);
+}
+
+pm_status pm_measure_until(pm_ctx *c, const pm_variant *v, void *const *bufs, const size_t *bytes,
+                           uint32_t nbufs, void *stream, int warmup, int reps, double deadline_s,
+                           double *t_reps, double *t_min, int32_t *reps_done, uint32_t *flags) {
+    return (pm_status)measure_impl(c, v, bufs, bytes, nbufs, stream, warmup, reps, deadline_s,
+                                   t_reps, t_min, reps_done, flags);
+}
+
+pm_status pm_launch_floor(pm_ctx *c, void *stream, double *t_sec) {
+    if (!c || !t_sec) return (pm_status)set_err(PM_EINVAL, "null argument");
+    // the empty kernel: one work-group of 64 work-items
+    pm_variant v{};
+    v.family = PM_FAM_EMPTY;
+    v.n[0] = 8;
+    v.wg[0] = 8;
+    v.wg[1] = 8;
+    const double keep = c->launch_floor;
+    double t = 0;
+    int st = measure_impl(c, &v, nullptr, nullptr, 0, stream, 4, 26, -1.0, nullptr, &t, nullptr,
+                          nullptr);
+    if (st) {
+        c->launch_floor = keep;
+        return (pm_status)st;
+    }
+    c->launch_floor = t;
+    *t_sec = t;
+    return PM_OK;
 }
 
 // ------------------------------------------------------------- testing ---

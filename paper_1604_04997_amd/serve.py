@@ -14,9 +14,11 @@ every step:
      pm_count_device) on the count stream -- requests that arrived while
      earlier batches were on the GPU join the next batch;
   4. admits waiting measure requests while their kernel buffers fit the
-     HBM budget next to those in flight, and launches their warm-up and
-     timed runs (pm_launch bracketed by events) on the measure stream, so
-     they overlap with the count batches.
+     HBM budget next to those in flight -- at most `measure_admit` per
+     step, so that the loop comes back to retire and launch predict
+     batches between them -- and launches their warm-up and timed runs
+     (pm_launch bracketed by events) on the measure stream, so they
+     overlap with the count batches.
 
 Latency of a request = time its result is on the host - its arrival time
 (with realtime=False every request arrives at the start).
@@ -39,13 +41,15 @@ VSIZE = ctypes.sizeof(Variant)
 class Server:
     def __init__(self, ctx: Context, model: Model, slots: int = 8192,
                  max_batch: int = 2048, hbm_budget: int = 32 << 30,
-                 bitmap_bytes: int = 1 << 30, warmup: int = 2, reps: int = 5):
+                 bitmap_bytes: int = 1 << 30, warmup: int = 2, reps: int = 5,
+                 measure_admit: int = 1):
         import torch
         self.torch = torch
         self.ctx, self.model = ctx, model
         self.slots, self.max_batch = slots, min(max_batch, slots)
         self.budget = hbm_budget
         self.warmup, self.reps = warmup, reps
+        self.measure_admit = measure_admit
         self.d_var = torch.zeros(slots * VSIZE, dtype=torch.uint8, device="cuda")
         self.d_counts = torch.zeros((slots, PM_NCOUNT), dtype=torch.int64, device="cuda")
         self.d_pred = torch.zeros(slots, dtype=torch.float64, device="cuda")
@@ -169,8 +173,9 @@ class Server:
                     used_slots += n
                     n_batches += 1
                     batch_sizes.append(n)
-            # 4. admit measures within the memory budget
-            while wait_m:
+            # 4. admit measures within the memory budget, a few per step
+            admitted = 0
+            while wait_m and admitted < self.measure_admit:
                 rid, v, ta = wait_m[0]
                 nbytes = sum(b for b, _ in buffers(v))
                 if mem + nbytes > self.budget and measures:
@@ -179,6 +184,7 @@ class Server:
                 ts, evs = self._launch_measure(rid, v)
                 measures.append((rid, v, nbytes, ts, evs, ta))
                 mem += nbytes
+                admitted += 1
             if not realtime and not arrivals and not wait_p and not wait_m:
                 torch.cuda.synchronize()
         wall = time.perf_counter() - t0

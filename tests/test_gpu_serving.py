@@ -41,11 +41,10 @@ def test_serving_results_equal_alone(ctx):
     print(stats, flush=True)
     assert stats["requests"] == len(trace) and stats["batches"] >= 1
     preds = [(i, t[2]) for i, t in enumerate(trace) if t[1] == "predict"]
-    alone_c = P.counts_numpy(ctx.count_raw([v for _, v in preds]))
-    for k, (i, v) in enumerate(preds):
+    for i, v in preds:  # each variant counted and predicted alone
         r = recs[i]
         assert r["status"] == 0
-        np.testing.assert_array_equal(r["counts"], alone_c[k])
+        np.testing.assert_array_equal(r["counts"], P.counts_numpy(ctx.count_raw([v]))[0])
         assert r["pred"] == float(ctx.predict(m, [v])[0])
     for i, (ta, kind, v) in enumerate(trace):
         if kind != "measure":
@@ -59,6 +58,12 @@ def test_serving_results_equal_alone(ctx):
             assert torch.equal(a, b) or (torch.isnan(a).all() and torch.isnan(b).all()), v
     lat = [r["done"] - r["arrival"] for r in recs]
     assert min(lat) >= 0 and stats["p99_ms"] >= stats["p50_ms"] > 0
+    # every request queued at once: batches form, results unchanged
+    recs2, stats2 = srv.run(trace, realtime=False, keep_counts=True)
+    assert stats2["max_batch"] > 1
+    for i, v in preds:
+        np.testing.assert_array_equal(recs2[i]["counts"], recs[i]["counts"])
+        assert recs2[i]["pred"] == recs[i]["pred"]
 
 
 def test_plain_replay(ctx):
