@@ -250,22 +250,23 @@ pm_status pm_get_schedule(pm_ctx *ctx, pm_schedule *s);
  * timing window (pm_profile(ctx, 2): the same with events around the
  * expansion kernel only, ms[0]; every recorded event adds a few
  * microseconds to a batch): every batch until pm_profile_read (at most
- * PM_PROFILE_MAX batches) records HIP events around each of its six
- * phases (per-variant expansion, count and finish; a scan phase that is
- * empty since work lists are claimed during the expansion; then for
- * variants handed on: clear, count, fill, finish) on the stream they run
- * on.  pm_profile_read waits for the recorded batches and writes the mean
- * duration of each phase in milliseconds to ms[6] (host) and the number of
- * batches to *nbatch; the window then restarts.  pm_profile(ctx, 0) stops
- * recording.  In the synchronous host calls (pm_count, pm_predict) the
- * chip-wide phases run only when the expansion handed variants on: the
- * host's read of the expansion's results then falls in the scan phase, and
- * phases that did not run read zero.
+ * PM_PROFILE_MAX batches) records HIP events around each of its three
+ * phases on the stream they run on: ms[0] the expansion kernel
+ * (per-variant expansion, count and finish), ms[1] the time between the two
+ * kernels (empty on the device path; in the synchronous host calls the
+ * host's read of the expansion's statuses), ms[2] the chip-wide kernel for
+ * the variants handed on (bitmap clearing, count and footprint chunks,
+ * fill, finish).  pm_profile_read waits for the recorded batches and
+ * writes the mean duration of each phase in milliseconds to
+ * ms[PM_NPHASE] (host) and the number of batches to *nbatch; the window
+ * then restarts.  pm_profile(ctx, 0) stops recording.  In the synchronous
+ * host calls the chip-wide kernel runs only when the expansion handed
+ * variants on; phases that did not run read zero.
  * pm_batch_stats writes, for the last batch, stats[0] work chunks,
  * stats[1] bitmap words cleared, stats[2] fill segments, stats[3] variants
- * handed on to the chip-wide kernels, stats[4] bitmap words requested
+ * handed on to the chip-wide kernel, stats[4] bitmap words requested
  * (host int64[8]); synchronous. */
-#define PM_NPHASE 6
+#define PM_NPHASE 3
 #define PM_PROFILE_MAX 4096
 pm_status pm_profile(pm_ctx *ctx, int enable);
 pm_status pm_profile_read(pm_ctx *ctx, double *ms, int *nbatch);

@@ -301,7 +301,7 @@ class Context:
         _check(lib().pm_predict(self._h, ctypes.byref(model), va, len(va), t))
         return np.array(t[:])
 
-    PHASES = ("build", "scan", "clear", "count", "fill", "finalize")
+    PHASES = ("build", "gap", "tail")
 
     def profile(self, enable=True):
         """True / 1: events around every phase; 2: around the expansion
@@ -310,7 +310,7 @@ class Context:
 
     def profile_read(self):
         """({kernel: mean milliseconds}, batches) since profiling started."""
-        ms = (ctypes.c_double * 6)()
+        ms = (ctypes.c_double * len(self.PHASES))()
         nb = ctypes.c_int()
         _check(lib().pm_profile_read(self._h, ms, ctypes.byref(nb)))
         return dict(zip(self.PHASES, ms[:])), nb.value

@@ -150,6 +150,7 @@ void free_arena(pm_ctx *c) {
     (void)hipFree(a.dlist);
     (void)hipFree(a.jobres);
     (void)hipFree(a.foot);
+    (void)hipFree(a.vdone);
     (void)hipFree(a.meta);
     (void)hipFree(c->d_var);
     (void)hipFree(c->d_counts);
@@ -197,6 +198,7 @@ int grow_cap(pm_ctx *c, size_t nv) {
     HIPCHK(hipMalloc(&a.dlist, 4 * cap));
     HIPCHK(hipMalloc(&a.jobres, 8 * cap * pm::MAXJOB));
     HIPCHK(hipMalloc(&a.foot, 16 * cap * pm::MAXARR));
+    HIPCHK(hipMalloc(&a.vdone, 16 * cap));
     HIPCHK(hipMalloc(&a.meta, 16 * pm::META_WORDS));
     HIPCHK(hipMemset(a.meta, 0, 16 * pm::META_WORDS));  // both halves start clear
     HIPCHK(hipDeviceSynchronize());

@@ -34,6 +34,8 @@ enum {
     M_SEGS = 2,    // packed: fill-list entries, segments
     M_DEFER = 3,   // variants handed on
     M_USED = 4,    // end of the last bitmap that fitted
+    M_TICKET = 5,  // chip-wide kernel: work items taken
+    M_ZDONE = 6,   // chip-wide kernel: bitmap clearing items done
 };
 struct Arena {
     size_t cap = 0;
@@ -49,6 +51,7 @@ struct Arena {
     int32_t *dlist = nullptr;     // [cap]: variants left to finish
     int64_t *jobres = nullptr;    // [cap * MAXJOB]
     int64_t *foot = nullptr;      // [cap * MAXARR * 2]
+    int64_t *vdone = nullptr;     // [cap * 2]: chunks and fill segments done
     int64_t *meta = nullptr;      // [2 * META_WORDS]
     uint64_t *bitmap = nullptr;   // [bitmap_words]
 };
@@ -57,9 +60,10 @@ size_t arena_bytes_per_variant();
 
 // Enqueue the counter launches for nv variants already in device memory
 // (d_var) on stream s; flips ar.parity.  d_counts / model / d_pred may be
-// null.  ev: null, or events recorded around the six phases (build, an
-// empty scan phase, clear, count, fill, finalize); the first `nmark` of the
-// seven are recorded (2: around the expansion kernel only).
+// null.  ev: null, or events recorded around the three phases (the
+// expansion kernel, the gap between the kernels, the chip-wide kernel);
+// the first `nmark` of the four are recorded (2: around the expansion
+// kernel only).
 // Schedule of the batched counter (pm_schedule): the most items a
 // variant's count jobs may hold to be counted by the work-group that
 // expands it (k_build; k_fused), and the work-groups per CU of the
@@ -73,11 +77,11 @@ struct Sched {
 int launch_batch(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var,
                  pm_counts *d_counts, const pm_model *model, double *d_pred,
                  int32_t *d_status, hipStream_t s, int n_cu,
-                 hipEvent_t *ev = nullptr, int nmark = 7);
+                 hipEvent_t *ev = nullptr, int nmark = 4);
 // The same in two parts: the expansion kernel (events 0 and 1; flips
-// ar.parity) and the chip-wide kernels for the variants it handed on
-// (events 2..6), which a caller that has read the expansion's meta half
-// may skip when it handed none on.
+// ar.parity) and the chip-wide kernel for the variants it handed on
+// (events 2 and 3), which a caller that has read the expansion's meta half may
+// skip when it handed none on.
 int launch_expand(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var, pm_counts *d_counts,
                   const pm_model *model, double *d_pred, int32_t *d_status, hipStream_t s,
                   hipEvent_t *ev, int nmark);

@@ -13,15 +13,15 @@
 //             others on with their descriptor and jobs in HBM.
 // A variant handed on claims, with atomics, its bitmap words (PM_ENOMEM
 // when they pass the arena's end) and entries in the chunk, segment and
-// finish lists (counter.h).  For handed-on variants only:
-//   k_clear     zero the used bitmap words
-//   k_count     every wavefront takes chunks round-robin: count chunks sum
-//               inner interval lengths, footprint chunks OR cell runs into
-//               the bitmaps
-//   k_fill      per array segment: |F| and |Fill| (F with every strided
-//               cell widened to its run of stride*vec cells)
-//   k_finalize  one wavefront per listed variant: count vector and
-//               prediction
+// finish lists (counter.h).  For handed-on variants only, one chip-wide
+// launch:
+//   k_tail      wavefronts take work items by ticket: clear the used bitmap
+//               words; count chunks (sums of inner interval lengths) and
+//               footprint chunks (cell runs OR-ed into the bitmaps); fill
+//               segments (|F| and |Fill|, F with every strided cell widened
+//               to its run of stride*vec cells); the count vector and
+//               prediction of each variant -- each item after the ones it
+//               needs (per-variant completion counters)
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -33,9 +33,6 @@
 
 namespace pm {
 
-constexpr int FILL_THREADS = 256;
-constexpr int FILL_WORDS_PER_THREAD = 16;  // 4096 words per segment
-constexpr int COUNT_THREADS = 256;
 constexpr int FUSED_THREADS = 256;
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 
@@ -224,6 +221,7 @@ struct HandOn {
     int64_t *meta;       // this batch's half
     int64_t *meta_next;  // the other half, cleared for the next batch by work-group 0
     int64_t *varoff;
+    int64_t *vdone;      // per variant: chunks done, segments done
     int32_t *clist, *slist, *dlist;
     int64_t *cend, *send;
     int64_t arena_words;
@@ -238,6 +236,7 @@ struct HandOn {
 // unfinished batch could give, is refused with PM_EDEVICE.)
 __device__ __forceinline__ int hand_on(const Prog &P, int i, const HandOn &h) {
     if (P.chunks >= MAX_VARIANT_CHUNKS) return PM_EOVERFLOW;
+    h.vdone[2 * (int64_t)i] = h.vdone[2 * (int64_t)i + 1] = 0;
     if (P.bitmap_words > 0) {
         const int64_t off = (int64_t)atomicAdd((unsigned long long *)&h.meta[M_WORDS],
                                                (unsigned long long)P.bitmap_words);
@@ -442,13 +441,6 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     if (t == 0) status[i] = s2;
 }
 
-__global__ void k_clear(uint64_t *bitmap, const int64_t *meta, int64_t arena_words) {
-    int64_t words = meta[M_USED] < arena_words ? meta[M_USED] : arena_words;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t i = t; i < words; i += stride) bitmap[i] = 0;
-}
-
 // first index j in [0, n) with pref[j] > x (pref non-decreasing)
 __device__ int64_t upper(const int64_t *pref, int64_t n, int64_t x) {
     int64_t lo = 0, hi = n;
@@ -466,157 +458,196 @@ struct DevOr {
     }
 };
 
-__global__ void __launch_bounds__(COUNT_THREADS)
-k_count(const Prog *prog, const Job *jobs, const int32_t *clist, const int64_t *cend,
-        const int64_t *varoff, uint64_t *bitmap, int64_t *jobres, const int64_t *meta,
-        int64_t cap) {
-    const int lane = threadIdx.x & 63;
-    const int64_t total = meta[M_CHUNKS] & LIST_OFF_MASK;
-    int64_t nlist = (int64_t)((unsigned long long)meta[M_CHUNKS] >> LIST_POS);
-    if (nlist > cap) nlist = cap;
-    const int64_t nwave = (int64_t)gridDim.x * (blockDim.x / 64);
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int64_t last = nlist ? cend[nlist - 1] : 0;  // chunks listed
-    for (int64_t ch = wave; ch < total && ch < last; ch += nwave) {
-        // chunk -> list entry (prefix over the list) -> variant -> job
-        const int64_t e = upper(cend, nlist, ch);
-        const int64_t v = clist[e];
-        int64_t local = ch - (e ? cend[e - 1] : 0);
-        const int64_t *cum = prog[v].jobcum;
-        int jl = 0;
-        while (cum[jl] <= local) jl++;
-        local -= jl ? cum[jl - 1] : 0;
-        int64_t j = v * MAXJOB + jl;
-        const Job &J = jobs[j];
-        int64_t it0 = local * J.chunk_items;
-        int64_t it1 = it0 + J.chunk_items;
-        if (it1 > J.items) it1 = J.items;
-        if (J.kind == JOB_COUNT) {
-            int64_t s = 0;
-            for (int64_t it = it0 + lane; it < it1; it += 64) s += count_item(J, it);
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (lane == 0 && s) atomicAdd((unsigned long long *)&jobres[j], (unsigned long long)s);
-        } else {
-            uint64_t *vb = bitmap + varoff[j / MAXJOB];
-            for (int64_t it = it0; it < it1; it++) foot_item(J, it, vb, lane, 64, DevOr{});
+// Agent-scope counters through which the chip-wide kernel's work items
+// hand their results on: a producer's writes are visible to a consumer
+// that has seen its increment.
+__device__ __forceinline__ void signal(int64_t *p) {
+    __hip_atomic_fetch_add(p, (int64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_for(const int64_t *p, int64_t need) {
+    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need)
+        __builtin_amdgcn_s_sleep(2);
+}
+
+// Words of bitmap one clearing item zeroes, and one fill segment reads
+// (64 lanes x FILL_WORDS_PER_LANE).
+constexpr int64_t ZERO_WORDS = 4096;
+constexpr int FILL_WORDS_PER_LANE = 64;
+static_assert(64 * FILL_WORDS_PER_LANE == SEG_WORDS, "fill segment = one wavefront's words");
+
+// Fill segment `local` of array `al` of variant v by one wavefront: |F|
+// and |Fill| of its words (Fill: F with every strided cell widened to its
+// run of w cells, including runs that start in earlier words) added to
+// foot.
+__device__ void fill_segment(const Prog &P, int al, int64_t local, const uint64_t *vb,
+                             int64_t *foot_v, int l) {
+    const ArrInfo &A = P.arr[al];
+    const uint64_t *F = vb + A.f_off;
+    const uint64_t *Bm = vb + A.b_off;
+    const int64_t w = A.w;
+    const int64_t k0 = local * SEG_WORDS;
+    const int64_t k1 = k0 + SEG_WORDS < A.words ? k0 + SEG_WORDS : A.words;
+    const int64_t a = k0 + (int64_t)l * FILL_WORDS_PER_LANE;
+    const int64_t e = a + FILL_WORDS_PER_LANE < k1 ? a + FILL_WORDS_PER_LANE : k1;
+    int64_t mylast = -1;
+    for (int64_t k = e - 1; k >= a; k--) {
+        const uint64_t b = Bm[k];
+        if (b) {
+            mylast = last_bit(b, k);
+            break;
         }
+    }
+    // the last strided cell before the segment, within reach w
+    const int64_t L = (w + 63) / 64 + 1;
+    int64_t blast = -1;
+    for (int64_t k = (k0 - L > 0 ? k0 - L : 0) + l; k < k0; k += 64) {
+        const int64_t x = last_bit(Bm[k], k);
+        if (x > blast) blast = x;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t y = __shfl_xor(blast, off);
+        if (y > blast) blast = y;
+    }
+    // exclusive max-scan of mylast over the lanes
+    int64_t incl = mylast;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(incl, off);
+        if (l >= off && y > incl) incl = y;
+    }
+    int64_t carry = __shfl_up(incl, 1);
+    if (l == 0) carry = -1;
+    if (blast > carry) carry = blast;
+    unsigned long long pf = 0, pfill = 0;
+    for (int64_t k = a; k < e; k++) {
+        const uint64_t b = Bm[k];
+        const uint64_t d = dilate_word(b, w) | carry_mask(carry, w, k);
+        const uint64_t f = F[k];
+        pf += __popcll(f);
+        pfill += __popcll(f | d);
+        if (b) carry = last_bit(b, k);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        pf += __shfl_xor(pf, off);
+        pfill += __shfl_xor(pfill, off);
+    }
+    if (l == 0) {
+        atomicAdd((unsigned long long *)&foot_v[al * 2], pf);
+        atomicAdd((unsigned long long *)&foot_v[al * 2 + 1], pfill);
     }
 }
 
-__global__ void __launch_bounds__(FILL_THREADS)
-k_fill(const Prog *prog, const int32_t *slist, const int64_t *send, const int64_t *varoff,
-       const uint64_t *bitmap, int64_t *foot, const int64_t *meta, int64_t cap) {
-    __shared__ int64_t sh[FILL_THREADS];
-    __shared__ unsigned long long red[2];
-    const int64_t total = meta[M_SEGS] & LIST_OFF_MASK;
-    int64_t nlist = (int64_t)((unsigned long long)meta[M_SEGS] >> LIST_POS);
-    if (nlist > cap) nlist = cap;
-    const int64_t last = nlist ? send[nlist - 1] : 0;  // segments listed
-    const int t = threadIdx.x;
-    for (int64_t sg = blockIdx.x; sg < total && sg < last; sg += gridDim.x) {
-        const int64_t le = upper(send, nlist, sg);
-        const int64_t v = slist[le];
-        int64_t local = sg - (le ? send[le - 1] : 0);
-        const int64_t *cum = prog[v].arrcum;
-        int al = 0;
-        while (cum[al] <= local) al++;
-        local -= al ? cum[al - 1] : 0;
-        int64_t j = v * MAXARR + al;
-        const ArrInfo &A = prog[v].arr[al];
-        const uint64_t *F = bitmap + varoff[v] + A.f_off;
-        const uint64_t *Bm = bitmap + varoff[v] + A.b_off;
-        const int64_t w = A.w;
-        const int64_t seg_words = (int64_t)FILL_THREADS * FILL_WORDS_PER_THREAD;
-        int64_t k0 = local * seg_words;
-        int64_t k1 = k0 + seg_words < A.words ? k0 + seg_words : A.words;
-        int64_t a = k0 + (int64_t)t * FILL_WORDS_PER_THREAD;
-        int64_t e = a + FILL_WORDS_PER_THREAD < k1 ? a + FILL_WORDS_PER_THREAD : k1;
-        int64_t mylast = -1;
-        for (int64_t k = e - 1; k >= a; k--) {
-            uint64_t b = Bm[k];
-            if (b) {
-                mylast = last_bit(b, k);
-                break;
-            }
-        }
-        // the last strided cell before the segment, within reach w
-        int64_t L = (w + 63) / 64 + 1;
-        int64_t lb0 = k0 - L > 0 ? k0 - L : 0;
-        int64_t blast = -1;
-        for (int64_t k = lb0 + t; k < k0; k += FILL_THREADS) {
-            int64_t x = last_bit(Bm[k], k);
-            if (x > blast) blast = x;
-        }
-        sh[t] = blast;
-        __syncthreads();
-        for (int off = FILL_THREADS / 2; off > 0; off >>= 1) {
-            if (t < off && sh[t + off] > sh[t]) sh[t] = sh[t + off];
-            __syncthreads();
-        }
-        blast = sh[0];
-        __syncthreads();
-        // exclusive max-scan of mylast over threads
-        sh[t] = mylast;
-        __syncthreads();
-        for (int off = 1; off < FILL_THREADS; off <<= 1) {
-            int64_t y = t >= off ? sh[t - off] : -1;
-            __syncthreads();
-            if (y > sh[t]) sh[t] = y;
-            __syncthreads();
-        }
-        int64_t carry = t ? sh[t - 1] : -1;
-        if (blast > carry) carry = blast;
-        __syncthreads();
-        unsigned long long pf = 0, pfill = 0;
-        for (int64_t k = a; k < e; k++) {
-            uint64_t b = Bm[k];
-            uint64_t d = dilate_word(b, w) | carry_mask(carry, w, k);
-            uint64_t f = F[k];
-            pf += __popcll(f);
-            pfill += __popcll(f | d);
-            if (b) carry = last_bit(b, k);
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            pf += __shfl_xor(pf, off);
-            pfill += __shfl_xor(pfill, off);
-        }
-        if (t == 0) red[0] = red[1] = 0;
-        __syncthreads();
-        if ((t & 63) == 0) {
-            atomicAdd(&red[0], pf);
-            atomicAdd(&red[1], pfill);
-        }
-        __syncthreads();
-        if (t == 0) {
-            atomicAdd((unsigned long long *)&foot[j * 2], red[0]);
-            atomicAdd((unsigned long long *)&foot[j * 2 + 1], red[1]);
-        }
-        __syncthreads();
-    }
-}
-
-// One 64-wide work-group per variant left to finish (the dlist entries, in
-// a grid-stride loop).
+// The chip-wide pass over the variants the expansion kernel handed on, in
+// one launch of one-wavefront work-groups.  Every wavefront takes work
+// items by ticket (meta[M_TICKET]) until the tickets run out:
+//   [0, Z)             clear ZERO_WORDS of the bitmap words the batch uses
+//   [Z, Z+C)           count and footprint chunks (footprint chunks first
+//                      wait until the clearing is done)
+//   [Z+C, Z+C+S)       fill segments (each waits until its variant's
+//                      chunks are done)
+//   [Z+C+S, Z+C+S+D)   finish a variant: count vector and prediction
+//                      (waits until its chunks and segments are done)
+// A wavefront only ever waits for items with smaller tickets, which
+// wavefronts that are already running hold and finish without waiting
+// for larger ones, so every wait ends and every wavefront exits.
 __global__ void __launch_bounds__(64)
-k_finalize(const Prog *prog, const int64_t *jobres, const int64_t *foot,
-           const int32_t *dlist, int32_t *status, pm_counts *counts, pm_model model,
-           int has_model, double *pred, const int64_t *meta, int64_t cap) {
+k_tail(const Prog *prog, const Job *jobs, const int32_t *clist, const int64_t *cend,
+       const int32_t *slist, const int64_t *send, const int32_t *dlist, const int64_t *varoff,
+       uint64_t *bitmap, int64_t *jobres, int64_t *foot, int64_t *vdone, int32_t *status,
+       pm_counts *counts, pm_model model, int has_model, double *pred, int64_t *meta,
+       int64_t cap, int64_t arena_words) {
     __shared__ FinShared fin;
-    __shared__ int64_t F[MAXARR], Fill[MAXARR];
-    const int t = threadIdx.x;
-    const int64_t nd = meta[M_DEFER] < cap ? meta[M_DEFER] : cap;
-    for (int64_t d = blockIdx.x; d < nd; d += gridDim.x) {
-        const int i = dlist[d];
-        if (t < MAXARR) {
-            F[t] = foot[((int64_t)i * MAXARR + t) * 2];
-            Fill[t] = foot[((int64_t)i * MAXARR + t) * 2 + 1];
+    __shared__ int64_t Fs[MAXARR], Fills[MAXARR];
+    const int l = threadIdx.x;
+    // this batch's totals (written by the expansion kernel, an earlier launch)
+    int64_t used = meta[M_USED] < arena_words ? meta[M_USED] : arena_words;
+    const int64_t Z = (used + ZERO_WORDS - 1) / ZERO_WORDS;
+    int64_t nc = (int64_t)((unsigned long long)meta[M_CHUNKS] >> LIST_POS);
+    if (nc > cap) nc = cap;
+    const int64_t C = nc ? cend[nc - 1] : 0;
+    int64_t ns = (int64_t)((unsigned long long)meta[M_SEGS] >> LIST_POS);
+    if (ns > cap) ns = cap;
+    const int64_t S = ns ? send[ns - 1] : 0;
+    const int64_t D = meta[M_DEFER] < cap ? meta[M_DEFER] : cap;
+    const int64_t total = Z + C + S + D;
+    if (total == 0) return;
+    for (;;) {
+        int64_t tk = 0;
+        if (l == 0)
+            tk = (int64_t)atomicAdd((unsigned long long *)&meta[M_TICKET], 1ull);
+        tk = __shfl(tk, 0);
+        if (tk >= total) return;
+        if (tk < Z) {  // clear
+            const int64_t w0 = tk * ZERO_WORDS;
+            const int64_t w1 = w0 + ZERO_WORDS < used ? w0 + ZERO_WORDS : used;
+            for (int64_t k = w0 + l; k < w1; k += 64) bitmap[k] = 0;
+            __syncthreads();
+            if (l == 0) signal(&meta[M_ZDONE]);
+            continue;
         }
-        __syncthreads();
-        const int s2 = finalize_block(prog[i], jobres + (int64_t)i * MAXJOB, F, Fill, PM_OK,
-                                      fin, counts ? &counts[i] : nullptr, model, has_model,
-                                      pred ? &pred[i] : nullptr);
-        if (t == 0) status[i] = s2;
-        __syncthreads();
+        tk -= Z;
+        if (tk < C) {  // chunk -> list entry -> variant -> job
+            const int64_t e = upper(cend, nc, tk);
+            const int64_t v = clist[e];
+            int64_t local = tk - (e ? cend[e - 1] : 0);
+            const int64_t *cum = prog[v].jobcum;
+            int jl = 0;
+            while (cum[jl] <= local) jl++;
+            local -= jl ? cum[jl - 1] : 0;
+            const int64_t j = v * MAXJOB + jl;
+            const Job &J = jobs[j];
+            const int64_t it0 = local * J.chunk_items;
+            const int64_t it1 = it0 + J.chunk_items < J.items ? it0 + J.chunk_items : J.items;
+            if (J.kind == JOB_COUNT) {
+                int64_t s = 0;
+                for (int64_t it = it0 + l; it < it1; it += 64) s += count_item(J, it);
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                if (l == 0 && s) atomicAdd((unsigned long long *)&jobres[j], (unsigned long long)s);
+            } else {
+                if (l == 0) wait_for(&meta[M_ZDONE], Z);
+                __syncthreads();
+                uint64_t *vb = bitmap + varoff[v];
+                for (int64_t it = it0; it < it1; it++) foot_item(J, it, vb, l, 64, DevOr{});
+            }
+            __syncthreads();
+            if (l == 0) signal(&vdone[2 * v]);
+            continue;
+        }
+        tk -= C;
+        if (tk < S) {  // fill segment
+            const int64_t le = upper(send, ns, tk);
+            const int64_t v = slist[le];
+            int64_t local = tk - (le ? send[le - 1] : 0);
+            const Prog &P = prog[v];
+            int al = 0;
+            while (P.arrcum[al] <= local) al++;
+            local -= al ? P.arrcum[al - 1] : 0;
+            if (l == 0) wait_for(&vdone[2 * v], P.chunks);
+            __syncthreads();
+            fill_segment(P, al, local, bitmap + varoff[v], foot + v * MAXARR * 2, l);
+            __syncthreads();
+            if (l == 0) signal(&vdone[2 * v + 1]);
+            continue;
+        }
+        tk -= S;
+        {  // finish variant dlist[tk]
+            const int i = dlist[tk];
+            const Prog &P = prog[i];
+            if (l == 0) {
+                wait_for(&vdone[2 * (int64_t)i], P.chunks);
+                wait_for(&vdone[2 * (int64_t)i + 1], P.segs);
+            }
+            __syncthreads();
+            if (l < MAXARR) {
+                Fs[l] = foot[((int64_t)i * MAXARR + l) * 2];
+                Fills[l] = foot[((int64_t)i * MAXARR + l) * 2 + 1];
+            }
+            __syncthreads();
+            const int s2 = finalize_block(P, jobres + (int64_t)i * MAXJOB, Fs, Fills, PM_OK, fin,
+                                          counts ? &counts[i] : nullptr, model, has_model,
+                                          pred ? &pred[i] : nullptr);
+            if (l == 0) status[i] = s2;
+            __syncthreads();
+        }
     }
 }
 
@@ -642,8 +673,8 @@ int launch_expand(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var, p
     int64_t *meta = ar.meta + META_WORDS * ar.parity;
     int64_t *meta_next = ar.meta + META_WORDS * (ar.parity ^ 1);
     ar.parity ^= 1;
-    const HandOn h{meta, meta_next, ar.varoff, ar.clist, ar.slist, ar.dlist, ar.cend, ar.send,
-                   (int64_t)ar.bitmap_words, (int64_t)ar.cap};
+    const HandOn h{meta, meta_next, ar.varoff, ar.vdone, ar.clist, ar.slist, ar.dlist, ar.cend,
+                   ar.send, (int64_t)ar.bitmap_words, (int64_t)ar.cap};
     if (ev && nmark > 0) (void)hipEventRecord(ev[0], s);
     if (nv <= FUSED_MAX_NV)
         hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
@@ -673,33 +704,22 @@ int launch_rest(Arena &ar, const Sched &sc, int nv, pm_counts *d_counts, const p
         m = *model;
         has = 1;
     }
-    const int64_t *meta = ar.meta + META_WORDS * (ar.parity ^ 1);  // the last expansion's
-    mark();  // the scan phase: work lists are claimed by atomics during the expansion
-    hipLaunchKernelGGL(k_clear, dim3(grid), dim3(256), 0, s, ar.bitmap, meta,
-                       (int64_t)ar.bitmap_words);
-    mark();
-    hipLaunchKernelGGL(k_count, dim3(grid), dim3(COUNT_THREADS), 0, s,
-                       (const Prog *)ar.prog, (const Job *)ar.jobs,
-                       (const int32_t *)ar.clist, (const int64_t *)ar.cend,
-                       (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, meta, (int64_t)ar.cap);
-    mark();
-    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(FILL_THREADS), 0, s,
-                       (const Prog *)ar.prog, (const int32_t *)ar.slist,
-                       (const int64_t *)ar.send, (const int64_t *)ar.varoff,
-                       (const uint64_t *)ar.bitmap, ar.foot, meta, (int64_t)ar.cap);
-    mark();
-    const int nfin = nv < grid ? nv : grid;
-    hipLaunchKernelGGL(k_finalize, dim3(nfin), dim3(64), 0, s, (const Prog *)ar.prog,
-                       (const int64_t *)ar.jobres, (const int64_t *)ar.foot,
-                       (const int32_t *)ar.dlist, d_status, d_counts, m, has, d_pred, meta,
-                       (int64_t)ar.cap);
+    int64_t *meta = ar.meta + META_WORDS * (ar.parity ^ 1);  // the last expansion's
+    mark();  // end of the gap between the kernels
+    // one-wavefront work-groups: 4 x tail_wgs_per_cu per CU
+    hipLaunchKernelGGL(k_tail, dim3(4 * grid), dim3(64), 0, s, (const Prog *)ar.prog,
+                       (const Job *)ar.jobs, (const int32_t *)ar.clist, (const int64_t *)ar.cend,
+                       (const int32_t *)ar.slist, (const int64_t *)ar.send,
+                       (const int32_t *)ar.dlist, (const int64_t *)ar.varoff, ar.bitmap,
+                       ar.jobres, ar.foot, ar.vdone, d_status, d_counts, m, has, d_pred, meta,
+                       (int64_t)ar.cap, (int64_t)ar.bitmap_words);
     mark();
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
 size_t arena_bytes_per_variant() {
     return sizeof(Prog) + sizeof(Job) * MAXJOB +
-           sizeof(int64_t) * (1 + 2 + MAXJOB + 2 * MAXARR) + sizeof(int32_t) * 3;
+           sizeof(int64_t) * (1 + 2 + 2 + MAXJOB + 2 * MAXARR) + sizeof(int32_t) * 3;
 }
 
 // ------------------------------------------------------- host execution ---

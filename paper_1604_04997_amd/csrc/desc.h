@@ -64,6 +64,8 @@ enum { JOB_NONE = 0, JOB_COUNT = 1, JOB_FOOT = 2 };
 // inner points handled by one footprint work item
 constexpr int64_t SEG_CONTIG = 16384;
 constexpr int64_t SEG_STRIDED = 1024;
+// bitmap words per fill segment (one wavefront of the chip-wide kernel)
+constexpr int64_t SEG_WORDS = 4096;
 // work items per chunk taken from the queue by one wavefront
 constexpr int64_t CHUNK_COUNT = 2048;
 constexpr int64_t CHUNK_FOOT = 4;
@@ -1477,7 +1479,7 @@ PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj) {
         } else {
             A.b_off = A.f_off;
         }
-        A.segs = cdiv(A.words, 4096);
+        A.segs = cdiv(A.words, SEG_WORDS);
         for (int j = 0; j < nj; j++) {
             Job &J = jobs[j];
             if (J.kind != JOB_FOOT || J.arr != ai) continue;

@@ -8,6 +8,7 @@ sums, single-rounding FMA chains, the stencil), within stated error bounds
 otherwise (matmul, n-body, rsqrt)."""
 import ctypes
 import math
+import os
 
 import numpy as np
 import pytest
@@ -18,6 +19,7 @@ from oracle import outputs as O
 from synth import suite_batched, suite_instructive, suite_test, suite_tiny, uniform
 
 from closed_forms import counts as closed_counts
+from golden.make_sweep_counts import variants_digest as sweep_digest
 from test_lib_host import FAMILY_CASES, FILLED_SC
 
 pytestmark = pytest.mark.gpu
@@ -89,6 +91,13 @@ def test_bench_workload_on_the_device_path(ctx):
     for k, v in enumerate(vs):
         for name, x in closed_counts(v).items():
             want[k, names.index(name)] = x
+    # the oracle's enumeration of the same 4096 variants, stored by
+    # tests/golden/make_sweep_counts.py (CPU only)
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "sweep4096_counts.npz"))
+    assert str(gold["digest"]) == sweep_digest(vs) and gold["done"].all()
+    oracle = np.zeros((nv, P.PM_NCOUNT), dtype=np.int64)
+    for col, name in enumerate(gold["names"]):
+        oracle[:, names.index(str(name))] = gold["counts"][:, col]
     pred = None
     default = ctx.schedule()
     try:
@@ -102,6 +111,7 @@ def test_bench_workload_on_the_device_path(ctx):
             assert (d_s.cpu() == 0).all()
             got = d_c.cpu().numpy()
             np.testing.assert_array_equal(got, want)
+            np.testing.assert_array_equal(got, oracle)  # row by row, bit for bit
             if pred is None:
                 arr = ctx.count_raw(vs)
                 pred = np.array([P.features(arr[i], "ext") @ alpha for i in range(nv)])

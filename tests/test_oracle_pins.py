@@ -507,3 +507,25 @@ def test_stream_touched_elements():
     v = dict(n=4, wg=2, s=1, gs=1, vec=2, U=2)
     assert list(O.stream_elements(v)) == [0, 1, 2, 3, 4, 5, 6, 7,
                                           8, 9, 10, 11, 12, 13, 14, 15]
+
+
+def test_sweep_golden_file_matches_generator_and_closed_forms():
+    """The stored oracle enumeration of the 4096-variant sweep (written by
+    tests/golden/make_sweep_counts.py from oracle/ alone) belongs to the
+    current variant generator, is complete, and agrees with the closed
+    forms on every variant at its full size (2^16..2^30 domain points): the
+    simulated execution and the hand-derived counts agree where no small
+    case reaches."""
+    import os
+    from golden.make_sweep_counts import variants_digest
+    from synth import suite_batched
+    from closed_forms import counts as closed
+    vs = suite_batched(4096)
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "sweep4096_counts.npz"))
+    assert str(g["digest"]) == variants_digest(vs)
+    assert g["done"].all()
+    names = [str(x) for x in g["names"]]
+    assert names == [x for x in C.names() if not x.startswith("foot.")]
+    for k, v in enumerate(vs):
+        got = {nm: int(x) for nm, x in zip(names, g["counts"][k]) if x}
+        assert got == closed(v), (k, v)
