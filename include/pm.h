@@ -219,6 +219,29 @@ pm_status pm_count_device(pm_ctx *ctx, const pm_variant *d_v, size_t nv,
                           pm_counts *d_counts, const pm_model *m, double *d_t,
                           int32_t *d_status, void *hip_stream);
 
+/*
+ * pm_count_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the counter's working
+ * memory in a fixed device array of the library (about 40 MB on every
+ * device it runs on, held until the process ends) instead of the
+ * context's arena.  Allocates nothing: no hipMalloc, hipFree or
+ * allocating library call.  Arguments as pm_count_device; at most
+ * PM_NOALLOC_MAX_VARIANTS variants (else PM_EINVAL, nothing enqueued);
+ * variants whose footprint bitmaps do not fit in PM_NOALLOC_BITMAP_BYTES
+ * (together with those of the variants before them in the batch) get
+ * status PM_ENOMEM.  Every call on one GPU uses that GPU's one array: calls
+ * that may overlap on the device (different streams with no order between
+ * them) race, and the caller must order them.  The array keeps the last
+ * call's contents; what a batch needs cleared it clears itself.  Asynchronous
+ * on `hip_stream`, like pm_count_device.
+ */
+#define PM_NOALLOC_MAX_VARIANTS 1024
+#define PM_NOALLOC_BITMAP_BYTES (16u << 20)
+pm_status pm_count_device_noalloc(pm_ctx *ctx, const pm_variant *d_v, size_t nv,
+                                  pm_counts *d_counts, const pm_model *m, double *d_t,
+                                  int32_t *d_status, void *hip_stream);
+
 /* Size the context's device arenas for batches of up to nv variants whose
  * footprint bitmaps total up to bitmap_bytes.  Fails with PM_ENOMEM beyond
  * the HBM budget. */

@@ -20,6 +20,7 @@ PM_NCOUNT = 112
 PM_NFEAT_MAX = 160
 PM_MAXBUF = 8
 PM_BATCH_MAX = 65536
+PM_NOALLOC_MAX_VARIANTS = 1024
 PROJ = {"p3": 0, "p12": 1, "full": 2, "ext": 3}
 NFEAT = {"p3": 3, "p12": 12, "full": 154, "ext": 157}
 
@@ -99,6 +100,7 @@ def lib():
             "pm_count": (ctypes.c_int, [vp, P(Variant), ctypes.c_size_t, P(Counts)]),
             "pm_predict": (ctypes.c_int, [vp, P(Model), P(Variant), ctypes.c_size_t, P(ctypes.c_double)]),
             "pm_count_device": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, P(Model), vp, vp, vp]),
+            "pm_count_device_noalloc": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, P(Model), vp, vp, vp]),
             "pm_reserve": (ctypes.c_int, [vp, ctypes.c_size_t, ctypes.c_size_t]),
             "pm_bitmap_bytes": (ctypes.c_int, [P(Variant), P(ctypes.c_size_t)]),
             "pm_features": (ctypes.c_int, [P(Counts), ctypes.c_uint32, P(ctypes.c_double), P(ctypes.c_uint32)]),
@@ -347,6 +349,17 @@ class Context:
         """Device-resident batched count (+ predict), asynchronous on the
         given stream; all pointers are device addresses (ints)."""
         _check(lib().pm_count_device(
+            self._h, ctypes.c_void_p(d_variants_ptr), nv,
+            ctypes.c_void_p(d_counts_ptr) if d_counts_ptr else None,
+            ctypes.byref(model) if model is not None else None,
+            ctypes.c_void_p(d_t_ptr) if d_t_ptr else None,
+            ctypes.c_void_p(d_status_ptr), ctypes.c_void_p(stream_ptr)))
+
+    def count_device_noalloc(self, d_variants_ptr, nv, d_counts_ptr, model, d_t_ptr,
+                             d_status_ptr, stream_ptr):
+        """pm_count_device_noalloc: count_device with the library's fixed
+        device array as working memory (no allocation)."""
+        _check(lib().pm_count_device_noalloc(
             self._h, ctypes.c_void_p(d_variants_ptr), nv,
             ctypes.c_void_p(d_counts_ptr) if d_counts_ptr else None,
             ctypes.byref(model) if model is not None else None,

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -135,6 +136,90 @@ struct pm_ctx {
         return &pev[(size_t)(pcount++) * (PM_NPHASE + 1)];
     }
 };
+
+// ------------------------------------------------ allocation-free path ---
+// pm_count_device_noalloc runs the batched counter in `scratch`, a
+// file-scope device array that every device the library runs on holds
+// until the process ends, laid out as a counter arena (the one pm_ctx
+// allocates for pm_count_device) for PM_NOALLOC_MAX_VARIANTS variants and
+// PM_NOALLOC_BITMAP_BYTES of footprint bitmaps.  In host code `scratch`
+// names a host-side stand-in, not the device array: its device address is
+// looked up once per device (hipGetSymbolAddress, in pm_create) and only
+// that address is used.
+namespace noalloc {
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t CAP = PM_NOALLOC_MAX_VARIANTS;
+constexpr size_t OFF_META = 0;
+constexpr size_t OFF_PROG = align256(OFF_META + 16 * pm::META_WORDS);
+constexpr size_t OFF_JOBS = align256(OFF_PROG + sizeof(pm::Prog) * CAP);
+constexpr size_t OFF_VAROFF = align256(OFF_JOBS + sizeof(pm::Job) * CAP * pm::MAXJOB);
+constexpr size_t OFF_CLIST = align256(OFF_VAROFF + 8 * CAP);
+constexpr size_t OFF_CEND = align256(OFF_CLIST + 4 * CAP);
+constexpr size_t OFF_SLIST = align256(OFF_CEND + 8 * CAP);
+constexpr size_t OFF_SEND = align256(OFF_SLIST + 4 * CAP);
+constexpr size_t OFF_DLIST = align256(OFF_SEND + 8 * CAP);
+constexpr size_t OFF_JOBRES = align256(OFF_DLIST + 4 * CAP);
+constexpr size_t OFF_FOOT = align256(OFF_JOBRES + 8 * CAP * pm::MAXJOB);
+constexpr size_t OFF_VDONE = align256(OFF_FOOT + 16 * CAP * pm::MAXARR);
+constexpr size_t OFF_BITMAP = align256(OFF_VDONE + 16 * CAP);
+constexpr size_t BYTES = OFF_BITMAP + PM_NOALLOC_BITMAP_BYTES;
+
+static __device__ __align__(256) uint8_t scratch[BYTES];
+
+constexpr int MAX_DEVICES = 64;
+struct Dev {
+    uint8_t *ptr = nullptr;  // device address of `scratch` on this device
+    int parity = 0;          // meta half of the next batch
+};
+Dev g_dev[MAX_DEVICES];
+std::mutex g_mu;
+
+__global__ void k_zero(int64_t *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// Once per device, with that device current: the array's device address,
+// and its two list-counter halves cleared (a fill kernel on `s`).
+int setup(int dev, hipStream_t s) {
+    if (dev < 0 || dev >= MAX_DEVICES) return set_err(PM_EDEVICE, "device number too large");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_dev[dev].ptr) return PM_OK;
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return set_err(PM_EDEVICE, "no device address for the scratch array");
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, (int64_t *)((uint8_t *)ptr + OFF_META),
+                       2 * pm::META_WORDS);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    g_dev[dev].ptr = (uint8_t *)ptr;
+    g_dev[dev].parity = 0;
+    return PM_OK;
+}
+
+// The arena inside the array at device address `base`.
+pm::Arena arena(uint8_t *base, int parity) {
+    pm::Arena a;
+    a.cap = CAP;
+    a.bitmap_words = PM_NOALLOC_BITMAP_BYTES / 8;
+    a.parity = parity;
+    a.meta = (int64_t *)(base + OFF_META);
+    a.prog = (pm::Prog *)(base + OFF_PROG);
+    a.jobs = (pm::Job *)(base + OFF_JOBS);
+    a.varoff = (int64_t *)(base + OFF_VAROFF);
+    a.clist = (int32_t *)(base + OFF_CLIST);
+    a.cend = (int64_t *)(base + OFF_CEND);
+    a.slist = (int32_t *)(base + OFF_SLIST);
+    a.send = (int64_t *)(base + OFF_SEND);
+    a.dlist = (int32_t *)(base + OFF_DLIST);
+    a.jobres = (int64_t *)(base + OFF_JOBRES);
+    a.foot = (int64_t *)(base + OFF_FOOT);
+    a.vdone = (int64_t *)(base + OFF_VDONE);
+    a.bitmap = (uint64_t *)(base + OFF_BITMAP);
+    return a;
+}
+
+}  // namespace noalloc
 
 namespace {
 
@@ -479,6 +564,7 @@ pm_status pm_create(pm_ctx **out, int device, size_t budget) {
         return (pm_status)set_err(PM_EDEVICE, "stream creation failed");
     if (hipEventCreateWithFlags(&c->arena_done, hipEventDisableTiming) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "event creation failed");
+    if (noalloc::setup(device, c->stream) != PM_OK) return PM_EDEVICE;
     if (hipHostMalloc(&c->h_meta, 8 * pm::META_WORDS, 0) != hipSuccess)
         return (pm_status)set_err(PM_EDEVICE, "pinned allocation failed");
     const unsigned zf = hipHostMallocMapped | hipHostMallocCoherent;
@@ -566,6 +652,29 @@ pm_status pm_count_device(pm_ctx *c, const pm_variant *d_v, size_t nv, pm_counts
                           c->next_events(), c->nmarks());
     if (st) return (pm_status)set_err(st, "counter launch failed");
     return (pm_status)arena_leave(c, s);
+}
+
+pm_status pm_count_device_noalloc(pm_ctx *c, const pm_variant *d_v, size_t nv,
+                                  pm_counts *d_counts, const pm_model *m, double *d_t,
+                                  int32_t *d_status, void *stream) {
+    if (!c || (!d_v && nv) || (!d_status && nv)) return (pm_status)set_err(PM_EINVAL, "null argument");
+    if (nv > PM_NOALLOC_MAX_VARIANTS)
+        return (pm_status)set_err(PM_EINVAL, "batch of " + std::to_string(nv) +
+                                                 " variants exceeds PM_NOALLOC_MAX_VARIANTS (" +
+                                                 std::to_string(PM_NOALLOC_MAX_VARIANTS) + ")");
+    if (m && (pm::nfeat(m->proj) < 0 || (int)m->nfeat != pm::nfeat(m->proj)))
+        return (pm_status)set_err(PM_EINVAL, "model projection / feature count mismatch");
+    if (nv == 0) return PM_OK;
+    if (c->device < 0 || c->device >= noalloc::MAX_DEVICES || !noalloc::g_dev[c->device].ptr)
+        return (pm_status)set_err(PM_EDEVICE, "scratch array not set up on this device");
+    DeviceGuard g(c->device);
+    noalloc::Dev &D = noalloc::g_dev[c->device];
+    pm::Arena ar = noalloc::arena(D.ptr, D.parity);
+    const int st = pm::launch_batch(ar, c->sched, (int)nv, d_v, d_counts, (m && d_t) ? m : nullptr,
+                                    d_t, d_status, (hipStream_t)stream, c->n_cu, nullptr, 0);
+    D.parity = ar.parity;  // the launch flipped it
+    if (st) return (pm_status)set_err(st, "counter launch failed");
+    return PM_OK;
 }
 
 pm_status pm_reserve(pm_ctx *c, size_t nv, size_t bitmap_bytes) {
