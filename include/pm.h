@@ -271,10 +271,10 @@ pm_status pm_get_schedule(pm_ctx *ctx, pm_schedule *s);
 
 /* Per-kernel timing of the batched counter.  pm_profile(ctx, 1) starts a
  * timing window (pm_profile(ctx, 2): the same with events around the
- * expansion kernel only, ms[0]; every recorded event adds a few
- * microseconds to a batch): every batch until pm_profile_read (at most
- * PM_PROFILE_MAX batches) records HIP events around each of its three
- * phases on the stream they run on: ms[0] the expansion kernel
+ * expansion kernel only, ms[0]): every batch until pm_profile_read (at most
+ * PM_PROFILE_MAX batches) takes HIP events at the start and end of its
+ * kernels, recorded by the kernels' own dispatches (no packets of their
+ * own on the stream), which bound its three phases: ms[0] the expansion kernel
  * (per-variant expansion, count and finish), ms[1] the time between the two
  * kernels (empty on the device path; in the synchronous host calls the
  * host's read of the expansion's statuses), ms[2] the chip-wide kernel for

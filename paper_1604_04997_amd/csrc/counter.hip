@@ -22,6 +22,7 @@
 //               to its run of stride*vec cells); the count vector and
 //               prediction of each variant -- each item after the ones it
 //               needs (per-variant completion counters)
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -56,16 +57,19 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
     }
     __syncthreads();
     if (sh[0] != PM_OK) return sh[0];
+    auto temp = [&]() -> Job * {
+        const int k = atomicAdd(&sh[1 + MAXSTMT], 1);
+        return k < NTEMP ? &jt[k] : nullptr;
+    };
     if (t < p->nstmt) {
         int made;
-        auto temp = [&]() -> Job * {
-            const int k = atomicAdd(&sh[1 + MAXSTMT], 1);
-            return k < NTEMP ? &jt[k] : nullptr;
-        };
         sh[1 + t] = analyze_stmt(p, t, jobs, temp, 2 * t, 2 * t + 2, PM_SEQ, &made);
     }
     __syncthreads();
-    if (t == 0) sh[0] = build_slots_finish(v, p, jobs, &jt[0], sh + 1);
+    if (t == 0) {
+        sh[1 + MAXSTMT] = 0;  // the fallback hands the buffers out again
+        sh[0] = build_slots_finish_seq(v, p, jobs, temp, sh + 1);
+    }
     __syncthreads();
     return sh[0];
 }
@@ -338,28 +342,27 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
         }
         __syncthreads();
     }
-    if (ncj >= 0 || st != PM_OK) {  // finished here (or failed: zero outputs)
-        const int s2 = finalize_block(P, jr, zero, zero, st, U.fin,
-                                      counts ? &counts[i] : nullptr, model, has_model,
-                                      pred ? &pred[i] : nullptr);
-        if (t == 0) status[i] = s2;
-        return;
+    int sfin = st;  // finished here, or failed: zero outputs
+    if (ncj < 0 && st == PM_OK) {  // handed on
+        if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
+        if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
+        // the program to HBM: header and used statements
+        const int ns = P.nstmt < MAXSTMT ? P.nstmt : MAXSTMT;
+        const size_t words = (offsetof(Prog, st) + (size_t)ns * sizeof(Stmt)) / 8;
+        const uint64_t *src = (const uint64_t *)&P;
+        uint64_t *dst = (uint64_t *)&prog[i];
+        for (size_t w = t; w < words; w += 64) dst[w] = src[w];
+        if (t == 0) sh[0] = hand_on(P, i, h);
+        __syncthreads();
+        sfin = sh[0];
+        if (sfin == PM_DEFER) {
+            if (t == 0) status[i] = sfin;
+            return;
+        }
     }
-    if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
-    if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
-    // the program to HBM: header and used statements
-    const int ns = P.nstmt < MAXSTMT ? P.nstmt : MAXSTMT;
-    const size_t words = (offsetof(Prog, st) + (size_t)ns * sizeof(Stmt)) / 8;
-    const uint64_t *src = (const uint64_t *)&P;
-    uint64_t *dst = (uint64_t *)&prog[i];
-    for (size_t w = t; w < words; w += 64) dst[w] = src[w];
-    if (t == 0) sh[0] = hand_on(P, i, h);
-    __syncthreads();
-    const int sd = sh[0];
-    if (t == 0) status[i] = sd;
-    if (sd != PM_DEFER)
-        finalize_block(P, jr, zero, zero, sd, U.fin, counts ? &counts[i] : nullptr, model,
-                       has_model, pred ? &pred[i] : nullptr);
+    const int s2 = finalize_block(P, jr, zero, zero, sfin, U.fin, counts ? &counts[i] : nullptr,
+                                  model, has_model, pred ? &pred[i] : nullptr);
+    if (t == 0) status[i] = s2;
 }
 
 // Sum of x over the work-group (FUSED_THREADS threads); all threads get it.
@@ -675,16 +678,17 @@ int launch_expand(Arena &ar, const Sched &sc, int nv, const pm_variant *d_var, p
     ar.parity ^= 1;
     const HandOn h{meta, meta_next, ar.varoff, ar.vdone, ar.clist, ar.slist, ar.dlist, ar.cend,
                    ar.send, (int64_t)ar.bitmap_words, (int64_t)ar.cap};
-    if (ev && nmark > 0) (void)hipEventRecord(ev[0], s);
+    // profiling events are taken by the dispatch itself (no extra packets
+    // on the stream): start and end of the kernel
+    hipEvent_t e0 = ev && nmark > 0 ? ev[0] : nullptr, e1 = ev && nmark > 1 ? ev[1] : nullptr;
     if (nv <= FUSED_MAX_NV)
-        hipLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, nv, d_var,
-                           ar.prog, ar.jobs, d_status, ar.jobres, ar.foot, h, d_counts, m,
-                           has, d_pred, sc.fused_items);
+        hipExtLaunchKernelGGL(k_fused, dim3(nv), dim3(FUSED_THREADS), 0, s, e0, e1, 0, nv, d_var,
+                              ar.prog, ar.jobs, d_status, ar.jobres, ar.foot, h, d_counts, m,
+                              has, d_pred, sc.fused_items);
     else
-        hipLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, nv, d_var, ar.prog, ar.jobs,
-                           d_status, ar.jobres, ar.foot, h, d_counts, m, has, d_pred,
-                           sc.inblock_items);
-    if (ev && nmark > 1) (void)hipEventRecord(ev[1], s);
+        hipExtLaunchKernelGGL(k_build, dim3(nv), dim3(64), 0, s, e0, e1, 0, nv, d_var, ar.prog,
+                              ar.jobs, d_status, ar.jobres, ar.foot, h, d_counts, m, has, d_pred,
+                              sc.inblock_items);
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
@@ -693,11 +697,6 @@ int launch_rest(Arena &ar, const Sched &sc, int nv, pm_counts *d_counts, const p
                 int nmark) {
     if (nv <= 0) return PM_OK;
     const int grid = n_cu * sc.tail_wgs_per_cu;
-    int q = 2;
-    auto mark = [&]() {
-        if (ev && q < nmark) (void)hipEventRecord(ev[q], s);
-        q++;
-    };
     pm_model m{};
     int has = 0;
     if (model) {
@@ -705,15 +704,16 @@ int launch_rest(Arena &ar, const Sched &sc, int nv, pm_counts *d_counts, const p
         has = 1;
     }
     int64_t *meta = ar.meta + META_WORDS * (ar.parity ^ 1);  // the last expansion's
-    mark();  // end of the gap between the kernels
-    // one-wavefront work-groups: 4 x tail_wgs_per_cu per CU
-    hipLaunchKernelGGL(k_tail, dim3(4 * grid), dim3(64), 0, s, (const Prog *)ar.prog,
-                       (const Job *)ar.jobs, (const int32_t *)ar.clist, (const int64_t *)ar.cend,
-                       (const int32_t *)ar.slist, (const int64_t *)ar.send,
-                       (const int32_t *)ar.dlist, (const int64_t *)ar.varoff, ar.bitmap,
-                       ar.jobres, ar.foot, ar.vdone, d_status, d_counts, m, has, d_pred, meta,
-                       (int64_t)ar.cap, (int64_t)ar.bitmap_words);
-    mark();
+    // one-wavefront work-groups: 4 x tail_wgs_per_cu per CU; events (taken
+    // by the dispatch) at its start and end
+    hipEvent_t e2 = ev && nmark > 2 ? ev[2] : nullptr, e3 = ev && nmark > 3 ? ev[3] : nullptr;
+    hipExtLaunchKernelGGL(k_tail, dim3(4 * grid), dim3(64), 0, s, e2, e3, 0, (const Prog *)ar.prog,
+                          (const Job *)ar.jobs, (const int32_t *)ar.clist,
+                          (const int64_t *)ar.cend, (const int32_t *)ar.slist,
+                          (const int64_t *)ar.send, (const int32_t *)ar.dlist,
+                          (const int64_t *)ar.varoff, ar.bitmap, ar.jobres, ar.foot, ar.vdone,
+                          d_status, d_counts, m, has, d_pred, meta, (int64_t)ar.cap,
+                          (int64_t)ar.bitmap_words);
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 

@@ -151,6 +151,11 @@ struct Job {
 };
 
 // ------------------------------------------------------------- helpers ---
+// Out of line: the rare 64-bit division stays out of the expansion
+// kernels' hot code (which must fit the instruction cache).
+#define PM_COLD __host__ __device__ __attribute__((noinline)) inline
+PM_COLD int64_t div64_slow(int64_t a, int64_t b) { return a / b; }
+
 PM_HD bool mul_ovf(int64_t a, int64_t b, int64_t *r) {
     // both factors within 32 bits (the usual case): the product fits
     if ((uint64_t)a + 0x80000000ull < 0x100000000ull &&
@@ -167,7 +172,7 @@ PM_HD bool add_ovf(int64_t a, int64_t b, int64_t *r) {
 // which is far shorter than the 64-bit sequence on the GPU.
 PM_HD int64_t tdiv(int64_t a, int64_t b) {
     if (a == (int32_t)a && b == (int32_t)b && b != -1) return (int32_t)a / (int32_t)b;
-    return a / b;
+    return div64_slow(a, b);
 }
 PM_HD int64_t cdiv(int64_t a, int64_t b) { return tdiv(a + b - 1, b); }
 // floor(a / b) and ceil(a / b) for b > 0, any sign of a
@@ -1253,9 +1258,8 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
         if (nj >= cap) return over;
         if (s.ncomp >= MAXCOMP) return PM_EINVAL;
         if (!asked) jt = temp(), asked = true;
-        // the job, assembled in a fast buffer when one was given (a call per
-        // memory, so each knows where J lives): 1 made, 0 an interval (its
-        // count in c), < 0 a status
+        // the job, assembled in a fast buffer when one was given, else in
+        // its slot: 1 made, 0 an interval (its count in c), < 0 a status
         auto count_job = [&](Job &J) __attribute__((always_inline)) -> int {
             J.kind = JOB_COUNT;
             J.nv = 0;
@@ -1325,7 +1329,8 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
             J.ivok = 0;
             return 1;
         };
-        const int rj = jt ? count_job(*jt) : count_job(jobs[nj]);
+        Job &Jc = jt ? *jt : jobs[nj];  // one copy of the builder for both memories
+        const int rj = count_job(Jc);
         if (rj < 0) return rj;
         if (rj == 0) {
             if (mul_ovf(fixed, c, &fixed)) return PM_EOVERFLOW;
@@ -1433,7 +1438,8 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
             if (J.ivok) J.ivst = ival_sizes(J, &J.ivF, &J.ivFill);
             return 1;
         };
-        const int rf = jt ? foot_job(*jt) : foot_job(jobs[nj]);
+        Job &Jf = jt ? *jt : jobs[nj];
+        const int rf = foot_job(Jf);
         if (rf < 0) return rf;
         if (jt) put_job(&jobs[nj], *jt);
         nj++;
@@ -1534,6 +1540,38 @@ PM_HD int build_slots_finish(const pm_variant &v, Prog *p, Job *jobs, Job *jt, c
     const int ns = p->nstmt;
     for (int si = 0; si < ns; si++) {
         if (r[si] == PM_SEQ) return build_prog(v, p, jobs, jt);
+        if (r[si] != PM_OK) return p->status = r[si];
+    }
+    return build_tail(v, p, jobs, 2 * ns);
+}
+
+// The sequential re-analysis build_slots_finish falls back to, on a
+// program whose statements are already laid out (build_head ran): job
+// slots compact from 0, each statement analysed in order with the same
+// temp() as the per-statement pass (so both share one analyze_stmt).
+template <class TEMP>
+PM_HD int build_seq(const pm_variant &v, Prog *p, Job *jobs, TEMP temp) {
+    for (int j = 0; j < MAXJOB; j++) {
+        jobs[j].kind = JOB_NONE;
+        jobs[j].chunks = 0;
+    }
+    int nj = 0;
+    for (int si = 0; si < p->nstmt; si++) {
+        int k;
+        const int st = analyze_stmt(p, si, jobs, temp, nj, MAXJOB, PM_EINVAL, &k);
+        if (st != PM_OK) return p->status = st;
+        nj += k;
+    }
+    return build_tail(v, p, jobs, nj);
+}
+
+// build_slots_finish with the fallback through build_seq.
+template <class TEMP>
+PM_HD int build_slots_finish_seq(const pm_variant &v, Prog *p, Job *jobs, TEMP temp,
+                                 const int *r) {
+    const int ns = p->nstmt;
+    for (int si = 0; si < ns; si++) {
+        if (r[si] == PM_SEQ) return build_seq(v, p, jobs, temp);
         if (r[si] != PM_OK) return p->status = r[si];
     }
     return build_tail(v, p, jobs, 2 * ns);
