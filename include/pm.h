@@ -292,6 +292,10 @@ pm_status pm_get_schedule(pm_ctx *ctx, pm_schedule *s);
 #define PM_NPHASE 3
 #define PM_PROFILE_MAX 4096
 pm_status pm_profile(pm_ctx *ctx, int enable);
+/* Events on one batch in `every` (>= 1, default 1) of a timing window, so
+ * that a long run of batches carries the events' cost on a few of them
+ * only; the means pm_profile_read gives are over the batches recorded. */
+pm_status pm_profile_sample(pm_ctx *ctx, int every);
 pm_status pm_profile_read(pm_ctx *ctx, double *ms, int *nbatch);
 pm_status pm_batch_stats(pm_ctx *ctx, int64_t *stats);
 

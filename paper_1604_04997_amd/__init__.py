@@ -119,6 +119,7 @@ def lib():
             "pm_count_host_seq": (ctypes.c_int, [P(Variant), P(Counts), P(ctypes.c_int64)]),
             "pm_profile": (ctypes.c_int, [vp, ctypes.c_int]),
             "pm_profile_read": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int)]),
+            "pm_profile_sample": (ctypes.c_int, [vp, ctypes.c_int]),
             "pm_batch_stats": (ctypes.c_int, [vp, P(ctypes.c_int64)]),
             "pm_set_schedule": (ctypes.c_int, [vp, P(Schedule)]),
             "pm_get_schedule": (ctypes.c_int, [vp, P(Schedule)]),
@@ -309,6 +310,10 @@ class Context:
         """True / 1: events around every phase; 2: around the expansion
         kernel only (the lightest); False / 0: off."""
         _check(lib().pm_profile(self._h, int(enable)))
+
+    def profile_sample(self, every: int):
+        """Events on one batch in `every` of the timing window."""
+        _check(lib().pm_profile_sample(self._h, int(every)))
 
     def profile_read(self):
         """({kernel: mean milliseconds}, batches) since profiling started."""

@@ -126,3 +126,69 @@ def tune_counter(ctx, step, candidates=None, warmup: int = 2, reps: int = 10):
     chosen = min(table, key=lambda r: r[1])[0]
     ctx.set_schedule(**chosen)
     return chosen, table
+
+
+def schedule_features(ctx, step, sched, n_cu: int = 256):
+    """Properties of one counter pass under `sched` (the counter's own
+    count vector, read from one untimed pass): 1, variants handed on to the
+    chip-wide kernel, its work chunks, fill segments and bitmap words, and
+    the chip-wide kernel's one-wavefront work-groups."""
+    import torch
+    ctx.set_schedule(**sched)
+    step()
+    torch.cuda.synchronize()
+    st = ctx.batch_stats()
+    wgs = 4 * n_cu * ctx.schedule()["tail_wgs_per_cu"]
+    return np.array([1.0, st["handed_on"], st["chunks"], st["fill_segments"],
+                     st["bitmap_words"], wgs], dtype=np.float64)
+
+
+def _time_pass(step, warmup, reps):
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for _ in range(warmup):
+        step()
+    for e0, e1 in ev:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    return min(e0.elapsed_time(e1) for e0, e1 in ev)
+
+
+def tune_counter_model(ctx, step, candidates=None, n_timed: int = 8, warmup: int = 2,
+                       reps: int = 10, n_cu: int = 256):
+    """The counter's schedule ranked by a linear model of its own pass time
+    (the method of Sec. 4.3 applied to the counter): every candidate's
+    properties come from one untimed pass; `n_timed` candidates spread over
+    the list are timed; T = sum_i a_i f_i is fitted to them by relative-error
+    least squares in FP64; every candidate is predicted and the predicted
+    fastest is set on `ctx` and timed.  Returns (chosen, report)."""
+    cands = candidates or COUNTER_SCHEDULES
+    F = np.array([schedule_features(ctx, step, sc, n_cu) for sc in cands])
+    idx = sorted(set(np.linspace(0, len(cands) - 1, min(n_timed, len(cands))).round().astype(int)))
+    T = {}
+    for i in idx:
+        ctx.set_schedule(**cands[i])
+        T[i] = _time_pass(step, warmup, reps)
+    A = F[idx] / np.array([T[i] for i in idx])[:, None]
+    keep = np.abs(A).sum(axis=0) > 0
+    alpha = np.zeros(F.shape[1])
+    alpha[keep] = np.linalg.lstsq(A[:, keep], np.ones(len(idx)), rcond=None)[0]
+    pred = F @ alpha
+    best = int(np.argmin(pred))
+    chosen = ctx.set_schedule(**cands[best])
+    t_best = T.get(best)
+    if t_best is None:
+        t_best = _time_pass(step, warmup, reps)
+    timed_fast = min(T, key=T.get)
+    rp = np.argsort(np.argsort([pred[i] for i in idx]))
+    rm = np.argsort(np.argsort([T[i] for i in idx]))
+    report = {"timed": [[cands[i]["inblock_items"], cands[i]["tail_wgs_per_cu"],
+                         round(T[i], 4), round(float(pred[i]), 4)] for i in idx],
+              "chosen_ms": round(t_best, 4), "fastest_timed_ms": round(T[timed_fast], 4),
+              "spearman_timed": float(np.corrcoef(rp, rm)[0, 1]) if len(idx) > 2 else None,
+              "passes": len(cands) + len(idx) * (warmup + reps) +
+                        (0 if best in T else warmup + reps)}
+    return chosen, report

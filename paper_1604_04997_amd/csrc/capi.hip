@@ -124,9 +124,12 @@ struct pm_ctx {
     int profile = 0;  // 0 off, 1 every phase, 2 the expansion kernel only
     std::vector<hipEvent_t> pev;  // (PM_NPHASE + 1) per recorded batch
     int pcount = 0;
+    int pevery = 1;      // events on one batch in pevery
+    int64_t pseen = 0;   // batches since the window opened
     int nmarks() const { return profile == 2 ? 2 : PM_NPHASE + 1; }
     hipEvent_t *next_events() {
         if (!profile || pcount >= PM_PROFILE_MAX) return nullptr;
+        if (pseen++ % pevery != 0) return nullptr;
         size_t need = (size_t)(pcount + 1) * (PM_NPHASE + 1);
         while (pev.size() < need) {
             hipEvent_t e;
@@ -691,6 +694,14 @@ pm_status pm_profile(pm_ctx *c, int enable) {
     if (enable < 0 || enable > 2) return (pm_status)set_err(PM_EINVAL, "profile mode is 0, 1 or 2");
     c->profile = enable;
     c->pcount = 0;
+    c->pseen = 0;
+    return PM_OK;
+}
+
+pm_status pm_profile_sample(pm_ctx *c, int every) {
+    if (!c || every < 1) return (pm_status)set_err(PM_EINVAL, "sampling period is at least 1");
+    c->pevery = every;
+    c->pseen = 0;
     return PM_OK;
 }
 
@@ -736,6 +747,7 @@ pm_status pm_profile_read(pm_ctx *c, double *ms, int *nbatch) {
         for (int i = 0; i < PM_NPHASE; i++) ms[i] /= n;
     if (nbatch) *nbatch = n;
     c->pcount = 0;
+    c->pseen = 0;
     return PM_OK;
 }
 

@@ -43,10 +43,12 @@ constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 // statement si in job slots 2si and 2si+1, thread 0 finishes
 // (build_slots_finish).  p and the NTEMP job buffers jt are in LDS, handed
 // to the first statements that make jobs (the others make theirs in
-// place); sh holds 2 + MAXSTMT ints.
+// place); with `keep` (= jt) each statement's last job stays in its buffer
+// (p->jtmp) instead of going to its slot in `jobs`; sh holds 2 + MAXSTMT
+// ints.
 constexpr int NTEMP = 4;
 __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jobs, Job *jt,
-                                           int *sh) {
+                                           int *sh, Job *keep) {
     const int t = threadIdx.x;
     if (t < 64) {  // the first wavefront lays out the statements, all lanes together
         const int st = build_head<LaneAff>(v, p, jobs);
@@ -63,12 +65,12 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
     };
     if (t < p->nstmt) {
         int made;
-        sh[1 + t] = analyze_stmt(p, t, jobs, temp, 2 * t, 2 * t + 2, PM_SEQ, &made);
+        sh[1 + t] = analyze_stmt(p, t, jobs, temp, 2 * t, 2 * t + 2, PM_SEQ, &made, keep);
     }
     __syncthreads();
     if (t == 0) {
         sh[1 + MAXSTMT] = 0;  // the fallback hands the buffers out again
-        sh[0] = build_slots_finish_seq(v, p, jobs, temp, sh + 1);
+        sh[0] = build_slots_finish_seq(v, p, jobs, temp, sh + 1, keep);
     }
     __syncthreads();
     return sh[0];
@@ -290,7 +292,9 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     __shared__ int64_t jr[MAXJOB];
     __shared__ int64_t zero[MAXARR];
     __shared__ int sh[2 + MAXSTMT];
-    __shared__ int jid[NTEMP];
+    __shared__ int jid[NTEMP];   // count-job slots
+    __shared__ int jbuf[NTEMP];  // the buffers they are counted from
+    __shared__ int jfetch;       // of those, the first jfetch come from their slots
     __shared__ int64_t jitems[MAXJOB];  // items of count-job slots, -1 for others
     const int i = blockIdx.x, t = threadIdx.x;
     if (i == 0 && t < META_WORDS) h.meta_next[t] = 0;
@@ -299,9 +303,11 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     if (t < MAXARR) zero[t] = 0;
     const pm_variant v = var[i];
     Job *vj = &jobs[(int64_t)i * MAXJOB];
-    int st = build_block(v, &P, vj, U.jt, sh);
+    int st = build_block(v, &P, vj, U.jt, sh, U.jt);
     bool here = st == PM_OK && P.bitmap_words == 0 && !(P.flags & PM_FLAG_ENUMERATE);
-    if (here && t < P.njob) jitems[t] = vj[t].kind == JOB_COUNT ? vj[t].items : -1;
+    if (here && t < P.njob)
+        jitems[t] = P.jkind[t] != JOB_COUNT ? -1
+                    : P.jtmp[t] >= 0 ? U.jt[P.jtmp[t]].items : vj[t].items;
     __syncthreads();
     if (t == 0) {  // can this work-group finish the variant?
         int ncj = 0;
@@ -312,26 +318,50 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
             else jid[ncj++] = j;
             items += jitems[j];
         }
-        sh[0] = here && items <= max_items ? ncj : -1;
+        here = here && items <= max_items;
+        sh[0] = here ? ncj : -1;
+        if (here) {
+            // jobs still in a buffer are counted there; the others are
+            // fetched from their slots into buffers no count job holds
+            uint32_t held = 0;
+            for (int k = 0; k < ncj; k++)
+                if (P.jtmp[jid[k]] >= 0) held |= 1u << P.jtmp[jid[k]];
+            int nf = 0;
+            for (int k = 0; k < ncj; k++)
+                if (P.jtmp[jid[k]] < 0) {
+                    int b = 0;
+                    while ((held >> b) & 1) b++;
+                    held |= 1u << b;
+                    jbuf[k] = b;
+                    // fetched ones first: swap into place nf
+                    const int tj = jid[nf], tb = jbuf[nf];
+                    jid[nf] = jid[k], jbuf[nf] = jbuf[k];
+                    jid[k] = tj, jbuf[k] = tb;
+                    nf++;
+                }
+            for (int k = nf; k < ncj; k++) jbuf[k] = P.jtmp[jid[k]];
+            jfetch = nf;
+        }
     }
     __syncthreads();
     const int ncj = sh[0];
     if (ncj > 0) {
         constexpr int JW = sizeof(Job) / 8;
-        for (int w = t; w < ncj * JW; w += 64)  // stage the count jobs in LDS
-            ((uint64_t *)U.jt)[w] = ((const uint64_t *)&vj[jid[w / JW]])[w % JW];
+        for (int w = t; w < jfetch * JW; w += 64)  // count jobs not in a buffer
+            ((uint64_t *)&U.jt[jbuf[w / JW]])[w % JW] =
+                ((const uint64_t *)&vj[jid[w / JW]])[w % JW];
         __syncthreads();
         // the jobs' items as one range, spread over the lanes
         int64_t pre[NTEMP + 1];
         pre[0] = 0;
 #pragma unroll
-        for (int k = 0; k < NTEMP; k++) pre[k + 1] = pre[k] + (k < ncj ? U.jt[k].items : 0);
+        for (int k = 0; k < NTEMP; k++) pre[k + 1] = pre[k] + (k < ncj ? U.jt[jbuf[k]].items : 0);
         int64_t s0[NTEMP] = {};
         for (int64_t x = t; x < pre[ncj]; x += 64) {
             int k = 0;
 #pragma unroll
             for (int q = 1; q < NTEMP; q++) k += x >= pre[q];
-            const int64_t c = count_item(U.jt[k], x - pre[k]);
+            const int64_t c = count_item(U.jt[jbuf[k]], x - pre[k]);
 #pragma unroll
             for (int q = 0; q < NTEMP; q++) s0[q] += q == k ? c : 0;
         }
@@ -344,6 +374,16 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     }
     int sfin = st;  // finished here, or failed: zero outputs
     if (ncj < 0 && st == PM_OK) {  // handed on
+        {  // jobs still in their buffers to their slots
+            constexpr int JW = sizeof(Job) / 8;
+            for (int w = t; w < NTEMP * JW; w += 64) {
+                const int b = w / JW;
+                int j = -1;
+                for (int q = 0; q < P.njob; q++)
+                    if (P.jtmp[q] == b) j = q;
+                if (j >= 0) ((uint64_t *)&vj[j])[w % JW] = ((const uint64_t *)&U.jt[b])[w % JW];
+            }
+        }
         if (t < MAXJOB) jobres[(int64_t)i * MAXJOB + t] = 0;
         if (t < 2 * MAXARR) foot[(int64_t)i * MAXARR * 2 + t] = 0;
         // the program to HBM: header and used statements
@@ -395,12 +435,12 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     if (i == 0 && t < META_WORDS) h.meta_next[t] = 0;
     if (i >= nv) return;
     const pm_variant v = var[i];
-    const int sb = build_block(v, &P, J, JT, bsh);
+    const int sb = build_block(v, &P, J, JT, bsh, nullptr);
     if (t == 0) {
         int st = sb;
         int64_t items = 0;
         for (int j = 0; j < P.njob; j++)
-            if (J[j].kind != JOB_NONE) items += J[j].items;
+            if (P.jkind[j] != JOB_NONE) items += J[j].items;
         const bool enumerate = (P.flags & PM_FLAG_ENUMERATE) && items > 0;
         if (st == PM_OK && (P.bitmap_words > 0 || items > max_items || enumerate))
             st = PM_DEFER;
@@ -430,8 +470,8 @@ k_fused(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs,
     }
     if (st == PM_OK) {
         for (int j = 0; j < P.njob; j++) {
+            if (P.jkind[j] != JOB_COUNT) continue;  // uniform over the group
             const Job &Jb = J[j];
-            if (Jb.kind != JOB_COUNT) continue;  // uniform over the group
             int64_t s0 = 0;
             for (int64_t it = t; it < Jb.items; it += FUSED_THREADS) s0 += count_item(Jb, it);
             s0 = block_sum(s0, red);
@@ -738,9 +778,9 @@ int count_host(const pm_variant &v, pm_counts *out, int64_t *foot_out, bool sequ
     int64_t jobres[MAXJOB] = {0};
     int64_t F[MAXARR] = {0}, Fill[MAXARR] = {0};
     for (int j = 0; j < p.njob; j++) {
-        if (J[j].kind == JOB_COUNT) {
+        if (p.jkind[j] == JOB_COUNT) {
             for (int64_t it = 0; it < J[j].items; it++) jobres[j] += count_item(J[j], it);
-        } else if (J[j].kind == JOB_FOOT) {
+        } else if (p.jkind[j] == JOB_FOOT) {
             for (int64_t it = 0; it < J[j].items; it++) foot_item(J[j], it, bm.data(), 0, 1, HostOr{});
         }
     }

@@ -117,6 +117,13 @@ struct ArrInfo {
 
 struct Prog {
     int32_t status, nstmt, narr, njob;
+    // kind of the job in each slot (JOB_*): kept with the program so that a
+    // variant counted where it was expanded never reads or clears slots in
+    // the (slow) job memory it does not use
+    int8_t jkind[MAXJOB];
+    // the fast job buffer still holding the job of each slot (-1: the job
+    // is only in its slot), when the expansion keeps jobs in its buffers
+    int8_t jtmp[MAXJOB];
     int32_t wg_size;
     uint32_t flags;            // the variant's PM_FLAG_*
     int64_t n_wg;
@@ -1174,8 +1181,8 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     default: b.fail(PM_EINVAL);
     }
     AP::each(MAXJOB, [=](int j) {
-        jobs[j].kind = JOB_NONE;
-        jobs[j].chunks = 0;
+        p->jkind[j] = JOB_NONE;
+        p->jtmp[j] = -1;
     });
     // arrays needing footprints got their fill widths as accesses were added
     if (p->status == PM_OK && b.werr) b.fail(PM_EINVAL);
@@ -1185,16 +1192,38 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
 // Counts of statement si (its fixed factor and components) and its jobs,
 // numbered from `base`: a job number reaching `cap` returns `over`.  Jobs
 // are assembled in the buffer temp() gives when the first one is made
-// (fast memory next to a slow `jobs`), else (nullptr) in their slots.
-// *made: jobs made.  Reads the program and writes only statement si and its
-// job slots, so statements may be analysed concurrently.  Returns a status.
+// (fast memory next to a slow `jobs`), else (nullptr) in their slots, and
+// copied to their slots -- except, when `keep` (the first of the buffers
+// temp() hands out) is given, the statement's last job, which stays in its
+// buffer (p->jtmp).  *made: jobs made.  Reads the program and writes only
+// statement si and its job slots, so statements may be analysed
+// concurrently.  Returns a status.
 template <class TEMP>
 PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap, int over,
-                       int *made) {
+                       int *made, const Job *keep = nullptr) {
     int nj = base;
     *made = 0;
     Job *jt = nullptr;
     bool asked = false;
+    int prev = -1;  // slot whose job the buffer still holds (keep)
+    // the buffer is about to take another job: its last one goes to its slot
+    auto release = [&]() {
+        if (jt && prev >= 0) {
+            put_job(&jobs[prev], *jt);
+            p->jtmp[prev] = -1;
+            prev = -1;
+        }
+    };
+    // job nj is complete in the buffer: keep it there, or copy it out
+    auto settle = [&]() {
+        if (!jt) return;
+        if (keep) {
+            p->jtmp[nj] = (int8_t)(jt - keep);
+            prev = nj;
+        } else {
+            put_job(&jobs[nj], *jt);
+        }
+    };
     Stmt &s = p->st[si];
     s.ncomp = 0;
     const int nvar = s.nvar, ng = s.nguard;
@@ -1258,6 +1287,7 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
         if (nj >= cap) return over;
         if (s.ncomp >= MAXCOMP) return PM_EINVAL;
         if (!asked) jt = temp(), asked = true;
+        release();
         // the job, assembled in a fast buffer when one was given, else in
         // its slot: 1 made, 0 an interval (its count in c), < 0 a status
         auto count_job = [&](Job &J) __attribute__((always_inline)) -> int {
@@ -1336,7 +1366,8 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
             if (mul_ovf(fixed, c, &fixed)) return PM_EOVERFLOW;
             continue;
         }
-        if (jt) put_job(&jobs[nj], *jt);
+        settle();
+        p->jkind[nj] = JOB_COUNT;
         s.comp_job[s.ncomp++] = nj++;
     }
     s.fixed = fixed;
@@ -1347,6 +1378,7 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
         if (!A.w) continue;
         if (nj >= cap) return over;
         if (!asked) jt = temp(), asked = true;
+        release();
         // assembled like the count jobs: 1 made, < 0 a status
         auto foot_job = [&](Job &J) __attribute__((always_inline)) -> int {
             J.kind = JOB_FOOT;
@@ -1441,7 +1473,8 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
         Job &Jf = jt ? *jt : jobs[nj];
         const int rf = foot_job(Jf);
         if (rf < 0) return rf;
-        if (jt) put_job(&jobs[nj], *jt);
+        settle();
+        p->jkind[nj] = JOB_FOOT;
         nj++;
     }
     *made = nj - base;
@@ -1450,8 +1483,11 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
 
 // Footprint mode of every strided array over job slots [0, nj), then the
 // chunk and segment prefixes.  Returns the status.
-PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj) {
+PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj,
+                     Job *keep = nullptr) {
     p->njob = nj;
+    // slot j's job: in its buffer when the expansion kept it there
+    auto JB = [&](int j) -> Job & { return keep && p->jtmp[j] >= 0 ? keep[p->jtmp[j]] : jobs[j]; };
 
     // Each strided array: interval mode when its footprint is a sequence of
     // equally spaced runs (ival_ok, sizes in closed form), else bitmaps.
@@ -1461,13 +1497,14 @@ PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj) {
         if (!A.w) continue;
         int nfj = 0, fj = -1;
         for (int j = 0; j < nj; j++)
-            if (jobs[j].kind == JOB_FOOT && jobs[j].arr == ai) nfj++, fj = j;
-        if (nfj == 1 && !(v.flags & PM_FLAG_BITMAP) && jobs[fj].ivok) {
-            Job &J = jobs[fj];
+            if (p->jkind[j] == JOB_FOOT && JB(j).arr == ai) nfj++, fj = j;
+        if (nfj == 1 && !(v.flags & PM_FLAG_BITMAP) && JB(fj).ivok) {
+            Job &J = JB(fj);
             if (J.ivst != PM_OK) return p->status = PM_EOVERFLOW;
             A.fixF = J.ivF;
             A.fixFill = J.ivFill;
             J.kind = JOB_NONE;  // nothing left to enumerate
+            p->jkind[fj] = JOB_NONE;
             J.items = J.chunks = 0;
             A.words = 0;
             A.segs = 0;
@@ -1475,7 +1512,7 @@ PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj) {
         }
         bool mixed = false;  // a stride <= 1 access: widened cells kept apart
         for (int j = 0; j < nj; j++)
-            if (jobs[j].kind == JOB_FOOT && jobs[j].arr == ai && !jobs[j].mark_b) mixed = true;
+            if (p->jkind[j] == JOB_FOOT && JB(j).arr == ai && !JB(j).mark_b) mixed = true;
         A.words = (A.cells + A.w + 8 + 63) / 64 + 1;
         A.f_off = off;
         off += A.words;
@@ -1487,8 +1524,9 @@ PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj) {
         }
         A.segs = cdiv(A.words, SEG_WORDS);
         for (int j = 0; j < nj; j++) {
-            Job &J = jobs[j];
-            if (J.kind != JOB_FOOT || J.arr != ai) continue;
+            if (p->jkind[j] != JOB_FOOT) continue;
+            Job &J = JB(j);
+            if (J.arr != ai) continue;
             J.f_off = A.f_off;
             J.b_off = J.mark_b ? A.b_off : -1;
             J.mark_b = J.mark_b && A.b_off != A.f_off;
@@ -1498,7 +1536,7 @@ PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj) {
     p->bitmap_words = off;
     int64_t cum = 0;
     for (int j = 0; j < MAXJOB; j++) {
-        cum += j < nj ? jobs[j].chunks : 0;
+        cum += j < nj && p->jkind[j] != JOB_NONE ? JB(j).chunks : 0;
         p->jobcum[j] = cum;
     }
     p->chunks = cum;
@@ -1552,8 +1590,8 @@ PM_HD int build_slots_finish(const pm_variant &v, Prog *p, Job *jobs, Job *jt, c
 template <class TEMP>
 PM_HD int build_seq(const pm_variant &v, Prog *p, Job *jobs, TEMP temp) {
     for (int j = 0; j < MAXJOB; j++) {
-        jobs[j].kind = JOB_NONE;
-        jobs[j].chunks = 0;
+        p->jkind[j] = JOB_NONE;
+        p->jtmp[j] = -1;
     }
     int nj = 0;
     for (int si = 0; si < p->nstmt; si++) {
@@ -1568,13 +1606,13 @@ PM_HD int build_seq(const pm_variant &v, Prog *p, Job *jobs, TEMP temp) {
 // build_slots_finish with the fallback through build_seq.
 template <class TEMP>
 PM_HD int build_slots_finish_seq(const pm_variant &v, Prog *p, Job *jobs, TEMP temp,
-                                 const int *r) {
+                                 const int *r, Job *keep) {
     const int ns = p->nstmt;
     for (int si = 0; si < ns; si++) {
         if (r[si] == PM_SEQ) return build_seq(v, p, jobs, temp);
         if (r[si] != PM_OK) return p->status = r[si];
     }
-    return build_tail(v, p, jobs, 2 * ns);
+    return build_tail(v, p, jobs, 2 * ns, keep);
 }
 
 // Host form of the same: the statements one after another.

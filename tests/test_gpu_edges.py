@@ -196,3 +196,39 @@ def test_profile_and_batch_stats(ctx):
     plain = [v for v in FAMILY_CASES if v["family"] == "matmul"][:40]
     ctx.count(plain)
     assert ctx.batch_stats()["handed_on"] == 0
+
+
+def test_model_ranked_counter_schedule(ctx):
+    """The counter's schedule ranked by the model fitted to its own timed
+    passes: the pick is one of the candidates, and the counts under it equal
+    the oracle's (batches that hand variants on and ones that do not)."""
+    import torch
+    from paper_1604_04997_amd import autotune as AT
+    vs = [dict(v, bitmap=True) if k % 2 else v
+          for k, v in enumerate(FAMILY_CASES) if v["family"] in ("transpose", "stencil")][:48]
+    va = P.variant_array(vs)
+    nv = len(vs)
+    d_v = torch.frombuffer(bytearray(bytes(memoryview(va).cast("B"))), dtype=torch.uint8).cuda()
+    d_c = torch.zeros((nv, P.PM_NCOUNT), dtype=torch.int64, device="cuda")
+    d_s = torch.zeros(nv, dtype=torch.int32, device="cuda")
+    ctx.reserve(nv, sum(P.bitmap_bytes(v) for v in vs))
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        ctx.count_device(d_v.data_ptr(), nv, d_c.data_ptr(), None, 0, d_s.data_ptr(), stream)
+
+    default = ctx.schedule()
+    try:
+        chosen, rep = AT.tune_counter_model(ctx, step, n_timed=6, reps=3)
+        assert {k: chosen[k] for k in ("inblock_items", "tail_wgs_per_cu")} in AT.COUNTER_SCHEDULES
+        assert rep["chosen_ms"] > 0 and len(rep["timed"]) == 6
+        d_c.zero_()
+        step()
+        torch.cuda.synchronize()
+        assert (d_s.cpu() == 0).all()
+        names = P.count_names()
+        got = d_c.cpu().numpy()
+        for k, v in enumerate(vs):
+            assert {names[i]: int(x) for i, x in enumerate(got[k]) if x} == _strip(C.count(v)), v
+    finally:
+        ctx.set_schedule(**default)
