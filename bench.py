@@ -179,7 +179,7 @@ def c1_phase(ctx, P):
             "below_launch_floor": int(low.sum())}
 
 
-def model_phase(ctx, P, proj_list=("p12", "full", "ext")):
+def model_phase(ctx, P, proj_list=("p12", "full", "ext", "bank")):
     from synth import suite_instructive, suite_test
     # the paper's instructive suite, plus grids smaller than the GPU holds at
     # once, which only the extension projection is fitted on
@@ -193,7 +193,8 @@ def model_phase(ctx, P, proj_list=("p12", "full", "ext")):
     out = {}
     models = {}
     for proj in proj_list:
-        rows = [i for i, v in enumerate(meas) if proj == "ext" or not v.get("extension")]
+        rows = [i for i, v in enumerate(meas)
+                if proj in ("ext", "bank") or not v.get("extension")]
         sub = (P.Counts * len(rows))(*[cm[i] for i in rows])
         m, cond, resid, rank = P.fit(sub, Tm[rows], proj)
         pred = ctx.predict(m, test)  # counted and predicted on the GPU
@@ -651,7 +652,7 @@ def main():
         json.dump(detail, fh, indent=1, default=float)
     gm = None
     if model_info:
-        gm = {p: model_info[p]["geomean"] for p in ("ext", "full", "p12")}
+        gm = {p: model_info[p]["geomean"] for p in ("ext", "bank", "full", "p12")}
         gm["ext_paper_test_kernels"] = model_info["ext"]["geomean_paper_test_kernels"]
         gm["tiny_p3"] = c1["geomean"] if c1 else None
         gm["sweep_top8"] = c4["geomean_rel_err"] if c4 else None

@@ -134,9 +134,15 @@ typedef struct {
  *              special (rsqrt, sqrt, ...), fma; dtype f32, f64
  *   108 barriers summed over work-items, 109 barriers summed over groups,
  *   110 work-groups, 111 work-items
+ *   [112, 154) the LDS accesses of [90, 96) again, split by bank-stride bin
+ *              (Sec. 6.2: binning the stride of local memory access):
+ *              [dir][size][bin], bin 0 a broadcast (the address does not
+ *              move with the lane index), bins 1..6 an address that moves
+ *              by s 4-byte words per lane with s odd, 2 x odd, 4 x odd,
+ *              8 x odd, 16 x odd, a multiple of 32
  * pm_count_name() gives the name of each slot.
  */
-#define PM_NCOUNT 112
+#define PM_NCOUNT 154
 typedef struct { int64_t c[PM_NCOUNT]; } pm_counts;
 
 /* Feature projections of a count vector:
@@ -159,10 +165,14 @@ typedef struct { int64_t c[PM_NCOUNT]; } pm_counts;
  *                  PM_RESIDENT_WI)), and min(arithmetic instructions, global
  *                  bytes) for arithmetic overlapped with data motion --
  *                  157 features.  Arithmetic instructions: the sum of the
- *                  ten flop counts (an FMA once). */
-enum { PM_PROJ_P3 = 0, PM_PROJ_P12 = 1, PM_PROJ_FULL = 2, PM_PROJ_EXT = 3 };
+ *                  ten flop counts (an FMA once).
+ *   PM_PROJ_BANK  PM_PROJ_EXT with its 6 LDS counts replaced by the 42 LDS
+ *                  counts by bank-stride bin (slots [112, 154); Sec. 6.2)
+ *                  -- 193 features: global (90), LDS by bin (42), then
+ *                  PM_PROJ_EXT's features from the flops on (61). */
+enum { PM_PROJ_P3 = 0, PM_PROJ_P12 = 1, PM_PROJ_FULL = 2, PM_PROJ_EXT = 3, PM_PROJ_BANK = 4 };
 #define PM_RESIDENT_WI 524288 /* 256 CUs x 2048 work-items */
-#define PM_NFEAT_MAX 160
+#define PM_NFEAT_MAX 200
 typedef struct {
     uint32_t nfeat, proj;
     double alpha[PM_NFEAT_MAX]; /* seconds per unit of each feature */

@@ -23,7 +23,12 @@
  *     accesses filled in).  Classes: s=0 -> '0', s=1 -> '1', s>=2 ->
  *     'k/q' with q = min(s,4) and k = ceil(q * |F| / |Fill|) in exact
  *     integer arithmetic ('>4' bins for s>4);
- *   - LDS accesses by size and direction, no stride (Sec. 2.1, last par.);
+ *   - LDS accesses by size and direction (Sec. 2.1, last par.), and again
+ *     by bank-stride bin (Sec. 6.2, binning the stride of local memory
+ *     access): the stride of an LDS site is the change of its element
+ *     index when local id 0 grows by one (the unmasked affine index, guards
+ *     ignored), in 4-byte words; bin 0 for stride 0, else 1 + the number of
+ *     factors 2 in it, at most 6;
  *   - flops by kind (add/sub, mul, div, exp/pow, special, fma) and fp32 or
  *     fp64; integer and index arithmetic is not counted (Sec. 2.2);
  *   - barriers summed over all work-items (Sec. 2.3) and per work-group;
@@ -48,7 +53,9 @@
 #define O_BARWG (O_BARWI + 1)
 #define O_WG (O_BARWI + 2)
 #define O_WI (O_BARWI + 3)
-#define O_FOOT (O_BARWI + 4)          /* per array: |F|, |Fill| : 16 */
+#define O_NLBIN 7
+#define O_LDSB (O_BARWI + 4)          /* [dir][size][bank bin] : 42 */
+#define O_FOOT (O_LDSB + 2 * O_NSZ * O_NLBIN) /* per array: |F|, |Fill| : 16 */
 #define O_NOUT (O_FOOT + 2 * O_MAXARR)
 
 enum { K_ADD, K_MUL, K_DIV, K_EXP, K_SPEC, K_FMA };
@@ -78,6 +85,7 @@ typedef struct {
     arr_t arr[O_MAXARR];
     int narr;
     int64_t lds[2][O_NSZ];
+    int64_t ldsb[2][O_NSZ][O_NLBIN];
     int64_t flop[O_NKIND][2];
     int64_t bar_wi, bar_wg, wg, wi;
     int err;
@@ -161,8 +169,23 @@ static void gacc(sim_t *S, int site, int a, int dir, int elem, int vec,
     }
 }
 
-static void lds(sim_t *S, int dir, int bytes, int64_t times) {
-    S->lds[dir][size_index(bytes)] += times;
+/* `times` LDS accesses of `bytes` bytes at one site whose element index is
+ * i0 for this work-item and i1 for the one with local id 0 one higher. */
+static void lds(sim_t *S, int dir, int bytes, int64_t i0, int64_t i1, int64_t times) {
+    int z = size_index(bytes);
+    S->lds[dir][z] += times;
+    int64_t words = (i1 - i0) * bytes / 4;
+    if (words < 0) words = -words;
+    int bin = 0;
+    if (words) {
+        int twos = 0;
+        while (words % 2 == 0) {
+            words /= 2;
+            twos++;
+        }
+        bin = 1 + (twos < 5 ? twos : 5);
+    }
+    S->ldsb[dir][z][bin] += times;
 }
 static void flop(sim_t *S, int kind, int ebytes, int64_t times) {
     S->flop[kind][ebytes == 4 ? 0 : 1] += times;
@@ -255,15 +278,17 @@ static void sim_lds(sim_t *S, const oparams *p) {
     new_array(S, 0, G * wg);
     for (int64_t g = 0; g < G; g++)
         for (int64_t l = 0; l < wg; l++) {
+            int64_t b = p->s; /* bank stride: lds[(l*b + r) mod W] */
             if (p->op == 0) { /* read */
-                lds(S, D_ST, 4, W / wg);
+                for (int64_t c = 0; c < W / wg; c++)
+                    lds(S, D_ST, 4, c * wg + l, c * wg + l + 1, 1);
                 bar(S, l == 0);
-                lds(S, D_LD, 4, R);
+                lds(S, D_LD, 4, l * b, (l + 1) * b, R);
                 flop(S, K_ADD, 4, R);
             } else { /* write */
-                lds(S, D_ST, 4, R);
+                lds(S, D_ST, 4, l * b, (l + 1) * b, R);
                 bar(S, l == 0);
-                lds(S, D_LD, 4, 1);
+                lds(S, D_LD, 4, l * b, (l + 1) * b, 1);
             }
             gacc(S, 0, 0, D_ST, 4, 1, g * wg + l, g * wg + l + 1);
         }
@@ -344,14 +369,16 @@ static void sim_matmul(sim_t *S, const oparams *p) {
                             if (row < n && kt * T + lx < m)
                                 gacc(S, 0, 0, D_LD, 4, 1, row * m + kt * T + lx,
                                      row * m + kt * T + lx + 1);
-                            lds(S, D_ST, 4, 1);
+                            lds(S, D_ST, 4, ly * T + lx, ly * T + lx + 1, 1); /* As[ly][lx] */
                             if (kt * T + ly < m && col < L)
                                 gacc(S, 1, 1, D_LD, 4, 1, (kt * T + ly) * L + col,
                                      (kt * T + ly) * L + col + 1);
-                            lds(S, D_ST, 4, 1);
+                            /* Bs[ly][lx], rows of T + 1 */
+                            lds(S, D_ST, 4, ly * (T + 1) + lx, ly * (T + 1) + lx + 1, 1);
                             bar(S, lane0);
                             for (int64_t kk = 0; kk < T; kk++) {
-                                lds(S, D_LD, 4, 2);
+                                lds(S, D_LD, 4, ly * T + kk, ly * T + kk, 1); /* As[ly][kk] */
+                                lds(S, D_LD, 4, kk * (T + 1) + lx, kk * (T + 1) + lx + 1, 1);
                                 flop(S, K_FMA, 4, 1);
                             }
                             bar(S, lane0);
@@ -386,12 +413,13 @@ static void sim_transpose(sim_t *S, const oparams *p) {
                     if (p->op == 0) { /* tiled through LDS */
                         if (r < n && c < n) {
                             gacc(S, 0, 0, D_LD, 4, 1, r * n + c, r * n + c + 1);
-                            lds(S, D_ST, 4, 1);
+                            /* tile[ly][lx], rows of T + 1 */
+                            lds(S, D_ST, 4, ly * (T + 1) + lx, ly * (T + 1) + lx + 1, 1);
                         }
                         bar(S, lx == 0 && ly == 0);
                         int64_t r2 = gx * T + ly, c2 = gy * T + lx;
                         if (r2 < n && c2 < n) {
-                            lds(S, D_LD, 4, 1);
+                            lds(S, D_LD, 4, lx * (T + 1) + ly, (lx + 1) * (T + 1) + ly, 1);
                             gacc(S, 1, 1, D_ST, 4, 1, r2 * n + c2, r2 * n + c2 + 1);
                         }
                     } else if (r < n && c < n) {
@@ -411,6 +439,7 @@ static void sim_transpose(sim_t *S, const oparams *p) {
 /* --------------------------------------------------------------- stencil */
 static void sim_stencil(sim_t *S, const oparams *p) {
     int64_t n = p->n, T = p->T, G = cdiv(n, T), P = n + 2;
+    int64_t Q = T + 2; /* the LDS tile: rows of T + 2 with the halo */
     int e = (int)p->ebytes;
     new_array(S, 0, P * P);
     new_array(S, 1, n * n);
@@ -423,35 +452,40 @@ static void sim_stencil(sim_t *S, const oparams *p) {
                     /* the tile, then its four halo edges */
                     if (in) {
                         gacc(S, 0, 0, D_LD, e, 1, (i + 1) * P + j + 1, (i + 1) * P + j + 2);
-                        lds(S, D_ST, e, 1);
+                        lds(S, D_ST, e, (ly + 1) * Q + lx + 1, (ly + 1) * Q + lx + 2, 1);
                     }
                     if (ly == 0 && j < n) {
                         gacc(S, 1, 0, D_LD, e, 1, i * P + j + 1, i * P + j + 2);
-                        lds(S, D_ST, e, 1);
+                        lds(S, D_ST, e, lx + 1, lx + 2, 1);
                     }
                     if (ly == T - 1 && in) {
                         gacc(S, 2, 0, D_LD, e, 1, (i + 2) * P + j + 1, (i + 2) * P + j + 2);
-                        lds(S, D_ST, e, 1);
+                        lds(S, D_ST, e, (T + 1) * Q + lx + 1, (T + 1) * Q + lx + 2, 1);
                     }
                     if (ly < T - 1 && i == n - 1 && j < n) {
                         gacc(S, 3, 0, D_LD, e, 1, (i + 2) * P + j + 1, (i + 2) * P + j + 2);
-                        lds(S, D_ST, e, 1);
+                        lds(S, D_ST, e, (ly + 2) * Q + lx + 1, (ly + 2) * Q + lx + 2, 1);
                     }
                     if (lx == 0 && i < n) {
                         gacc(S, 4, 0, D_LD, e, 1, (i + 1) * P + j, (i + 1) * P + j + 1);
-                        lds(S, D_ST, e, 1);
+                        lds(S, D_ST, e, (ly + 1) * Q, (ly + 1) * Q, 1); /* column 0 */
                     }
                     if (lx == T - 1 && in) {
                         gacc(S, 5, 0, D_LD, e, 1, (i + 1) * P + j + 2, (i + 1) * P + j + 3);
-                        lds(S, D_ST, e, 1);
+                        lds(S, D_ST, e, (ly + 1) * Q + T + 1, (ly + 1) * Q + T + 1, 1);
                     }
                     if (lx < T - 1 && j == n - 1 && i < n) {
                         gacc(S, 6, 0, D_LD, e, 1, (i + 1) * P + j + 2, (i + 1) * P + j + 3);
-                        lds(S, D_ST, e, 1);
+                        lds(S, D_ST, e, (ly + 1) * Q + lx + 2, (ly + 1) * Q + lx + 3, 1);
                     }
                     bar(S, lx == 0 && ly == 0);
                     if (in) {
-                        lds(S, D_LD, e, 5);
+                        /* the point, north, south, west, east */
+                        lds(S, D_LD, e, (ly + 1) * Q + lx + 1, (ly + 1) * Q + lx + 2, 1);
+                        lds(S, D_LD, e, ly * Q + lx + 1, ly * Q + lx + 2, 1);
+                        lds(S, D_LD, e, (ly + 2) * Q + lx + 1, (ly + 2) * Q + lx + 2, 1);
+                        lds(S, D_LD, e, (ly + 1) * Q + lx, (ly + 1) * Q + lx + 1, 1);
+                        lds(S, D_LD, e, (ly + 1) * Q + lx + 2, (ly + 1) * Q + lx + 3, 1);
                         flop(S, K_ADD, e, 4); /* N+S, +W, +E, + h^2 c^2 */
                         flop(S, K_MUL, e, 3); /* c*c, h^2*(.), 0.25*(.) */
                         gacc(S, 7, 1, D_ST, e, 1, i * n + j, i * n + j + 1);
@@ -477,12 +511,13 @@ static void sim_nbody(sim_t *S, const oparams *p) {
                 if (j < N)
                     for (int c = 0; c < 3; c++) {
                         gacc(S, 3 + c, 0, D_LD, 4, 1, 3 * j + c, 3 * (j + 1) + c);
-                        lds(S, D_ST, 4, 1);
+                        lds(S, D_ST, 4, c * Gs + l, c * Gs + l + 1, 1); /* sh[c*G + l] */
                     }
                 bar(S, l == 0);
                 for (int64_t jj = 0; jj < Gs; jj++)
                     if (jb * Gs + jj < N) {
-                        lds(S, D_LD, 4, 3);
+                        for (int c = 0; c < 3; c++) /* sh[c*G + jj], one word for all */
+                            lds(S, D_LD, 4, c * Gs + jj, c * Gs + jj, 1);
                         flop(S, K_ADD, 4, 6); /* 3 sub, 2 add in r^2, 1 into the block's partial */
                         flop(S, K_MUL, 4, 3);
                         flop(S, K_SPEC, 4, 1); /* rsqrt, self pair masked by select */
@@ -519,7 +554,7 @@ static void sim_conv(sim_t *S, const oparams *p) {
                                 int64_t t = k * T * T + ly * T + lx;
                                 if (t < 147) {
                                     gacc(S, 0, 1, D_LD, 4, 1, zj * 147 + t, zj * 147 + t + 1);
-                                    lds(S, D_ST, 4, 1);
+                                    lds(S, D_ST, 4, t, t + 1, 1); /* fl[t] */
                                 }
                             }
                             for (int64_t a = 0; a < KA; a++)
@@ -530,7 +565,9 @@ static void sim_conv(sim_t *S, const oparams *p) {
                                         for (int64_t c = 0; c < 3; c++) {
                                             int64_t id = ((zi * P + X) * P + Y) * 3 + c;
                                             gacc(S, 1 + (int)c, 0, D_LD, 4, 1, id, id + 3);
-                                            lds(S, D_ST, 4, 1);
+                                            /* tile[r][q][c], channel fastest */
+                                            lds(S, D_ST, 4, (r * TT + q) * 3 + c,
+                                                (r * TT + q + 1) * 3 + c, 1);
                                         }
                                 }
                             bar(S, lane0);
@@ -538,7 +575,12 @@ static void sim_conv(sim_t *S, const oparams *p) {
                             if (x < n && y < n) {
                                 for (int64_t u = 0; u < 7; u++)
                                     for (int64_t v = 0; v < 7; v++) {
-                                        lds(S, D_LD, 4, 6);
+                                        for (int64_t c = 0; c < 3; c++) {
+                                            int64_t a0 = ((ly + 6 - u) * TT + lx + 6 - v) * 3 + c;
+                                            lds(S, D_LD, 4, a0, a0 + 3, 1); /* tile */
+                                            int64_t f0 = (u * 7 + v) * 3 + c;
+                                            lds(S, D_LD, 4, f0, f0, 1);     /* fl */
+                                        }
                                         flop(S, K_FMA, 4, 3);
                                     }
                                 int64_t o = ((zi * 3 + zj) * n + x) * n + y;
@@ -590,7 +632,11 @@ static void finish(sim_t *S, int64_t *out) {
         out[O_GACC + (t->dir * O_NSZ + si) * O_NCLS + c] += t->count;
     }
     for (int d = 0; d < 2; d++)
-        for (int z = 0; z < O_NSZ; z++) out[O_LDS + d * O_NSZ + z] = S->lds[d][z];
+        for (int z = 0; z < O_NSZ; z++) {
+            out[O_LDS + d * O_NSZ + z] = S->lds[d][z];
+            for (int b = 0; b < O_NLBIN; b++)
+                out[O_LDSB + (d * O_NSZ + z) * O_NLBIN + b] = S->ldsb[d][z][b];
+        }
     for (int k = 0; k < O_NKIND; k++)
         for (int d = 0; d < 2; d++) out[O_FLOP + k * 2 + d] = S->flop[k][d];
     out[O_BARWI] = S->bar_wi;
@@ -625,6 +671,10 @@ int oracle_name(int i, char *buf, int cap) {
         snprintf(buf, cap, "wg");
     } else if (i == O_WI) {
         snprintf(buf, cap, "wi");
+    } else if (i < O_FOOT) {
+        static const char *bn[O_NLBIN] = {"b0", "b1", "b2", "b4", "b8", "b16", "b32"};
+        int r = i - O_LDSB, dz = r / O_NLBIN;
+        snprintf(buf, cap, "%s.%s.%s", dz / O_NSZ ? "lst" : "lld", szn[dz % O_NSZ], bn[r % O_NLBIN]);
     } else {
         int r = i - O_FOOT;
         snprintf(buf, cap, "foot.%s.%d", r % 2 ? "fill" : "F", r / 2);

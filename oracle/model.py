@@ -22,6 +22,10 @@ Feature sets (projections of the count dict of oracle.count.count):
   ext   full and the extensions the paper names as future work (Sec. 6):
         arithmetic instructions and global bytes per resident work-item,
         min(arithmetic instructions, global bytes)
+  bank  ext with its six LDS counts replaced by the LDS counts per
+        (direction, size, bank-stride bin) -- the binning of the LDS stride
+        Sec. 6.2 proposes (bins b0 = broadcast, b1 = odd stride, b2 ... b32
+        = the power of two in the stride, 32 and more together)
 """
 from __future__ import annotations
 
@@ -127,8 +131,20 @@ def features_ext(c):
                                float(min(ops, gb))]
 
 
+BANK_BINS = ["b0", "b1", "b2", "b4", "b8", "b16", "b32"]
+
+
+def features_bank(c):
+    """features_ext with the 6 LDS counts (after the 90 global ones) replaced
+    by the 42 LDS counts by bank-stride bin."""
+    e = features_ext(c)
+    binned = [float(_g(c, "%s.%d.%s" % (d, sz, b)))
+              for d in ("lld", "lst") for sz in SIZES for b in BANK_BINS]
+    return e[:90] + binned + e[96:]
+
+
 FEATURES = {"p3": features_p3, "p12": features_p12, "full": features_full,
-            "ext": features_ext}
+            "ext": features_ext, "bank": features_bank}
 
 
 def feature_matrix(counts, proj):

@@ -16,13 +16,13 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpm.so")
 
-PM_NCOUNT = 112
-PM_NFEAT_MAX = 160
+PM_NCOUNT = 154
+PM_NFEAT_MAX = 200
 PM_MAXBUF = 8
 PM_BATCH_MAX = 65536
 PM_NOALLOC_MAX_VARIANTS = 1024
-PROJ = {"p3": 0, "p12": 1, "full": 2, "ext": 3}
-NFEAT = {"p3": 3, "p12": 12, "full": 154, "ext": 157}
+PROJ = {"p3": 0, "p12": 1, "full": 2, "ext": 3, "bank": 4}
+NFEAT = {"p3": 3, "p12": 12, "full": 154, "ext": 157, "bank": 193}
 
 FAMILY = {"stream": 0, "lds": 1, "fma": 2, "rsqrt": 3, "barrier": 4,
           "empty": 5, "matmul": 6, "transpose": 7, "stencil": 8, "nbody": 9,

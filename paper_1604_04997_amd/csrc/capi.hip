@@ -616,9 +616,13 @@ pm_status pm_count_name(int i, char *buf, size_t cap) {
     } else if (i < pm::C_BARWI) {
         int r = i - pm::C_FLOP;
         snprintf(buf, cap, "%s.%s", kind[r / 2], r % 2 ? "f64" : "f32");
-    } else {
+    } else if (i < pm::C_LDSB) {
         static const char *tail[4] = {"bar.wi", "bar.wg", "wg", "wi"};
         snprintf(buf, cap, "%s", tail[i - pm::C_BARWI]);
+    } else {  // LDS by bank-stride bin: broadcast, then odd, 2 x odd, ..., 32 x
+        static const char *bin[pm::NLBIN] = {"b0", "b1", "b2", "b4", "b8", "b16", "b32"};
+        const int r = i - pm::C_LDSB, dz = r / pm::NLBIN;
+        snprintf(buf, cap, "%s.%s.%s", dz / 3 ? "lst" : "lld", sz[dz % 3], bin[r % pm::NLBIN]);
     }
     return PM_OK;
 }

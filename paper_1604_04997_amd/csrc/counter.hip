@@ -133,6 +133,12 @@ __device__ Agg wave_aggregates(const int64_t *c, int l) {
 
 // feature_one(c, proj, j), with the sums over many slots taken from `a`.
 __device__ double feature_dev(const int64_t *c, uint32_t proj, int j, const Agg &a) {
+    if (proj == PM_PROJ_BANK) {
+        int slot = 0;
+        j = bank_to_ext(j, &slot);
+        if (j < 0) return (double)c[slot];
+        proj = PM_PROJ_EXT;
+    }
     if (proj == PM_PROJ_P3) return j == 0 ? a.gb : feature_one(c, proj, j);
     if (proj == PM_PROJ_P12) {
         switch (j) {

@@ -56,6 +56,30 @@ constexpr int C_BARWI = 108;
 constexpr int C_BARWG = 109;
 constexpr int C_WG = 110;
 constexpr int C_WI = 111;
+// LDS accesses again, split by bank-stride bin: [dir][size][bin]
+constexpr int NLBIN = 7;
+constexpr int C_LDSB = 112;
+static_assert(C_LDSB + 2 * 3 * NLBIN == PM_NCOUNT, "count-vector layout");
+
+// Bank-stride bin of an LDS access whose address moves `words` 4-byte
+// words when the lane index grows by one (Sec. 6.2: binning the stride of
+// local memory access): 0 for a broadcast (stride 0), else 1 + the number
+// of factors 2 in the stride, at most 6 -- odd strides (1), 2 x odd, ...,
+// multiples of 32 (6).  With power-of-two bank counts the lanes of a
+// wavefront that share a bank grow with that power of two.
+PM_HD int lds_bin(int64_t words) {
+    if (words == 0) return 0;
+    const uint64_t w = (uint64_t)(words < 0 ? -words : words);
+    const int v2 = __builtin_ctzll(w);
+    return 1 + (v2 < NLBIN - 2 ? v2 : NLBIN - 2);
+}
+// An LDS access site of a statement: per instance `count` accesses of
+// direction dir and size index z whose address moves `stride` words per
+// lane, packed as count | bin << 16 | dir << 19 | z << 20 (0: no site).
+constexpr int MAXLSITE = 4;
+PM_HD uint32_t lsite_pack(int dir, int z, int bin, int count) {
+    return (uint32_t)count | (uint32_t)bin << 16 | (uint32_t)dir << 19 | (uint32_t)z << 20;
+}
 
 enum { K_ADD = 0, K_MUL, K_DIV, K_EXP, K_SPEC, K_FMA };
 enum { D_LD = 0, D_ST = 1 };
@@ -98,6 +122,7 @@ struct Stmt {
     Aff guard[MAXGUARD];
     int32_t acc0;  // its accesses are Prog::acc[acc0, acc0 + nacc)
     int32_t lds[2][3];
+    uint32_t lsite[MAXLSITE];  // the same LDS accesses by site (lsite_pack)
     int32_t flop[6][2];
     int32_t bar;
     int32_t ncomp;
@@ -271,13 +296,13 @@ struct BT {
     // variable and guard indices of a builder are compile-time constants.
     // Builders fill one statement at a time: additions go to the latest.
     Stmt *cur = nullptr;
-    int nvar = 0, nguard = 0, nacc = 0, lane = 0;
+    int nvar = 0, nguard = 0, nacc = 0, lane = 0, nls = 0;
     bool werr = false;  // an access with no whole lane stride, or two widths on one array
     PM_HD void fail(int st) {
         if (p->status == PM_OK) p->status = st;
     }
     PM_HD Stmt *stmt(int lane_var) {
-        nvar = nguard = nacc = 0;
+        nvar = nguard = nacc = nls = 0;
         lane = lane_var;
         cur = nullptr;
         if (p->nstmt >= MAXSTMT) {
@@ -294,6 +319,7 @@ struct BT {
         s->gmask = 0;
         AP::each(MAXVAR, [=](int i) { s->ext[i] = 1; });
         AP::each(6, [=](int i) { (&s->lds[0][0])[i] = 0; });
+        AP::each(MAXLSITE, [=](int i) { s->lsite[i] = 0; });
         AP::each(12, [=](int i) { (&s->flop[0][0])[i] = 0; });
         s->bar = 0;
         s->ncomp = 0;
@@ -362,6 +388,17 @@ struct BT {
             if (A.w && A.w != w) werr = true;
             else A.w = w;
         }
+    }
+    // `count` LDS accesses of `bytes` bytes per instance whose element index
+    // moves `stride` elements when the lane index grows by one
+    PM_HD void lds(Stmt *s, int dir, int bytes, int64_t stride, int count) {
+        const int z = size_index(bytes);
+        if (s != cur || nls >= MAXLSITE || z < 0 || count <= 0 || count >= (1 << 16)) {
+            fail(PM_EINVAL);
+            return;
+        }
+        s->lds[dir][z] += count;
+        s->lsite[nls++] = lsite_pack(dir, z, lds_bin(stride * bytes / 4), count);
     }
     PM_HD void array(int a, int64_t cells) {
         if (a >= MAXARR) {
@@ -477,18 +514,18 @@ PM_HD void build_lds(BB &b, const pm_variant &v) {
     int g = b.var(S, G), l = b.var(S, wg);
     b.acc(S, 0, D_ST, 4, 1, b.av(b.av(b.mk(0), g, wg), l, 1));
     S->bar = 1;
+    if (v.op == PM_LDS_READ) b.lds(S, D_ST, 4, 1, (int)(W / wg));  // initialisation lds[c*wg + l]
+    else b.lds(S, D_LD, 4, v.stride, 1);  // read-back lds[(l*b) mod W]
     Stmt *L = b.stmt(1);
     if (!L) return;
     b.var(L, G);
     b.var(L, wg);
     b.var(L, R);
     if (v.op == PM_LDS_READ) {
-        S->lds[D_ST][0] = (int32_t)(W / wg);  // initialisation
-        L->lds[D_LD][0] = 1;
+        b.lds(L, D_LD, 4, v.stride, 1);  // lds[(l*b + r) mod W]
         L->flop[K_ADD][0] = 1;
     } else {
-        L->lds[D_ST][0] = 1;
-        S->lds[D_LD][0] = 1;  // read-back
+        b.lds(L, D_ST, 4, v.stride, 1);
     }
 }
 
@@ -607,14 +644,15 @@ PM_HD void build_matmul(BB &b, const pm_variant &v) {
         if (!Sl) return;
         head(Sl);
         b.var(Sl, KT);
-        Sl->lds[D_ST][0] = 2;
+        b.lds(Sl, D_ST, 4, 1, 2);  // As[ly][lx], Bs[ly][lx]
         Sl->bar = 2;
         Stmt *Si = b.stmt(3);  // inner product step
         if (!Si) return;
         head(Si);
         b.var(Si, KT);
         b.var(Si, T);
-        Si->lds[D_LD][0] = 2;
+        b.lds(Si, D_LD, 4, 0, 1);  // As[ly][k]: the same word for every lane
+        b.lds(Si, D_LD, 4, 1, 1);  // Bs[k][lx]
         Si->flop[K_FMA][0] = 1;
     } else {
         Stmt *S = b.stmt(3);
@@ -665,7 +703,7 @@ PM_HD void build_transpose(BB &b, const pm_variant &v) {
         b.lt(S, r, n);
         b.lt(S, c, n);
         b.acc(S, 0, D_LD, 4, 1, rn_c);
-        S->lds[D_ST][0] = 1;
+        b.lds(S, D_ST, 4, 1, 1);  // tile[ly][lx], rows of T + 1
         Stmt *Sb = b.stmt(3);
         if (!Sb) return;
         head(Sb);
@@ -675,7 +713,7 @@ PM_HD void build_transpose(BB &b, const pm_variant &v) {
         head(St);
         b.lt(St, b.av(b.av(b.mk(0), 1, T), 2, 1), n);
         b.lt(St, b.av(b.av(b.mk(0), 0, T), 3, 1), n);
-        St->lds[D_LD][0] = 1;
+        b.lds(St, D_LD, 4, T + 1, 1);  // tile[lx][ly]
         b.acc(St, 1, D_ST, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 1, T * n), 2, n), 0, T), 3, 1));
     } else {
         Stmt *S = b.stmt(3);
@@ -703,7 +741,6 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
     }
     int e = v.dtype == PM_F64 ? 8 : 4;
     int dt = v.dtype == PM_F64 ? 1 : 0;
-    int z = e == 8 ? 1 : 0;
     int64_t G = cdiv(n, T), P = n + 2;
     b.p->n_wg = G * G;
     b.p->wg_size = (int32_t)(T * T);
@@ -722,7 +759,9 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
         b.var(S, G);
         b.var(S, T);
         b.var(S, T);
-        S->lds[D_ST][z] = 1;
+        // tile cell (ly + 1, lx + 1) and the halo rows: lane stride 1; the
+        // halo columns (lx == 0, lx == T-1) are written at a fixed column
+        b.lds(S, D_ST, e, q == 4 || q == 5 ? 0 : 1, 1);
         switch (q) {
         case 0:  // the tile
             b.lt(S, i, n), b.lt(S, j, n);
@@ -761,7 +800,7 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
     if (!Sc) return;
     b.var(Sc, G), b.var(Sc, G), b.var(Sc, T), b.var(Sc, T);
     b.lt(Sc, i, n), b.lt(Sc, j, n);
-    Sc->lds[D_LD][z] = 5;
+    b.lds(Sc, D_LD, e, 1, 5);  // the point and its four neighbours, rows of T + 2
     Sc->flop[K_ADD][dt] = 4;  // N+S, +W, +E, + h^2 c^2
     Sc->flop[K_MUL][dt] = 3;  // c*c, h^2*(.), 0.25*(.)
     b.acc(Sc, 1, D_ST, e, 1, b.av(b.av(b.av(b.av(b.mk(0), 0, T * n), 2, n), 1, T), 3, 1));
@@ -795,7 +834,7 @@ PM_HD void build_nbody(BB &b, const pm_variant &v) {
     b.lt(Sk, b.av(b.av(b.mk(0), jb, Gs), l, 1), N);
     for (int c = 0; c < 3; c++)
         b.acc(Sk, 0, D_LD, 4, 1, b.av(b.av(b.mk(c), jb, 3 * Gs), l, 3));
-    Sk->lds[D_ST][0] = 3;
+    b.lds(Sk, D_ST, 4, 1, 3);  // sh[c*G + l]
     Stmt *Sb = b.stmt(1);
     if (!Sb) return;
     b.var(Sb, GB), b.var(Sb, Gs), b.var(Sb, GB);
@@ -806,7 +845,7 @@ PM_HD void build_nbody(BB &b, const pm_variant &v) {
     jb = b.var(Sp, GB);
     int jj = b.var(Sp, Gs);
     b.lt(Sp, b.av(b.av(b.mk(0), jb, Gs), jj, 1), N);
-    Sp->lds[D_LD][0] = 3;
+    b.lds(Sp, D_LD, 4, 0, 3);  // sh[c*G + jj]: the same word for every lane
     Sp->flop[K_ADD][0] = 6;   // 3 differences, 2 adds in r^2, 1 into the block's partial
     Sp->flop[K_MUL][0] = 3;
     Sp->flop[K_SPEC][0] = 1;  // rsqrt; the self pair is masked by a select
@@ -854,7 +893,7 @@ PM_HD void build_conv(BB &b, const pm_variant &v) {
     auto t = b.av(b.av(b.av(b.mk(0), k, T * T), 4, T), 5, 1);
     b.lt(Sf, t, 147);
     b.acc(Sf, 1, D_LD, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 3, 147), k, T * T), 4, T), 5, 1));
-    Sf->lds[D_ST][0] = 1;
+    b.lds(Sf, D_ST, 4, 1, 1);  // fl[t]
     Stmt *Si = b.stmt(5);  // image tile cell (a*T + ly, b*T + lx), 3 channels
     if (!Si) return;
     head(Si);
@@ -867,7 +906,7 @@ PM_HD void build_conv(BB &b, const pm_variant &v) {
         b.acc(Si, 0, D_LD, 4, 1,
               b.av(b.av(b.av(b.av(b.av(b.av(b.av(b.mk(c), 2, P * P * 3), 0, T * P * 3), a, T * P * 3),
                              4, P * 3), 1, T * 3), bb, T * 3), 5, 3));
-    Si->lds[D_ST][0] = 3;
+    b.lds(Si, D_ST, 4, 3, 3);  // tile[r][q][c], channel fastest
     Stmt *Sb = b.stmt(5);
     if (!Sb) return;
     head(Sb);
@@ -880,7 +919,8 @@ PM_HD void build_conv(BB &b, const pm_variant &v) {
     auto x = b.av(b.av(b.mk(0), 0, T), 4, 1), y = b.av(b.av(b.mk(0), 1, T), 5, 1);
     b.lt(Sm, x, n);
     b.lt(Sm, y, n);
-    Sm->lds[D_LD][0] = 6;
+    b.lds(Sm, D_LD, 4, 3, 3);  // tile[ly + 6 - u][lx + 6 - v][c]
+    b.lds(Sm, D_LD, 4, 0, 3);  // fl[(u*7 + v)*3 + c]: the same word for every lane
     Sm->flop[K_FMA][0] = 3;
     Stmt *So = b.stmt(5);
     if (!So) return;
@@ -1755,7 +1795,7 @@ PM_HD int class_index(int64_t s, int64_t F, int64_t Fill) {
 // by direction and size, flops by kind and dtype, barriers -- of which only
 // the non-zero ones enter the list.  The same helpers serve the host loop
 // (finalize) and the 64-lane version on the device.
-constexpr int NENT = MAXACC + 6 + 12 + 1;
+constexpr int NENT = MAXACC + 6 + 12 + 1 + MAXLSITE;
 struct Contrib {
     int16_t slot, stmt;
     int32_t mult;
@@ -1800,9 +1840,14 @@ PM_HD bool contrib(const Prog &p, int si, int e, const int64_t *F, const int64_t
         e -= 6;
         c->slot = (int16_t)(C_FLOP + e);
         c->mult = s.flop[e / 2][e % 2];
-    } else {
+    } else if (e == 18) {
         c->slot = (int16_t)C_BARWI;
         c->mult = s.bar;
+    } else {  // an LDS site, in its bank-stride bin
+        const uint32_t w = s.lsite[e - 19];
+        const int dir = (w >> 19) & 1, z = (w >> 20) & 3, bin = (w >> 16) & 7;
+        c->slot = (int16_t)(C_LDSB + (dir * 3 + z) * NLBIN + bin);
+        c->mult = (int32_t)(w & 0xffff);
     }
     return c->mult != 0;
 }
@@ -1855,7 +1900,18 @@ PM_HD int finalize(const Prog &p, const int64_t *jobres, const int64_t *F,
 // ------------------------------------------------------------- features ---
 PM_HD int nfeat(uint32_t proj) {
     return proj == PM_PROJ_P3 ? 3 : proj == PM_PROJ_P12 ? 12 : proj == PM_PROJ_FULL ? 154 :
-           proj == PM_PROJ_EXT ? 157 : -1;
+           proj == PM_PROJ_EXT ? 157 : proj == PM_PROJ_BANK ? 193 : -1;
+}
+// PM_PROJ_BANK feature j: the 42 binned LDS counts in place of
+// PM_PROJ_EXT's 6 (features 90..95); returns the PM_PROJ_EXT feature it
+// equals, or -1 with *slot the count slot it reads.
+PM_HD int bank_to_ext(int j, int *slot) {
+    if (j < 90) return j;
+    if (j < 90 + 42) {
+        *slot = C_LDSB + (j - 90);
+        return -1;
+    }
+    return j - 36;
 }
 
 PM_HD bool full_use_class(int cl) {  // '0', '1', '2/2', '3/3', '4/4'
@@ -1865,6 +1921,12 @@ PM_HD bool full_use_class(int cl) {  // '0', '1', '2/2', '3/3', '4/4'
 // Feature j of projection `proj` from count vector c.
 PM_HD double feature_one(const int64_t *c, uint32_t proj, int j) {
     const double SZ[3] = {4, 8, 16};
+    if (proj == PM_PROJ_BANK) {
+        int slot = 0;
+        j = bank_to_ext(j, &slot);
+        if (j < 0) return (double)c[slot];
+        proj = PM_PROJ_EXT;
+    }
     if (proj == PM_PROJ_P3) {
         if (j == 0) {  // global bytes, every class and direction
             double gb = 0;

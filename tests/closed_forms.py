@@ -7,13 +7,30 @@ def cdiv(a, b):
     return -(-a // b)
 
 
+def bank(e, stride):
+    """Bank-stride bin name of an LDS site whose element index moves by
+    `stride` elements of e bytes per lane: b0 for a broadcast, else b2^k
+    for 2^k the power of two in the word stride, at most 32."""
+    w = stride * e // 4
+    if w == 0:
+        return "b0"
+    k = 0
+    while w % 2 == 0 and k < 5:
+        w //= 2
+        k += 1
+    return "b%d" % (1 << k)
+
+
 def matmul(v):
     n, m, l, T = v["n"], v["m"], v["l"], v["T"]
     GX, GY, KT = cdiv(l, T), cdiv(n, T), cdiv(m, T)
     wi = GX * GY * T * T
     if v["op"] == "tiled":
+        # As[ly][lx], Bs[ly][lx] stored at lane stride 1; As[ly][k] read by
+        # every lane of a row at one word, Bs[k][lx] at lane stride 1
         return {"gld.4.1": n * m * GX + m * l * GY, "gst.4.1": n * l,
                 "lst.4": 2 * wi * KT, "lld.4": 2 * wi * KT * T,
+                "lst.4.b1": 2 * wi * KT, "lld.4.b0": wi * KT * T, "lld.4.b1": wi * KT * T,
                 "fma.f32": wi * KT * T, "bar.wi": 2 * wi * KT,
                 "bar.wg": 2 * GX * GY * KT, "wg": GX * GY, "wi": wi}
     return {"gld.4.0": n * m * l, "gld.4.1": n * m * l, "gst.4.1": n * l,
@@ -26,8 +43,10 @@ def transpose(v):
     base = {"wg": G * G, "wi": G * G * T * T}
     strided = "4/>4" if n > 4 else {2: "2/2", 3: "3/3", 4: "4/4"}.get(n, "1")
     if v["op"] == "tiled":
+        # tile[ly][lx] stored at lane stride 1, tile[lx][ly] read at T + 1
         base.update({"gld.4.1": n * n, "gst.4.1": n * n, "lst.4": n * n,
-                     "lld.4": n * n, "bar.wi": G * G * T * T, "bar.wg": G * G})
+                     "lld.4": n * n, "lst.4.b1": n * n, "lld.4." + bank(4, T + 1): n * n,
+                     "bar.wi": G * G * T * T, "bar.wg": G * G})
     elif v["op"] == "naive_wc":
         base.update({"gld.4." + strided: n * n, "gst.4.1": n * n})
     else:
@@ -43,8 +62,13 @@ def stencil(v):
     e = 4 if dt == "f32" else 8
     G = cdiv(n, T)
     halo = 4 * n * G
+    # halo columns written at a fixed column (lane stride 0): the left one
+    # in every tile column, the right one in the full tile columns
+    col0 = G * n + (n // T) * n
     return {"gld.%d.1" % e: n * n + halo, "lst.%d" % e: n * n + halo,
-            "lld.%d" % e: 5 * n * n, "add." + dt: 4 * n * n,
+            "lst.%d.b0" % e: col0, "lst.%d.%s" % (e, bank(e, 1)): n * n + halo - col0,
+            "lld.%d" % e: 5 * n * n, "lld.%d.%s" % (e, bank(e, 1)): 5 * n * n,
+            "add." + dt: 4 * n * n,
             "mul." + dt: 3 * n * n, "gst.%d.1" % e: n * n,
             "bar.wi": G * G * T * T, "bar.wg": G * G, "wg": G * G,
             "wi": G * G * T * T}
@@ -54,8 +78,10 @@ def nbody(v):
     N, G = v["n"], v["wg"]
     B = cdiv(N, G)
     wi = B * G
+    # sh[c*G + l] stored at lane stride 1; sh[c*G + jj] read at one word
     return {"gld.4.3/3": 3 * N + 3 * N * B, "gst.4.1": N, "lst.4": 3 * N * B,
-            "lld.4": 3 * wi * N, "add.f32": 6 * wi * N + wi * B, "mul.f32": 3 * wi * N,
+            "lld.4": 3 * wi * N, "lst.4.b1": 3 * N * B, "lld.4.b0": 3 * wi * N,
+            "add.f32": 6 * wi * N + wi * B, "mul.f32": 3 * wi * N,
             "spec.f32": wi * N, "bar.wi": 2 * wi * B, "bar.wg": 2 * B * B,
             "wg": B, "wi": wi}
 
@@ -109,10 +135,13 @@ def chain(v):
 def lds(v):
     G, wg, R, W = v["groups"], v["wg"], v["R"], v["W"]
     out = {"gst.4.1": G * wg, "bar.wi": G * wg, "bar.wg": G, "wg": G, "wi": G * wg}
+    b = bank(4, v["b"])  # lds[(l*b + r) mod W]: lane stride b
     if v["op"] == "read":
-        out.update({"lst.4": G * W, "lld.4": G * wg * R, "add.f32": G * wg * R})
+        out.update({"lst.4": G * W, "lld.4": G * wg * R, "add.f32": G * wg * R,
+                    "lst.4.b1": G * W, "lld.4." + b: G * wg * R})
     else:
-        out.update({"lst.4": G * wg * R, "lld.4": G * wg})
+        out.update({"lst.4": G * wg * R, "lld.4": G * wg,
+                    "lst.4." + b: G * wg * R, "lld.4." + b: G * wg})
     return {k: x for k, x in out.items() if x}
 
 
@@ -135,8 +164,12 @@ def conv(v):
     img = 9 * rows * rows * 3
     filt = 9 * G * G * 147
     wi = 9 * G * G * T * T
+    # fl[t] (lane stride 1) and tile[r][q][c] (3) stored; per tap the tile
+    # read at lane stride 3 and fl at one word for every lane
     return {"gld.4.1": filt, "gld.4.3/3": img, "lst.4": img + filt,
-            "lld.4": 9 * n * n * 294, "fma.f32": 9 * n * n * 147,
+            "lld.4": 9 * n * n * 294, "lst.4.b1": img + filt,
+            "lld.4.b1": 9 * n * n * 147, "lld.4.b0": 9 * n * n * 147,
+            "fma.f32": 9 * n * n * 147,
             "gst.4.1": 9 * n * n, "bar.wi": wi, "bar.wg": 9 * G * G,
             "wg": 9 * G * G, "wi": wi}
 

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_count_names_match_the_oracle_vocabulary():
     names = P.count_names()
-    assert len(names) == 112 and len(set(names)) == 112
+    assert len(names) == P.PM_NCOUNT == 154 and len(set(names)) == 154
     orc = [n for n in C.names() if not n.startswith("foot.")]
     assert sorted(names) == sorted(orc)
 
@@ -228,7 +228,7 @@ def _small(v):
     return v
 
 
-@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext"])
+@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext", "bank"])
 def test_features_match_oracle(proj):
     vs = [_small(v) for v in suite_tiny() + suite_test()[::3]]
     arr = _lib_counts(vs)
@@ -238,7 +238,7 @@ def test_features_match_oracle(proj):
         np.testing.assert_array_equal(lib, np.array(orc, dtype=np.float64))
 
 
-@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext"])
+@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext", "bank"])
 def test_fit_matches_numpy_oracle(proj):
     vs = [_small(v) for v in suite_instructive(roofline_points=False, extended=True)
           + suite_test()]

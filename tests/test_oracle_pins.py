@@ -93,11 +93,29 @@ def test_lds_closed_forms(op):
     got = C.count(dict(family="lds", op=op, groups=G, wg=wg, b=4, R=R, W=W))
     want = {"gst.4.1": G * wg, "bar.wi": G * wg, "bar.wg": G, "wg": G,
             "wi": G * wg}
+    # bank stride 4 words: bin b4; the read kernel's initialisation moves one
+    # word per lane
     if op == "read":
-        want.update({"lst.4": G * W, "lld.4": G * wg * R, "add.f32": G * wg * R})
+        want.update({"lst.4": G * W, "lld.4": G * wg * R, "add.f32": G * wg * R,
+                     "lst.4.b1": G * W, "lld.4.b4": G * wg * R})
     else:
-        want.update({"lst.4": G * wg * R, "lld.4": G * wg})
+        want.update({"lst.4": G * wg * R, "lld.4": G * wg,
+                     "lst.4.b4": G * wg * R, "lld.4.b4": G * wg})
     assert got == want
+
+
+@pytest.mark.parametrize("b,bin_", [(1, "b1"), (3, "b1"), (2, "b2"), (6, "b2"), (4, "b4"),
+                                    (12, "b4"), (8, "b8"), (16, "b16"), (48, "b16"),
+                                    (32, "b32"), (64, "b32"), (96, "b32")])
+def test_lds_bank_stride_bins(b, bin_):
+    """Sec. 6.2 binning of the LDS stride: an access whose address moves b
+    words per lane falls in the bin of the power of two in b (lanes of one
+    wavefront that share a bank on power-of-two banks), 32 and beyond
+    together; the stride, not its size, decides (3 and 1, 6 and 2 agree)."""
+    G, wg, R, W = 2, 64, 5, 8192
+    got = C.count(dict(family="lds", op="read", groups=G, wg=wg, b=b, R=R, W=W))
+    assert got["lld.4." + bin_] == G * wg * R
+    assert sum(x for k, x in got.items() if k.startswith("lld.4.")) == got["lld.4"]
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
@@ -128,8 +146,13 @@ def test_matmul_closed_forms(n, m, l, T):
     got = C.count(dict(family="matmul", op="tiled", n=n, m=m, l=l, T=T))
     # every A element is fetched once per column tile, every B element once
     # per row tile; inner products run over padded k-tiles
+    # LDS by bank-stride bin (Sec. 6.2): the tiles are stored at lane stride
+    # 1; in the inner product As[ly][k] is one word for all lanes of a row
+    # (b0) and Bs[k][lx] moves one word per lane (b1)
     assert got == {"gld.4.1": n * m * GX + m * l * GY, "gst.4.1": n * l,
                    "lst.4": 2 * wi * KT, "lld.4": 2 * wi * KT * T,
+                   "lst.4.b1": 2 * wi * KT, "lld.4.b0": wi * KT * T,
+                   "lld.4.b1": wi * KT * T,
                    "fma.f32": wi * KT * T, "bar.wi": 2 * wi * KT,
                    "bar.wg": 2 * GX * GY * KT, "wg": GX * GY, "wi": wi}
     if T == 16 and n == m == l:  # the textbook n^3 forms
@@ -144,8 +167,11 @@ def test_matmul_closed_forms(n, m, l, T):
 def test_transpose_closed_forms(n, T):
     G = cdiv(n, T)
     got = C.count(dict(family="transpose", op="tiled", n=n, T=T))
+    # the tile is stored by rows (lane stride 1) and read by columns of the
+    # padded T + 1 rows: an odd word stride, bank-conflict free (b1)
     assert got == {"gld.4.1": n * n, "gst.4.1": n * n, "lst.4": n * n,
-                   "lld.4": n * n, "bar.wi": G * G * T * T, "bar.wg": G * G,
+                   "lld.4": n * n, "lst.4.b1": n * n, "lld.4.b1": n * n,
+                   "bar.wi": G * G * T * T, "bar.wg": G * G,
                    "wg": G * G, "wi": G * G * T * T}
     # the strided side moves n cells per lane; every cell is used: 4/>4
     got = C.count(dict(family="transpose", op="naive_wc", n=n, T=T))
@@ -163,8 +189,16 @@ def test_stencil_closed_forms(dt, n, T):
     e = 4 if dt == "f32" else 8
     got = C.count(dict(family="stencil", dtype=dt, n=n, T=T))
     halo = 4 * n * G  # four tile edges per tile row / column
+    # LDS stores: the halo columns go to a fixed column (one word for all
+    # lanes: the left column in all G tile columns, the right one in the
+    # n // T full ones); every other store and all five loads move one
+    # element per lane -- one word in fp32 (b1), two in fp64 (b2)
+    col0 = G * n + (n // T) * n
+    s1 = "b1" if e == 4 else "b2"
     assert got == {"gld.%d.1" % e: n * n + halo, "lst.%d" % e: n * n + halo,
-                   "lld.%d" % e: 5 * n * n, "add." + dt: 4 * n * n,
+                   "lst.%d.b0" % e: col0, "lst.%d.%s" % (e, s1): n * n + halo - col0,
+                   "lld.%d" % e: 5 * n * n, "lld.%d.%s" % (e, s1): 5 * n * n,
+                   "add." + dt: 4 * n * n,
                    "mul." + dt: 3 * n * n, "gst.%d.1" % e: n * n,
                    "bar.wi": G * G * T * T, "bar.wg": G * G, "wg": G * G,
                    "wi": G * G * T * T}
@@ -179,8 +213,11 @@ def test_nbody_closed_forms(N, G):
     got = C.count(dict(family="nbody", n=N, wg=G))
     # per pair 3 differences, 2 adds in r^2 and 1 add into the block's
     # partial; per (work-item, block) 1 add of the partial into the total
+    # a block's positions are stored at lane stride 1 and every pair reads
+    # one word for all lanes (b0)
     assert got == {"gld.4.3/3": 3 * N + 3 * N * B, "gst.4.1": N,
                    "lst.4": 3 * N * B, "lld.4": 3 * wi * N,
+                   "lst.4.b1": 3 * N * B, "lld.4.b0": 3 * wi * N,
                    "add.f32": 6 * wi * N + wi * B, "mul.f32": 3 * wi * N,
                    "spec.f32": wi * N, "bar.wi": 2 * wi * B,
                    "bar.wg": 2 * B * B, "wg": B, "wi": wi}
@@ -396,6 +433,23 @@ def test_features_ext_of_a_known_count_dict(wi, div):
     # arithmetic dominates the byte count the other way round
     c2 = dict(c, **{"gld.4.1": 1000})
     assert M.features_ext(c2)[156] == ops
+
+
+def test_features_bank_of_a_known_count_dict():
+    """The bank projection: the 90 global counts, then the 42 LDS counts by
+    (direction, size, bank-stride bin) in that order -- loads before stores,
+    4/8/16-byte, bins b0 b1 b2 b4 b8 b16 b32 -- in place of the 6 plain LDS
+    counts, then the rest of the extended list."""
+    c = {"gld.4.1": 10, "lld.4": 9, "lld.4.b0": 4, "lld.4.b1": 3, "lld.4.b32": 2,
+         "lst.8": 5, "lst.8.b2": 5, "fma.f32": 7, "wg": 3, "wi": 300}
+    f = M.features_bank(c)
+    e = M.features_ext(c)
+    assert len(f) == 193
+    assert f[:90] == e[:90] and f[132:] == e[96:]
+    lds = f[90:132]
+    assert lds[0] == 4 and lds[1] == 3 and lds[6] == 2     # lld.4: b0, b1, b32
+    assert lds[21 + 7 + 2] == 5                             # lst.8.b2
+    assert sum(lds) == 9 + 5 and e[90] == 9 and e[94] == 5  # plain: lld.4, lst.8
 
 
 # -------------------------------------------------------------- outputs ---
