@@ -79,7 +79,6 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
 struct FinShared {
     int64_t c[PM_NCOUNT];
     int64_t sc[MAXSTMT];
-    Contrib list[MAXSTMT * NENT];
     int bad, big;
 };
 
@@ -96,7 +95,7 @@ __device__ inline double wave_sum(double x) {
 }
 __device__ Agg wave_aggregates(const int64_t *c, int l) {
     Agg a{};
-    for (int k = l; k < PM_NCOUNT; k += 64) {
+    for (int k = l; k < C_LDSB; k += 64) {  // the binned LDS slots repeat [C_LDS, C_FLOP)
         const double x = (double)c[k];
         if (k < C_LDS) {
             const int d = k / 45, z = (k % 45) / NCLS, cl = k % NCLS;
@@ -163,10 +162,10 @@ __device__ double feature_dev(const int64_t *c, uint32_t proj, int j, const Agg 
 
 // Count vector and prediction of one variant by one work-group: every
 // thread calls this, the first wavefront does the work.  Lanes take the
-// statement counts and the non-zero contributions (compacted by ballot)
-// and add the contributions into the slots with LDS atomics (exact: while
+// statement counts, then the statements' contributions e = l, l + 64, ...,
+// adding each non-zero one into its slot with an LDS atomic (exact: while
 // every product is below 2^54 no sum of at most MAXSTMT*NENT of them can
-// pass int64; larger products take the per-slot sums with overflow
+// pass int64; larger products take exact per-slot sums with overflow
 // checks).  Lane l then owns the features i = l (mod 64); the
 // prediction's 64 partial sums meet in a butterfly, the order predict()
 // fixes.  st != PM_OK: zero counts, prediction 0.
@@ -179,21 +178,12 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
     if (t == 0) sh.bad = sh.big = 0;
     if (w0)
         for (int k = l; k < PM_NCOUNT; k += 64) sh.c[k] = 0;
-    __syncthreads();
     if (w0 && l < nst && !stmt_count(p, l, jobres, &sh.sc[l])) sh.bad = 1;
-    int n = 0;
-    for (int e0 = 0; e0 < nst * NENT; e0 += 64) {
-        Contrib cc;
-        const int e = e0 + l;
-        const bool has = w0 && e < nst * NENT && contrib(p, e / NENT, e % NENT, F, Fill, &cc);
-        const uint64_t mask = __ballot(has);
-        if (has) sh.list[n + __popcll(mask & ((1ull << l) - 1))] = cc;
-        n += __popcll(mask);
-    }
     __syncthreads();
     if (w0 && st == PM_OK) {
-        for (int i = l; i < n; i += 64) {
-            const Contrib cc = sh.list[i];
+        for (int e = l; e < nst * NENT; e += 64) {
+            Contrib cc;
+            if (!contrib(p, e / NENT, e % NENT, F, Fill, &cc)) continue;
             int64_t v;
             if (mul_ovf(sh.sc[cc.stmt], (int64_t)cc.mult, &v)) sh.bad = 1;
             else if (v >= (1ll << 54)) sh.big = 1;
@@ -207,8 +197,7 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
     __syncthreads();
     if (w0 && st == PM_OK && sh.big)  // products this large: exact sums slot by slot
         for (int k = l; k < PM_NCOUNT; k += 64)
-            if (k != C_BARWG && k != C_WG && k != C_WI &&
-                !slot_value(p, k, sh.list, n, sh.sc, &sh.c[k]))
+            if (k != C_BARWG && k != C_WG && k != C_WI && !slot_sum(p, k, F, Fill, sh.sc, &sh.c[k]))
                 sh.bad = 1;
     __syncthreads();
     if (t == 0 && st == PM_OK) sh.c[C_BARWG] = p.wg_size ? sh.c[C_BARWI] / p.wg_size : 0;

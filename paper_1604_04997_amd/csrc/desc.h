@@ -1855,8 +1855,10 @@ PM_HD bool contrib(const Prog &p, int si, int e, const int64_t *F, const int64_t
 // Value of count slot k from the contribution list; false on overflow.
 // Slots without entries are 0; C_WG / C_WI come from the launch shape and
 // C_BARWG from C_BARWI (set by the caller).
-PM_HD bool slot_value(const Prog &p, int k, const Contrib *list, int n, const int64_t *sc,
-                      int64_t *out) {
+// Slot k of the count vector summed exactly (overflow-checked) over every
+// statement's contributions.
+PM_HD bool slot_sum(const Prog &p, int k, const int64_t *F, const int64_t *Fill,
+                    const int64_t *sc, int64_t *out) {
     if (k == C_WG) {
         *out = p.n_wg;
         return true;
@@ -1864,31 +1866,25 @@ PM_HD bool slot_value(const Prog &p, int k, const Contrib *list, int n, const in
     if (k == C_WI) return !mul_ovf(p.n_wg, (int64_t)p.wg_size, out);
     int64_t v = 0, t;
     bool ok = true;
-    for (int i = 0; i < n; i++) {
-        if (list[i].slot != k) continue;
-        if (mul_ovf(sc[list[i].stmt], (int64_t)list[i].mult, &t) || add_ovf(v, t, &v)) ok = false;
-    }
+    for (int si = 0; si < p.nstmt; si++)
+        for (int e = 0; e < NENT; e++) {
+            Contrib cc;
+            if (!contrib(p, si, e, F, Fill, &cc) || cc.slot != k) continue;
+            if (mul_ovf(sc[si], (int64_t)cc.mult, &t) || add_ovf(v, t, &v)) ok = false;
+        }
     *out = v;
     return ok;
 }
-
-// Assemble the count vector from statement counts (component job results
-// `jobres`) and per-array footprint sizes F/Fill.  Returns a status.
 PM_HD int finalize(const Prog &p, const int64_t *jobres, const int64_t *F,
                    const int64_t *Fill, int64_t *c) {
     for (int i = 0; i < PM_NCOUNT; i++) c[i] = 0;
     if (p.status != PM_OK) return p.status;
     bool ok = true;
     int64_t sc[MAXSTMT];
-    Contrib list[MAXSTMT * NENT];
-    int n = 0;
-    for (int si = 0; si < p.nstmt; si++) {
+    for (int si = 0; si < p.nstmt; si++)
         if (!stmt_count(p, si, jobres, &sc[si])) ok = false;
-        for (int e = 0; e < NENT; e++)
-            if (contrib(p, si, e, F, Fill, &list[n])) n++;
-    }
     for (int k = 0; k < PM_NCOUNT; k++)
-        if (k != C_BARWG && !slot_value(p, k, list, n, sc, &c[k])) ok = false;
+        if (k != C_BARWG && !slot_sum(p, k, F, Fill, sc, &c[k])) ok = false;
     c[C_BARWG] = p.wg_size ? c[C_BARWI] / p.wg_size : 0;
     if (!ok) {
         for (int i = 0; i < PM_NCOUNT; i++) c[i] = 0;
