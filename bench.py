@@ -279,6 +279,43 @@ def c4_phase(ctx, P, vs, pred, per_family=8):
     return out
 
 
+def qpoly_phase(ctx, P, vs, counts, reps=20):
+    """Counts as quasi-polynomials of the size (Sec. 3.2, re-evaluated
+    cheaply, Sec. 2): for every single-size configuration of the sweep
+    (stencil and transpose by op, dtype and tile) the counts are derived
+    once from the batched counter (period = the tile, from n = 64), then
+    every such sweep variant is evaluated on the host (pm_qpoly_eval_many)
+    and compared with the GPU's counts of the timed pass."""
+    groups = {}
+    for i, v in enumerate(vs):
+        if v["family"] in ("stencil", "transpose"):
+            groups.setdefault((v["family"], v.get("op"), v.get("dtype"), v["T"]), []).append(i)
+    t0 = time.perf_counter()
+    qps = {}
+    for key, idx in groups.items():
+        d = {k: x for k, x in vs[idx[0]].items() if k != "seed"}
+        d["n"] = 0
+        qps[key] = ctx.qpoly_derive(d, fields=1, scale=1, period=key[3], x0=64)
+    t_derive = time.perf_counter() - t0
+    xs = {key: [vs[i]["n"] for i in idx] for key, idx in groups.items()}
+    best = 1e9
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        outs = {key: P.qpoly_eval_many(qps[key], xs[key]) for key in groups}
+        best = min(best, time.perf_counter() - t1)
+    n = sum(len(idx) for idx in groups.values())
+    mism = 0
+    for key, idx in groups.items():
+        ev = P.counts_numpy(outs[key])
+        mism += int((ev != counts[idx]).any(axis=1).sum())
+    assert mism == 0, "%d quasi-polynomial evaluations differ from the counter" % mism
+    return {"configurations": len(groups), "variants": n,
+            "derivation_s": round(t_derive, 4),
+            "derivation_variants_counted": int(sum(6 * k[3] for k in groups)),
+            "eval_per_s": round(n / best, 1), "us_per_eval": round(best / n * 1e6, 3),
+            "equal_to_counter": n - mism}
+
+
 def suite_roofline(ctx, P):
     """Unit-stride stream kernels against the 8 TB/s HBM peak (1 GiB+
     working sets, far past the 256 MB last-level cache) and FMA loops
@@ -539,6 +576,9 @@ def main():
         torch.cuda.synchronize()
         del cts
 
+    qpoly = qpoly_phase(ctx, P, vs, counts)
+    log("quasi-polynomials:", json.dumps(qpoly))
+
     c4 = None
     if models:
         log("model ranking of the sweep: measuring the top-8 per family")
@@ -639,7 +679,7 @@ def main():
         cpu = cpu_baseline(vs, counts, P.count_names(), args.cpu_seconds)
         log("cpu oracle:", cpu)
 
-    detail = {"model": model_info, "tiny_suite": c1, "sweep_ranking": c4,
+    detail = {"model": model_info, "tiny_suite": c1, "sweep_ranking": c4, "qpoly": qpoly,
               "autotune": tune, "serving": serving, "suite_roofline": suite_roof,
               "counter_schedule": {
                   "chosen": sched, "default": default_sched, "model": sched_model,
@@ -682,6 +722,7 @@ def main():
         "counter_schedule": {"model_choice": sched, "model_choice_ms": sched_model["chosen_ms"],
                              "fastest_timed_ms": sched_model["exhaustive_best_ms"]},
         "sweep_ranking": {k: c4[k] for k in ("mean_spearman", "geomean_rel_err")} if c4 else None,
+        "qpoly": {k: qpoly[k] for k in ("variants", "us_per_eval", "equal_to_counter")},
         "autotune": {k: round(tune[k], 4) for k in ("choice_is_best", "geomean_slowdown",
                                                     "mean_spearman")} if tune else None,
         "serving": srv,

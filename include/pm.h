@@ -252,6 +252,42 @@ pm_status pm_count_device_noalloc(pm_ctx *ctx, const pm_variant *d_v, size_t nv,
                                   pm_counts *d_counts, const pm_model *m, double *d_t,
                                   int32_t *d_status, void *hip_stream);
 
+/*
+ * Counts as quasi-polynomials of one size, re-evaluated in O(1) (Sec. 3.2:
+ * the counts are piecewise quasi-polynomials in the size parameters; Sec. 2:
+ * once found they are cheaply re-evaluated for changed sizes).  Take the
+ * variant `base` with each size field n[i] in `fields` (bit i) set to
+ * scale * x.  For x >= x0 every count is then, on each residue
+ * r = (x - x0) mod period, a polynomial of degree at most PM_QPOLY_DEGREE
+ * in q = (x - x0) div period, written in the binomial basis:
+ * count = sum_k coef[r][k] * C(q, k).
+ * pm_qpoly_derive finds the coefficients from the counter itself: one
+ * batched pm_count of the variants at x = x0 + r + period*q for every
+ * residue r and q = 0 .. PM_QPOLY_DEGREE + 2, exact integer forward
+ * differences in q, and a check that the differences of order
+ * PM_QPOLY_DEGREE + 1 vanish at both extra points of every residue and
+ * count.  PM_EINVAL (the message says which) for a bad argument, an invalid
+ * variant at some x, or counts that are no such quasi-polynomial with this
+ * period from x0; the status of pm_count otherwise.  `out` is caller-owned.
+ * pm_qpoly_eval writes the counts at x (host, no GPU): PM_EINVAL for
+ * x < x0, PM_EOVERFLOW when a count leaves int64.
+ */
+#define PM_QPOLY_MAXPERIOD 64
+#define PM_QPOLY_DEGREE 3
+typedef struct {
+    pm_variant base;
+    uint32_t fields;
+    int32_t period;
+    int64_t scale, x0;
+    int64_t coef[PM_QPOLY_MAXPERIOD][PM_QPOLY_DEGREE + 1][PM_NCOUNT];
+} pm_qpoly;
+pm_status pm_qpoly_derive(pm_ctx *ctx, const pm_variant *base, uint32_t fields, int64_t scale,
+                          int32_t period, int64_t x0, pm_qpoly *out);
+pm_status pm_qpoly_eval(const pm_qpoly *qp, int64_t x, pm_counts *out);
+/* pm_qpoly_eval at nx sizes xs[nx] (host) into out[nx]; stops at the first
+ * failing size and returns its status. */
+pm_status pm_qpoly_eval_many(const pm_qpoly *qp, const int64_t *xs, size_t nx, pm_counts *out);
+
 /* Size the context's device arenas for batches of up to nv variants whose
  * footprint bitmaps total up to bitmap_bytes.  Fails with PM_ENOMEM beyond
  * the HBM budget. */

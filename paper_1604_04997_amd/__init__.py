@@ -65,6 +65,16 @@ class Schedule(ctypes.Structure):
                 ("tail_wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+QPOLY_MAXPERIOD = 64
+QPOLY_DEGREE = 3
+
+
+class QPoly(ctypes.Structure):
+    _fields_ = [("base", Variant), ("fields", ctypes.c_uint32), ("period", ctypes.c_int32),
+                ("scale", ctypes.c_int64), ("x0", ctypes.c_int64),
+                ("coef", ctypes.c_int64 * PM_NCOUNT * (QPOLY_DEGREE + 1) * QPOLY_MAXPERIOD)]
+
+
 class PMError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (STATUS.get(code, code), msg))
@@ -102,6 +112,11 @@ def lib():
             "pm_count_device": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, P(Model), vp, vp, vp]),
             "pm_count_device_noalloc": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, P(Model), vp, vp, vp]),
             "pm_reserve": (ctypes.c_int, [vp, ctypes.c_size_t, ctypes.c_size_t]),
+            "pm_qpoly_derive": (ctypes.c_int, [vp, P(Variant), ctypes.c_uint32, ctypes.c_int64,
+                                               ctypes.c_int32, ctypes.c_int64, P(QPoly)]),
+            "pm_qpoly_eval": (ctypes.c_int, [P(QPoly), ctypes.c_int64, P(Counts)]),
+            "pm_qpoly_eval_many": (ctypes.c_int, [P(QPoly), P(ctypes.c_int64), ctypes.c_size_t,
+                                                  P(Counts)]),
             "pm_bitmap_bytes": (ctypes.c_int, [P(Variant), P(ctypes.c_size_t)]),
             "pm_features": (ctypes.c_int, [P(Counts), ctypes.c_uint32, P(ctypes.c_double), P(ctypes.c_uint32)]),
             "pm_fit": (ctypes.c_int, [P(Counts), P(ctypes.c_double), ctypes.c_size_t, ctypes.c_uint32,
@@ -235,6 +250,33 @@ def fit(counts, T, proj: str):
     return m, cond.value, np.array(resid[:]), rank.value
 
 
+def qpoly_eval(qp: QPoly, x: int) -> Counts:
+    """Counts of the quasi-polynomial at size x (host, O(1))."""
+    c = Counts()
+    _check(lib().pm_qpoly_eval(ctypes.byref(qp), int(x), ctypes.byref(c)))
+    return c
+
+
+def qpoly_eval_many(qp: QPoly, xs) -> ctypes.Array:
+    """Counts of the quasi-polynomial at every size in xs (host)."""
+    n = len(xs)
+    xa = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in xs])
+    out = (Counts * max(n, 1))()
+    _check(lib().pm_qpoly_eval_many(ctypes.byref(qp), xa, n, out))
+    return out
+
+
+def qpoly_sizes(d: dict, fields: int, scale: int, x: int) -> dict:
+    """The variant dict with the size fields of `fields` set to scale * x
+    (the variant a quasi-polynomial's value at x describes)."""
+    keys = ["n", "m", "l"] if d["family"] == "matmul" else ["n"]
+    out = dict(d)
+    for i, k in enumerate(keys):
+        if (fields >> i) & 1:
+            out[k] = scale * x
+    return out
+
+
 def buffers(d: dict):
     """[(bytes, role)] of the variant's kernel buffers."""
     v = variant_struct(d)
@@ -359,6 +401,17 @@ class Context:
             ctypes.byref(model) if model is not None else None,
             ctypes.c_void_p(d_t_ptr) if d_t_ptr else None,
             ctypes.c_void_p(d_status_ptr), ctypes.c_void_p(stream_ptr)))
+
+    def qpoly_derive(self, d: dict, fields: int = 1, scale: int = 1, period: int = 1,
+                     x0: int = 1) -> QPoly:
+        """pm_qpoly_derive: the counts of `d` with its size fields (bit 0 n,
+        1 m, 2 l) set to scale * x, as quasi-polynomials in x derived by the
+        batched counter."""
+        qp = QPoly()
+        v = variant_struct(d)
+        _check(lib().pm_qpoly_derive(self._h, ctypes.byref(v), fields, scale, period, x0,
+                                     ctypes.byref(qp)))
+        return qp
 
     def count_device_noalloc(self, d_variants_ptr, nv, d_counts_ptr, model, d_t_ptr,
                              d_status_ptr, stream_ptr):

@@ -684,6 +684,91 @@ pm_status pm_count_device_noalloc(pm_ctx *c, const pm_variant *d_v, size_t nv,
     return PM_OK;
 }
 
+pm_status pm_qpoly_derive(pm_ctx *c, const pm_variant *base, uint32_t fields, int64_t scale,
+                          int32_t period, int64_t x0, pm_qpoly *out) {
+    if (!c || !base || !out) return (pm_status)set_err(PM_EINVAL, "null argument");
+    if (fields == 0 || fields > 7 || scale < 1 || period < 1 || period > PM_QPOLY_MAXPERIOD ||
+        x0 < 1)
+        return (pm_status)set_err(PM_EINVAL, "qpoly: fields 1..7, scale >= 1, period 1..64, x0 >= 1");
+    constexpr int DEG = PM_QPOLY_DEGREE, NQ = PM_QPOLY_DEGREE + 3;
+    const int64_t xmax = x0 + (int64_t)period * NQ;
+    if (xmax > (int64_t)1 << 40 || scale > ((int64_t)1 << 40) / xmax)
+        return (pm_status)set_err(PM_EINVAL, "qpoly: sizes too large");
+    std::vector<pm_variant> vs((size_t)period * NQ);
+    for (int r = 0; r < period; r++)
+        for (int q = 0; q < NQ; q++) {
+            pm_variant v = *base;
+            const int64_t x = x0 + r + (int64_t)period * q;
+            for (int i = 0; i < 3; i++)
+                if ((fields >> i) & 1) v.n[i] = scale * x;
+            vs[(size_t)r * NQ + q] = v;
+        }
+    std::vector<pm_counts> cnt(vs.size());
+    const pm_status st = pm_count(c, vs.data(), vs.size(), cnt.data());
+    if (st != PM_OK) return st;
+    std::memset(out, 0, sizeof(*out));
+    out->base = *base;
+    out->fields = fields;
+    out->period = period;
+    out->scale = scale;
+    out->x0 = x0;
+    for (int r = 0; r < period; r++)
+        for (int k = 0; k < PM_NCOUNT; k++) {
+            // forward differences in q, exact in 128 bits
+            __int128 d[NQ];
+            for (int q = 0; q < NQ; q++) d[q] = cnt[(size_t)r * NQ + q].c[k];
+            for (int ord = 0; ord <= DEG + 1; ord++) {
+                if (ord <= DEG) {
+                    if (d[0] > INT64_MAX || d[0] < INT64_MIN)
+                        return (pm_status)set_err(PM_EOVERFLOW, "qpoly: coefficient beyond int64");
+                    out->coef[r][ord][k] = (int64_t)d[0];
+                } else if (d[0] != 0 || d[1] != 0) {
+                    return (pm_status)set_err(
+                        PM_EINVAL, "qpoly: count slot " + std::to_string(k) + " at residue " +
+                                       std::to_string(r) + " is no polynomial of degree <= " +
+                                       std::to_string(DEG) + " in q (period " +
+                                       std::to_string(period) + " from x0 " + std::to_string(x0) + ")");
+                }
+                for (int q = 0; q + ord + 1 < NQ; q++) d[q] = d[q + 1] - d[q];
+            }
+        }
+    return PM_OK;
+}
+
+pm_status pm_qpoly_eval(const pm_qpoly *qp, int64_t x, pm_counts *out) {
+    if (!qp || !out) return (pm_status)set_err(PM_EINVAL, "null argument");
+    if (qp->period < 1 || qp->period > PM_QPOLY_MAXPERIOD)
+        return (pm_status)set_err(PM_EINVAL, "qpoly: not derived");
+    if (x < qp->x0) return (pm_status)set_err(PM_EINVAL, "qpoly: x below x0");
+    if (x - qp->x0 > ((int64_t)1 << 50)) return (pm_status)set_err(PM_EOVERFLOW, "qpoly: x too large");
+    const int64_t r = (x - qp->x0) % qp->period, q = (x - qp->x0) / qp->period;
+    // C(q, k) for k = 0 .. PM_QPOLY_DEGREE
+    __int128 b[PM_QPOLY_DEGREE + 1];
+    b[0] = 1;
+    for (int k = 1; k <= PM_QPOLY_DEGREE; k++) b[k] = b[k - 1] * (q - (k - 1)) / k;
+    for (int k = 0; k < PM_NCOUNT; k++) {
+        __int128 v = 0, t;
+        bool ovf = false;
+        for (int j = 0; j <= PM_QPOLY_DEGREE; j++) {
+            ovf |= __builtin_mul_overflow((__int128)qp->coef[r][j][k], b[j], &t);
+            ovf |= __builtin_add_overflow(v, t, &v);
+        }
+        if (ovf || v > INT64_MAX || v < INT64_MIN)
+            return (pm_status)set_err(PM_EOVERFLOW, "qpoly: count beyond int64 at this size");
+        out->c[k] = (int64_t)v;
+    }
+    return PM_OK;
+}
+
+pm_status pm_qpoly_eval_many(const pm_qpoly *qp, const int64_t *xs, size_t nx, pm_counts *out) {
+    if (!qp || (nx && (!xs || !out))) return (pm_status)set_err(PM_EINVAL, "null argument");
+    for (size_t i = 0; i < nx; i++) {
+        const pm_status st = pm_qpoly_eval(qp, xs[i], &out[i]);
+        if (st != PM_OK) return st;
+    }
+    return PM_OK;
+}
+
 pm_status pm_reserve(pm_ctx *c, size_t nv, size_t bitmap_bytes) {
     if (!c) return (pm_status)set_err(PM_EINVAL, "null context");
     if (nv > PM_BATCH_MAX) return (pm_status)set_err(PM_EINVAL, "batch larger than PM_BATCH_MAX");

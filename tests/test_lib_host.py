@@ -302,3 +302,28 @@ def test_host_counts_full_size_closed_forms():
     from closed_forms import counts as closed
     for v in suite_batched(4096) + suite_instructive() + suite_test() + suite_tiny():
         assert P.count_host(v) == closed(v), v
+
+
+def test_qpoly_eval_binomial_basis():
+    """pm_qpoly_eval on a hand-made form: on residue r of (x - x0) mod 2,
+    count = c0 + c1 q + c2 C(q,2) + c3 C(q,3), q = (x - x0) div 2; below x0
+    refused; a count past int64 reported."""
+    import math
+    qp = P.QPoly()
+    qp.period, qp.x0, qp.scale, qp.fields = 2, 5, 1, 1
+    co = {0: [3, 2, 4, 6], 1: [-7, 0, 0, 1]}
+    for r, cs in co.items():
+        for j, x in enumerate(cs):
+            qp.coef[r][j][0] = x
+            qp.coef[r][j][111] = 1 if j == 1 else 0   # wi = q on both residues
+    for x in list(range(5, 40)) + [10 ** 6 + 3]:
+        r, q = (x - 5) % 2, (x - 5) // 2
+        want = sum(c * math.comb(q, j) for j, c in enumerate(co[r]))
+        got = P.qpoly_eval(qp, x)
+        assert got.c[0] == want and got.c[111] == q and got.c[5] == 0, x
+    with pytest.raises(P.PMError):
+        P.qpoly_eval(qp, 4)
+    qp.coef[0][3][7] = 1 << 62
+    with pytest.raises(P.PMError) as e:
+        P.qpoly_eval(qp, 5 + 2 * 100)
+    assert e.value.code == -5
