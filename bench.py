@@ -237,6 +237,60 @@ def model_phase(ctx, P, proj_list=("p12", "full", "ext", "bank")):
     return out, models, (meas, Tm, test, Tt)
 
 
+def wg_phase(ctx, P, models, fitdata, proj_list=("ext", "p12")):
+    """Work-group size sensitivity (Sec. 5): the measurement kernels and
+    the n-body test kernel at 128, 256 and 512 work-items per group, total
+    work fixed.  Per kernel, the spread of measured and of predicted run
+    time over the sizes (largest / smallest - 1); per size, the geometric
+    mean relative error of the fitted model and its rank among the sizes
+    (1 = most accurate); and the test suite's error when the model is
+    fitted, as in the paper, on the measurement kernels at every size
+    rather than at 256 alone."""
+    from synth import WG_SIZES, suite_wg
+    vs = suite_wg()
+    log("work-group sizes: measuring %d variants" % len(vs))
+    T, low = measure_suite(ctx, P, vs)
+    cw = ctx.count_raw(vs)
+    meas, Tm, test, Tt = fitdata
+    cm = ctx.count_raw(meas)
+    bases = sorted({v["base"] for v in vs})
+    of = {b: [i for i, v in enumerate(vs) if v["base"] == b] for b in bases}
+
+    def spread(t):
+        sp = np.array([max(t[i] for i in of[b]) / min(t[i] for i in of[b]) - 1 for b in bases])
+        worst = bases[int(np.argmax(sp))]
+        v = vs[of[worst][0]]
+        return {"median": round(float(np.median(sp)), 4), "max": round(float(sp.max()), 4),
+                "under_30pct": round(float(np.mean(sp < 0.3)), 4),
+                "largest": "%s.%s" % (v["family"], v.get("op", v.get("dtype", "")))}
+
+    out = {"variants": len(vs), "kernels": len(bases), "sizes": list(WG_SIZES),
+           "below_launch_floor": int(low.sum()), "runtime_spread": spread(T)}
+    wrows = [i for i, v in enumerate(vs) if v["family"] != "nbody"]
+    for proj in proj_list:
+        if proj not in models:
+            continue
+        pred = ctx.predict(models[proj], vs)
+        err = np.abs(pred - T) / T
+        by = {wg: geomean([err[i] for i, v in enumerate(vs) if v["wg"] == wg]) for wg in WG_SIZES}
+        order = sorted(WG_SIZES, key=lambda w: by[w])
+        nb = {wg: geomean([err[i] for i, v in enumerate(vs) if v["wg"] == wg and
+                           v["family"] == "nbody"]) for wg in WG_SIZES}
+        rows = [i for i, v in enumerate(meas) if proj in ("ext", "bank") or not v.get("extension")]
+        sub = (P.Counts * (len(rows) + len(wrows)))(*([cm[i] for i in rows] +
+                                                      [cw[i] for i in wrows]))
+        m2, _, _, _ = P.fit(sub, np.concatenate([Tm[rows], T[wrows]]), proj)
+        e1 = np.abs(ctx.predict(models[proj], test) - Tt) / Tt
+        e2 = np.abs(ctx.predict(m2, test) - Tt) / Tt
+        out[proj] = {"geomean_by_wg": {str(w): round(by[w], 4) for w in WG_SIZES},
+                     "wg256_rank": order.index(256) + 1,
+                     "nbody_geomean_by_wg": {str(w): round(nb[w], 4) for w in WG_SIZES},
+                     "predicted_spread": spread(pred),
+                     "test_geomean_fit_wg256": round(geomean(e1), 4),
+                     "test_geomean_fit_all_wg": round(geomean(e2), 4)}
+    return out
+
+
 def c4_phase(ctx, P, vs, pred, per_family=8):
     """Model ranking of the batched sweep: every variant's FP64 prediction
     comes from the counted pass; per family the `per_family` variants with
@@ -244,15 +298,15 @@ def c4_phase(ctx, P, vs, pred, per_family=8):
     autotuning objective) are measured (4 untimed + 26 timed runs, minimum).
     Reported per family: the rank correlation of predicted and measured rate
     among them, whether the predicted-best is the measured-best, and the
-    geometric-mean relative error of their predictions."""
+    geometric-mean relative error of their predictions.  The top variants'
+    predicted rates lie close together, so the same is reported for
+    `per_family` variants spread evenly over the family's predicted-rate
+    ranking (its first, last and evenly spaced ranks between)."""
     import torch
-    out, errs = {}, []
-    for fam in ("matmul", "stencil", "transpose"):
-        idx = [i for i, v in enumerate(vs) if v["family"] == fam]
-        rate = {i: domain_points(vs[i]) / pred[i] for i in idx}
-        top = sorted(idx, key=lambda i: -rate[i])[:per_family]
+
+    def measure(sel):
         T = []
-        for i in top:
+        for i in sel:
             ts, _ = P.device_buffers(vs[i], vs[i].get("seed", i), fast=True)
             r = ctx.measure_until(vs[i], ts, warmup=4, reps=26)
             assert r["status"] == 0
@@ -260,22 +314,41 @@ def c4_phase(ctx, P, vs, pred, per_family=8):
             del ts
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        T = np.array(T)
-        pr = np.array([rate[i] for i in top])
-        mr = np.array([domain_points(vs[i]) for i in top]) / T
+        return np.array(T)
+
+    def agree(sel, T, rate):
+        pr = np.array([rate[i] for i in sel])
+        mr = np.array([domain_points(vs[i]) for i in sel]) / T
         rp, rm = np.argsort(np.argsort(-pr)), np.argsort(np.argsort(-mr))
-        e = np.abs(np.array([pred[i] for i in top]) - T) / T
+        e = np.abs(np.array([pred[i] for i in sel]) - T) / T
+        rows = [[vs[i].get("op", vs[i].get("dtype")), vs[i].get("T"), int(domain_points(vs[i])),
+                 round(float(pred[i]) * 1e3, 4), round(float(t) * 1e3, 4)]
+                for i, t in zip(sel, T)]
+        return float(np.corrcoef(rp, rm)[0, 1]), bool(rm[0] == 0), e, rows
+
+    out, errs, serrs = {}, [], []
+    for fam in ("matmul", "stencil", "transpose"):
+        idx = [i for i, v in enumerate(vs) if v["family"] == fam]
+        rate = {i: domain_points(vs[i]) / pred[i] for i in idx}
+        order = sorted(idx, key=lambda i: -rate[i])
+        top = order[:per_family]
+        rho, best, e, rows = agree(top, measure(top), rate)
         errs += list(e)
-        out[fam] = {"spearman": round(float(np.corrcoef(rp, rm)[0, 1]), 4),
-                    "predicted_best_is_measured_best": bool(rm[0] == 0),
-                    "geomean_rel_err": round(geomean(e), 4),
-                    "measured": [[vs[i].get("op"), vs[i].get("T"), int(domain_points(vs[i])),
-                                  round(float(pred[i]) * 1e3, 4), round(float(t) * 1e3, 4)]
-                                 for i, t in zip(top, T)]}
+        spread = [order[int(k)] for k in np.linspace(0, len(order) - 1, per_family).round()]
+        srho, _, se, srows = agree(spread, measure(spread), rate)
+        serrs += list(se)
+        out[fam] = {"spearman": round(rho, 4), "predicted_best_is_measured_best": best,
+                    "geomean_rel_err": round(geomean(e), 4), "measured": rows,
+                    "spread_spearman": round(srho, 4),
+                    "spread_geomean_rel_err": round(geomean(se), 4), "spread_measured": srows}
+    fams = ("matmul", "stencil", "transpose")
     out["geomean_rel_err"] = round(geomean(errs), 4)
-    out["mean_spearman"] = round(float(np.mean([out[f]["spearman"] for f in
-                                                ("matmul", "stencil", "transpose")])), 4)
-    out["note"] = "measured rows: op, tile, domain points, predicted ms, measured ms"
+    out["mean_spearman"] = round(float(np.mean([out[f]["spearman"] for f in fams])), 4)
+    out["spread_geomean_rel_err"] = round(geomean(serrs), 4)
+    out["spread_mean_spearman"] = round(float(np.mean([out[f]["spread_spearman"]
+                                                       for f in fams])), 4)
+    out["note"] = ("measured rows: op (stencil: dtype), tile, domain points, predicted ms, "
+                   "measured ms")
     return out
 
 
@@ -494,12 +567,14 @@ def main():
     log("launch floor: %.2f us" % (floor * 1e6))
 
     # ------------------------------------------------------------- model --
-    model_info, models, c1 = None, {}, None
+    model_info, models, c1, wgs = None, {}, None, None
     if not args.skip_model:
         c1 = c1_phase(ctx, P)
         log("tiny plain-method suite:", json.dumps(c1))
-        model_info, models, _ = model_phase(ctx, P)
+        model_info, models, fitdata = model_phase(ctx, P)
         log("model:", json.dumps(model_info))
+        wgs = wg_phase(ctx, P, models, fitdata)
+        log("work-group sizes:", json.dumps(wgs))
     # prediction: the paper's property list with its named extensions
     m = models.get("ext") or P.model_struct("ext", [1e-12] * 157)
 
@@ -679,7 +754,8 @@ def main():
         cpu = cpu_baseline(vs, counts, P.count_names(), args.cpu_seconds)
         log("cpu oracle:", cpu)
 
-    detail = {"model": model_info, "tiny_suite": c1, "sweep_ranking": c4, "qpoly": qpoly,
+    detail = {"model": model_info, "tiny_suite": c1, "work_group_sizes": wgs,
+              "sweep_ranking": c4, "qpoly": qpoly,
               "autotune": tune, "serving": serving, "suite_roofline": suite_roof,
               "counter_schedule": {
                   "chosen": sched, "default": default_sched, "model": sched_model,
@@ -721,8 +797,16 @@ def main():
         "kernel_ms": {k: round(x, 4) for k, x in phase_ms.items()},
         "counter_schedule": {"model_choice": sched, "model_choice_ms": sched_model["chosen_ms"],
                              "fastest_timed_ms": sched_model["exhaustive_best_ms"]},
-        "sweep_ranking": {k: c4[k] for k in ("mean_spearman", "geomean_rel_err")} if c4 else None,
+        "sweep_ranking": {k: c4[k] for k in ("mean_spearman", "geomean_rel_err",
+                                             "spread_mean_spearman", "spread_geomean_rel_err")}
+        if c4 else None,
         "qpoly": {k: qpoly[k] for k in ("variants", "us_per_eval", "equal_to_counter")},
+        "work_group_sizes": {
+            "runtime_spread_median": wgs["runtime_spread"]["median"],
+            "ext_geomean_by_wg": wgs["ext"]["geomean_by_wg"],
+            "ext_test_fit_wg256_vs_all": [wgs["ext"]["test_geomean_fit_wg256"],
+                                          wgs["ext"]["test_geomean_fit_all_wg"]]}
+        if wgs and "ext" in wgs else None,
         "autotune": {k: round(tune[k], 4) for k in ("choice_is_best", "geomean_slowdown",
                                                     "mean_spearman")} if tune else None,
         "serving": srv,

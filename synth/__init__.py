@@ -7,4 +7,5 @@ random number generation for kernel input buffers and the parameter lists
 from .inputs import (  # noqa: F401
     SEED_BASE, seed_for, uniform,
     suite_tiny, suite_instructive, suite_test, suite_batched, serving_trace,
+    WG_SIZES, suite_wg,
 )

@@ -194,6 +194,47 @@ def suite_test():
 
 
 # ---------------------------------------------------------------------------
+# work-group size sensitivity (Sec. 5): the same kernels at several group sizes
+# ---------------------------------------------------------------------------
+WG_SIZES = (128, 256, 512)
+
+
+def suite_wg(sizes=WG_SIZES):
+    """Measurement kernels (global stream by direction and lane stride, FMA
+    chains, rsqrt, LDS by bank stride, barriers) and the n-body test kernel,
+    each at every work-group size in `sizes` with the total number of
+    work-items fixed.  `base` numbers the kernel a variant belongs to: the
+    variants of one base differ only in work-group size."""
+    bases = []
+    for op in ("load", "store", "copy"):
+        for s in (1, 2, 4):
+            for n in (1 << 23, 1 << 26):
+                bases.append(lambda wg, op=op, s=s, n=n: _v(
+                    "stream", op=op, dtype="f32", n=n, wg=wg, s=s, gs=1, vec=1, U=1))
+    for dt in ("f32", "f64"):
+        for F in (64, 256):
+            bases.append(lambda wg, dt=dt, F=F: _v("fma", dtype=dt, n=1 << 24, wg=wg, F=F, K=8))
+    bases.append(lambda wg: _v("rsqrt", n=1 << 22, wg=wg, F=64, K=4))
+    for op in ("read", "write"):
+        for b in (1, 4, 32):
+            bases.append(lambda wg, op=op, b=b: _v("lds", op=op, groups=(1 << 20) // wg,
+                                                   wg=wg, b=b, R=1024, W=4096))
+    for B in (4, 16):
+        bases.append(lambda wg, B=B: _v("barrier", groups=(1 << 20) // wg, wg=wg, B=B))
+    for n in (16384, 65536):
+        bases.append(lambda wg, n=n: _v("nbody", n=n, wg=wg, kernel="nbody"))
+    out = []
+    for bi, mk in enumerate(bases):
+        for wg in sizes:
+            v = mk(wg)
+            v["base"] = bi
+            out.append(v)
+    for i, v in enumerate(out):
+        v["seed"] = seed_for(6, i)
+    return out
+
+
+# ---------------------------------------------------------------------------
 # workload 4: batched autotune sweep over uneven iteration domains
 # ---------------------------------------------------------------------------
 def _not_multiple(x: int, T: int) -> int:

@@ -232,3 +232,35 @@ def test_model_ranked_counter_schedule(ctx):
             assert {names[i]: int(x) for i, x in enumerate(got[k]) if x} == _strip(C.count(v)), v
     finally:
         ctx.set_schedule(**default)
+
+
+def test_work_group_size_enters_predictions_through_the_group_count(ctx):
+    """Sec. 5: kernel configurations that differ only in work-group size get
+    the same prediction but for the per-group launch overhead.  For the
+    study's measurement kernels (stream, FMA, rsqrt, LDS writes, barriers)
+    at 128, 256 and 512 work-items per group, the counted features differ
+    in the group count alone, and the device predictions differ by its
+    weight times the change in groups."""
+    from synth import suite_wg
+    vs = [v for v in suite_wg() if v["family"] in ("stream", "fma", "rsqrt", "barrier")
+          or (v["family"] == "lds" and v["op"] == "write")]
+    print("wg study variants", len(vs), flush=True)
+    counts = ctx.count_raw(vs)
+    feats = np.array([P.features(counts[i], "ext") for i in range(len(vs))])
+    alpha = np.random.default_rng(11).uniform(1e-12, 1e-9, P.NFEAT["ext"])
+    pred = ctx.predict(P.model_struct("ext", alpha), vs)
+    wg_col = set()
+    for b in sorted({v["base"] for v in vs}):
+        idx = [i for i, v in enumerate(vs) if v["base"] == b]
+        for i in idx[1:]:
+            j = idx[0]
+            d = feats[i] - feats[j]
+            nz = np.flatnonzero(d)
+            assert len(nz) == 1, (vs[i], nz)
+            k = int(nz[0])
+            wg_col.add(k)
+            groups = lambda v: v.get("groups", v.get("n", 0) // v["wg"])
+            assert d[k] == groups(vs[i]) - groups(vs[j])
+            want = alpha[k] * d[k]
+            assert abs((pred[i] - pred[j]) - want) <= 1e-12 * max(abs(pred[i]), abs(pred[j]))
+    assert len(wg_col) == 1

@@ -583,3 +583,54 @@ def test_sweep_golden_file_matches_generator_and_closed_forms():
     for k, v in enumerate(vs):
         got = {nm: int(x) for nm, x in zip(names, g["counts"][k]) if x}
         assert got == closed(v), (k, v)
+
+
+WG_SMALL = [
+    lambda wg: dict(family="stream", op="load", dtype="f32", n=1 << 13, wg=wg, s=2, gs=1, vec=1, U=1),
+    lambda wg: dict(family="stream", op="copy", dtype="f32", n=1 << 13, wg=wg, s=4, gs=1, vec=1, U=1),
+    lambda wg: dict(family="stream", op="store", dtype="f32", n=1 << 13, wg=wg, s=1, gs=1, vec=1, U=1),
+    lambda wg: dict(family="fma", dtype="f64", n=1 << 12, wg=wg, F=16, K=8),
+    lambda wg: dict(family="rsqrt", n=1 << 12, wg=wg, F=8, K=4),
+    lambda wg: dict(family="lds", op="read", groups=(1 << 12) // wg, wg=wg, b=4, R=8, W=4096),
+    lambda wg: dict(family="lds", op="write", groups=(1 << 12) // wg, wg=wg, b=32, R=8, W=4096),
+    lambda wg: dict(family="barrier", groups=(1 << 12) // wg, wg=wg, B=4),
+]
+
+
+@pytest.mark.parametrize("mk", WG_SMALL, ids=lambda mk: "%s-%s" % (mk(128)["family"],
+                                                                    mk(128).get("op", "")))
+def test_work_group_size_changes_only_group_counts(mk):
+    """Sec. 5: kernel configurations that differ only in work-group size have
+    the same properties apart from the launch's group count (and barriers
+    summed per group), so the model predicts them alike but for the
+    per-group overhead -- except where a group does fixed work of its own,
+    as the LDS read kernel's filling of its W words."""
+    vs = {wg: mk(wg) for wg in (128, 256, 512)}
+    cs = {wg: C.count(v) for wg, v in vs.items()}
+    init = ("lst.4", "lst.4.b1") if vs[128]["family"] == "lds" and vs[128]["op"] == "read" else ()
+    rest = [{k: x for k, x in c.items() if k not in ("wg", "bar.wg") + init}
+            for c in cs.values()]
+    assert rest[0] == rest[1] == rest[2]
+    for wg, c in cs.items():
+        assert c["wg"] * wg == c["wi"]
+        if "bar.wi" in c:
+            assert c["bar.wg"] * wg == c["bar.wi"]
+        if init:  # every group first fills its W words of LDS
+            assert c["lst.4"] == c["lst.4.b1"] == vs[wg]["groups"] * vs[wg]["W"]
+
+
+def test_nbody_work_group_size_enters_staging():
+    """The n-body kernel stages every body through LDS once per work-group
+    (Sec. 5's exception: the group size changes the kernel's memory
+    transactions): from 128 to 512 work-items per group the staged global
+    loads, LDS stores and barriers per work-item fall as N/G, while the
+    LDS loads and the pair arithmetic stay."""
+    N = 4096
+    c = {G: C.count(dict(family="nbody", n=N, wg=G)) for G in (128, 256, 512)}
+    for G in (128, 256, 512):
+        B = N // G
+        assert c[G]["gld.4.3/3"] == 3 * N + 3 * N * B
+        assert c[G]["lst.4"] == 3 * N * B
+        assert c[G]["bar.wi"] == 2 * N * B
+        assert c[G]["lld.4"] == 3 * N * N
+        assert c[G]["mul.f32"] == 3 * N * N
