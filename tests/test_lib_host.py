@@ -214,8 +214,10 @@ def _small(v):
     """The same variant shape at a size the simulated-execution oracle
     finishes in milliseconds."""
     v = dict(v)
-    if v["family"] in ("stream", "fma", "rsqrt"):
+    if v["family"] in ("stream", "fma", "rsqrt", "arith"):
         v["n"] = min(v["n"], 1 << 12)
+    if v["family"] == "conv":
+        v["n"] = min(v["n"], 40) + 3
     if v["family"] in ("lds", "barrier"):
         v["groups"] = min(v["groups"], 8)
     if v["family"] in ("matmul", "transpose", "stencil"):
@@ -228,28 +230,42 @@ def _small(v):
     return v
 
 
-@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext", "bank"])
-def test_features_match_oracle(proj):
+@pytest.fixture(scope="module")
+def feature_cases():
+    """Small variants of the tiny and test suites with their library and
+    oracle counts (counted once for every projection)."""
     vs = [_small(v) for v in suite_tiny() + suite_test()[::3]]
-    arr = _lib_counts(vs)
+    return vs, _lib_counts(vs), [C.count(v) for v in vs]
+
+
+@pytest.fixture(scope="module")
+def fit_cases():
+    """Small variants of the instructive and test suites with their library
+    and oracle counts (counted once for every projection)."""
+    vs = [_small(v) for v in suite_instructive(roofline_points=False, extended=True)
+          + suite_test()]
+    return vs, _lib_counts(vs), [C.count(v) for v in vs]
+
+
+@pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext", "bank"])
+def test_features_match_oracle(proj, feature_cases):
+    vs, arr, oc = feature_cases
     for i, v in enumerate(vs):
         lib = P.features(arr[i], proj)
-        orc = M.FEATURES[proj](C.count(v))
+        orc = M.FEATURES[proj](oc[i])
         np.testing.assert_array_equal(lib, np.array(orc, dtype=np.float64))
 
 
 @pytest.mark.parametrize("proj", ["p3", "p12", "full", "ext", "bank"])
-def test_fit_matches_numpy_oracle(proj):
-    vs = [_small(v) for v in suite_instructive(roofline_points=False, extended=True)
-          + suite_test()]
-    arr = _lib_counts(vs)
+def test_fit_matches_numpy_oracle(proj, fit_cases):
+    vs, arr, oc = fit_cases
     F = np.array([P.features(arr[i], proj) for i in range(len(vs))])
     rng = np.random.default_rng(7)
     a_true = np.abs(rng.normal(size=F.shape[1])) * 1e-12 + 1e-15
     T = F @ a_true * rng.uniform(0.8, 1.25, size=len(vs)) + 2e-6
     m, cond, resid, rank = P.fit(arr, T, proj)
     alpha = P.model_alpha(m)
-    Fo = M.feature_matrix([C.count(v) for v in vs], proj)
+    Fo = M.feature_matrix(oc, proj)
     ao, rank_o = M.fit(Fo, T)
     pred, pred_o = F @ alpha, Fo @ ao
     np.testing.assert_allclose(pred, pred_o, rtol=1e-9)
