@@ -76,6 +76,25 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
     return sh[0];
 }
 
+// Tally entry k (0 .. NENT - MAXACC - 1) of statement s, as contrib()
+// gives it for entry MAXACC + k: LDS accesses by direction and size, flops
+// by kind and dtype, barriers, LDS sites by bank-stride bin.  The tallies
+// are one block of words in the statement, so every lane takes the same
+// path: one load, the slot and multiplier by selects.
+static_assert(offsetof(Stmt, lsite) == offsetof(Stmt, lds) + 6 * 4 &&
+              offsetof(Stmt, flop) == offsetof(Stmt, lsite) + MAXLSITE * 4 &&
+              offsetof(Stmt, bar) == offsetof(Stmt, flop) + 12 * 4,
+              "tally words of a statement: lds, lsite, flop, bar");
+constexpr int NTALLY = NENT - MAXACC;
+__device__ inline void tally_entry(const Stmt &s, int k, int *slot, int32_t *mult) {
+    const int wi = k < 6 ? k : k < 18 ? k + MAXLSITE : k == 18 ? 6 + MAXLSITE + 12 : k - 13;
+    const uint32_t w = ((const uint32_t *)&s.lds[0][0])[wi];
+    const int dir = (w >> 19) & 1, z = (w >> 20) & 3, bin = (w >> 16) & 7;
+    *slot = k < 6 ? C_LDS + k : k < 18 ? C_FLOP + k - 6 : k == 18 ? C_BARWI
+          : C_LDSB + (dir * 3 + z) * NLBIN + bin;
+    *mult = k < 19 ? (int32_t)w : (int32_t)(w & 0xffff);
+}
+
 struct FinShared {
     int64_t c[PM_NCOUNT];
     int64_t sc[MAXSTMT];
@@ -130,6 +149,48 @@ __device__ Agg wave_aggregates(const int64_t *c, int l) {
     return a;
 }
 
+// The two sums the extension features read (global bytes, arithmetic
+// operations), by the 64 lanes: lane l takes global slots l and l + 64 and
+// flop slot l; exact like wave_aggregates.
+__device__ Agg wave_aggregates_ext(const int64_t *c, int l) {
+    Agg a{};
+    const double g0 = (double)c[l], g1 = l + 64 < C_LDS ? (double)c[l + 64] : 0.0;
+    const int z0 = (l % 45) / NCLS, z1 = ((l + 64) % 45) / NCLS;
+    a.gb = wave_sum((z0 == 0 ? 4.0 : z0 == 1 ? 8.0 : 16.0) * g0 +
+                    (z1 == 0 ? 4.0 : z1 == 1 ? 8.0 : 16.0) * g1);
+    a.ops = wave_sum(l < C_BARWI - C_FLOP ? (double)c[C_FLOP + l] : 0.0);
+    return a;
+}
+
+// Feature i of PM_PROJ_FULL, PM_PROJ_EXT or PM_PROJ_BANK, equal to
+// feature_one's bit for bit, on one path for every lane: the slots a
+// feature reads and how it combines them are chosen by selects, so lanes
+// on different kinds of feature do not diverge.  e0..e2: the extension
+// features 154..156 (the same in every lane).
+__device__ inline double feature_sel(const int64_t *c, uint32_t proj, int i, double e0,
+                                     double e1, double e2) {
+    int j = i, binned = 0;
+    if (proj == PM_PROJ_BANK) {  // binned LDS counts at 90..131, EXT's features shifted past them
+        binned = i >= 90 && i < 132;
+        j = i < 90 ? i : binned ? 1000 : i - 36;
+    }
+    const bool g = j < 90, lds = j >= 90 && j < 96, fl = j >= 96 && j < 106;
+    const bool mn = j >= 109 && j < 154;
+    const int k = (j - 96) >> 1, d = (j - 96) & 1;
+    const int z = (j - 109) / NCLS, cl = (j - 109) % NCLS;
+    int A = g ? C_GACC + j : lds ? C_LDS + j - 90 : fl ? C_FLOP + 2 * k + d
+          : j == 106 ? C_BARWI : j == 107 ? C_WG : mn ? C_GACC + z * NCLS + cl : 0;
+    A = binned ? C_LDSB + i - 90 : A;
+    const int B = fl ? C_FLOP + 2 * K_FMA + d : mn ? C_GACC + (3 + z) * NCLS + cl : 0;
+    const int64_t a = c[A], b = c[B];
+    double v = (double)a;
+    v = fl && (k == K_ADD || k == K_MUL) ? v + (double)b : v;  // an FMA is an add and a mul
+    v = mn ? (double)(a < b ? a : b) : v;
+    v = j == 108 ? 1.0 : v;
+    v = j == 154 ? e0 : j == 155 ? e1 : j == 156 ? e2 : v;
+    return v;
+}
+
 // feature_one(c, proj, j), with the sums over many slots taken from `a`.
 __device__ double feature_dev(const int64_t *c, uint32_t proj, int j, const Agg &a) {
     if (proj == PM_PROJ_BANK) {
@@ -162,7 +223,8 @@ __device__ double feature_dev(const int64_t *c, uint32_t proj, int j, const Agg 
 
 // Count vector and prediction of one variant by one work-group: every
 // thread calls this, the first wavefront does the work.  Lanes take the
-// statement counts, then the statements' contributions e = l, l + 64, ...,
+// statement counts, then the statements' contributions -- first their
+// global accesses, then their other tallies, e = l, l + 64, ... in each --
 // adding each non-zero one into its slot with an LDS atomic (exact: while
 // every product is below 2^54 no sum of at most MAXSTMT*NENT of them can
 // pass int64; larger products take exact per-slot sums with overflow
@@ -181,13 +243,22 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
     if (w0 && l < nst && !stmt_count(p, l, jobres, &sh.sc[l])) sh.bad = 1;
     __syncthreads();
     if (w0 && st == PM_OK) {
-        for (int e = l; e < nst * NENT; e += 64) {
-            Contrib cc;
-            if (!contrib(p, e / NENT, e % NENT, F, Fill, &cc)) continue;
+        auto add = [&](int si, int slot, int32_t mult) {
             int64_t v;
-            if (mul_ovf(sh.sc[cc.stmt], (int64_t)cc.mult, &v)) sh.bad = 1;
+            if (mul_ovf(sh.sc[si], (int64_t)mult, &v)) sh.bad = 1;
             else if (v >= (1ll << 54)) sh.big = 1;
-            else if (v) atomicAdd((unsigned long long *)&sh.c[cc.slot], (unsigned long long)v);
+            else if (v) atomicAdd((unsigned long long *)&sh.c[slot], (unsigned long long)v);
+        };
+        for (int e = l; e < nst * MAXACC; e += 64) {  // global accesses
+            Contrib cc;
+            if (contrib(p, e / MAXACC, e % MAXACC, F, Fill, &cc)) add(cc.stmt, cc.slot, cc.mult);
+        }
+        for (int e = l; e < nst * NTALLY; e += 64) {  // the other tallies
+            const int si = e / NTALLY;
+            int slot;
+            int32_t mult;
+            tally_entry(p.st[si], e % NTALLY, &slot, &mult);
+            if (mult) add(si, slot, mult);
         }
         if (l == 0) {
             sh.c[C_WG] = p.n_wg;
@@ -206,11 +277,19 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
     if (out)
         for (int k = t; k < PM_NCOUNT; k += blockDim.x) out->c[k] = st2 == PM_OK ? sh.c[k] : 0;
     if (w0 && has_model && pred) {
-        const Agg a = wave_aggregates(sh.c, l);
-        const int nf = nfeat(model.proj) < (int)model.nfeat ? nfeat(model.proj) : (int)model.nfeat;
+        const uint32_t proj = model.proj;
+        const bool sel = proj == PM_PROJ_FULL || proj == PM_PROJ_EXT || proj == PM_PROJ_BANK;
+        const Agg a = sel ? wave_aggregates_ext(sh.c, l) : wave_aggregates(sh.c, l);
+        const int nf = nfeat(proj) < (int)model.nfeat ? nfeat(proj) : (int)model.nfeat;
         double part = 0.0;
-        if (st2 == PM_OK)
-            for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_dev(sh.c, model.proj, i, a);
+        if (st2 == PM_OK && sel) {
+            const double wi = (double)(sh.c[C_WI] < PM_RESIDENT_WI ? sh.c[C_WI] : PM_RESIDENT_WI);
+            const double e0 = wi > 0 ? a.ops / wi : 0.0, e1 = wi > 0 ? a.gb / wi : 0.0;
+            const double e2 = a.ops < a.gb ? a.ops : a.gb;
+            for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_sel(sh.c, proj, i, e0, e1, e2);
+        } else if (st2 == PM_OK) {
+            for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_dev(sh.c, proj, i, a);
+        }
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         if (t == 0) *pred = st2 == PM_OK ? part : 0.0;
     }

@@ -151,9 +151,29 @@ def test_device_resident_path_and_prediction(ctx, proj):
     want = P.counts_numpy(ctx.count_raw(vs))
     np.testing.assert_array_equal(d_c.cpu().numpy(), want)
     arr = ctx.count_raw(vs)
-    pred = np.array([P.features(arr[i], proj) @ alpha for i in range(nv)])
+    F = np.array([P.features(arr[i], proj) for i in range(nv)])
+    pred = F @ alpha
     np.testing.assert_allclose(d_t.cpu().numpy(), pred, rtol=1e-12)
     np.testing.assert_allclose(ctx.predict(m, vs), pred, rtol=1e-12)
+    # and bit for bit in the summation order the library fixes: 64 partial
+    # sums over features i = l, l + 64, ... in increasing order, combined
+    # pairwise at distances 32, 16, ..., 1
+    want_bits = np.array([_butterfly(F[i], alpha) for i in range(nv)])
+    np.testing.assert_array_equal(d_t.cpu().numpy(), want_bits)
+    np.testing.assert_array_equal(ctx.predict(m, vs), want_bits)
+
+
+def _butterfly(f, alpha):
+    part = np.zeros(64)
+    for lane in range(64):
+        x = 0.0
+        for i in range(lane, len(f), 64):
+            x = x + float(alpha[i]) * float(f[i])
+        part[lane] = x
+    lanes = np.arange(64)
+    for off in (32, 16, 8, 4, 2, 1):
+        part = part + part[lanes ^ off]
+    return part[0]
 
 
 def test_small_budget_reports_enomem():
