@@ -369,7 +369,6 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     __shared__ int jid[NTEMP];   // count-job slots
     __shared__ int jbuf[NTEMP];  // the buffers they are counted from
     __shared__ int jfetch;       // of those, the first jfetch come from their slots
-    __shared__ int64_t jitems[MAXJOB];  // items of count-job slots, -1 for others
     const int i = blockIdx.x, t = threadIdx.x;
     if (i == 0 && t < META_WORDS) h.meta_next[t] = 0;
     if (i >= nv) return;
@@ -378,47 +377,42 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     const pm_variant v = var[i];
     Job *vj = &jobs[(int64_t)i * MAXJOB];
     int st = build_block(v, &P, vj, U.jt, sh, U.jt);
-    bool here = st == PM_OK && P.bitmap_words == 0 && !(P.flags & PM_FLAG_ENUMERATE);
-    if (here && t < P.njob)
-        jitems[t] = P.jkind[t] != JOB_COUNT ? -1
-                    : P.jtmp[t] >= 0 ? U.jt[P.jtmp[t]].items : vj[t].items;
-    __syncthreads();
-    if (t == 0) {  // can this work-group finish the variant?
-        int ncj = 0;
-        int64_t items = 0;
-        for (int j = 0; j < P.njob && here; j++) {
-            if (jitems[j] < 0) continue;
-            if (ncj == NTEMP) here = false;
-            else jid[ncj++] = j;
-            items += jitems[j];
-        }
-        here = here && items <= max_items;
-        sh[0] = here ? ncj : -1;
-        if (here) {
-            // jobs still in a buffer are counted there; the others are
-            // fetched from their slots into buffers no count job holds
+    // Can this work-group finish the variant?  The lanes of the job slots
+    // decide together (the work-group is one wavefront): at most NTEMP
+    // count jobs holding at most max_items items.  Jobs still in a buffer
+    // are counted there; the others are fetched from their slots into the
+    // buffers no count job holds, the r-th fetched job (by slot) into the
+    // r-th free buffer, and listed first.
+    int ncj = -1;
+    if (st == PM_OK && P.bitmap_words == 0 && !(P.flags & PM_FLAG_ENUMERATE)) {
+        const bool cj = t < P.njob && P.jkind[t] == JOB_COUNT;
+        const int tb = cj ? P.jtmp[t] : -1;
+        int64_t items = cj ? (tb >= 0 ? U.jt[tb].items : vj[t].items) : 0;
+        for (int off = 32; off > 0; off >>= 1) items += __shfl_xor(items, off);
+        const uint64_t m = __ballot(cj), fm = __ballot(cj && tb < 0);
+        const int n = __popcll(m);
+        if (n <= NTEMP && items <= max_items) {
             uint32_t held = 0;
-            for (int k = 0; k < ncj; k++)
-                if (P.jtmp[jid[k]] >= 0) held |= 1u << P.jtmp[jid[k]];
-            int nf = 0;
-            for (int k = 0; k < ncj; k++)
-                if (P.jtmp[jid[k]] < 0) {
-                    int b = 0;
-                    while ((held >> b) & 1) b++;
-                    held |= 1u << b;
-                    jbuf[k] = b;
-                    // fetched ones first: swap into place nf
-                    const int tj = jid[nf], tb = jbuf[nf];
-                    jid[nf] = jid[k], jbuf[nf] = jbuf[k];
-                    jid[k] = tj, jbuf[k] = tb;
-                    nf++;
+#pragma unroll
+            for (int b = 0; b < NTEMP; b++)
+                if (__ballot(cj && tb == b)) held |= 1u << b;
+            const uint64_t below = (1ull << t) - 1;
+            const int nf = __popcll(fm);
+            if (cj) {
+                int pos = nf + __popcll(m & ~fm & below), buf = tb;
+                if (tb < 0) {
+                    pos = __popcll(fm & below);
+                    for (int b = 0, r = pos; b < NTEMP; b++)
+                        if (!((held >> b) & 1) && r-- == 0) buf = b;
                 }
-            for (int k = nf; k < ncj; k++) jbuf[k] = P.jtmp[jid[k]];
-            jfetch = nf;
+                jid[pos] = t;
+                jbuf[pos] = buf;
+            }
+            if (t == 0) jfetch = nf;
+            ncj = n;
         }
     }
     __syncthreads();
-    const int ncj = sh[0];
     if (ncj > 0) {
         constexpr int JW = sizeof(Job) / 8;
         for (int w = t; w < jfetch * JW; w += 64)  // count jobs not in a buffer

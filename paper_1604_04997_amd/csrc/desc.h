@@ -1079,12 +1079,14 @@ PM_HD void inner_range(const Job &J, const int64_t *r, int64_t *lo_out,
 
 // Decompose outer point o (over vars 1..nv-1, var 1 fastest) and evaluate
 // the guards and the index map on it.
+// o is below the product of the outer extents, so the last variable's
+// digit is what is left of o, with no division.
 PM_HD void eval_outer(const Job &J, int64_t o, int64_t *r, int64_t *base) {
     for (int q = 0; q < J.ng; q++) r[q] = J.f[q][MAXVAR];
     int64_t b = J.f[J.ng][MAXVAR];
     for (int v = 1; v < J.nv; v++) {
-        int64_t e = J.ext[v];
-        const int64_t q = tdiv(o, e), x = o - q * e;
+        const int64_t e = J.ext[v];
+        const int64_t q = v + 1 < J.nv ? tdiv(o, e) : 0, x = o - q * e;
         o = q;
         for (int q = 0; q < J.ng; q++) r[q] += J.f[q][v] * x;
         b += J.f[J.ng][v] * x;
