@@ -70,7 +70,24 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
     __syncthreads();
     if (t == 0) {
         sh[1 + MAXSTMT] = 0;  // the fallback hands the buffers out again
-        sh[0] = build_slots_finish_seq(v, p, jobs, temp, sh + 1, keep);
+        sh[0] = build_slots_finish_seq(v, p, jobs, temp, sh + 1, keep, false);
+    }
+    __syncthreads();
+    if (sh[0] == PM_OK && t < 64) {
+        // the job-chunk and fill-segment prefixes (build_tail's), as scans
+        // over the first wavefront's lanes
+        const int j = t;
+        int64_t c = 0, g = 0;
+        if (j < p->njob && p->jkind[j] != JOB_NONE)
+            c = keep && p->jtmp[j] >= 0 ? keep[p->jtmp[j]].chunks : jobs[j].chunks;
+        if (j < p->narr && p->arr[j].w && p->arr[j].words) g = p->arr[j].segs;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t c1 = __shfl_up(c, d), g1 = __shfl_up(g, d);
+            if (j >= d) c += c1, g += g1;
+        }
+        if (j < MAXJOB) p->jobcum[j] = c;
+        if (j < MAXARR) p->arrcum[j] = g;
+        if (j == 63) p->chunks = c, p->segs = g;
     }
     __syncthreads();
     return sh[0];

@@ -1525,8 +1525,10 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
 
 // Footprint mode of every strided array over job slots [0, nj), then the
 // chunk and segment prefixes.  Returns the status.
+// `prefix`: also the job-chunk and fill-segment prefixes (a caller that
+// computes them itself, from the same values, passes false).
 PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj,
-                     Job *keep = nullptr) {
+                     Job *keep = nullptr, bool prefix = true) {
     p->njob = nj;
     // slot j's job: in its buffer when the expansion kept it there
     auto JB = [&](int j) -> Job & { return keep && p->jtmp[j] >= 0 ? keep[p->jtmp[j]] : jobs[j]; };
@@ -1576,6 +1578,7 @@ PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj,
         }
     }
     p->bitmap_words = off;
+    if (!prefix) return p->status;
     int64_t cum = 0;
     for (int j = 0; j < MAXJOB; j++) {
         cum += j < nj && p->jkind[j] != JOB_NONE ? JB(j).chunks : 0;
@@ -1648,13 +1651,13 @@ PM_HD int build_seq(const pm_variant &v, Prog *p, Job *jobs, TEMP temp) {
 // build_slots_finish with the fallback through build_seq.
 template <class TEMP>
 PM_HD int build_slots_finish_seq(const pm_variant &v, Prog *p, Job *jobs, TEMP temp,
-                                 const int *r, Job *keep) {
+                                 const int *r, Job *keep, bool prefix = true) {
     const int ns = p->nstmt;
     for (int si = 0; si < ns; si++) {
         if (r[si] == PM_SEQ) return build_seq(v, p, jobs, temp);
         if (r[si] != PM_OK) return p->status = r[si];
     }
-    return build_tail(v, p, jobs, 2 * ns, keep);
+    return build_tail(v, p, jobs, 2 * ns, keep, prefix);
 }
 
 // Host form of the same: the statements one after another.
