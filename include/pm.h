@@ -105,7 +105,9 @@ enum { PM_TRANSPOSE_TILED = 0, PM_TRANSPOSE_NAIVE_WC = 1, PM_TRANSPOSE_NAIVE_RC 
  *             filt[j][u][v][c] for 3 images (n+6)^2 x 3 and 3 filters
  *             7 x 7 x 3, channel fastest; fp32
  * flags: PM_FLAG_BITMAP counts every footprint with bitmaps, also where
- * the interval form applies; PM_FLAG_ENUMERATE runs every count job in the
+ * the interval form applies; PM_FLAG_ENUMERATE counts every guarded
+ * component of two or more variables by enumerating its points (Alg. 1),
+ * also where a closed form applies, and runs every such count job in the
  * chip-wide count kernel, also where the work-group that expanded the
  * descriptor could count it itself (same counts; both for cross-checks).
  * PM_FLAG_STREAMING (STREAM only, ignored elsewhere): every access of the

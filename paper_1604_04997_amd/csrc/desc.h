@@ -297,6 +297,11 @@ struct BT {
     // Builders fill one statement at a time: additions go to the latest.
     Stmt *cur = nullptr;
     int nvar = 0, nguard = 0, nacc = 0, lane = 0, nls = 0;
+    // the program's statement, access and array counts and the current
+    // statement's guard variable mask, also kept here: the builder stores
+    // them without reading them back (the program starts empty)
+    int nstmt = 0, nacc_all = 0, narr = 0;
+    uint64_t gmask = 0;
     bool werr = false;  // an access with no whole lane stride, or two widths on one array
     PM_HD void fail(int st) {
         if (p->status == PM_OK) p->status = st;
@@ -305,18 +310,19 @@ struct BT {
         nvar = nguard = nacc = nls = 0;
         lane = lane_var;
         cur = nullptr;
-        if (p->nstmt >= MAXSTMT) {
+        if (nstmt >= MAXSTMT) {
             fail(PM_EINVAL);
             return nullptr;
         }
-        Stmt *s = &p->st[p->nstmt++];
+        Stmt *s = &p->st[nstmt++];
+        p->nstmt = nstmt;
         cur = s;
         s->nvar = 0;
         s->lane = lane_var;
         s->nguard = 0;
         s->nacc = 0;
-        s->acc0 = p->nacc_all;
-        s->gmask = 0;
+        s->acc0 = nacc_all;
+        s->gmask = gmask = 0;
         AP::each(MAXVAR, [=](int i) { s->ext[i] = 1; });
         AP::each(6, [=](int i) { (&s->lds[0][0])[i] = 0; });
         AP::each(MAXLSITE, [=](int i) { s->lsite[i] = 0; });
@@ -349,7 +355,8 @@ struct BT {
             return;
         }
         AP::put(&s->guard[nguard], a);
-        s->gmask |= AP::vars(a) << (8 * nguard);
+        gmask |= AP::vars(a) << (8 * nguard);
+        s->gmask = gmask;
         s->nguard = ++nguard;
     }
     PM_HD void lt(Stmt *s, V a, int64_t b) {  // a < b  <=>  (b-1) - a >= 0
@@ -363,11 +370,12 @@ struct BT {
         lt(s, a, b + 1);
     }
     PM_HD void acc(Stmt *s, int arr, int dir, int elem, int vec, V idx) {
-        if (s != cur || nacc >= MAXACC || p->nacc_all >= MAXACC_ALL || arr >= p->narr) {
+        if (s != cur || nacc >= MAXACC || nacc_all >= MAXACC_ALL || arr >= narr) {
             fail(PM_EINVAL);
             return;
         }
-        GAcc &g = p->acc[p->nacc_all++];
+        GAcc &g = p->acc[nacc_all++];
+        p->nacc_all = nacc_all;
         g.arr = arr;
         g.dir = dir;
         g.elem = elem;
@@ -411,7 +419,8 @@ struct BT {
         p->arr[a].w = 0;
         p->arr[a].segs = 0;
         p->arr[a].fixF = p->arr[a].fixFill = 0;
-        if (a + 1 > p->narr) p->narr = a + 1;
+        if (a + 1 > narr) narr = a + 1;
+        p->narr = narr;
     }
 };
 
@@ -1007,6 +1016,61 @@ PM_HD int64_t interval_count(int64_t ext, int ng, const int64_t (*g)[MAXVAR + 1]
 // with two that fuse (as fuse() would fuse them: (a, b) tried before
 // (b, a)); guards `qs` (bit q: guard q touches the component).  Returns
 // false when the component needs enumeration; *ovf on overflow.
+// A two-variable component that does not fuse as a whole, but whose
+// coupling guards (those on both variables) all act on one mixed-radix
+// index x = major * E + minor (E the minor variable's extent) while every
+// other guard bounds one of the two alone: the coupling guards bound x to
+// an interval, the others bound the major digit and the minor digit
+// (x mod E) to intervals, and the points are the x of the intersected
+// interval whose remainder lies in the minor digit's interval -- a
+// difference of two closed forms.  False when the component has no such
+// form (it is then enumerated).
+PM_HD bool mixed_radix_count(const int64_t *ca, const int64_t *cb, const int64_t *kq, uint32_t qs,
+                             int64_t ea, int64_t eb, int64_t *cnt, bool *ovf) {
+    bool a_major = true, b_major = true;  // orientations the coupling guards allow
+    int64_t want;
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++) {
+        if (!((qs >> q) & 1) || !ca[q] || !cb[q]) continue;
+        if (mul_ovf(cb[q], eb, &want) || ca[q] != want) a_major = false;
+        if (mul_ovf(ca[q], ea, &want) || cb[q] != want) b_major = false;
+    }
+    if (!a_major && !b_major) return false;
+    const int64_t *cM = a_major ? ca : cb, *cm = a_major ? cb : ca;
+    const int64_t eM = a_major ? ea : eb, E = a_major ? eb : ea;
+    int64_t X = 0;
+    if (mul_ovf(eM, E, &X)) {
+        *ovf = true;
+        return true;
+    }
+    int64_t xlo = 0, xhi = X, mlo = 0, mhi = eM, nlo = 0, nhi = E;
+#pragma unroll
+    for (int q = 0; q < MAXGUARD; q++) {
+        if (!((qs >> q) & 1)) continue;
+        if (cM[q] && cm[q]) clip(cm[q], kq[q], xlo, xhi);  // cm * x + k >= 0
+        else if (cM[q]) clip(cM[q], kq[q], mlo, mhi);
+        else clip(cm[q], kq[q], nlo, nhi);
+    }
+    if (xhi <= xlo || mhi <= mlo || nhi <= nlo) {
+        *cnt = 0;
+        return true;
+    }
+    const int64_t x0 = xlo > mlo * E ? xlo : mlo * E;  // 0 <= mlo < mhi <= eM: no overflow
+    const int64_t x1 = xhi < mhi * E ? xhi : mhi * E;
+    if (x1 <= x0) {
+        *cnt = 0;
+        return true;
+    }
+    const int64_t w = nhi - nlo;
+    // points x in [0, y) with x mod E in [nlo, nhi)
+    auto below = [&](int64_t y) {
+        const int64_t qy = tdiv(y, E), r = y - qy * E - nlo;
+        return qy * w + (r < 0 ? 0 : r > w ? w : r);
+    };
+    *cnt = below(x1) - below(x0);
+    return true;
+}
+
 PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt, bool *ovf) {
     const int a = __builtin_ctz(M);
     const uint32_t rest = M & (M - 1);
@@ -1037,7 +1101,7 @@ PM_HD bool small_component(const Stmt &s, uint32_t M, uint32_t qs, int64_t *cnt,
             if (cb[q] ? (!ca[q] || mul_ovf(cb[q], eb, &want) || ca[q] != want) : ca[q] != 0)
                 fba = false;
         }
-        if (!fab && !fba) return false;
+        if (!fab && !fba) return mixed_radix_count(ca, cb, kq, qs, ea, eb, cnt, ovf);
         use_b = !fab;
         if (mul_ovf(ea, eb, &ext)) {
             *ovf = true;
@@ -1322,7 +1386,8 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
             if ((gm >> (8 * q)) & M) qs |= 1u << q;
         int64_t c;
         bool ovf = false;
-        if (small_component(s, M, qs, &c, &ovf)) {  // closed form
+        // closed form, unless the variant asks for enumeration (cross-checks)
+        if (!(p->flags & PM_FLAG_ENUMERATE) && small_component(s, M, qs, &c, &ovf)) {
             if (ovf || mul_ovf(fixed, c, &fixed)) return PM_EOVERFLOW;
             continue;
         }
@@ -1366,6 +1431,7 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
             }
             // two variables reach here only when small_component found that
             // they fuse in neither order, which is fuse()'s test on these rows
+            // (or when enumeration is asked for: then they stay two)
             if (ncol > 2) J.nv = fuse(J.nv, J.ext, J.ng, J.f, &ovf);
             if (ovf) return PM_EOVERFLOW;
             if (J.nv == 1) {  // an interval: closed form, the slot is reused

@@ -320,6 +320,22 @@ def test_host_counts_full_size_closed_forms():
         assert P.count_host(v) == closed(v), v
 
 
+def test_partial_tile_guards_every_size():
+    """Every size from 1 to 199 and every tile: the guards of the partial
+    tiles (halo rows and columns of the last tile, matrix edges), counted
+    in closed form where the coupled guards share one mixed-radix index and
+    enumerated where they do not, against the closed forms derived from the
+    kernels."""
+    from closed_forms import counts as closed
+    for n in range(1, 200):
+        for T in (8, 16, 32):
+            for v in (dict(family="stencil", dtype="f32", n=n, T=T),
+                      dict(family="transpose", op="tiled", n=n, T=T),
+                      dict(family="transpose", op="naive_rc", n=n, T=T),
+                      dict(family="matmul", op="tiled", n=n, m=n + 5, l=max(n - 3, 1), T=T)):
+                assert P.count_host(v) == closed(v), v
+
+
 def test_qpoly_eval_binomial_basis():
     """pm_qpoly_eval on a hand-made form: on residue r of (x - x0) mod 2,
     count = c0 + c1 q + c2 C(q,2) + c3 C(q,3), q = (x - x0) div 2; below x0
