@@ -130,8 +130,11 @@ def counter_roofline(phase, ms, nv):
         ws = (COPY_BYTES / 2) / (cal["WRITE_SIZE"] * 1024)
         roof["traffic"] = round((r["FETCH_SIZE"] * fs + r["WRITE_SIZE"] * ws) * 1024)
         roof["traffic_scale"] = {"fetch": round(fs, 3), "write": round(ws, 3)}
-        # algorithmic bytes: variants in, count vectors, predictions, statuses out
-        roof["algorithmic_bytes"] = nv * (88 + 896 + 8 + 4)
+        # algorithmic bytes: variants in (88 B), count vectors (PM_NCOUNT
+        # int64), predictions (8 B) and statuses (4 B) out
+        import ctypes
+        import paper_1604_04997_amd as P
+        roof["algorithmic_bytes"] = nv * (ctypes.sizeof(P.Variant) + 8 * P.PM_NCOUNT + 8 + 4)
     return roof
 
 
