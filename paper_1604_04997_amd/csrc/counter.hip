@@ -248,24 +248,9 @@ __device__ double feature_dev(const int64_t *c, uint32_t proj, int j, const Agg 
 // checks).  Lane l then owns the features i = l (mod 64); the
 // prediction's 64 partial sums meet in a butterfly, the order predict()
 // fixes.  st != PM_OK: zero counts, prediction 0.
-// Lane l's model weights alpha[l + 64 r], r < ALPHA_PER_LANE (0 past nfeat),
-// read once so that their load overlaps earlier work.
-constexpr int ALPHA_PER_LANE = (PM_NFEAT_MAX + 63) / 64;
-struct LaneAlpha {
-    double a[ALPHA_PER_LANE];
-};
-__device__ inline LaneAlpha lane_alpha(const pm_model &model, int l) {
-    LaneAlpha w;
-#pragma unroll
-    for (int r = 0; r < ALPHA_PER_LANE; r++)
-        w.a[r] = l + 64 * r < (int)model.nfeat && l + 64 * r < PM_NFEAT_MAX ? model.alpha[l + 64 * r] : 0.0;
-    return w;
-}
-
 __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobres, const int64_t *F,
                               const int64_t *Fill, int st, FinShared &sh, pm_counts *out,
-                              const pm_model &model, int has_model, double *pred,
-                              const LaneAlpha *wl = nullptr) {
+                              const pm_model &model, int has_model, double *pred) {
     const int t = threadIdx.x, l = t & 63;
     const bool w0 = t < 64;
     const int nst = st == PM_OK ? p.nstmt : 0;
@@ -318,13 +303,7 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
             const double wi = (double)(sh.c[C_WI] < PM_RESIDENT_WI ? sh.c[C_WI] : PM_RESIDENT_WI);
             const double e0 = wi > 0 ? a.ops / wi : 0.0, e1 = wi > 0 ? a.gb / wi : 0.0;
             const double e2 = a.ops < a.gb ? a.ops : a.gb;
-            if (wl) {  // weights already in registers
-#pragma unroll
-                for (int r = 0; r < ALPHA_PER_LANE; r++)
-                    if (l + 64 * r < nf) part += wl->a[r] * feature_sel(sh.c, proj, l + 64 * r, e0, e1, e2);
-            } else {
-                for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_sel(sh.c, proj, i, e0, e1, e2);
-            }
+            for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_sel(sh.c, proj, i, e0, e1, e2);
         } else if (st2 == PM_OK) {
             for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_dev(sh.c, proj, i, a);
         }
@@ -410,8 +389,6 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     const int i = blockIdx.x, t = threadIdx.x;
     if (i == 0 && t < META_WORDS) h.meta_next[t] = 0;
     if (i >= nv) return;
-    LaneAlpha wl;
-    if (has_model && pred) wl = lane_alpha(model, t);
     if (t < MAXJOB) jr[t] = 0;
     if (t < MAXARR) zero[t] = 0;
     const pm_variant v = var[i];
@@ -509,7 +486,7 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
         }
     }
     const int s2 = finalize_block(P, jr, zero, zero, sfin, U.fin, counts ? &counts[i] : nullptr,
-                                  model, has_model, pred ? &pred[i] : nullptr, &wl);
+                                  model, has_model, pred ? &pred[i] : nullptr);
     if (t == 0) status[i] = s2;
 }
 
