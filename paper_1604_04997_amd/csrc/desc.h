@@ -703,9 +703,8 @@ PM_HD void build_transpose(BB &b, const pm_variant &v) {
         b.var(S, T);  // 3 lx
     };
     auto r = b.av(b.av(b.mk(0), 0, T), 2, 1), c = b.av(b.av(b.mk(0), 1, T), 3, 1);
-    auto rn_c = b.av(b.av(b.av(b.av(b.mk(0), 0, T * n), 2, n), 1, T), 3, 1);  // r*n + c
-    auto cn_r = b.av(b.av(b.av(b.av(b.mk(0), 1, T * n), 3, n), 0, T), 2, 1);  // c*n + r
     if (v.op == PM_TRANSPOSE_TILED) {
+        auto rn_c = b.av(b.av(b.av(b.av(b.mk(0), 0, T * n), 2, n), 1, T), 3, 1);  // r*n + c
         Stmt *S = b.stmt(3);
         if (!S) return;
         head(S);
@@ -725,17 +724,25 @@ PM_HD void build_transpose(BB &b, const pm_variant &v) {
         b.lds(St, D_LD, 4, T + 1, 1);  // tile[lx][ly]
         b.acc(St, 1, D_ST, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 1, T * n), 2, n), 0, T), 3, 1));
     } else {
-        Stmt *S = b.stmt(3);
+        // one element per work-item and nothing shared within a group: the
+        // domain written over the fused indices r = gy*T + ly and
+        // c = gx*T + lx (extents G*T; c moves with the lane, by one per
+        // lane like lx) -- the same points, index maps and lane strides
+        Stmt *S = b.stmt(1);
         if (!S) return;
-        head(S);
-        b.lt(S, r, n);
-        b.lt(S, c, n);
+        b.var(S, G * T);  // 0 r
+        b.var(S, G * T);  // 1 c
+        const auto rf = b.av(b.mk(0), 0, 1), cf = b.av(b.mk(0), 1, 1);
+        b.lt(S, rf, n);
+        b.lt(S, cf, n);
+        const auto rn_cf = b.av(b.av(b.mk(0), 0, n), 1, 1);  // r*n + c
+        const auto cn_rf = b.av(b.av(b.mk(0), 1, n), 0, 1);  // c*n + r
         if (v.op == PM_TRANSPOSE_NAIVE_WC) {
-            b.acc(S, 0, D_LD, 4, 1, cn_r);
-            b.acc(S, 1, D_ST, 4, 1, rn_c);
+            b.acc(S, 0, D_LD, 4, 1, cn_rf);
+            b.acc(S, 1, D_ST, 4, 1, rn_cf);
         } else {
-            b.acc(S, 0, D_LD, 4, 1, rn_c);
-            b.acc(S, 1, D_ST, 4, 1, cn_r);
+            b.acc(S, 0, D_LD, 4, 1, rn_cf);
+            b.acc(S, 1, D_ST, 4, 1, cn_rf);
         }
     }
 }
