@@ -762,64 +762,90 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
     b.p->wg_size = (int32_t)(T * T);
     b.array(0, P * P);
     b.array(1, n * n);
-    auto i = b.av(b.av(b.mk(0), 0, T), 2, 1), j = b.av(b.av(b.mk(0), 1, T), 3, 1);
-    // flat index of input cell (i + di, j + dj)
-    auto at = [&](int64_t di, int64_t dj) {
-        return b.av(b.av(b.av(b.av(b.mk(di * P + dj), 0, T * P), 2, P), 1, T), 3, 1);
+    // Work-item (gy, gx, ly, lx) handles cell (i, j) = (gy*T + ly, gx*T + lx).
+    // Each statement is written over the coarsest variables its guards allow:
+    // (i, j) when it tests only i and j, (gy, ly, j) when it tests the row
+    // within the tile, (i, gx, lx) when it tests the column within the tile.
+    // These are the same points; the lane variable is lx, or j where lx is
+    // part of it (j moves by one per lane, as lx does).
+    auto ij = [&](Stmt *S) {  // 0 i, 1 j
+        b.var(S, G * T);
+        b.var(S, G * T);
     };
-    auto ly = b.av(b.mk(0), 2, 1), lx = b.av(b.mk(0), 3, 1);
+    auto rj = [&](Stmt *S) {  // 0 gy, 1 ly, 2 j
+        b.var(S, G);
+        b.var(S, T);
+        b.var(S, G * T);
+    };
+    auto ic = [&](Stmt *S) {  // 0 i, 1 gx, 2 lx
+        b.var(S, G * T);
+        b.var(S, G);
+        b.var(S, T);
+    };
+    // flat index of input cell (i + di, j + dj) in each variable set
+    auto at_ij = [&](int64_t di, int64_t dj) {
+        return b.av(b.av(b.mk(di * P + dj), 0, P), 1, 1);
+    };
+    auto at_rj = [&](int64_t di, int64_t dj) {
+        return b.av(b.av(b.av(b.mk(di * P + dj), 0, T * P), 1, P), 2, 1);
+    };
+    auto at_ic = [&](int64_t di, int64_t dj) {
+        return b.av(b.av(b.av(b.mk(di * P + dj), 0, P), 1, T), 2, 1);
+    };
+    const auto v0 = b.av(b.mk(0), 0, 1), v1 = b.av(b.mk(0), 1, 1), v2 = b.av(b.mk(0), 2, 1);
+    const auto row = b.av(b.av(b.mk(0), 0, T), 1, 1);  // gy*T + ly in (gy, ly, j)
+    const auto col = b.av(b.av(b.mk(0), 1, T), 2, 1);  // gx*T + lx in (i, gx, lx)
     for (int q = 0; q < 7; q++) {
-        Stmt *S = b.stmt(3);
+        // the tile and the halo rows: lane stride 1; the halo columns
+        // (lx == 0, lx == T-1) are written at a fixed column
+        Stmt *S = b.stmt(q == 0 ? 1 : 2);
         if (!S) return;
-        b.var(S, G);
-        b.var(S, G);
-        b.var(S, T);
-        b.var(S, T);
-        // tile cell (ly + 1, lx + 1) and the halo rows: lane stride 1; the
-        // halo columns (lx == 0, lx == T-1) are written at a fixed column
+        if (q == 0) ij(S);
+        else if (q <= 3) rj(S);
+        else ic(S);
         b.lds(S, D_ST, e, q == 4 || q == 5 ? 0 : 1, 1);
         switch (q) {
         case 0:  // the tile
-            b.lt(S, i, n), b.lt(S, j, n);
-            b.acc(S, 0, D_LD, e, 1, at(1, 1));
+            b.lt(S, v0, n), b.lt(S, v1, n);
+            b.acc(S, 0, D_LD, e, 1, at_ij(1, 1));
             break;
         case 1:  // top halo row, loaded by ly == 0
-            b.eq(S, ly, 0), b.lt(S, j, n);
-            b.acc(S, 0, D_LD, e, 1, at(0, 1));
+            b.eq(S, v1, 0), b.lt(S, v2, n);
+            b.acc(S, 0, D_LD, e, 1, at_rj(0, 1));
             break;
         case 2:  // bottom halo row of a full tile, loaded by ly == T-1
-            b.eq(S, ly, T - 1), b.lt(S, i, n), b.lt(S, j, n);
-            b.acc(S, 0, D_LD, e, 1, at(2, 1));
+            b.eq(S, v1, T - 1), b.lt(S, row, n), b.lt(S, v2, n);
+            b.acc(S, 0, D_LD, e, 1, at_rj(2, 1));
             break;
         case 3:  // bottom halo row of the last, partial tile row
-            b.lt(S, ly, T - 1), b.eq(S, i, n - 1), b.lt(S, j, n);
-            b.acc(S, 0, D_LD, e, 1, at(2, 1));
+            b.lt(S, v1, T - 1), b.eq(S, row, n - 1), b.lt(S, v2, n);
+            b.acc(S, 0, D_LD, e, 1, at_rj(2, 1));
             break;
         case 4:  // left halo column, loaded by lx == 0
-            b.eq(S, lx, 0), b.lt(S, i, n);
-            b.acc(S, 0, D_LD, e, 1, at(1, 0));
+            b.eq(S, v2, 0), b.lt(S, v0, n);
+            b.acc(S, 0, D_LD, e, 1, at_ic(1, 0));
             break;
         case 5:  // right halo column of a full tile
-            b.eq(S, lx, T - 1), b.lt(S, i, n), b.lt(S, j, n);
-            b.acc(S, 0, D_LD, e, 1, at(1, 2));
+            b.eq(S, v2, T - 1), b.lt(S, v0, n), b.lt(S, col, n);
+            b.acc(S, 0, D_LD, e, 1, at_ic(1, 2));
             break;
         default:  // right halo column of the last, partial tile column
-            b.lt(S, lx, T - 1), b.eq(S, j, n - 1), b.lt(S, i, n);
-            b.acc(S, 0, D_LD, e, 1, at(1, 2));
+            b.lt(S, v2, T - 1), b.eq(S, col, n - 1), b.lt(S, v0, n);
+            b.acc(S, 0, D_LD, e, 1, at_ic(1, 2));
         }
     }
-    Stmt *Sb = b.stmt(3);
+    Stmt *Sb = b.stmt(1);  // every work-item, once
     if (!Sb) return;
-    b.var(Sb, G), b.var(Sb, G), b.var(Sb, T), b.var(Sb, T);
+    ij(Sb);
     Sb->bar = 1;
-    Stmt *Sc = b.stmt(3);
+    Stmt *Sc = b.stmt(1);
     if (!Sc) return;
-    b.var(Sc, G), b.var(Sc, G), b.var(Sc, T), b.var(Sc, T);
-    b.lt(Sc, i, n), b.lt(Sc, j, n);
+    ij(Sc);
+    b.lt(Sc, v0, n), b.lt(Sc, v1, n);
     b.lds(Sc, D_LD, e, 1, 5);  // the point and its four neighbours, rows of T + 2
     Sc->flop[K_ADD][dt] = 4;  // N+S, +W, +E, + h^2 c^2
     Sc->flop[K_MUL][dt] = 3;  // c*c, h^2*(.), 0.25*(.)
-    b.acc(Sc, 1, D_ST, e, 1, b.av(b.av(b.av(b.av(b.mk(0), 0, T * n), 2, n), 1, T), 3, 1));
+    b.acc(Sc, 1, D_ST, e, 1, b.av(b.av(b.mk(0), 0, n), 1, 1));
 }
 
 // --- all-pairs n-body: out[i] = sum_{j != i} rsqrt(|x_i - x_j|^2) ---
