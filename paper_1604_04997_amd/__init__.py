@@ -402,6 +402,24 @@ class Context:
             ctypes.c_void_p(d_t_ptr) if d_t_ptr else None,
             ctypes.c_void_p(d_status_ptr), ctypes.c_void_p(stream_ptr)))
 
+    def count_device_call(self, d_variants_ptr, nv, d_counts_ptr, model, d_t_ptr,
+                          d_status_ptr, stream_ptr):
+        """count_device with its arguments marshalled once: returns a
+        function of no arguments that enqueues the same batch again (for a
+        loop that repeats one batch on buffers that stay where they are)."""
+        f = lib().pm_count_device
+        args = (self._h, ctypes.c_void_p(d_variants_ptr), ctypes.c_size_t(nv),
+                ctypes.c_void_p(d_counts_ptr) if d_counts_ptr else None,
+                ctypes.byref(model) if model is not None else None,
+                ctypes.c_void_p(d_t_ptr) if d_t_ptr else None,
+                ctypes.c_void_p(d_status_ptr), ctypes.c_void_p(stream_ptr))
+
+        def call(_keep=(model, args)):
+            st = f(*args)
+            if st:
+                _check(st)
+        return call
+
     def qpoly_derive(self, d: dict, fields: int = 1, scale: int = 1, period: int = 1,
                      x0: int = 1) -> QPoly:
         """pm_qpoly_derive: the counts of `d` with its size fields (bit 0 n,

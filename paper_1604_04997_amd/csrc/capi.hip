@@ -111,12 +111,16 @@ struct pm_ctx {
     double *zd_pred = nullptr;
     int32_t *zd_status = nullptr;
     std::vector<hipEvent_t> events;
-    // Order of batches on the shared arena: every batch waits for the event
-    // the previous batch recorded on its stream (when that stream differs)
-    // and records it again after its last kernel.
+    // Order of batches on the shared arena: a batch on another stream than
+    // the previous batch's waits for an event recorded on that stream after
+    // the previous batch.  The event is recorded after every batch on a
+    // caller's stream; after a batch on the null stream or the context's own
+    // stream (which stay valid) only when a batch on another stream needs
+    // it (arena_lazy), so that batches following each other on one such
+    // stream pay no event (one costs about 3 us of queue time per batch).
     hipEvent_t arena_done = nullptr;
     hipStream_t arena_stream = nullptr;
-    bool arena_used = false;
+    bool arena_used = false, arena_lazy = false;
     // measurement: the last timed launch of a call that timed out (a later
     // call waits for it before reusing the events), the launch floor
     hipEvent_t measure_pending = nullptr;
@@ -324,12 +328,16 @@ int grow_bitmap(pm_ctx *c, size_t words) {
 // Make stream s wait for the previous batch on the shared arena when that
 // batch ran on another stream.
 int arena_enter(pm_ctx *c, hipStream_t s) {
-    if (c->arena_used && c->arena_stream != s) HIPCHK(hipStreamWaitEvent(s, c->arena_done, 0));
+    if (c->arena_used && c->arena_stream != s) {
+        if (c->arena_lazy) HIPCHK(hipEventRecord(c->arena_done, c->arena_stream));
+        HIPCHK(hipStreamWaitEvent(s, c->arena_done, 0));
+    }
     return PM_OK;
 }
 // The batch on stream s has enqueued its last kernel.
 int arena_leave(pm_ctx *c, hipStream_t s) {
-    HIPCHK(hipEventRecord(c->arena_done, s));
+    c->arena_lazy = s == nullptr || s == c->stream;
+    if (!c->arena_lazy) HIPCHK(hipEventRecord(c->arena_done, s));
     c->arena_stream = s;
     c->arena_used = true;
     return PM_OK;

@@ -111,3 +111,41 @@ def test_batches_on_different_streams_are_ordered(ctx):
             got = {names[i]: int(x) for i, x in enumerate(cnt[k]) if x}
             assert got == want[key][k], (key, v)
     assert host == want["c"]
+
+
+def test_null_stream_batch_then_side_stream_batch(ctx):
+    """A device batch on the null stream (whose arena event the context
+    records only when a batch on another stream needs it), then, before any
+    wait, one on a side stream and another on the null stream: each gets the
+    counts it gets alone."""
+    import torch
+    bm = [dict(v, bitmap=True) for v in FAMILY_CASES
+          if v["family"] in ("transpose", "stream", "nbody")]
+    a = (bm * 8)[:48]                                   # handed on: bitmaps
+    b = [v for v in FAMILY_CASES if v["family"] in ("matmul", "stencil")][:40]
+    c = [v for v in FAMILY_CASES if v["family"] in ("conv", "stream")][:30]
+    want = {k: [C.count(v) for v in vs] for k, vs in (("a", a), ("b", b), ("c", c))}
+    ctx.reserve(64, sum(P.bitmap_bytes(v) for v in a + c))
+    names = P.count_names()
+    print("null stream, side stream, null stream: %d, %d, %d variants" % (len(a), len(b), len(c)),
+          flush=True)
+    torch.cuda.synchronize()
+    s1 = torch.cuda.Stream()
+    outs = {}
+    for key, vs, s in (("a", a, None), ("b", b, s1), ("c", c, None)):
+        d_v = _dev_variants(vs)
+        d_c = torch.full((len(vs), P.PM_NCOUNT), 7, dtype=torch.int64, device="cuda")
+        d_s = torch.full((len(vs),), 99, dtype=torch.int32, device="cuda")
+        if s is not None:
+            s.wait_stream(torch.cuda.current_stream())
+        ctx.count_device(d_v.data_ptr(), len(vs), d_c.data_ptr(), None, 0,
+                         d_s.data_ptr(), s.cuda_stream if s is not None else 0)
+        outs[key] = (d_v, d_c, d_s)
+    torch.cuda.synchronize()
+    for key, vs in (("a", a), ("b", b), ("c", c)):
+        _, d_c, d_s = outs[key]
+        assert (d_s.cpu().numpy() == 0).all(), key
+        cnt = d_c.cpu().numpy()
+        for k, v in enumerate(vs):
+            got = {names[i]: int(x) for i, x in enumerate(cnt[k]) if x}
+            assert got == want[key][k], (key, v)
