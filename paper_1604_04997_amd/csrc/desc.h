@@ -257,6 +257,10 @@ struct RowAff {
     static PM_HD void each(int n, F f) {  // f(i) for i < n
         for (int i = 0; i < n; i++) f(i);
     }
+    template <class F>
+    static PM_HD void one(F f) {  // scalar stores
+        f();
+    }
 };
 
 struct LaneAff {
@@ -284,8 +288,13 @@ struct LaneAff {
     static __device__ void each(int n, F f) {  // f(i) for i < n (n <= 64), lane i
         if (lane() < n) f(lane());
     }
+    template <class F>
+    static __device__ void one(F f) {  // scalar stores: by one lane, not 64 to one address
+        if (lane() == 0) f();
+    }
 };
 static_assert(offsetof(Aff, k) == MAXVAR * sizeof(int64_t), "row layout: c then k");
+static_assert(sizeof(Stmt) % 8 == 0 && sizeof(Stmt) / 8 <= 64, "a statement is cleared one word per lane");
 static_assert(MAXJOB <= 64 && MAXVAR < 64, "LaneAff::each covers one wavefront");
 
 template <class AP>
@@ -298,16 +307,38 @@ struct BT {
     Stmt *cur = nullptr;
     int nvar = 0, nguard = 0, nacc = 0, lane = 0, nls = 0;
     // the program's statement, access and array counts and the current
-    // statement's guard variable mask, also kept here: the builder stores
-    // them without reading them back (the program starts empty)
+    // statement's guard variable mask, also kept here (the program starts
+    // empty); flush() stores them, once per statement and at the end
     int nstmt = 0, nacc_all = 0, narr = 0;
     uint64_t gmask = 0;
     bool werr = false;  // an access with no whole lane stride, or two widths on one array
     PM_HD void fail(int st) {
         if (p->status == PM_OK) p->status = st;
     }
+    // store the counts kept in registers (the current statement's and the
+    // program's); the builder calls it when it starts a statement, the
+    // caller when the family's builder has returned
+    PM_HD void flush() {
+        Stmt *s = cur;
+        const int nv = nvar, ng = nguard, na = nacc, ns = nstmt, naa = nacc_all, nar = narr;
+        const uint64_t gm = gmask;
+        Prog *pp = p;
+        AP::one([=] {
+            if (s) {
+                s->nvar = nv;
+                s->nguard = ng;
+                s->nacc = na;
+                s->gmask = gm;
+            }
+            pp->nstmt = ns;
+            pp->nacc_all = naa;
+            pp->narr = nar;
+        });
+    }
     PM_HD Stmt *stmt(int lane_var) {
+        flush();
         nvar = nguard = nacc = nls = 0;
+        gmask = 0;
         lane = lane_var;
         cur = nullptr;
         if (nstmt >= MAXSTMT) {
@@ -315,21 +346,15 @@ struct BT {
             return nullptr;
         }
         Stmt *s = &p->st[nstmt++];
-        p->nstmt = nstmt;
         cur = s;
-        s->nvar = 0;
-        s->lane = lane_var;
-        s->nguard = 0;
-        s->nacc = 0;
-        s->acc0 = nacc_all;
-        s->gmask = gmask = 0;
+        // every field zero (one 8-byte word per lane), then the extents 1
+        AP::each((int)(sizeof(Stmt) / 8), [=](int i) { ((int64_t *)s)[i] = 0; });
         AP::each(MAXVAR, [=](int i) { s->ext[i] = 1; });
-        AP::each(6, [=](int i) { (&s->lds[0][0])[i] = 0; });
-        AP::each(MAXLSITE, [=](int i) { s->lsite[i] = 0; });
-        AP::each(12, [=](int i) { (&s->flop[0][0])[i] = 0; });
-        s->bar = 0;
-        s->ncomp = 0;
-        s->fixed = 0;
+        const int a0 = nacc_all;
+        AP::one([=] {
+            s->lane = lane_var;
+            s->acc0 = a0;
+        });
         return s;
     }
     // declare variables in order; returns their ids 0..  (The id does not
@@ -342,8 +367,8 @@ struct BT {
             return MAXVAR - 1;
         }
         if (ext < 0) fail(PM_EINVAL);
-        s->ext[nvar] = ext;
-        s->nvar = nvar + 1;
+        const int x = nvar;
+        AP::one([=] { s->ext[x] = ext; });
         return nvar++;
     }
     // affine forms of this builder
@@ -356,8 +381,7 @@ struct BT {
         }
         AP::put(&s->guard[nguard], a);
         gmask |= AP::vars(a) << (8 * nguard);
-        s->gmask = gmask;
-        s->nguard = ++nguard;
+        ++nguard;
     }
     PM_HD void lt(Stmt *s, V a, int64_t b) {  // a < b  <=>  (b-1) - a >= 0
         ge0(s, AP::add_k(AP::neg(a), b - 1));
@@ -374,14 +398,15 @@ struct BT {
             fail(PM_EINVAL);
             return;
         }
-        GAcc &g = p->acc[nacc_all++];
-        p->nacc_all = nacc_all;
-        g.arr = arr;
-        g.dir = dir;
-        g.elem = elem;
-        g.vec = vec;
-        AP::put(&g.idx, idx);
-        s->nacc = ++nacc;
+        GAcc *g = &p->acc[nacc_all++];
+        AP::one([=] {
+            g->arr = arr;
+            g->dir = dir;
+            g->elem = elem;
+            g->vec = vec;
+        });
+        AP::put(&g->idx, idx);
+        ++nacc;
         // the array's fill width: lane stride (in accesses) times the width
         // of a strided (stride >= 2) access
         const int64_t cl = AP::coef(idx, lane);
@@ -391,10 +416,10 @@ struct BT {
         if (st < 0 || size_index(elem * vec) < 0) {
             werr = true;
         } else if (st >= 2) {
-            ArrInfo &A = p->arr[arr];
+            ArrInfo *A = &p->arr[arr];
             const int64_t w = st * vec;
-            if (A.w && A.w != w) werr = true;
-            else A.w = w;
+            if (A->w && A->w != w) werr = true;
+            else AP::one([=] { A->w = w; });
         }
     }
     // `count` LDS accesses of `bytes` bytes per instance whose element index
@@ -405,22 +430,28 @@ struct BT {
             fail(PM_EINVAL);
             return;
         }
-        s->lds[dir][z] += count;
-        s->lsite[nls++] = lsite_pack(dir, z, lds_bin(stride * bytes / 4), count);
+        const uint32_t site = lsite_pack(dir, z, lds_bin(stride * bytes / 4), count);
+        const int k = nls++;
+        AP::one([=] {
+            s->lds[dir][z] += count;
+            s->lsite[k] = site;
+        });
     }
     PM_HD void array(int a, int64_t cells) {
         if (a >= MAXARR) {
             fail(PM_EINVAL);
             return;
         }
-        p->arr[a].cells = cells;
-        p->arr[a].words = 0;
-        p->arr[a].f_off = p->arr[a].b_off = -1;
-        p->arr[a].w = 0;
-        p->arr[a].segs = 0;
-        p->arr[a].fixF = p->arr[a].fixFill = 0;
+        ArrInfo *A = &p->arr[a];
+        AP::one([=] {
+            A->cells = cells;
+            A->words = 0;
+            A->f_off = A->b_off = -1;
+            A->w = 0;
+            A->segs = 0;
+            A->fixF = A->fixFill = 0;
+        });
         if (a + 1 > narr) narr = a + 1;
-        p->narr = narr;
     }
 };
 
@@ -1319,6 +1350,7 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     case PM_FAM_NBODY: build_nbody(b, v); break;
     default: b.fail(PM_EINVAL);
     }
+    b.flush();
     AP::each(MAXJOB, [=](int j) {
         p->jkind[j] = JOB_NONE;
         p->jtmp[j] = -1;
