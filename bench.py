@@ -527,6 +527,38 @@ def cpu_baseline(workload, gpu_counts, names, budget_s=15.0, par_budget_s=8.0,
     return res
 
 
+def output_oracle_timing(ctx, P, n=2048, max_threads=16):
+    """The output oracle of the matmul test kernel (NumPy, FP64) timed on the
+    host with its BLAS pinned to one thread and to every core (at most
+    max_threads), beside the GPU's tiled fp32 kernel of the same size
+    (minimum of 26 timed runs)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import outputs as O
+    from synth import uniform
+    A = uniform(11, n * n).reshape(n, n)
+    B = uniform(12, n * n).reshape(n, n)
+    flop = 2.0 * n ** 3
+    out = {"kernel": "C = A B, n = m = l = %d: NumPy FP64 (the oracle) vs the tiled fp32 "
+                     "kernel (T = 16)" % n}
+    _, ncpu = host_cpu()
+    for key, thr in (("1_thread", 1), ("all_cores", max(1, min(ncpu, max_threads)))):
+        with threadpool_limits(limits=thr):
+            O.matmul(A, B)  # warm
+            best = 1e9
+            for _ in range(3):
+                t0 = time.perf_counter()
+                O.matmul(A, B)
+                best = min(best, time.perf_counter() - t0)
+        out["oracle_gflops_" + key] = round(flop / best / 1e9, 1)
+        out["threads_" + key] = thr
+    v = dict(family="matmul", op="tiled", n=n, m=n, l=n, T=16)
+    ts, _ = P.device_buffers(v, 13, fast=True)
+    r = ctx.measure_until(v, ts, warmup=4, reps=26)
+    del ts
+    out["gpu_gflops"] = round(flop / r["t_min"] / 1e9, 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -755,6 +787,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(vs, counts, P.count_names(), args.cpu_seconds)
+        cpu["output_oracle"] = output_oracle_timing(ctx, P)
         log("cpu oracle:", cpu)
 
     detail = {"model": model_info, "tiny_suite": c1, "work_group_sizes": wgs,
