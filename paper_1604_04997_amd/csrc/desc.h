@@ -824,16 +824,29 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
         return b.av(b.av(b.av(b.mk(di * P + dj), 0, P), 1, T), 2, 1);
     };
     const auto v0 = b.av(b.mk(0), 0, 1), v1 = b.av(b.mk(0), 1, 1), v2 = b.av(b.mk(0), 2, 1);
-    const auto row = b.av(b.av(b.mk(0), 0, T), 1, 1);  // gy*T + ly in (gy, ly, j)
-    const auto col = b.av(b.av(b.mk(0), 1, T), 2, 1);  // gx*T + lx in (i, gx, lx)
+    // the last cell's tile and place in it: the partial last tile row
+    // (column) is tile gl = (n-1) div T, its last row (column) rl = (n-1) mod T
+    const int64_t gl = (n - 1) / T, rl = (n - 1) % T;
     for (int q = 0; q < 7; q++) {
         // the tile and the halo rows: lane stride 1; the halo columns
-        // (lx == 0, lx == T-1) are written at a fixed column
-        Stmt *S = b.stmt(q == 0 ? 1 : 2);
+        // (lx == 0, lx == T-1) are written at a fixed column.  The guards of
+        // the last tile's halo are solved for the pinned variables:
+        // ly == T-1 && gy*T + ly < n  <=>  ly == T-1 && gy < n div T, and
+        // ly < T-1 && gy*T + ly == n-1  <=>  gy == gl && ly == rl < T-1
+        // (that statement is written without gy); the same for columns
+        Stmt *S = b.stmt(q == 0 || q == 3 ? 1 : 2);
         if (!S) return;
         if (q == 0) ij(S);
-        else if (q <= 3) rj(S);
-        else ic(S);
+        else if (q <= 2) rj(S);
+        else if (q == 3) {  // 0 ly, 1 j; gy = gl
+            b.var(S, T);
+            b.var(S, G * T);
+        } else if (q <= 5) ic(S);
+        else {  // 0 i, 1 gx (unused, extent 1), 2 lx; gx = gl
+            b.var(S, G * T);
+            b.var(S, 1);
+            b.var(S, T);
+        }
         b.lds(S, D_ST, e, q == 4 || q == 5 ? 0 : 1, 1);
         switch (q) {
         case 0:  // the tile
@@ -845,24 +858,30 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
             b.acc(S, 0, D_LD, e, 1, at_rj(0, 1));
             break;
         case 2:  // bottom halo row of a full tile, loaded by ly == T-1
-            b.eq(S, v1, T - 1), b.lt(S, row, n), b.lt(S, v2, n);
+            b.eq(S, v1, T - 1), b.lt(S, v0, n / T), b.lt(S, v2, n);
             b.acc(S, 0, D_LD, e, 1, at_rj(2, 1));
             break;
-        case 3:  // bottom halo row of the last, partial tile row
-            b.lt(S, v1, T - 1), b.eq(S, row, n - 1), b.lt(S, v2, n);
-            b.acc(S, 0, D_LD, e, 1, at_rj(2, 1));
+        case 3:  // bottom halo row of the last, partial tile row (none if it is full)
+            if (rl < T - 1) b.eq(S, v0, rl);
+            else b.lt(S, v0, 0);
+            b.lt(S, v1, n);
+            // cell (gl*T + ly + 2, j + 1)
+            b.acc(S, 0, D_LD, e, 1, b.av(b.av(b.mk((gl * T + 2) * P + 1), 0, P), 1, 1));
             break;
         case 4:  // left halo column, loaded by lx == 0
             b.eq(S, v2, 0), b.lt(S, v0, n);
             b.acc(S, 0, D_LD, e, 1, at_ic(1, 0));
             break;
         case 5:  // right halo column of a full tile
-            b.eq(S, v2, T - 1), b.lt(S, v0, n), b.lt(S, col, n);
+            b.eq(S, v2, T - 1), b.lt(S, v0, n), b.lt(S, v1, n / T);
             b.acc(S, 0, D_LD, e, 1, at_ic(1, 2));
             break;
-        default:  // right halo column of the last, partial tile column
-            b.lt(S, v2, T - 1), b.eq(S, col, n - 1), b.lt(S, v0, n);
-            b.acc(S, 0, D_LD, e, 1, at_ic(1, 2));
+        default:  // right halo column of the last, partial tile column (none if full)
+            if (rl < T - 1) b.eq(S, v2, rl);
+            else b.lt(S, v2, 0);
+            b.lt(S, v0, n);
+            // cell (i + 1, gl*T + lx + 2)
+            b.acc(S, 0, D_LD, e, 1, b.av(b.av(b.mk(P + gl * T + 2), 0, P), 2, 1));
         }
     }
     Stmt *Sb = b.stmt(1);  // every work-item, once
