@@ -664,22 +664,29 @@ PM_HD void build_matmul(BB &b, const pm_variant &v) {
         b.var(S, T);
         b.var(S, T);
     };
-    auto row = b.av(b.av(b.mk(0), 0, T), 2, 1), col = b.av(b.av(b.mk(0), 1, T), 3, 1);
+    // Statements with guards are written over the fused indices their
+    // guards test (row r = gy*T + ly, column c = gx*T + lx, and the k
+    // offsets kt*T + lx or kt*T + ly of the tiles): the same points, each
+    // guard on one variable; the lane variable is the index whose least
+    // significant digit is lx
+    const auto v0 = b.av(b.mk(0), 0, 1), v1 = b.av(b.mk(0), 1, 1), v2 = b.av(b.mk(0), 2, 1);
     if (v.op == PM_MATMUL_TILED) {
-        Stmt *S = b.stmt(3);  // A tile element -> LDS
+        Stmt *S = b.stmt(2);  // A tile element -> LDS: A[r][kt*T + lx]
         if (!S) return;
-        head(S);
-        int kt = b.var(S, KT);
-        b.lt(S, row, n);
-        b.lt(S, b.av(b.av(b.mk(0), kt, T), 3, 1), m);
-        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 0, T * m), 2, m), kt, T), 3, 1));
-        Stmt *Sb = b.stmt(3);  // B tile element -> LDS
+        b.var(S, GY * T);  // 0 r
+        b.var(S, GX);      // 1 gx
+        b.var(S, KT * T);  // 2 kt*T + lx
+        b.lt(S, v0, n);
+        b.lt(S, v2, m);
+        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.mk(0), 0, m), 2, 1));
+        Stmt *Sb = b.stmt(2);  // B tile element -> LDS: B[kt*T + ly][c]
         if (!Sb) return;
-        head(Sb);
-        kt = b.var(Sb, KT);
-        b.lt(Sb, b.av(b.av(b.mk(0), kt, T), 2, 1), m);
-        b.lt(Sb, col, L);
-        b.acc(Sb, 1, D_LD, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), kt, T * L), 2, L), 1, T), 3, 1));
+        b.var(Sb, GY);      // 0 gy
+        b.var(Sb, KT * T);  // 1 kt*T + ly
+        b.var(Sb, GX * T);  // 2 c
+        b.lt(Sb, v1, m);
+        b.lt(Sb, v2, L);
+        b.acc(Sb, 1, D_LD, 4, 1, b.av(b.av(b.mk(0), 1, L), 2, 1));
         Stmt *Sl = b.stmt(3);  // LDS stores (zero-padded outside) + 2 barriers
         if (!Sl) return;
         head(Sl);
@@ -695,22 +702,24 @@ PM_HD void build_matmul(BB &b, const pm_variant &v) {
         b.lds(Si, D_LD, 4, 1, 1);  // Bs[k][lx]
         Si->flop[K_FMA][0] = 1;
     } else {
-        Stmt *S = b.stmt(3);
+        Stmt *S = b.stmt(1);  // C[r][c] += A[r][k] * B[k][c]
         if (!S) return;
-        head(S);
-        int k = b.var(S, m);
-        b.lt(S, row, n);
-        b.lt(S, col, L);
-        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.av(b.mk(0), 0, T * m), 2, m), k, 1));
-        b.acc(S, 1, D_LD, 4, 1, b.av(b.av(b.av(b.mk(0), k, L), 1, T), 3, 1));
+        b.var(S, GY * T);  // 0 r
+        b.var(S, GX * T);  // 1 c
+        b.var(S, m);       // 2 k
+        b.lt(S, v0, n);
+        b.lt(S, v1, L);
+        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.mk(0), 0, m), 2, 1));
+        b.acc(S, 1, D_LD, 4, 1, b.av(b.av(b.mk(0), 2, L), 1, 1));
         S->flop[K_FMA][0] = 1;
     }
-    Stmt *Sc = b.stmt(3);
+    Stmt *Sc = b.stmt(1);  // C[r][c]
     if (!Sc) return;
-    head(Sc);
-    b.lt(Sc, row, n);
-    b.lt(Sc, col, L);
-    b.acc(Sc, 2, D_ST, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 0, T * L), 2, L), 1, T), 3, 1));
+    b.var(Sc, GY * T);  // 0 r
+    b.var(Sc, GX * T);  // 1 c
+    b.lt(Sc, v0, n);
+    b.lt(Sc, v1, L);
+    b.acc(Sc, 2, D_ST, 4, 1, b.av(b.av(b.mk(0), 0, L), 1, 1));
 }
 
 // --- transpose: out[c][r] = in[r][c], n x n ---
@@ -733,27 +742,30 @@ PM_HD void build_transpose(BB &b, const pm_variant &v) {
         b.var(S, T);  // 2 ly
         b.var(S, T);  // 3 lx
     };
-    auto r = b.av(b.av(b.mk(0), 0, T), 2, 1), c = b.av(b.av(b.mk(0), 1, T), 3, 1);
     if (v.op == PM_TRANSPOSE_TILED) {
-        auto rn_c = b.av(b.av(b.av(b.av(b.mk(0), 0, T * n), 2, n), 1, T), 3, 1);  // r*n + c
-        Stmt *S = b.stmt(3);
+        // the guarded statements over the fused indices they test (the
+        // lane variable holds lx as its least significant digit)
+        const auto f0 = b.av(b.mk(0), 0, 1), f1 = b.av(b.mk(0), 1, 1);
+        Stmt *S = b.stmt(1);  // in[r][c] -> tile[ly][lx]; r = gy*T + ly, c = gx*T + lx
         if (!S) return;
-        head(S);
-        b.lt(S, r, n);
-        b.lt(S, c, n);
-        b.acc(S, 0, D_LD, 4, 1, rn_c);
+        b.var(S, G * T);
+        b.var(S, G * T);
+        b.lt(S, f0, n);
+        b.lt(S, f1, n);
+        b.acc(S, 0, D_LD, 4, 1, b.av(b.av(b.mk(0), 0, n), 1, 1));
         b.lds(S, D_ST, 4, 1, 1);  // tile[ly][lx], rows of T + 1
         Stmt *Sb = b.stmt(3);
         if (!Sb) return;
         head(Sb);
         Sb->bar = 1;
-        Stmt *St = b.stmt(3);  // r2 = gx*T + ly, c2 = gy*T + lx
+        Stmt *St = b.stmt(1);  // tile[lx][ly] -> out[r2][c2]; r2 = gx*T + ly, c2 = gy*T + lx
         if (!St) return;
-        head(St);
-        b.lt(St, b.av(b.av(b.mk(0), 1, T), 2, 1), n);
-        b.lt(St, b.av(b.av(b.mk(0), 0, T), 3, 1), n);
+        b.var(St, G * T);
+        b.var(St, G * T);
+        b.lt(St, f0, n);
+        b.lt(St, f1, n);
         b.lds(St, D_LD, 4, T + 1, 1);  // tile[lx][ly]
-        b.acc(St, 1, D_ST, 4, 1, b.av(b.av(b.av(b.av(b.mk(0), 1, T * n), 2, n), 0, T), 3, 1));
+        b.acc(St, 1, D_ST, 4, 1, b.av(b.av(b.mk(0), 0, n), 1, 1));
     } else {
         // one element per work-item and nothing shared within a group: the
         // domain written over the fused indices r = gy*T + ly and
