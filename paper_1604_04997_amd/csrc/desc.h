@@ -861,9 +861,13 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
         }
         b.lds(S, D_ST, e, q == 4 || q == 5 ? 0 : 1, 1);
         switch (q) {
-        case 0:  // the tile
+        case 0:  // the tile, and the update of its cell (the same points)
             b.lt(S, v0, n), b.lt(S, v1, n);
             b.acc(S, 0, D_LD, e, 1, at_ij(1, 1));
+            b.lds(S, D_LD, e, 1, 5);  // the point and its four neighbours, rows of T + 2
+            S->flop[K_ADD][dt] = 4;  // N+S, +W, +E, + h^2 c^2
+            S->flop[K_MUL][dt] = 3;  // c*c, h^2*(.), 0.25*(.)
+            b.acc(S, 1, D_ST, e, 1, b.av(b.av(b.mk(0), 0, n), 1, 1));
             break;
         case 1:  // top halo row, loaded by ly == 0
             b.eq(S, v1, 0), b.lt(S, v2, n);
@@ -896,18 +900,10 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
             b.acc(S, 0, D_LD, e, 1, b.av(b.av(b.mk(P + gl * T + 2), 0, P), 2, 1));
         }
     }
-    Stmt *Sb = b.stmt(1);  // every work-item, once
+    Stmt *Sb = b.stmt(1);  // the barrier: every work-item, once
     if (!Sb) return;
     ij(Sb);
     Sb->bar = 1;
-    Stmt *Sc = b.stmt(1);
-    if (!Sc) return;
-    ij(Sc);
-    b.lt(Sc, v0, n), b.lt(Sc, v1, n);
-    b.lds(Sc, D_LD, e, 1, 5);  // the point and its four neighbours, rows of T + 2
-    Sc->flop[K_ADD][dt] = 4;  // N+S, +W, +E, + h^2 c^2
-    Sc->flop[K_MUL][dt] = 3;  // c*c, h^2*(.), 0.25*(.)
-    b.acc(Sc, 1, D_ST, e, 1, b.av(b.av(b.mk(0), 0, n), 1, 1));
 }
 
 // --- all-pairs n-body: out[i] = sum_{j != i} rsqrt(|x_i - x_j|^2) ---
