@@ -1629,9 +1629,16 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
                 for (int t = 0; t < MAXVAR; t++) ic[t] = row[t];
                 ic[MAXVAR] = a.idx.k;
             }
-            // fuse over guards and the index map together
+            // fuse over guards and the index map together (two variables
+            // can fuse only when they appear in the same rows)
             bool ovf = false;
-            J.nv = fuse(J.nv, J.ext, J.ng + 1, J.f, &ovf);
+            bool same_rows = J.nv > 2;
+            if (J.nv == 2) {
+                same_rows = true;
+                for (int q = 0; q <= J.ng; q++)
+                    if ((J.f[q][0] != 0) != (J.f[q][1] != 0)) same_rows = false;
+            }
+            if (same_rows) J.nv = fuse(J.nv, J.ext, J.ng + 1, J.f, &ovf);
             if (ovf) return PM_EOVERFLOW;
             if (J.nv == 0) {  // a single access point
                 J.nv = 1;
