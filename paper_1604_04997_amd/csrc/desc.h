@@ -207,6 +207,7 @@ PM_HD int64_t tdiv(int64_t a, int64_t b) {
     return div64_slow(a, b);
 }
 PM_HD int64_t cdiv(int64_t a, int64_t b) { return tdiv(a + b - 1, b); }
+PM_HD int64_t tmod(int64_t a, int64_t b) { return a - tdiv(a, b) * b; }  // a % b
 // floor(a / b) and ceil(a / b) for b > 0, any sign of a
 PM_HD int64_t fdiv(int64_t a, int64_t b) {
     const int64_t q = tdiv(a, b);
@@ -472,13 +473,13 @@ PM_HD void build_stream(BB &b, const pm_variant &v) {
             vec = v.vec, U = v.reps;
     int e = v.dtype == PM_F64 ? 8 : 4;
     int dt = v.dtype == PM_F64 ? 1 : 0;
-    if (N <= 0 || wg <= 0 || wg > 1024 || N % wg || s < 1 || gs < 1 ||
+    if (N <= 0 || wg <= 0 || wg > 1024 || tmod(N, wg) || s < 1 || gs < 1 ||
         U < 1 || !(vec == 1 || vec == 2 || vec == 4) || e * vec > 16 ||
         v.op > PM_STREAM_AXPBY) {
         b.fail(PM_EINVAL);
         return;
     }
-    int64_t G = N / wg;
+    int64_t G = tdiv(N, wg);
     b.p->n_wg = G;
     b.p->wg_size = (int32_t)wg;
     if (v.op == PM_STREAM_FILLED) {
@@ -542,7 +543,7 @@ template <class BB>
 PM_HD void build_lds(BB &b, const pm_variant &v) {
     int64_t G = v.n[0], wg = v.wg[0], R = v.reps, W = v.words;
     if (G <= 0 || wg <= 0 || wg > 1024 || R < 0 || v.stride < 1 ||
-        !pow2(W) || W > 16384 || W % wg || v.op > PM_LDS_WRITE) {
+        !pow2(W) || W > 16384 || tmod(W, wg) || v.op > PM_LDS_WRITE) {
         b.fail(PM_EINVAL);
         return;
     }
@@ -554,7 +555,7 @@ PM_HD void build_lds(BB &b, const pm_variant &v) {
     int g = b.var(S, G), l = b.var(S, wg);
     b.acc(S, 0, D_ST, 4, 1, b.av(b.av(b.mk(0), g, wg), l, 1));
     S->bar = 1;
-    if (v.op == PM_LDS_READ) b.lds(S, D_ST, 4, 1, (int)(W / wg));  // initialisation lds[c*wg + l]
+    if (v.op == PM_LDS_READ) b.lds(S, D_ST, 4, 1, (int)tdiv(W, wg));  // initialisation lds[c*wg + l]
     else b.lds(S, D_LD, 4, v.stride, 1);  // read-back lds[(l*b) mod W]
     Stmt *L = b.stmt(1);
     if (!L) return;
@@ -579,18 +580,18 @@ PM_HD void build_chain(BB &b, const pm_variant &v, int kind) {
     bool rsq = kind == 1;
     bool kok = kind ? (K == 1 || K == 2 || K == 4 || K == 8)
                     : (K == 1 || K == 2 || K == 4 || K == 8 || K == 16);
-    if (N <= 0 || wg <= 0 || wg > 1024 || N % wg || !kok || F < 0 || F % K ||
+    if (N <= 0 || wg <= 0 || wg > 1024 || tmod(N, wg) || !kok || F < 0 || tmod(F, K) ||
         F > (1 << 24) || (rsq && v.dtype != PM_F32) || (kind >= 2 && v.op > PM_ARITH_EXP)) {
         b.fail(PM_EINVAL);
         return;
     }
-    b.p->n_wg = N / wg;
+    b.p->n_wg = tdiv(N, wg);
     b.p->wg_size = (int32_t)wg;
     b.array(0, N);
     b.array(1, N);
     Stmt *S = b.stmt(1);
     if (!S) return;
-    int g = b.var(S, N / wg), l = b.var(S, wg);
+    int g = b.var(S, tdiv(N, wg)), l = b.var(S, wg);
     auto i = b.av(b.av(b.mk(0), g, wg), l, 1);
     b.acc(S, 0, D_LD, e, 1, i);
     b.acc(S, 1, D_ST, e, 1, i);
@@ -838,7 +839,7 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
     const auto v0 = b.av(b.mk(0), 0, 1), v1 = b.av(b.mk(0), 1, 1), v2 = b.av(b.mk(0), 2, 1);
     // the last cell's tile and place in it: the partial last tile row
     // (column) is tile gl = (n-1) div T, its last row (column) rl = (n-1) mod T
-    const int64_t gl = (n - 1) / T, rl = (n - 1) % T;
+    const int64_t gl = tdiv(n - 1, T), rl = n - 1 - gl * T, nt = tdiv(n, T);
     for (int q = 0; q < 7; q++) {
         // the tile and the halo rows: lane stride 1; the halo columns
         // (lx == 0, lx == T-1) are written at a fixed column.  The guards of
@@ -874,7 +875,7 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
             b.acc(S, 0, D_LD, e, 1, at_rj(0, 1));
             break;
         case 2:  // bottom halo row of a full tile, loaded by ly == T-1
-            b.eq(S, v1, T - 1), b.lt(S, v0, n / T), b.lt(S, v2, n);
+            b.eq(S, v1, T - 1), b.lt(S, v0, nt), b.lt(S, v2, n);
             b.acc(S, 0, D_LD, e, 1, at_rj(2, 1));
             break;
         case 3:  // bottom halo row of the last, partial tile row (none if it is full)
@@ -889,7 +890,7 @@ PM_HD void build_stencil(BB &b, const pm_variant &v) {
             b.acc(S, 0, D_LD, e, 1, at_ic(1, 0));
             break;
         case 5:  // right halo column of a full tile
-            b.eq(S, v2, T - 1), b.lt(S, v0, n), b.lt(S, v1, n / T);
+            b.eq(S, v2, T - 1), b.lt(S, v0, n), b.lt(S, v1, nt);
             b.acc(S, 0, D_LD, e, 1, at_ic(1, 2));
             break;
         default:  // right halo column of the last, partial tile column (none if full)
