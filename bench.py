@@ -742,12 +742,17 @@ def main():
         log("autotune: %d problems, every configuration measured" % len(probs))
         res = autotune.rank_and_measure(ctx, m, probs, measure_all=True)
         tune = autotune.summary(res)
+        tune["per_problem"] = [
+            {"problem": r["problem"],
+             "configs": ["%s/%s" % (c.get("op", ""), c.get("T", c.get("wg", ""))) for c in r["configs"]],
+             "predicted_ms": [round(x * 1e3, 5) for x in r["predicted"]],
+             "measured_ms": [round(x * 1e3, 5) for x in r["measured"]]} for r in res]
         tune["per_family"] = {}
         for fam in ("matmul", "stencil", "transpose"):
             rr = [r for r in res if r["problem"]["family"] == fam]
             if rr:
                 tune["per_family"][fam] = autotune.summary(rr)
-        log("autotune:", json.dumps(tune))
+        log("autotune:", json.dumps({k: x for k, x in tune.items() if k != "per_problem"}))
 
     # ----------------------------------------------------------- serving --
     serving = None
@@ -844,7 +849,8 @@ def main():
                                           wgs["ext"]["test_geomean_fit_all_wg"]]}
         if wgs and "ext" in wgs else None,
         "autotune": {k: round(tune[k], 4) for k in ("choice_is_best", "geomean_slowdown",
-                                                    "mean_spearman")} if tune else None,
+                                                    "mean_spearman", "top2_geomean_slowdown",
+                                                    "top3_geomean_slowdown")} if tune else None,
         "serving": srv,
         "hbm": {k: suite_roof[k]["frac_8TBs"] for k in
                 ("best_load", "best_copy", "best_load_4B", "best_copy_4B")} if suite_roof else None,

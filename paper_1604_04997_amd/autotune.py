@@ -83,16 +83,34 @@ def rank_and_measure(ctx, model, problems, top_k: int = 3, measure_all=False,
     return out
 
 
-def summary(results):
+def topk_slowdown(rec, k: int):
+    """Slowdown, against the fastest configuration measured, of keeping the
+    fastest of the k configurations with the lowest predicted time (the
+    selection protocol of measuring only the model's best few).  Needs the
+    record's k best-predicted configurations measured."""
+    order = sorted(range(len(rec["predicted"])), key=lambda i: rec["predicted"][i])
+    if k > len(order):
+        k = len(order)
+    return min(rec["measured"][i] for i in order[:k]) / min(rec["measured"])
+
+
+def summary(results, ks=(2, 3)):
     """Geomean slowdown of the predicted choice, fraction of problems where
-    it is the measured best, mean rank correlation."""
+    it is the measured best, mean rank correlation, and the geomean slowdown
+    of measuring the model's top k and keeping the fastest (for each k in
+    `ks`; meaningful when every configuration was measured)."""
     sl = [r["slowdown"] for r in results]
     sp = [r["spearman"] for r in results if "spearman" in r and not math.isnan(r["spearman"])]
-    return {"problems": len(results),
-            "choice_is_best": float(np.mean([s <= 1.0 + 1e-12 for s in sl])),
-            "geomean_slowdown": float(math.exp(np.mean(np.log(sl)))),
-            "max_slowdown": float(max(sl)),
-            "mean_spearman": float(np.mean(sp)) if sp else None}
+    out = {"problems": len(results),
+           "choice_is_best": float(np.mean([s <= 1.0 + 1e-12 for s in sl])),
+           "geomean_slowdown": float(math.exp(np.mean(np.log(sl)))),
+           "max_slowdown": float(max(sl)),
+           "mean_spearman": float(np.mean(sp)) if sp else None}
+    for k in ks:
+        tk = [topk_slowdown(r, k) for r in results]
+        out["top%d_geomean_slowdown" % k] = float(math.exp(np.mean(np.log(tk))))
+        out["top%d_max_slowdown" % k] = float(max(tk))
+    return out
 
 
 # Schedules of the batched counter tried by tune_counter: the in-block item

@@ -359,3 +359,25 @@ def test_qpoly_eval_binomial_basis():
     with pytest.raises(P.PMError) as e:
         P.qpoly_eval(qp, 5 + 2 * 100)
     assert e.value.code == -5
+
+
+def test_autotune_summary_top_k_selection():
+    """The selection summaries on hand-made records: the model's pick, and
+    keeping the fastest of its top k measured (host logic only)."""
+    from paper_1604_04997_amd import autotune
+    # predicted order c, a, b; measured fastest b
+    r1 = {"predicted": [2.0, 3.0, 1.0], "measured": [1.5, 1.0, 2.0], "slowdown": 2.0,
+          "spearman": -0.5}
+    # the model's pick is the measured best
+    r2 = {"predicted": [1.0, 2.0], "measured": [1.0, 4.0], "slowdown": 1.0}
+    assert autotune.topk_slowdown(r1, 1) == 2.0
+    assert autotune.topk_slowdown(r1, 2) == 1.5
+    assert autotune.topk_slowdown(r1, 3) == 1.0
+    assert autotune.topk_slowdown(r2, 5) == 1.0  # k past the configurations
+    s = autotune.summary([r1, r2], ks=(2, 3))
+    assert s["problems"] == 2 and s["choice_is_best"] == 0.5
+    assert s["geomean_slowdown"] == pytest.approx(2.0 ** 0.5)
+    assert s["top2_geomean_slowdown"] == pytest.approx(1.5 ** 0.5)
+    assert s["top2_max_slowdown"] == 1.5
+    assert s["top3_geomean_slowdown"] == 1.0
+    assert s["mean_spearman"] == -0.5
