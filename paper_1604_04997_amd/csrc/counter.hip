@@ -37,6 +37,55 @@ namespace pm {
 constexpr int FUSED_THREADS = 256;
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 
+// Sums and scans over one wavefront's 64 lanes, every lane active.  Steps
+// that cross a row of 16 lanes go through ds_bpermute (__shfl_xor); steps
+// inside a row through DPP, which stays in the vector ALU.  row_ror:k gives
+// lane i the value of lane (i - k) mod 16 of its row: once lanes that
+// differ only in bits above k hold equal values, that is lane i xor k's, so
+// xsum adds the same pairs in the same order as a xor butterfly over 32,
+// 16, ..., 1 (bit for bit, also in floating point).  scan_incl: row_shr
+// steps inside each row, then each row adds the totals of the rows below
+// it through row_bcast:15 and row_bcast:31.
+constexpr int DPP_ROW_SHR = 0x110, DPP_ROW_ROR = 0x120, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+template <int CTRL, int ROWMASK = 0xF>
+__device__ inline uint64_t dpp64(uint64_t u) {  // lanes with no source, or in masked rows: 0
+    constexpr bool zero_oob = ROWMASK == 0xF;
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWMASK, 0xF, zero_oob);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWMASK, 0xF, zero_oob);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+    return __longlong_as_double((long long)dpp64<CTRL>((uint64_t)__double_as_longlong(x)));
+}
+__device__ inline double xsum(double x) {
+    x += __shfl_xor(x, 32);
+    x += __shfl_xor(x, 16);
+    x += dpp_f64<DPP_ROW_ROR + 8>(x);
+    x += dpp_f64<DPP_ROW_ROR + 4>(x);
+    x += dpp_f64<DPP_ROW_ROR + 2>(x);
+    x += dpp_f64<DPP_ROW_ROR + 1>(x);
+    return x;
+}
+__device__ inline int64_t xsum(int64_t x) {
+    x += __shfl_xor(x, 32);
+    x += __shfl_xor(x, 16);
+    x += (int64_t)dpp64<DPP_ROW_ROR + 8>((uint64_t)x);
+    x += (int64_t)dpp64<DPP_ROW_ROR + 4>((uint64_t)x);
+    x += (int64_t)dpp64<DPP_ROW_ROR + 2>((uint64_t)x);
+    x += (int64_t)dpp64<DPP_ROW_ROR + 1>((uint64_t)x);
+    return x;
+}
+__device__ inline int64_t scan_incl(int64_t c) {  // lane j: the sum over lanes 0..j
+    c += (int64_t)dpp64<DPP_ROW_SHR + 1>((uint64_t)c);
+    c += (int64_t)dpp64<DPP_ROW_SHR + 2>((uint64_t)c);
+    c += (int64_t)dpp64<DPP_ROW_SHR + 4>((uint64_t)c);
+    c += (int64_t)dpp64<DPP_ROW_SHR + 8>((uint64_t)c);
+    c += (int64_t)dpp64<DPP_BCAST15, 0xA>((uint64_t)c);  // rows 1 and 3: lane 15 of the row below
+    c += (int64_t)dpp64<DPP_BCAST31, 0xC>((uint64_t)c);  // rows 2 and 3: lane 31
+    return c;
+}
+
 // Expansion of one variant by a work-group (at least MAXSTMT threads; all
 // call this): the first wavefront lays out the statements (affine forms
 // spread over its lanes), thread si analyses
@@ -81,10 +130,8 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
         if (j < p->njob && p->jkind[j] != JOB_NONE)
             c = keep && p->jtmp[j] >= 0 ? keep[p->jtmp[j]].chunks : jobs[j].chunks;
         if (j < p->narr && p->arr[j].w && p->arr[j].words) g = p->arr[j].segs;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t c1 = __shfl_up(c, d), g1 = __shfl_up(g, d);
-            if (j >= d) c += c1, g += g1;
-        }
+        c = scan_incl(c);
+        g = scan_incl(g);
         if (j < MAXJOB) p->jobcum[j] = c;
         if (j < MAXARR) p->arrcum[j] = g;
         if (j == 63) p->chunks = c, p->segs = g;
@@ -125,10 +172,7 @@ struct FinShared {
 struct Agg {
     double gb, ops, sp, ldsb, full0, full1, part0, part1, s10, s11;
 };
-__device__ inline double wave_sum(double x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    return x;
-}
+__device__ inline double wave_sum(double x) { return xsum(x); }
 __device__ Agg wave_aggregates(const int64_t *c, int l) {
     Agg a{};
     for (int k = l; k < C_LDSB; k += 64) {  // the binned LDS slots repeat [C_LDS, C_FLOP)
@@ -307,7 +351,7 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
         } else if (st2 == PM_OK) {
             for (int i = l; i < nf; i += 64) part += model.alpha[i] * feature_dev(sh.c, proj, i, a);
         }
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        part = xsum(part);
         if (t == 0) *pred = st2 == PM_OK ? part : 0.0;
     }
     return st2;
@@ -405,7 +449,7 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
         const bool cj = t < P.njob && P.jkind[t] == JOB_COUNT;
         const int tb = cj ? P.jtmp[t] : -1;
         int64_t items = cj ? (tb >= 0 ? U.jt[tb].items : vj[t].items) : 0;
-        for (int off = 32; off > 0; off >>= 1) items += __shfl_xor(items, off);
+        items = xsum(items);
         const uint64_t m = __ballot(cj), fm = __ballot(cj && tb < 0);
         const int n = __popcll(m);
         if (n <= NTEMP && items <= max_items) {
@@ -452,7 +496,7 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
         }
 #pragma unroll
         for (int q = 0; q < NTEMP; q++) {
-            for (int off = 32; off > 0; off >>= 1) s0[q] += __shfl_xor(s0[q], off);
+            s0[q] = xsum(s0[q]);
             if (t == 0 && q < ncj) jr[jid[q]] = s0[q];
         }
         __syncthreads();
