@@ -37,15 +37,17 @@ namespace pm {
 constexpr int FUSED_THREADS = 256;
 constexpr int FUSED_MAX_NV = 32;       // batches up to this size use k_fused
 
-// Sums and scans over one wavefront's 64 lanes, every lane active.  Steps
-// that cross a row of 16 lanes go through ds_bpermute (__shfl_xor); steps
-// inside a row through DPP, which stays in the vector ALU.  row_ror:k gives
-// lane i the value of lane (i - k) mod 16 of its row: once lanes that
-// differ only in bits above k hold equal values, that is lane i xor k's, so
-// xsum adds the same pairs in the same order as a xor butterfly over 32,
-// 16, ..., 1 (bit for bit, also in floating point).  scan_incl: row_shr
-// steps inside each row, then each row adds the totals of the rows below
-// it through row_bcast:15 and row_bcast:31.
+// Sums and scans over one wavefront's 64 lanes, every lane active, in the
+// vector ALU (no ds_bpermute).  Across rows of 16 lanes: gfx950's
+// v_permlane32_swap / v_permlane16_swap of a value with itself give every
+// lane the lower and the upper of the two halves (rows) it pairs, whose sum
+// is its own value plus its xor-32 (xor-16) partner's.  Inside a row, DPP
+// row_ror:k gives lane i the value of lane (i - k) mod 16: once lanes that
+// differ only in bits above k hold equal values, that is lane i xor k's.
+// So xsum adds the same pairs in the same order as a xor butterfly over
+// 32, 16, ..., 1 (bit for bit, also in floating point).  scan_incl:
+// row_shr steps inside each row, then each row adds the totals of the rows
+// below it through row_bcast:15 and row_bcast:31.
 constexpr int DPP_ROW_SHR = 0x110, DPP_ROW_ROR = 0x120, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
 template <int CTRL, int ROWMASK = 0xF>
 __device__ inline uint64_t dpp64(uint64_t u) {  // lanes with no source, or in masked rows: 0
@@ -58,9 +60,36 @@ template <int CTRL>
 __device__ inline double dpp_f64(double x) {
     return __longlong_as_double((long long)dpp64<CTRL>((uint64_t)__double_as_longlong(x)));
 }
+template <int HALF>  // 32: lanes l and l ^ 32; 16: lanes l and l ^ 16
+__device__ inline void swap_pair(uint64_t u, uint64_t *lo_half, uint64_t *hi_half) {
+    const uint32_t a = (uint32_t)u, b = (uint32_t)(u >> 32);
+    if constexpr (HALF == 32) {
+        const auto pa = __builtin_amdgcn_permlane32_swap(a, a, false, false);
+        const auto pb = __builtin_amdgcn_permlane32_swap(b, b, false, false);
+        *lo_half = ((uint64_t)pb[0] << 32) | pa[0];
+        *hi_half = ((uint64_t)pb[1] << 32) | pa[1];
+    } else {
+        const auto pa = __builtin_amdgcn_permlane16_swap(a, a, false, false);
+        const auto pb = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+        *lo_half = ((uint64_t)pb[0] << 32) | pa[0];
+        *hi_half = ((uint64_t)pb[1] << 32) | pa[1];
+    }
+}
+template <int HALF>
+__device__ inline double pair_sum(double x) {
+    uint64_t p, q;
+    swap_pair<HALF>((uint64_t)__double_as_longlong(x), &p, &q);
+    return __longlong_as_double((long long)p) + __longlong_as_double((long long)q);
+}
+template <int HALF>
+__device__ inline int64_t pair_sum(int64_t x) {
+    uint64_t p, q;
+    swap_pair<HALF>((uint64_t)x, &p, &q);
+    return (int64_t)p + (int64_t)q;
+}
 __device__ inline double xsum(double x) {
-    x += __shfl_xor(x, 32);
-    x += __shfl_xor(x, 16);
+    x = pair_sum<32>(x);
+    x = pair_sum<16>(x);
     x += dpp_f64<DPP_ROW_ROR + 8>(x);
     x += dpp_f64<DPP_ROW_ROR + 4>(x);
     x += dpp_f64<DPP_ROW_ROR + 2>(x);
@@ -68,8 +97,8 @@ __device__ inline double xsum(double x) {
     return x;
 }
 __device__ inline int64_t xsum(int64_t x) {
-    x += __shfl_xor(x, 32);
-    x += __shfl_xor(x, 16);
+    x = pair_sum<32>(x);
+    x = pair_sum<16>(x);
     x += (int64_t)dpp64<DPP_ROW_ROR + 8>((uint64_t)x);
     x += (int64_t)dpp64<DPP_ROW_ROR + 4>((uint64_t)x);
     x += (int64_t)dpp64<DPP_ROW_ROR + 2>((uint64_t)x);
