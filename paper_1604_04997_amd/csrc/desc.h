@@ -313,6 +313,27 @@ struct BT {
     int nstmt = 0, nacc_all = 0, narr = 0;
     uint64_t gmask = 0;
     bool werr = false;  // an access with no whole lane stride, or two widths on one array
+    // the current statement's LDS access counts by direction and size
+    // (index dir * 3 + size) and the arrays' fill widths, kept here too, so
+    // that lds() and acc() store without reading LDS back; a select chain
+    // keeps them in scalar registers whatever the index
+    int32_t lc0 = 0, lc1 = 0, lc2 = 0, lc3 = 0, lc4 = 0, lc5 = 0;
+    int64_t aw0 = 0, aw1 = 0, aw2 = 0, aw3 = 0, aw4 = 0, aw5 = 0;
+    static_assert(MAXARR == 6, "one width register per array");
+    PM_HD int64_t width(int a) const {
+        return a == 0 ? aw0 : a == 1 ? aw1 : a == 2 ? aw2 : a == 3 ? aw3 : a == 4 ? aw4 : aw5;
+    }
+    PM_HD void set_width(int a, int64_t w) {
+        aw0 = a == 0 ? w : aw0, aw1 = a == 1 ? w : aw1, aw2 = a == 2 ? w : aw2;
+        aw3 = a == 3 ? w : aw3, aw4 = a == 4 ? w : aw4, aw5 = a == 5 ? w : aw5;
+    }
+    PM_HD int32_t add_lds(int k, int32_t count) {  // returns the new total of slot k
+        const int32_t t = count + (k == 0 ? lc0 : k == 1 ? lc1 : k == 2 ? lc2
+                                   : k == 3 ? lc3 : k == 4 ? lc4 : lc5);
+        lc0 = k == 0 ? t : lc0, lc1 = k == 1 ? t : lc1, lc2 = k == 2 ? t : lc2;
+        lc3 = k == 3 ? t : lc3, lc4 = k == 4 ? t : lc4, lc5 = k == 5 ? t : lc5;
+        return t;
+    }
     PM_HD void fail(int st) {
         if (p->status == PM_OK) p->status = st;
     }
@@ -339,6 +360,7 @@ struct BT {
     PM_HD Stmt *stmt(int lane_var) {
         flush();
         nvar = nguard = nacc = nls = 0;
+        lc0 = lc1 = lc2 = lc3 = lc4 = lc5 = 0;
         gmask = 0;
         lane = lane_var;
         cur = nullptr;
@@ -418,9 +440,13 @@ struct BT {
             werr = true;
         } else if (st >= 2) {
             ArrInfo *A = &p->arr[arr];
-            const int64_t w = st * vec;
-            if (A->w && A->w != w) werr = true;
-            else AP::one([=] { A->w = w; });
+            const int64_t w = st * vec, w0 = width(arr);
+            if (w0 && w0 != w) {
+                werr = true;
+            } else {
+                set_width(arr, w);
+                AP::one([=] { A->w = w; });
+            }
         }
     }
     // `count` LDS accesses of `bytes` bytes per instance whose element index
@@ -433,8 +459,9 @@ struct BT {
         }
         const uint32_t site = lsite_pack(dir, z, lds_bin(stride * bytes / 4), count);
         const int k = nls++;
+        const int32_t tot = add_lds(dir * 3 + z, count);
         AP::one([=] {
-            s->lds[dir][z] += count;
+            s->lds[dir][z] = tot;
             s->lsite[k] = site;
         });
     }
@@ -444,6 +471,7 @@ struct BT {
             return;
         }
         ArrInfo *A = &p->arr[a];
+        set_width(a, 0);
         AP::one([=] {
             A->cells = cells;
             A->words = 0;
