@@ -146,9 +146,22 @@ __device__ __forceinline__ int build_block(const pm_variant &v, Prog *p, Job *jo
         sh[1 + t] = analyze_stmt(p, t, jobs, temp, 2 * t, 2 * t + 2, PM_SEQ, &made, keep);
     }
     __syncthreads();
-    if (t == 0) {
-        sh[1 + MAXSTMT] = 0;  // the fallback hands the buffers out again
-        sh[0] = build_slots_finish_seq(v, p, jobs, temp, sh + 1, keep, false);
+    if (t < 64) {
+        // the usual case, decided by the lanes together: every statement
+        // analysed in its two slots and no strided array, where the tail
+        // only records the job slots (build_tail with no footprint to place)
+        const int ns = p->nstmt, r = t < ns ? sh[1 + t] : PM_OK;
+        const bool plain = __ballot(r != PM_OK) == 0 && __ballot(t < p->narr && p->arr[t].w) == 0;
+        if (plain) {
+            if (t == 0) {
+                p->njob = 2 * ns;
+                p->bitmap_words = 0;
+                sh[0] = p->status;
+            }
+        } else if (t == 0) {
+            sh[1 + MAXSTMT] = 0;  // the fallback hands the buffers out again
+            sh[0] = build_slots_finish_seq(v, p, jobs, temp, sh + 1, keep, false);
+        }
     }
     __syncthreads();
     if (sh[0] == PM_OK && t < 64) {
@@ -476,12 +489,18 @@ k_build(int nv, const pm_variant *__restrict__ var, Prog *prog, Job *jobs, int32
     int ncj = -1;
     if (st == PM_OK && P.bitmap_words == 0 && !(P.flags & PM_FLAG_ENUMERATE)) {
         const bool cj = t < P.njob && P.jkind[t] == JOB_COUNT;
+        const uint64_t m = __ballot(cj);
         const int tb = cj ? P.jtmp[t] : -1;
-        int64_t items = cj ? (tb >= 0 ? U.jt[tb].items : vj[t].items) : 0;
-        items = xsum(items);
-        const uint64_t m = __ballot(cj), fm = __ballot(cj && tb < 0);
+        int64_t items = 0;
+        if (m) {  // (no count job: nothing to sum, nothing to place)
+            items = cj ? (tb >= 0 ? U.jt[tb].items : vj[t].items) : 0;
+            items = xsum(items);
+        }
+        const uint64_t fm = __ballot(cj && tb < 0);
         const int n = __popcll(m);
-        if (n <= NTEMP && items <= max_items) {
+        if (!m && items <= max_items) {
+            ncj = 0;
+        } else if (n <= NTEMP && items <= max_items) {
             uint32_t held = 0;
 #pragma unroll
             for (int b = 0; b < NTEMP; b++)
