@@ -374,7 +374,7 @@ __device__ __forceinline__ int finalize_block(const Prog &p, const int64_t *jobr
             if (k != C_BARWG && k != C_WG && k != C_WI && !slot_sum(p, k, F, Fill, sh.sc, &sh.c[k]))
                 sh.bad = 1;
     __syncthreads();
-    if (t == 0 && st == PM_OK) sh.c[C_BARWG] = p.wg_size ? sh.c[C_BARWI] / p.wg_size : 0;
+    if (t == 0 && st == PM_OK) sh.c[C_BARWG] = p.wg_size ? tdiv(sh.c[C_BARWI], p.wg_size) : 0;
     __syncthreads();
     const int st2 = st == PM_OK && sh.bad ? PM_EOVERFLOW : st;
     if (out)
