@@ -254,6 +254,22 @@ struct RowAff {
         return m;
     }
     static PM_HD void put(Aff *dst, const V &a) { *dst = a; }
+    // a new statement: every field zero, the extents 1, its lane variable
+    // and first access
+    static PM_HD void stmt_init(Stmt *s, int lane_var, int a0) {
+        for (size_t i = 0; i < sizeof(Stmt) / 8; i++) ((int64_t *)s)[i] = 0;
+        for (int i = 0; i < MAXVAR; i++) s->ext[i] = 1;
+        s->lane = lane_var;
+        s->acc0 = a0;
+    }
+    // a global access: its header and index map
+    static PM_HD void put_acc(GAcc *g, const V &idx, int arr, int dir, int elem, int vec) {
+        g->arr = arr;
+        g->dir = dir;
+        g->elem = elem;
+        g->vec = vec;
+        g->idx = idx;
+    }
     template <class F>
     static PM_HD void each(int n, F f) {  // f(i) for i < n
         for (int i = 0; i < n; i++) f(i);
@@ -285,6 +301,31 @@ struct LaneAff {
     static __device__ void put(Aff *dst, const V &a) {
         if (lane() <= MAXVAR) ((int64_t *)dst)[lane()] = a.v;  // c[0..MAXVAR), then k
     }
+    // the same two as RowAff's, each one store by the lanes together: word
+    // i of the statement by lane i (zero, 1 for the extents, the lane
+    // variable and acc0 in their half-words); the index map by lanes
+    // 0..MAXVAR as put() and the header's two words by the next two lanes
+    static __device__ void stmt_init(Stmt *s, int lane_var, int a0) {
+        constexpr int W = sizeof(Stmt) / 8, E0 = offsetof(Stmt, ext) / 8;
+        constexpr int A0 = offsetof(Stmt, acc0) / 8;
+        const int i = lane();
+        if (i < W) {
+            uint64_t v = i >= E0 && i < E0 + MAXVAR ? 1 : 0;
+            v = i == 0 ? (uint64_t)(uint32_t)lane_var << 32 : v;  // nvar 0, lane
+            v = i == A0 ? (uint64_t)(uint32_t)a0 : v;              // acc0, lds[0][0] 0
+            ((uint64_t *)s)[i] = v;
+        }
+    }
+    static __device__ void put_acc(GAcc *g, const V &idx, int arr, int dir, int elem, int vec) {
+        const int i = lane();
+        if (i <= MAXVAR + 2) {
+            const uint64_t h0 = (uint64_t)(uint32_t)dir << 32 | (uint32_t)arr;
+            const uint64_t h1 = (uint64_t)(uint32_t)vec << 32 | (uint32_t)elem;
+            const uint64_t v = i <= MAXVAR ? (uint64_t)idx.v : i == MAXVAR + 1 ? h0 : h1;
+            uint64_t *dst = i <= MAXVAR ? (uint64_t *)&g->idx + i : (uint64_t *)g + (i - MAXVAR - 1);
+            *dst = v;
+        }
+    }
     template <class F>
     static __device__ void each(int n, F f) {  // f(i) for i < n (n <= 64), lane i
         if (lane() < n) f(lane());
@@ -295,6 +336,11 @@ struct LaneAff {
     }
 };
 static_assert(offsetof(Aff, k) == MAXVAR * sizeof(int64_t), "row layout: c then k");
+static_assert(offsetof(Stmt, nvar) == 0 && offsetof(Stmt, lane) == 4 &&
+              offsetof(Stmt, acc0) % 8 == 0 && offsetof(Stmt, lds) == offsetof(Stmt, acc0) + 4 &&
+              offsetof(Stmt, ext) % 8 == 0, "statement words that stmt_init writes");
+static_assert(offsetof(GAcc, arr) == 0 && offsetof(GAcc, dir) == 4 && offsetof(GAcc, elem) == 8 &&
+              offsetof(GAcc, vec) == 12 && offsetof(GAcc, idx) == 16, "access header: two words");
 static_assert(sizeof(Stmt) % 8 == 0 && sizeof(Stmt) / 8 <= 64, "a statement is cleared one word per lane");
 static_assert(MAXJOB <= 64 && MAXVAR < 64, "LaneAff::each covers one wavefront");
 
@@ -370,14 +416,7 @@ struct BT {
         }
         Stmt *s = &p->st[nstmt++];
         cur = s;
-        // every field zero (one 8-byte word per lane), then the extents 1
-        AP::each((int)(sizeof(Stmt) / 8), [=](int i) { ((int64_t *)s)[i] = 0; });
-        AP::each(MAXVAR, [=](int i) { s->ext[i] = 1; });
-        const int a0 = nacc_all;
-        AP::one([=] {
-            s->lane = lane_var;
-            s->acc0 = a0;
-        });
+        AP::stmt_init(s, lane_var, nacc_all);
         return s;
     }
     // declare variables in order; returns their ids 0..  (The id does not
@@ -422,13 +461,7 @@ struct BT {
             return;
         }
         GAcc *g = &p->acc[nacc_all++];
-        AP::one([=] {
-            g->arr = arr;
-            g->dir = dir;
-            g->elem = elem;
-            g->vec = vec;
-        });
-        AP::put(&g->idx, idx);
+        AP::put_acc(g, idx, arr, dir, elem, vec);
         ++nacc;
         // the array's fill width: lane stride (in accesses) times the width
         // of a strided (stride >= 2) access
