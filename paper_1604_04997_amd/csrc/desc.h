@@ -262,6 +262,23 @@ struct RowAff {
         s->lane = lane_var;
         s->acc0 = a0;
     }
+    // a statement's extents as a form (coefficient x: variable x's extent),
+    // and their store with the statement's first ng guard rows
+    static PM_HD V ones() {
+        Aff a = aff(0);
+        for (int i = 0; i < MAXVAR; i++) a.c[i] = 1;
+        return a;
+    }
+    static PM_HD V set(V a, int x, int64_t v) {
+        a.c[x] = v;
+        return a;
+    }
+    static PM_HD void put_rows(Stmt *s, const V &ext, int ng, const V &g0, const V &g1,
+                               const V &g2, const V &g3) {
+        for (int x = 0; x < MAXVAR; x++) s->ext[x] = ext.c[x];
+        const V *g[4] = {&g0, &g1, &g2, &g3};
+        for (int q = 0; q < ng; q++) s->guard[q] = *g[q];
+    }
     // a global access: its header and index map
     static PM_HD void put_acc(GAcc *g, const V &idx, int arr, int dir, int elem, int vec) {
         g->arr = arr;
@@ -316,6 +333,23 @@ struct LaneAff {
             ((uint64_t *)s)[i] = v;
         }
     }
+    static __device__ V ones() { return V{1}; }
+    static __device__ V set(V a, int x, int64_t v) { return V{lane() == x ? v : a.v}; }
+    // lanes 0..MAXVAR together: the extents (lane x: variable x's; lane
+    // MAXVAR: guard row 0's constant, or 0 for a statement with no guard,
+    // whose zero rows stay zero), then each guard row as put()
+    static __device__ void put_rows(Stmt *s, const V &ext, int ng, const V &g0, const V &g1,
+                                    const V &g2, const V &g3) {
+        const int i = lane();
+        if (i <= MAXVAR) {
+            int64_t *row = (int64_t *)&s->guard[0];
+            *(i < MAXVAR ? &s->ext[i] : row + MAXVAR) = i < MAXVAR ? ext.v : ng > 0 ? g0.v : 0;
+            if (ng > 0) row[i] = g0.v;
+            if (ng > 1) row[(MAXVAR + 1) + i] = g1.v;
+            if (ng > 2) row[2 * (MAXVAR + 1) + i] = g2.v;
+            if (ng > 3) row[3 * (MAXVAR + 1) + i] = g3.v;
+        }
+    }
     static __device__ void put_acc(GAcc *g, const V &idx, int arr, int dir, int elem, int vec) {
         const int i = lane();
         if (i <= MAXVAR + 2) {
@@ -342,6 +376,7 @@ static_assert(offsetof(Stmt, nvar) == 0 && offsetof(Stmt, lane) == 4 &&
 static_assert(offsetof(GAcc, arr) == 0 && offsetof(GAcc, dir) == 4 && offsetof(GAcc, elem) == 8 &&
               offsetof(GAcc, vec) == 12 && offsetof(GAcc, idx) == 16, "access header: two words");
 static_assert(sizeof(Stmt) % 8 == 0 && sizeof(Stmt) / 8 <= 64, "a statement is cleared one word per lane");
+static_assert(MAXGUARD == 4 && sizeof(Aff) == (MAXVAR + 1) * 8, "put_rows: four guard rows of MAXVAR + 1 words");
 static_assert(MAXJOB <= 64 && MAXVAR < 64, "LaneAff::each covers one wavefront");
 
 template <class AP>
@@ -365,6 +400,12 @@ struct BT {
     // keeps them in scalar registers whatever the index
     int32_t lc0 = 0, lc1 = 0, lc2 = 0, lc3 = 0, lc4 = 0, lc5 = 0;
     int64_t aw0 = 0, aw1 = 0, aw2 = 0, aw3 = 0, aw4 = 0, aw5 = 0;
+    // the current statement's extents and guard rows, stored by flush()
+    // with one store each instead of one per declaration
+    V extv = AP::ones(), g0 = AP::mk(0), g1 = AP::mk(0), g2 = AP::mk(0), g3 = AP::mk(0);
+    PM_HD void set_guard(int q, const V &a) {
+        g0 = q == 0 ? a : g0, g1 = q == 1 ? a : g1, g2 = q == 2 ? a : g2, g3 = q == 3 ? a : g3;
+    }
     static_assert(MAXARR == 6, "one width register per array");
     PM_HD int64_t width(int a) const {
         return a == 0 ? aw0 : a == 1 ? aw1 : a == 2 ? aw2 : a == 3 ? aw3 : a == 4 ? aw4 : aw5;
@@ -391,6 +432,7 @@ struct BT {
         const int nv = nvar, ng = nguard, na = nacc, ns = nstmt, naa = nacc_all, nar = narr;
         const uint64_t gm = gmask;
         Prog *pp = p;
+        if (s) AP::put_rows(s, extv, ng, g0, g1, g2, g3);
         AP::one([=] {
             if (s) {
                 s->nvar = nv;
@@ -407,6 +449,8 @@ struct BT {
         flush();
         nvar = nguard = nacc = nls = 0;
         lc0 = lc1 = lc2 = lc3 = lc4 = lc5 = 0;
+        extv = AP::ones();
+        g0 = g1 = g2 = g3 = AP::mk(0);
         gmask = 0;
         lane = lane_var;
         cur = nullptr;
@@ -430,7 +474,7 @@ struct BT {
         }
         if (ext < 0) fail(PM_EINVAL);
         const int x = nvar;
-        AP::one([=] { s->ext[x] = ext; });
+        extv = AP::set(extv, x, ext);
         return nvar++;
     }
     // affine forms of this builder
@@ -441,7 +485,7 @@ struct BT {
             fail(PM_EINVAL);
             return;
         }
-        AP::put(&s->guard[nguard], a);
+        set_guard(nguard, a);
         gmask |= AP::vars(a) << (8 * nguard);
         ++nguard;
     }
