@@ -273,8 +273,13 @@ struct RowAff {
         a.c[x] = v;
         return a;
     }
-    static PM_HD void put_rows(Stmt *s, const V &ext, int ng, const V &g0, const V &g1,
-                               const V &g2, const V &g3) {
+    static PM_HD void put_rows(Stmt *s, int nv, int ln, int ng, int na, uint64_t gm, const V &ext,
+                               const V &g0, const V &g1, const V &g2, const V &g3) {
+        s->nvar = nv;
+        s->lane = ln;
+        s->nguard = ng;
+        s->nacc = na;
+        s->gmask = gm;
         for (int x = 0; x < MAXVAR; x++) s->ext[x] = ext.c[x];
         const V *g[4] = {&g0, &g1, &g2, &g3};
         for (int q = 0; q < ng; q++) s->guard[q] = *g[q];
@@ -335,13 +340,20 @@ struct LaneAff {
     }
     static __device__ V ones() { return V{1}; }
     static __device__ V set(V a, int x, int64_t v) { return V{lane() == x ? v : a.v}; }
-    // lanes 0..MAXVAR together: the extents (lane x: variable x's; lane
-    // MAXVAR: guard row 0's constant, or 0 for a statement with no guard,
-    // whose zero rows stay zero), then each guard row as put()
-    static __device__ void put_rows(Stmt *s, const V &ext, int ng, const V &g0, const V &g1,
-                                    const V &g2, const V &g3) {
+    // lanes 0..MAXVAR together: the statement's first three words (its
+    // counts and guard mask; lanes 0 and 1 the first two, the others the
+    // third, equal values to one address), the extents (lane x: variable x's; lane MAXVAR: guard row
+    // 0's constant, or 0 for a statement with no guard, whose zero rows
+    // stay zero), then each guard row as put()
+    static __device__ void put_rows(Stmt *s, int nv, int ln, int ng, int na, uint64_t gm,
+                                    const V &ext, const V &g0, const V &g1, const V &g2,
+                                    const V &g3) {
         const int i = lane();
         if (i <= MAXVAR) {
+            const int w = i < 2 ? i : 2;
+            const uint64_t hw = w == 0 ? (uint64_t)(uint32_t)ln << 32 | (uint32_t)nv
+                              : w == 1 ? (uint64_t)(uint32_t)na << 32 | (uint32_t)ng : gm;
+            ((uint64_t *)s)[w] = hw;
             int64_t *row = (int64_t *)&s->guard[0];
             *(i < MAXVAR ? &s->ext[i] : row + MAXVAR) = i < MAXVAR ? ext.v : ng > 0 ? g0.v : 0;
             if (ng > 0) row[i] = g0.v;
@@ -377,6 +389,8 @@ static_assert(offsetof(GAcc, arr) == 0 && offsetof(GAcc, dir) == 4 && offsetof(G
               offsetof(GAcc, vec) == 12 && offsetof(GAcc, idx) == 16, "access header: two words");
 static_assert(sizeof(Stmt) % 8 == 0 && sizeof(Stmt) / 8 <= 64, "a statement is cleared one word per lane");
 static_assert(MAXGUARD == 4 && sizeof(Aff) == (MAXVAR + 1) * 8, "put_rows: four guard rows of MAXVAR + 1 words");
+static_assert(offsetof(Stmt, nguard) == 8 && offsetof(Stmt, nacc) == 12 && offsetof(Stmt, gmask) == 16,
+              "put_rows: counts and guard mask in words 1 and 2");
 static_assert(MAXJOB <= 64 && MAXVAR < 64, "LaneAff::each covers one wavefront");
 
 template <class AP>
@@ -390,7 +404,8 @@ struct BT {
     int nvar = 0, nguard = 0, nacc = 0, lane = 0, nls = 0;
     // the program's statement, access and array counts and the current
     // statement's guard variable mask, also kept here (the program starts
-    // empty); flush() stores them, once per statement and at the end
+    // empty); flush() stores the statement's once it is complete and the
+    // program's at the end
     int nstmt = 0, nacc_all = 0, narr = 0;
     uint64_t gmask = 0;
     bool werr = false;  // an access with no whole lane stride, or two widths on one array
@@ -424,26 +439,21 @@ struct BT {
     PM_HD void fail(int st) {
         if (p->status == PM_OK) p->status = st;
     }
-    // store the counts kept in registers (the current statement's and the
-    // program's); the builder calls it when it starts a statement, the
-    // caller when the family's builder has returned
-    PM_HD void flush() {
+    // store what is kept in registers: the current statement's counts,
+    // guard mask, extents and guard rows when it starts the next statement,
+    // and with `last` (the caller, when the family's builder has returned)
+    // also the program's counts
+    PM_HD void flush(bool last = false) {
         Stmt *s = cur;
-        const int nv = nvar, ng = nguard, na = nacc, ns = nstmt, naa = nacc_all, nar = narr;
-        const uint64_t gm = gmask;
+        const int ns = nstmt, naa = nacc_all, nar = narr;
         Prog *pp = p;
-        if (s) AP::put_rows(s, extv, ng, g0, g1, g2, g3);
-        AP::one([=] {
-            if (s) {
-                s->nvar = nv;
-                s->nguard = ng;
-                s->nacc = na;
-                s->gmask = gm;
-            }
-            pp->nstmt = ns;
-            pp->nacc_all = naa;
-            pp->narr = nar;
-        });
+        if (s) AP::put_rows(s, nvar, lane, nguard, nacc, gmask, extv, g0, g1, g2, g3);
+        if (last)
+            AP::one([=] {
+                pp->nstmt = ns;
+                pp->nacc_all = naa;
+                pp->narr = nar;
+            });
     }
     PM_HD Stmt *stmt(int lane_var) {
         flush();
@@ -1483,7 +1493,7 @@ PM_HD int build_head(const pm_variant &v, Prog *p, Job *jobs) {
     case PM_FAM_NBODY: build_nbody(b, v); break;
     default: b.fail(PM_EINVAL);
     }
-    b.flush();
+    b.flush(true);
     AP::each(MAXJOB, [=](int j) {
         p->jkind[j] = JOB_NONE;
         p->jtmp[j] = -1;
