@@ -1386,57 +1386,50 @@ PM_HD int64_t lane_stride(const Stmt &s, const GAcc &a) {
 //   F    = union over x of its cells (a contiguous run when step <= vec,
 //          else cnt disjoint accesses of vec cells),
 //   Fill = union over x of [first, last cell + w)   (strided access), or F.
-// The sizes then follow in closed form (ival_sizes).
-PM_HD bool ival_ok(const Job &J) {
-    if (J.nv > 2 || J.f[J.ng][0] <= 0) return false;
-    if (J.nv == 2 && J.f[J.ng][1] <= 0) return false;
-    int64_t lo = 0, hi = J.ext[0];
-    for (int q = 0; q < J.ng; q++) {
-        if (J.nv == 2 && J.f[q][0] && J.f[q][1]) return false;
-        if (!J.f[q][0]) continue;
-        int64_t a = J.f[q][0], r = J.f[q][MAXVAR];
-        if (a > 0) {
-            int64_t t = ceil_div(-r, a);
-            if (t > lo) lo = t;
-        } else {
-            int64_t t = fdiv(r, -a) + 1;
-            if (t < hi) hi = t;
-        }
-    }
-    int64_t cnt = hi > lo ? hi - lo : 0;
-    int64_t step = J.f[J.ng][0], vec = J.vec;
-    if (cnt == 0) return true;
-    if (step > vec && J.nv == 2 && J.f[J.ng][1] < step * (cnt - 1) + vec) return false;  // runs interleave
-    if (J.w && step >= vec + J.w) return false;  // widened accesses leave gaps
-    return true;
-}
-
+// The sizes then follow in closed form (ival).
 // |F| and |Fill| of an array in interval mode.  Non-empty outer points x
 // form an interval of nx values; each covers cnt accesses first(x) +
 // step*t, first(x) = a0 + c1*x.  A run of accesses spans
 // L = step*(cnt-1) + vec cells and, widened, Lf = L - 1 + w; nx runs spaced
 // c1 apart cover L + (nx-1)*min(L, c1) cells when each run is contiguous
 // (step <= vec) and nx*cnt*vec cells otherwise (runs are disjoint).
-PM_HD int ival_sizes(const Job &J, int64_t *F, int64_t *Fill) {
+// One pass over the guards gives the inner range [lo, hi) (guards on t),
+// the outer one [xlo, xhi) (guards on x) and whether a guard on no
+// variable fails (the domain is empty).  *ok: the array qualifies (no
+// guard couples t and x, runs do not interleave, widened accesses leave no
+// gaps; an empty inner range qualifies); then F, Fill and the status (0, 0
+// and PM_OK for an empty domain; PM_EOVERFLOW), else 0, 0 and PM_OK.
+PM_HD int ival(const Job &J, bool *ok, int64_t *F, int64_t *Fill) {
+    *ok = false;
+    *F = *Fill = 0;
+    if (J.nv > 2 || J.f[J.ng][0] <= 0) return PM_OK;
+    if (J.nv == 2 && J.f[J.ng][1] <= 0) return PM_OK;
     int64_t lo = 0, hi = J.ext[0], xlo = 0, xhi = J.nv == 2 ? J.ext[1] : 1;
+    bool cempty = false;
     for (int q = 0; q < J.ng; q++) {
-        int v = J.f[q][0] ? 0 : (J.nv == 2 && J.f[q][1]) ? 1 : -1;
-        int64_t a = v >= 0 ? J.f[q][v] : 0, r = J.f[q][MAXVAR];
-        int64_t &l = v == 1 ? xlo : lo, &h = v == 1 ? xhi : hi;
-        if (v < 0) {
-            if (r < 0) h = l;
-        } else if (a > 0) {
-            int64_t t = ceil_div(-r, a);
+        const int64_t a = J.f[q][0], b = J.nv == 2 ? J.f[q][1] : 0, r = J.f[q][MAXVAR];
+        if (a && b) return PM_OK;
+        const int64_t c = a ? a : b;
+        int64_t &l = a ? lo : xlo, &h = a ? hi : xhi;
+        if (!c) {
+            if (r < 0) cempty = true;
+        } else if (c > 0) {
+            const int64_t t = ceil_div(-r, c);
             if (t > l) l = t;
         } else {
-            int64_t t = fdiv(r, -a) + 1;
+            const int64_t t = fdiv(r, -c) + 1;
             if (t < h) h = t;
         }
     }
-    *F = *Fill = 0;
-    int64_t cnt = hi - lo, nx = xhi - xlo;
-    if (cnt <= 0 || nx <= 0) return PM_OK;
-    int64_t step = J.f[J.ng][0], vec = J.vec, c1 = J.nv == 2 ? J.f[J.ng][1] : 0;
+    const int64_t cnt = hi > lo ? hi - lo : 0, step = J.f[J.ng][0], vec = J.vec;
+    if (cnt != 0) {
+        if (step > vec && J.nv == 2 && J.f[J.ng][1] < step * (cnt - 1) + vec) return PM_OK;
+        if (J.w && step >= vec + J.w) return PM_OK;
+    }
+    *ok = true;
+    const int64_t nx = xhi - xlo;
+    if (cempty || cnt <= 0 || nx <= 0) return PM_OK;
+    const int64_t c1 = J.nv == 2 ? J.f[J.ng][1] : 0;
     int64_t L, Lf, t;
     bool ovf = mul_ovf(step, cnt - 1, &L) || add_ovf(L, vec, &L);
     if (step <= vec) {
@@ -1787,10 +1780,13 @@ PM_HD int analyze_stmt(Prog *p, int si, Job *jobs, TEMP temp, int base, int cap,
             if (mul_ovf(J.outer, J.nseg, &J.items)) return PM_EOVERFLOW;
             J.chunk_items = CHUNK_FOOT;
             J.chunks = cdiv(J.items, CHUNK_FOOT);
-            J.ivok = ival_ok(J);
-            J.ivst = PM_OK;
-            J.ivF = J.ivFill = 0;
-            if (J.ivok) J.ivst = ival_sizes(J, &J.ivF, &J.ivFill);
+            bool ok;
+            int64_t fF, fFill;
+            const int ist = ival(J, &ok, &fF, &fFill);
+            J.ivok = ok;
+            J.ivst = ist;
+            J.ivF = fF;
+            J.ivFill = fFill;
             return 1;
         };
         Job &Jf = jt ? *jt : jobs[nj];
@@ -1815,7 +1811,7 @@ PM_HD int build_tail(const pm_variant &v, Prog *p, Job *jobs, int nj,
     auto JB = [&](int j) -> Job & { return keep && p->jtmp[j] >= 0 ? keep[p->jtmp[j]] : jobs[j]; };
 
     // Each strided array: interval mode when its footprint is a sequence of
-    // equally spaced runs (ival_ok, sizes in closed form), else bitmaps.
+    // equally spaced runs (ival: sizes in closed form), else bitmaps.
     int64_t off = 0;
     for (int ai = 0; ai < p->narr; ai++) {
         ArrInfo &A = p->arr[ai];
